@@ -1,0 +1,474 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.  A plain, slow, obviously correct CPU
+ * reference for the SPD solve of the paper (Klavik, Malossi, Bekas, Curioni,
+ * "Changing Computing Paradigms Towards Power Efficiency", Section 3.1).
+ *
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load this library.  It shares no code, header or constant with the GPU
+ * library; both are fed from the seeded generators in spdgen/.
+ *
+ * Conventions: every matrix is column-major (element (i,j) at p[i + j*ld]),
+ * indices are 0-based inside the code, `info` is 1-based like LAPACK.  A is
+ * symmetric and only its lower triangle (i >= j) is ever read.
+ *
+ * Contents
+ *   oracle_potrf     Cholesky A = L L^T (Section 3.1: A = R^T R with R = L^T)
+ *   oracle_fsub      forward substitution  L Y = B   (first half of Eq. (3))
+ *   oracle_bsub      back substitution   L^T X = Y   (second half of Eq. (3))
+ *   oracle_residual  R = B - A X in binary64 (Algorithm 1, residual step)
+ *   oracle_norm1_sym / oracle_backward_error  norms and eta
+ *   oracle_rne_f16 / oracle_rne_bf16  binary32 -> binary16 / bfloat16 rounding
+ *                    to nearest even, from the formats' definitions
+ *   oracle_ir        Algorithm 1 emulated step by step with a low-precision
+ *                    factor (binary32, or binary16/bfloat16 operands with
+ *                    binary32 accumulation) and binary64 residual/update.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define IDX(i, j, ld) ((size_t)(i) + (size_t)(j) * (size_t)(ld))
+
+/* ------------------------------------------------------------------------ */
+/* Cholesky factorisation A = L L^T, L lower with positive diagonal.
+ * Definition (Section 3.1; Golub & Van Loan's outer-product form):
+ *   for j = 0..n-1:
+ *     L_jj = sqrt(a_jj - sum_{k<j} L_jk^2)       (fail if radicand <= 0)
+ *     L_ij = (a_ij - sum_{k<j} L_ik L_jk) / L_jj  for i > j
+ * Written right-looking: after column j is final, its outer product is
+ * subtracted from the trailing lower triangle.  Returns 0, or the 1-based
+ * column whose radicand is not positive (L is then partially written).
+ * L may alias A only if ldl == lda and L == A. */
+int64_t oracle_potrf(int64_t n, const double *A, int64_t lda, double *L, int64_t ldl)
+{
+    if (L != A)
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < n; ++i)
+                L[IDX(i, j, ldl)] = (i >= j) ? A[IDX(i, j, lda)] : 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        double piv = L[IDX(j, j, ldl)];
+        if (!(piv > 0.0)) /* also catches NaN */
+            return j + 1;
+        double ljj = sqrt(piv);
+        L[IDX(j, j, ldl)] = ljj;
+        for (int64_t i = j + 1; i < n; ++i)
+            L[IDX(i, j, ldl)] /= ljj;
+        /* trailing update  a_ik -= L_ij L_kj  for j < k <= i */
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t k = j + 1; k < n; ++k) {
+            double lkj = L[IDX(k, j, ldl)];
+            for (int64_t i = k; i < n; ++i)
+                L[IDX(i, k, ldl)] -= L[IDX(i, j, ldl)] * lkj;
+        }
+    }
+    return 0;
+}
+
+/* Forward substitution, in place: Y <- L^{-1} Y for m columns (Eq. (3)). */
+void oracle_fsub(int64_t n, int64_t m, const double *L, int64_t ldl, double *Y, int64_t ldy)
+{
+    for (int64_t c = 0; c < m; ++c) {
+        double *y = Y + (size_t)c * (size_t)ldy;
+        for (int64_t j = 0; j < n; ++j) {
+            y[j] /= L[IDX(j, j, ldl)];
+            double yj = y[j];
+            for (int64_t i = j + 1; i < n; ++i)
+                y[i] -= L[IDX(i, j, ldl)] * yj;
+        }
+    }
+}
+
+/* Back substitution, in place: Y <- L^{-T} Y for m columns (Eq. (3)). */
+void oracle_bsub(int64_t n, int64_t m, const double *L, int64_t ldl, double *Y, int64_t ldy)
+{
+    for (int64_t c = 0; c < m; ++c) {
+        double *y = Y + (size_t)c * (size_t)ldy;
+        for (int64_t j = n - 1; j >= 0; --j) {
+            double s = y[j];
+            for (int64_t i = j + 1; i < n; ++i)
+                s -= L[IDX(i, j, ldl)] * y[i];
+            y[j] = s / L[IDX(j, j, ldl)];
+        }
+    }
+}
+
+/* Full solve X = L^{-T} L^{-1} B (Eq. (3)); X may alias B. */
+void oracle_potrs(int64_t n, int64_t m, const double *L, int64_t ldl,
+                  const double *B, int64_t ldb, double *X, int64_t ldx)
+{
+    if (X != B)
+        for (int64_t c = 0; c < m; ++c)
+            memcpy(X + (size_t)c * ldx, B + (size_t)c * ldb, (size_t)n * sizeof(double));
+    oracle_fsub(n, m, L, ldl, X, ldx);
+    oracle_bsub(n, m, L, ldl, X, ldx);
+}
+
+/* Symmetric element a_ij read from the lower triangle. */
+static inline double sym(const double *A, int64_t lda, int64_t i, int64_t j)
+{
+    return (i >= j) ? A[IDX(i, j, lda)] : A[IDX(j, i, lda)];
+}
+
+/* R = B - A X in binary64, A symmetric (lower triangle read).  Each residual
+ * entry is the plain sum b_i - sum_j a_ij x_j taken in index order. */
+void oracle_residual(int64_t n, int64_t m, const double *A, int64_t lda,
+                     const double *X, int64_t ldx, const double *B, int64_t ldb,
+                     double *R, int64_t ldr)
+{
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t c = 0; c < m; ++c)
+        for (int64_t i = 0; i < n; ++i) {
+            const double *x = X + (size_t)c * ldx;
+            double s = B[IDX(i, c, ldb)];
+            for (int64_t j = 0; j < n; ++j)
+                s -= sym(A, lda, i, j) * x[j];
+            R[IDX(i, c, ldr)] = s;
+        }
+}
+
+/* Residual of a subset of rows (used on large systems, where a full residual
+ * is too slow for a spot check): R[k, c] for the rows listed in `rows`. */
+void oracle_residual_rows(int64_t n, int64_t m, const double *A, int64_t lda,
+                          const double *X, int64_t ldx, const double *B, int64_t ldb,
+                          int64_t nrows, const int64_t *rows, double *R /* nrows x m */)
+{
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t c = 0; c < m; ++c)
+        for (int64_t k = 0; k < nrows; ++k) {
+            int64_t i = rows[k];
+            const double *x = X + (size_t)c * ldx;
+            double s = B[IDX(i, c, ldb)];
+            for (int64_t j = 0; j < n; ++j)
+                s -= sym(A, lda, i, j) * x[j];
+            R[IDX(k, c, nrows)] = s;
+        }
+}
+
+/* ||A||_inf = max_i sum_j |a_ij| (= ||A||_1 for symmetric A). */
+double oracle_norminf_sym(int64_t n, const double *A, int64_t lda)
+{
+    double best = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            s += fabs(sym(A, lda, i, j));
+        if (!(s <= best)) /* propagate NaN */
+            best = s;
+    }
+    return best;
+}
+
+static double vec_maxabs(int64_t n, const double *v)
+{
+    double best = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double a = fabs(v[i]);
+        if (!(a <= best))
+            best = a;
+    }
+    return best;
+}
+
+/* Normwise relative backward error per column, infinity norm:
+ *   eta_c = ||r_c||_inf / (||A||_inf ||x_c||_inf + ||b_c||_inf)
+ * with r_c = b_c - A x_c in binary64.  (The paper's loop test uses ||r||_2
+ * against an absolute tolerance; this scale-free form is the reading used to
+ * define "FP64-accurate".) */
+void oracle_backward_error(int64_t n, int64_t m, const double *A, int64_t lda,
+                           const double *X, int64_t ldx, const double *B, int64_t ldb,
+                           double *eta)
+{
+    double *R = (double *)malloc((size_t)n * (size_t)m * sizeof(double));
+    oracle_residual(n, m, A, lda, X, ldx, B, ldb, R, n);
+    double an = oracle_norminf_sym(n, A, lda);
+    for (int64_t c = 0; c < m; ++c) {
+        double rn = vec_maxabs(n, R + (size_t)c * n);
+        double xn = vec_maxabs(n, X + (size_t)c * ldx);
+        double bn = vec_maxabs(n, B + (size_t)c * ldb);
+        double den = an * xn + bn;
+        eta[c] = (den > 0.0) ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+        if (rn != rn)
+            eta[c] = NAN;
+    }
+    free(R);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rounding binary32 -> binary16 / bfloat16, round to nearest, ties to even,
+ * written from the formats' definitions (IEEE 754-2008 binary16: 1 sign,
+ * 5 exponent bits with bias 15, 10 fraction bits; bfloat16: the top 16 bits of
+ * binary32).  The result is returned widened back to binary32, which is exact. */
+static uint32_t f2u(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
+static float u2f(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
+
+float oracle_rne_f16(float x)
+{
+    if (x != x)
+        return x;
+    float a = fabsf(x);
+    float sgn = signbit(x) ? -1.0f : 1.0f;
+    /* largest finite binary16 is 65504; values at or above 65520 round to inf */
+    if (a >= 65520.0f)
+        return sgn * INFINITY;
+    /* quantum (spacing) of binary16 at |x|: 2^(e-10) for normal e >= -14,
+     * 2^-24 for the subnormal range */
+    int e;
+    frexpf(a, &e);           /* a = f * 2^e, f in [0.5, 1) -> unbiased exponent e-1 */
+    int ue = e - 1;
+    if (ue < -14)
+        ue = -14;
+    double q = ldexp(1.0, ue - 10);
+    double t = (double)a / q;        /* exact: a has 24 bits, q a power of two */
+    double r = nearbyint(t);         /* default rounding mode: ties to even */
+    return sgn * (float)(r * q);
+}
+
+float oracle_rne_bf16(float x)
+{
+    uint32_t u = f2u(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u)    /* NaN: keep it a quiet NaN */
+        return u2f((u | 0x00400000u) & 0xffff0000u);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;                     /* round half to even on bit 16 */
+    return u2f(u & 0xffff0000u);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1 (Cholesky with iterative refinement), emulated.
+ *
+ * Precision codes: 0 = bfloat16 operands, 1 = binary16 operands,
+ * 2 = binary32, 3 = binary64.  Status codes: 0 ok, 2 not SPD, 3 no convergence.
+ *
+ * Steps, in the paper's order, with the readings this project takes where the
+ * paper is silent:
+ *   scaling  D = diag(a_ii)^(-1/2) (for binary16/bfloat16/binary32 when
+ *            `equil` is set), mu = largest power of two <= theta * 65504 for
+ *            binary16 and 1 otherwise; H = round32(mu * D A D).
+ *   line 1   low-precision factor H ~ L L^T: right-looking Cholesky in binary32
+ *            arithmetic; for binary16/bfloat16 every update product uses the
+ *            operands rounded to that format (binary32 accumulation).
+ *            binary64 factors A itself in binary64.
+ *   line 2   x = s mu D L^{-T} L^{-1} round32(D b / s), s a power of two
+ *            normalising max |D b| (per column); binary32 substitution.
+ *   line 3   r = b - A x in binary64; eta per column as above.
+ *   line 4   the loop ends when max_c eta_c <= 2^-50 (binary64 floor), or
+ *            when eta <= tol and the last step shrank eta by less than half.
+ *            Divergence (only while eta > tol): eta not finite, eta above the
+ *            first eta, or two consecutive steps with eta_k > 0.9 eta_{k-1}.
+ *            At most `max_iter` corrections; then success iff eta <= tol.
+ *   line 5-7 z from the same low-precision solve of r; x += z (binary64);
+ *            new residual.
+ *   fallback on breakdown or divergence: binary16/bfloat16 -> binary32 ->
+ *            binary64 (if `fallback` is set).
+ * Iteration counts: low = number of low-precision solves (incl. line 2),
+ * high = number of binary64 residuals, both for the final precision.
+ */
+typedef struct {
+    int32_t status, prec_used, iters_low, iters_high, fallbacks;
+    int64_t info;
+    double eta;
+} oracle_report;
+
+static float round_op(float v, int prec)
+{
+    if (prec == 0) return oracle_rne_bf16(v);
+    if (prec == 1) return oracle_rne_f16(v);
+    return v;
+}
+
+/* binary32 Cholesky of the n x n lower triangle of H (column-major, ld n),
+ * operands of every update rounded to `prec`; accumulation in binary32. */
+static int64_t potrf_lowprec(int64_t n, float *H, int prec)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        float piv = H[IDX(j, j, n)];
+        if (!(piv > 0.0f))
+            return j + 1;
+        float ljj = sqrtf(piv);
+        H[IDX(j, j, n)] = ljj;
+        for (int64_t i = j + 1; i < n; ++i)
+            H[IDX(i, j, n)] /= ljj;
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t k = j + 1; k < n; ++k) {
+            float lkj = round_op(H[IDX(k, j, n)], prec);
+            for (int64_t i = k; i < n; ++i)
+                H[IDX(i, k, n)] -= round_op(H[IDX(i, j, n)], prec) * lkj;
+        }
+    }
+    return 0;
+}
+
+static void solve_f32(int64_t n, const float *L, float *y)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        y[j] /= L[IDX(j, j, n)];
+        float yj = y[j];
+        for (int64_t i = j + 1; i < n; ++i)
+            y[i] -= L[IDX(i, j, n)] * yj;
+    }
+    for (int64_t j = n - 1; j >= 0; --j) {
+        float s = y[j];
+        for (int64_t i = j + 1; i < n; ++i)
+            s -= L[IDX(i, j, n)] * y[i];
+        y[j] = s / L[IDX(j, j, n)];
+    }
+}
+
+/* power of two s with s/2 < v <= s (1 for v == 0 or non-finite) */
+/* Refinement keeps going past the requested tolerance while it still
+ * contracts, down to a few units of binary64 roundoff: eta <= tol alone leaves
+ * a forward error of about cond * tol, not cond * u. */
+#define ETA_FLOOR (0x1p-50)
+
+static double pow2_ceil(double v)
+{
+    if (!(v > 0.0) || isinf(v))
+        return 1.0;
+    int e;
+    double f = frexp(v, &e); /* v = f 2^e, f in [0.5,1) */
+    return (f == 0.5) ? ldexp(1.0, e - 1) : ldexp(1.0, e);
+}
+
+/* One attempt of Algorithm 1 at precision `prec`.  Returns status. */
+static int ir_attempt(int64_t n, int64_t m, const double *A, int64_t lda,
+                      const double *B, int64_t ldb, double *X, int64_t ldx, int prec,
+                      int equil, double theta, double tol, int max_iter,
+                      oracle_report *rep)
+{
+    size_t nn = (size_t)n * (size_t)n;
+    double *d = (double *)malloc((size_t)n * sizeof(double));
+    double *R = (double *)malloc((size_t)n * (size_t)m * sizeof(double));
+    double *eta = (double *)malloc((size_t)m * sizeof(double));
+    double *prev = (double *)malloc((size_t)m * sizeof(double));
+    float *y = (float *)malloc((size_t)n * sizeof(float));
+    double *L64 = NULL;
+    float *L32 = NULL;
+    double mu = 1.0;
+    int status = 0;
+    rep->info = 0;
+    rep->iters_low = rep->iters_high = 0;
+    rep->eta = NAN;
+
+    /* scaling (not in the paper; needed so binary16 neither overflows nor underflows) */
+    for (int64_t i = 0; i < n; ++i) {
+        double a = A[IDX(i, i, lda)];
+        d[i] = (prec != 3 && equil && a > 0.0) ? 1.0 / sqrt(a) : 1.0;
+    }
+    if (prec == 1) {
+        /* largest power of two <= theta * 65504 */
+        int e;
+        frexp(theta * 65504.0, &e);
+        mu = ldexp(1.0, e - 1);
+    }
+
+    /* line 1: low-precision factorisation */
+    if (prec == 3) {
+        L64 = (double *)malloc(nn * sizeof(double));
+        rep->info = oracle_potrf(n, A, lda, L64, n);
+    } else {
+        L32 = (float *)malloc(nn * sizeof(float));
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < n; ++i)
+                L32[IDX(i, j, n)] = (i >= j) ? (float)(mu * d[i] * A[IDX(i, j, lda)] * d[j]) : 0.0f;
+        rep->info = potrf_lowprec(n, L32, prec);
+    }
+    if (rep->info) {
+        status = 2;
+        goto done;
+    }
+
+    /* line 2 (first solve, from r = b) and lines 5-6 (corrections) share one
+     * routine: z = s mu D L^{-T} L^{-1} round(D r / s) */
+    for (int64_t c = 0; c < m; ++c)
+        for (int64_t i = 0; i < n; ++i)
+            X[IDX(i, c, ldx)] = 0.0;
+    for (int64_t c = 0; c < m; ++c)
+        for (int64_t i = 0; i < n; ++i)
+            R[IDX(i, c, n)] = B[IDX(i, c, ldb)];
+    int stalls = 0;
+    double eta0 = 0.0, prev_worst = 0.0;
+    for (;;) {
+        /* low-precision solve of the current residual, then x += z */
+        for (int64_t c = 0; c < m; ++c) {
+            double *r = R + (size_t)c * n;
+            if (prec == 3) {
+                oracle_fsub(n, 1, L64, n, r, n);
+                oracle_bsub(n, 1, L64, n, r, n);
+                for (int64_t i = 0; i < n; ++i)
+                    X[IDX(i, c, ldx)] += r[i];
+            } else {
+                double mx = 0.0;
+                for (int64_t i = 0; i < n; ++i)
+                    if (fabs(d[i] * r[i]) > mx) mx = fabs(d[i] * r[i]);
+                double s = pow2_ceil(mx);
+                for (int64_t i = 0; i < n; ++i)
+                    y[i] = (float)(d[i] * r[i] / s);
+                solve_f32(n, L32, y);
+                for (int64_t i = 0; i < n; ++i)
+                    X[IDX(i, c, ldx)] += s * mu * d[i] * (double)y[i];
+            }
+        }
+        rep->iters_low++;
+        /* binary64 residual and backward error */
+        oracle_residual(n, m, A, lda, X, ldx, B, ldb, R, n);
+        rep->iters_high++;
+        double an = oracle_norminf_sym(n, A, lda);
+        double worst = 0.0;
+        int finite = 1;
+        for (int64_t c = 0; c < m; ++c) {
+            double rn = vec_maxabs(n, R + (size_t)c * n);
+            double den = an * vec_maxabs(n, X + (size_t)c * ldx) + vec_maxabs(n, B + (size_t)c * ldb);
+            eta[c] = (den > 0.0) ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+            if (!isfinite(eta[c]) || rn != rn)
+                finite = 0;
+            if (eta[c] > worst) worst = eta[c];
+        }
+        rep->eta = finite ? worst : NAN;
+        if (!finite) { status = 3; break; }
+        /* binary64 floor reached: nothing more to gain */
+        if (worst <= ETA_FLOOR) { status = 0; break; }
+        if (rep->iters_high == 1) {
+            eta0 = worst;
+        } else {
+            /* inside the tolerance and no longer contracting: accept */
+            if (worst <= tol && worst > 0.5 * prev_worst) { status = 0; break; }
+            int stall = 1;
+            for (int64_t c = 0; c < m; ++c)
+                if (!(eta[c] > 0.9 * prev[c])) stall = 0;
+            stalls = stall ? stalls + 1 : 0;
+            if (worst > tol && (worst > eta0 || stalls >= 2)) { status = 3; break; }
+        }
+        if (rep->iters_low > max_iter) { status = (worst <= tol) ? 0 : 3; break; }
+        prev_worst = worst;
+        memcpy(prev, eta, (size_t)m * sizeof(double));
+    }
+done:
+    free(d); free(R); free(eta); free(prev); free(y); free(L64); free(L32);
+    return status;
+}
+
+int32_t oracle_ir(int64_t n, int64_t m, const double *A, int64_t lda,
+                  const double *B, int64_t ldb, double *X, int64_t ldx,
+                  int32_t prec, int32_t equil, double theta, double tol, int32_t max_iter,
+                  int32_t fallback, oracle_report *rep)
+{
+    rep->fallbacks = 0;
+    for (;;) {
+        rep->prec_used = prec;
+        int st = ir_attempt(n, m, A, lda, B, ldb, X, ldx, prec, equil, theta, tol, max_iter, rep);
+        rep->status = st;
+        if (st == 0 || !fallback || prec == 3)
+            return st;
+        prec = (prec < 2) ? 2 : 3;
+        rep->fallbacks++;
+    }
+}
+
+/* Threads the OpenMP runtime would use (reported beside CPU timings). */
+#ifdef _OPENMP
+#include <omp.h>
+int32_t oracle_threads(void) { return omp_get_max_threads(); }
+#else
+int32_t oracle_threads(void) { return 1; }
+#endif

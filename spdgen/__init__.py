@@ -1,0 +1,256 @@
+"""Seeded synthetic inputs for the SPD solve A X = B (Eq. (1)-(2) of the paper).
+
+This module only *builds inputs*: it holds none of the solver's arithmetic
+(no factorisation, no substitution, no refinement).  Both the CPU oracle and
+the GPU library are fed from here, so that they provably see identical bytes.
+
+Recipes
+-------
+* ``logspaced(n, cond, seed)``: A = Q diag(lambda) Q^T with Q from the QR of a
+  seeded N(0,1) n x n matrix (column signs fixed so diag(R) > 0) and lambda
+  log-spaced from 1 to ``cond``; then A <- (A + A^T)/2 so A is exactly
+  symmetric.  cond_2(A) = ``cond`` up to rounding.
+* ``rhs(n, m, seed)``: X_true ~ N(0,1), column-major n x m.
+* ``accurate_product(A, X)``: B = A X computed in double-double (error-free
+  products by Veltkamp/Dekker splitting, pairwise TwoSum reduction), so the
+  rounding of B does not pollute a forward-error check against X_true.
+* Closed-form matrices used as pins: the [-1, 2, -1] tridiagonal, min(i, j),
+  Hilbert, and the paper's model covariance matrix (Section 4:
+  a_ij = 1/|i-j|^d off the diagonal, 1 + sqrt(i) on it, 1-based i).
+* ``indefinite(n, j0, seed)``: an exactly symmetric matrix whose Cholesky
+  factorisation breaks down at column j0 (1-based) with a clearly negative
+  radicand.
+
+Seeds follow ``seed_G = 2**20 * config + 2 * system`` and ``seed_X = seed_G + 1``.
+Small n use numpy's PCG64 on the CPU; ``backend="torch"`` builds the same
+recipe with torch on a device (Philox), used for n >= 16384 where a CPU QR
+would take minutes.
+"""
+from __future__ import annotations
+
+import hashlib
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "seeds", "logspaced", "rhs", "accurate_product", "system",
+    "tridiag", "minij", "hilbert", "covariance", "indefinite",
+    "batch_shapes", "sha256", "SPDSystem",
+]
+
+
+def seeds(config: int, system: int = 0) -> tuple[int, int]:
+    g = (1 << 20) * config + 2 * system
+    return g, g + 1
+
+
+def _eigs(n: int, cond: float, xp, **kw):
+    if n == 1:
+        return xp.ones(1, **kw)
+    i = xp.arange(n, **kw)
+    return float(cond) ** (i / (n - 1))
+
+
+def logspaced(n: int, cond: float, seed: int, backend: str = "numpy", device=None):
+    """A = Q diag(lambda) Q^T, lambda_i = cond^((i-1)/(n-1)); exactly symmetric."""
+    if backend == "numpy":
+        rng = np.random.Generator(np.random.PCG64(seed))
+        G = rng.standard_normal((n, n))
+        Q, R = np.linalg.qr(G)
+        Q = Q * np.sign(np.diag(R))[None, :]
+        lam = _eigs(n, cond, np, dtype=np.float64)
+        A = (Q * lam[None, :]) @ Q.T
+        A = 0.5 * (A + A.T)
+        return np.asfortranarray(A)
+    if backend == "torch":
+        import torch
+        gen = torch.Generator(device=device)
+        gen.manual_seed(seed)
+        G = torch.randn(n, n, dtype=torch.float64, device=device, generator=gen)
+        Q, R = torch.linalg.qr(G)
+        del G
+        Q = Q * torch.sign(torch.diagonal(R))[None, :]
+        del R
+        lam = _eigs(n, cond, torch, dtype=torch.float64, device=device)
+        A = (Q * lam[None, :]) @ Q.T
+        del Q
+        A = 0.5 * (A + A.T)
+        # column-major view: A is symmetric, so A.T (contiguous as A^T) has the
+        # same values; callers read it with lda = n.
+        return A.contiguous()
+    raise ValueError(f"unknown backend {backend!r}")
+
+
+def rhs(n: int, m: int, seed: int, backend: str = "numpy", device=None):
+    """X_true ~ N(0,1), column-major: returned as an (m, n) row-major array whose
+    row c is column c of X (so the memory layout is column-major n x m)."""
+    if backend == "numpy":
+        rng = np.random.Generator(np.random.PCG64(seed))
+        return rng.standard_normal((m, n))
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    return torch.randn(m, n, dtype=torch.float64, device=device, generator=gen)
+
+
+# --- error-free transformations for an accurate right-hand side --------------
+_SPLIT = 134217729.0  # 2**27 + 1 (Veltkamp splitting constant for binary64)
+
+
+def _split(a):
+    c = a * _SPLIT
+    hi = c - (c - a)
+    return hi, a - hi
+
+
+def _two_prod(a, b):
+    p = a * b
+    ah, al = _split(a)
+    bh, bl = _split(b)
+    e = al * bl - (((p - ah * bh) - al * bh) - ah * bl)
+    return p, e
+
+
+def _two_sum(a, b):
+    s = a + b
+    bb = s - a
+    e = (a - (s - bb)) + (b - bb)
+    return s, e
+
+
+def _dd_rowsum(hi, lo, xp):
+    """Pairwise double-double reduction of hi+lo along axis 1."""
+    while hi.shape[1] > 1:
+        if hi.shape[1] % 2:
+            z = xp.zeros_like(hi[:, :1])
+            hi = xp.concatenate([hi, z], axis=1) if xp is np else xp.cat([hi, z], dim=1)
+            lo = xp.concatenate([lo, z], axis=1) if xp is np else xp.cat([lo, z], dim=1)
+        s, e = _two_sum(hi[:, 0::2], hi[:, 1::2])
+        lo = lo[:, 0::2] + lo[:, 1::2] + e
+        hi = s
+    return hi[:, 0] + lo[:, 0]
+
+
+def accurate_product(A, Xt, row_chunk: int | None = None):
+    """B = A X in double-double, rounded once to binary64.
+
+    ``A`` is symmetric n x n; ``Xt`` holds X column-major as (m, n).  Returns Bt
+    with the same (m, n) layout.  Works on numpy arrays or torch tensors.
+    """
+    is_np = isinstance(A, np.ndarray)
+    if is_np:
+        xp = np
+        out = np.empty_like(Xt)
+    else:
+        import torch as xp  # noqa: N813
+        out = xp.empty_like(Xt)
+    n = A.shape[0]
+    if row_chunk is None:
+        row_chunk = n if n <= 4096 else 2048
+    for c in range(Xt.shape[0]):
+        x = Xt[c]
+        for r0 in range(0, n, row_chunk):
+            blk = A[r0:r0 + row_chunk, :]
+            p, e = _two_prod(blk, x[None, :])
+            out[c, r0:r0 + row_chunk] = _dd_rowsum(p, e, xp)
+    return out
+
+
+@dataclass
+class SPDSystem:
+    A: np.ndarray          # n x n symmetric (column-major == row-major)
+    Xt: np.ndarray         # (m, n): column c of X_true
+    Bt: np.ndarray         # (m, n): column c of B = A X_true (double-double)
+    cond: float
+    seed_G: int
+    seed_X: int
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[0]
+
+    @property
+    def m(self) -> int:
+        return self.Xt.shape[0]
+
+
+def system(n: int, cond: float, m: int, config: int = 0, index: int = 0,
+           backend: str = "numpy", device=None) -> SPDSystem:
+    sg, sx = seeds(config, index)
+    A = logspaced(n, cond, sg, backend=backend, device=device)
+    Xt = rhs(n, m, sx, backend=backend, device=device)
+    Bt = accurate_product(A, Xt)
+    return SPDSystem(A, Xt, Bt, cond, sg, sx)
+
+
+# --- closed-form matrices (pins) --------------------------------------------
+def tridiag(n: int) -> np.ndarray:
+    """The [-1, 2, -1] second-difference matrix."""
+    A = 2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    return np.asfortranarray(A)
+
+
+def minij(n: int) -> np.ndarray:
+    """a_ij = min(i, j) (1-based); its Cholesky factor is the all-ones lower triangle."""
+    i = np.arange(1, n + 1, dtype=np.float64)
+    return np.asfortranarray(np.minimum.outer(i, i))
+
+
+def hilbert(n: int) -> np.ndarray:
+    i = np.arange(1, n + 1, dtype=np.float64)
+    return np.asfortranarray(1.0 / (i[:, None] + i[None, :] - 1.0))
+
+
+def covariance(n: int, d: float) -> np.ndarray:
+    """Model covariance matrix of Section 4: 1/|i-j|^d off the diagonal, 1+sqrt(i) on it (1-based i)."""
+    i = np.arange(1, n + 1, dtype=np.float64)
+    dist = np.abs(i[:, None] - i[None, :])
+    with np.errstate(divide="ignore"):
+        A = 1.0 / dist ** d
+    A[np.arange(n), np.arange(n)] = 1.0 + np.sqrt(i)
+    return np.asfortranarray(A)
+
+
+def indefinite(n: int, j0: int, seed: int = 7) -> np.ndarray:
+    """Symmetric A = M S M^T with M unit lower triangular (small random
+    off-diagonal entries, exactly representable) and S = diag(1,..,1,-1,1,..)
+    with the -1 at 1-based position j0.  The leading j0-1 pivots of the
+    Cholesky factorisation are exactly 1 and pivot j0 is exactly -1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    # entries are multiples of 1/8 in [-1/2, 1/2] so every product and sum in
+    # M S M^T is exact in binary64 for modest n.
+    M = np.tril(np.round(rng.uniform(-0.5, 0.5, (n, n)) * 8.0) / 8.0, -1) + np.eye(n)
+    s = np.ones(n)
+    s[j0 - 1] = -1.0
+    A = (M * s[None, :]) @ M.T
+    A = 0.5 * (A + A.T)
+    return np.asfortranarray(A)
+
+
+def batch_shapes(batch: int, config: int = 3, nmin: int = 32, nmax: int = 512,
+                 logc: tuple[float, float] = (1.0, 6.0), mmax: int = 8):
+    """Per-system (n, cond, m) for a batch: n ~ U{nmin..nmax}, cond = 10^U(logc), m ~ U{1..mmax}."""
+    rng = np.random.Generator(np.random.PCG64((1 << 20) * config + (1 << 19)))
+    ns = rng.integers(nmin, nmax + 1, size=batch)
+    conds = 10.0 ** rng.uniform(logc[0], logc[1], size=batch)
+    ms = rng.integers(1, mmax + 1, size=batch)
+    return [(int(a), float(b), int(c)) for a, b, c in zip(ns, conds, ms)]
+
+
+def sha256(arr) -> str:
+    if not isinstance(arr, np.ndarray):
+        arr = arr.detach().cpu().numpy()
+    return hashlib.sha256(np.ascontiguousarray(arr).tobytes()).hexdigest()
+
+
+def rnd_unif_rhs(n: int, m: int, seed: int) -> np.ndarray:
+    """Right-hand sides with entries uniform in [0, 1], as in Section 4 of the paper; (m, n)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(0.0, 1.0, (m, n))
+
+
+def log_uniform(lo: float, hi: float, size: int, seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return 10.0 ** rng.uniform(math.log10(lo), math.log10(hi), size=size)

@@ -1,0 +1,188 @@
+/*
+ * spd.h -- C ABI of libspd: mixed-precision Cholesky with iterative
+ * refinement for dense symmetric positive-definite systems on MI355X (gfx950).
+ *
+ * The problem is the paper's Eq. (1)-(2) (Klavik, Malossi, Bekas, Curioni,
+ * "Changing Computing Paradigms Towards Power Efficiency", Section 3):
+ *     A X = B,  A in R^{n x n} symmetric positive definite,  B, X in R^{n x m}.
+ * The method is its Algorithm 1 (Section 3.1): factor A ~ R^T R once in low
+ * precision, solve with the factor, then repeat { residual r = b - A x in
+ * binary64; correction z from the low-precision factor; x += z } until x is
+ * accurate to binary64 level.  This library stores L = R^T (lower triangular).
+ *
+ * Memory and ownership
+ *   - Every matrix argument is binary64 (double), COLUMN-MAJOR, in DEVICE
+ *     memory owned by the caller: element (i, j) of A is A[i + j*lda].
+ *   - Only the lower triangle (i >= j) of A is read; A is never written.
+ *   - A factor handle (spd_factor_t) owns every device buffer it allocates
+ *     (the low-precision factor, the equilibration vector, workspace); the
+ *     caller releases it with spd_factor_destroy.
+ *   - `hip_stream` is a hipStream_t (NULL = the null stream).  Work is ordered
+ *     on that stream; the library may fork internal streams of default
+ *     priority and always joins them back before returning.
+ *
+ * Errors
+ *   - Nothing throws across this ABI.  Argument errors are reported before
+ *     any device work (SPD_ERR_INVALID_ARG).  HIP runtime failures map to
+ *     SPD_ERR_DEVICE / SPD_ERR_OUT_OF_MEMORY.  spd_status_str() names a code.
+ *   - `info` follows LAPACK: 0 on success, else the 1-based column at which
+ *     the Cholesky radicand was not positive (A not SPD to the working
+ *     precision).
+ */
+#ifndef SPD_H
+#define SPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPD_OK = 0,
+    SPD_ERR_INVALID_ARG = 1,
+    SPD_ERR_NOT_SPD = 2,          /* a non-positive pivot; see `info` */
+    SPD_ERR_NO_CONVERGENCE = 3,   /* refinement diverged or ran out of iterations */
+    SPD_ERR_DEVICE = 4,
+    SPD_ERR_OUT_OF_MEMORY = 5,
+    SPD_ERR_UNSUPPORTED = 6
+} spd_status;
+
+/* Precision of the factorisation (the "low precision" of Algorithm 1).
+ * BF16/FP16: the trailing-update operands are rounded to that format and
+ * multiplied with binary32 accumulation, after symmetric diagonal
+ * equilibration (and, for FP16, a power-of-two scale).  FP32: binary32
+ * throughout.  FP64: plain binary64 Cholesky (the baseline and the last
+ * fallback).  AUTO: chosen per system by the library (batched entry point). */
+typedef enum { SPD_BF16 = 0, SPD_FP16 = 1, SPD_FP32 = 2, SPD_FP64 = 3, SPD_AUTO = 4 } spd_prec;
+
+/* Options; passing NULL means the defaults shown. */
+typedef struct {
+    double tol;          /* accept when the backward error eta <= tol (1e-14) */
+    int32_t max_iter;    /* maximum number of corrections (10) */
+    int32_t fallback;    /* on breakdown/divergence retry BF16/FP16 -> FP32 -> FP64 (1) */
+    int32_t equilibrate; /* scale by D = diag(a_ii)^{-1/2} before rounding (1) */
+    double theta;        /* FP16 headroom: mu = largest 2^k <= theta * 65504 (0.1) */
+} spd_opts;
+
+/* Outcome of a refinement (host memory).  iters_low counts low-precision
+ * solves including the first one; iters_high counts binary64 residuals, both
+ * for the precision finally used; eta is the final max backward error
+ * max_c ||b_c - A x_c||_inf / (||A||_inf ||x_c||_inf + ||b_c||_inf). */
+typedef struct {
+    int32_t status;
+    int32_t prec_used;
+    int32_t iters_low;
+    int32_t iters_high;
+    int32_t fallbacks;
+    int64_t info;
+    double eta;
+} spd_report;
+
+typedef struct spd_factor_s *spd_factor_t;
+
+/* Fill *o with the defaults. */
+void spd_opts_default(spd_opts *o);
+
+/* Algorithm 1, line 1: low-precision Cholesky factorisation of the lower
+ * triangle of A (n x n, leading dimension lda >= max(1, n)) at precision
+ * `prec` (BF16, FP16, FP32 or FP64).  If *F is NULL a new handle is created;
+ * a non-NULL *F from an earlier call is reused (its buffers are kept when they
+ * are large enough).  On return *info is 0 or the 1-based failing column, and
+ * the status is SPD_OK or SPD_ERR_NOT_SPD (the handle stays valid either way).
+ * Synchronises `hip_stream` once, to read the breakdown flag. */
+spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec,
+                      const spd_opts *o, void *hip_stream, spd_factor_t *F, int64_t *info);
+
+/* Algorithm 1, line 2: X = L^{-T} L^{-1} B with the handle's low-precision
+ * factor (binary32 substitution), including the equilibration scaling:
+ * X = s mu D L^{-T} L^{-1} round32(D B / s), s a power of two per column.
+ * B (n x nrhs, ldb >= n) is read; X (n x nrhs, ldx >= n) is written; X may
+ * equal B.  Asynchronous on `hip_stream`. */
+spd_status spd_solve(spd_factor_t F, const double *B, int64_t ldb, int64_t nrhs,
+                     double *X, int64_t ldx, void *hip_stream);
+
+/* Algorithm 1, lines 3-7: starting from the iterate in X, repeat
+ * { R = B - A X (binary64); eta; Z = low-precision solve of R; X += Z }
+ * until eta reaches the binary64 floor (2^-51), or eta <= o->tol and the
+ * last step no longer halves it; divergence (eta not finite, above the first
+ * eta, or stagnating while above tol) or max_iter corrections end it.  With
+ * o->fallback set, breakdown or divergence re-factors A at the next
+ * precision (BF16/FP16 -> FP32 -> FP64; F then holds that precision) and
+ * restarts from X = solve(B).  A must be the matrix F was built from.
+ * Synchronises `hip_stream` once per iteration (to read eta); *rep (host) is
+ * filled and rep->status equals the returned status. */
+spd_status spd_refine(spd_factor_t F, const double *A, int64_t lda, const double *B, int64_t ldb,
+                      int64_t nrhs, double *X, int64_t ldx, const spd_opts *o,
+                      spd_report *rep, void *hip_stream);
+
+/* The whole of Algorithm 1 in one call: spd_factor + spd_solve + spd_refine,
+ * with the fallback chain applied from the factorisation on.  *F as in
+ * spd_factor (reused if non-NULL). */
+spd_status spd_posv(const double *A, int64_t n, int64_t lda, const double *B, int64_t ldb,
+                    int64_t nrhs, double *X, int64_t ldx, spd_prec prec, const spd_opts *o,
+                    spd_report *rep, void *hip_stream, spd_factor_t *F);
+
+/* Algorithm 1, lines 3 and 7, on their own: R = B - A X in binary64 for the
+ * symmetric A (lower triangle read; n x n, lda >= n), X and B n x nrhs.
+ * R (device, ldr >= n) receives the residual unless NULL; eta (HOST array of
+ * nrhs, or NULL) receives the normwise backward errors
+ * ||r_c||_inf / (||A||_inf ||x_c||_inf + ||b_c||_inf).  Allocates its own
+ * scratch; synchronises `hip_stream` when eta is requested. */
+spd_status spd_residual(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx, const double *B,
+                        int64_t ldb, int64_t nrhs, double *R, int64_t ldr, double *eta, void *hip_stream);
+
+/* Many independent systems (Eq. (2) per system) in one persistent launch.
+ * Device arrays of length `batch`: n[s], nrhs[s], a_off[s] (offset of system
+ * s's matrix in A, in elements; leading dimension n[s]), b_off[s] (offset of
+ * its right-hand sides in B and of its solution in X; leading dimension
+ * n[s]); prec[s] is the requested precision on input (AUTO allowed) and the
+ * one used on output; reps[s] is written (device memory).  No host
+ * synchronisation; graph-capturable after a first uncaptured call with the
+ * same batch. Returns SPD_OK when every system converged, else the first
+ * failing status. */
+spd_status spd_solve_batched(int64_t batch, const int32_t *n, const int32_t *nrhs,
+                             const int64_t *a_off, const double *A, const int64_t *b_off,
+                             const double *B, double *X, spd_prec *prec, const spd_opts *o,
+                             spd_report *reps, void *hip_stream);
+
+/* Release every device buffer the handle owns.  NULL is ignored. */
+void spd_factor_destroy(spd_factor_t F);
+
+/* Introspection of a handle: n, the precision held, the panel width. */
+spd_status spd_factor_query(spd_factor_t F, int64_t *n, int32_t *prec, int32_t *nb);
+
+/* Copy the handle's factor out for inspection: Lout (device, binary64, n x n,
+ * ldl >= n) receives L of H = mu D A D ~ L L^T (zeros above the diagonal),
+ * dout (device, n) receives D's diagonal, *mu (host) the scale.  Any output
+ * pointer may be NULL.  Stream-ordered on `hip_stream`. */
+spd_status spd_factor_export(spd_factor_t F, double *Lout, int64_t ldl, double *dout,
+                             double *mu, void *hip_stream);
+
+/* Kernel timing for measurement tools.  While enabled, the library brackets
+ * every launch of the kernel classes below with HIP events recorded on the
+ * stream that launch uses, and tallies the algorithmic work of each launch:
+ *   SPD_K_UPDATE   trailing update H_ij -= L_ik L_jk^T (flops of the lower
+ *                  triangle, bytes = tiles of H read and written once plus
+ *                  their two panel operands)
+ *   SPD_K_RESIDUAL binary64 residual (2 n^2 m flops; bytes = the lower
+ *                  triangle of A plus X, B and R)
+ * spd_profile_query synchronises on the recorded events, folds them into the
+ * totals and returns launches, summed milliseconds, flops and bytes.  Not
+ * thread-safe against concurrent factorisations; meant for benchmarks. */
+enum { SPD_K_UPDATE = 0, SPD_K_RESIDUAL = 1, SPD_K_COUNT = 2 };
+void spd_profile_enable(int on);
+void spd_profile_reset(void);
+spd_status spd_profile_query(int kernel, int64_t *launches, double *total_ms, double *total_flops,
+                             double *total_bytes);
+
+/* Human-readable name of a status code (static string). */
+const char *spd_status_str(spd_status s);
+
+/* Library version string (static). */
+const char *spd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPD_H */

@@ -252,7 +252,7 @@ float oracle_rne_bf16(float x)
  *   line 2   x = s mu D L^{-T} L^{-1} round32(D b / s), s a power of two
  *            normalising max |D b| (per column); binary32 substitution.
  *   line 3   r = b - A x in binary64; eta per column as above.
- *   line 4   the loop ends when max_c eta_c <= 2^-50 (binary64 floor), or
+ *   line 4   the loop ends when max_c eta_c <= 2^-51 (binary64 floor), or
  *            when eta <= tol and the last step shrank eta by less than half.
  *            Divergence (only while eta > tol): eta not finite, eta above the
  *            first eta, or two consecutive steps with eta_k > 0.9 eta_{k-1}.
@@ -315,12 +315,13 @@ static void solve_f32(int64_t n, const float *L, float *y)
     }
 }
 
-/* power of two s with s/2 < v <= s (1 for v == 0 or non-finite) */
 /* Refinement keeps going past the requested tolerance while it still
  * contracts, down to a few units of binary64 roundoff: eta <= tol alone leaves
- * a forward error of about cond * tol, not cond * u. */
-#define ETA_FLOOR (0x1p-50)
+ * a forward error of about cond * tol, not cond * u; the relative forward
+ * error is at most about 2 cond eta, so 4u keeps it below 10 cond u. */
+#define ETA_FLOOR (0x1p-51)
 
+/* power of two s with s/2 < v <= s (1 for v == 0 or non-finite) */
 static double pow2_ceil(double v)
 {
     if (!(v > 0.0) || isinf(v))

@@ -1,0 +1,282 @@
+"""Python binding of libspd: mixed-precision Cholesky with iterative
+refinement for dense SPD systems on MI355X (gfx950).
+
+This module only marshals arguments to the C ABI declared in include/spd.h;
+every step of the computation runs in the library's HIP kernels.  There is no
+fallback: if libspd.so is missing or cannot be loaded, every call raises.
+PyTorch supplies device memory and the current stream.
+
+Layouts
+  A   (n, n) float64 CUDA tensor.  Column-major storage (A.stride(0) == 1) is
+      read as is; a row-major contiguous tensor is read as the column-major
+      matrix A^T -- identical for the symmetric matrices this library solves.
+      Only the lower triangle (of the column-major view) is read.
+  B, X  (n,) vectors or (m, n) row-major tensors whose row c is right-hand
+      side c -- i.e. the column-major n x m layout of Eq. (2).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspd.so")
+_lib = None
+
+# status and precision codes (spd.h)
+OK, ERR_INVALID_ARG, ERR_NOT_SPD, ERR_NO_CONVERGENCE, ERR_DEVICE, ERR_OUT_OF_MEMORY, ERR_UNSUPPORTED = range(7)
+PREC = {"bf16": 0, "fp16": 1, "fp32": 2, "fp64": 3, "auto": 4}
+PREC_NAME = {v: k for k, v in PREC.items()}
+
+
+class SPDError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+
+
+class Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("fallback", C.c_int32),
+                ("equilibrate", C.c_int32), ("theta", C.c_double)]
+
+
+class Report(C.Structure):
+    _fields_ = [("status", C.c_int32), ("prec_used", C.c_int32), ("iters_low", C.c_int32),
+                ("iters_high", C.c_int32), ("fallbacks", C.c_int32), ("info", C.c_int64),
+                ("eta", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# exported entry points: (name, restype, argtypes)
+_vp, _i64, _i32, _f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+_SIGS = [
+    ("spd_opts_default", None, [C.POINTER(Opts)]),
+    ("spd_factor", C.c_int, [_vp, _i64, _i64, C.c_int, C.POINTER(Opts), _vp, C.POINTER(_vp), C.POINTER(_i64)]),
+    ("spd_solve", C.c_int, [_vp, _vp, _i64, _i64, _vp, _i64, _vp]),
+    ("spd_refine", C.c_int, [_vp, _vp, _i64, _vp, _i64, _i64, _vp, _i64, C.POINTER(Opts), C.POINTER(Report), _vp]),
+    ("spd_posv", C.c_int, [_vp, _i64, _i64, _vp, _i64, _i64, _vp, _i64, C.c_int, C.POINTER(Opts),
+                           C.POINTER(Report), _vp, C.POINTER(_vp)]),
+    ("spd_residual", C.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _vp]),
+    ("spd_solve_batched", C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Opts), _vp, _vp]),
+    ("spd_factor_destroy", None, [_vp]),
+    ("spd_factor_query", C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32)]),
+    ("spd_factor_export", C.c_int, [_vp, _vp, _i64, _vp, C.POINTER(_f64), _vp]),
+    ("spd_profile_enable", None, [C.c_int]),
+    ("spd_profile_reset", None, []),
+    ("spd_profile_query", C.c_int, [C.c_int, C.POINTER(_i64), C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64)]),
+    ("spd_status_str", C.c_char_p, [C.c_int]),
+    ("spd_version", C.c_char_p, []),
+]
+
+
+def load(path: str | None = None):
+    """Load libspd.so (raises if it is missing: there is no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libspd.so not built ({p}); run `python -m paper_1405_4644_amd.build`")
+    lib = C.CDLL(p)
+    for name, res, args in _SIGS:
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_str(s: int) -> str:
+    return load().spd_status_str(int(s)).decode()
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    load().spd_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_dev(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+
+
+def _mat(A):
+    _check_dev(A, "A")
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    n = A.shape[0]
+    if A.stride(0) == 1 and (n <= 1 or A.stride(1) >= n):
+        ld = max(A.stride(1), 1)
+    elif A.stride(1) == 1:
+        ld = max(A.stride(0), 1)
+    else:
+        raise ValueError("A must have unit stride in one dimension")
+    return C.c_void_p(A.data_ptr()), n, max(ld, n, 1)
+
+
+def _rhs(B, n, name="B"):
+    _check_dev(B, name)
+    if B.dim() == 1:
+        if B.shape[0] != n or (n > 1 and B.stride(0) != 1):
+            raise ValueError(f"{name} must have length n and unit stride")
+        return C.c_void_p(B.data_ptr()), max(n, 1), 1
+    if B.dim() != 2 or B.shape[1] != n or (n > 1 and B.stride(1) != 1):
+        raise ValueError(f"{name} must be (m, n) with unit stride along n")
+    return C.c_void_p(B.data_ptr()), max(B.stride(0), n, 1), B.shape[0]
+
+
+class Factor:
+    """Owns an spd_factor_t handle (released by close() or garbage collection)."""
+
+    def __init__(self):
+        self.h = C.c_void_p()
+
+    def close(self):
+        if self.h:
+            load().spd_factor_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self):
+        n, p, nb = C.c_int64(), C.c_int32(), C.c_int32()
+        st = load().spd_factor_query(self.h, C.byref(n), C.byref(p), C.byref(nb))
+        if st:
+            raise SPDError(st, "spd_factor_query")
+        return {"n": n.value, "prec": PREC_NAME[p.value], "nb": nb.value}
+
+
+def _prec(p):
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+def factor(A, prec="fp32", opts: Opts | None = None, F: Factor | None = None, check=True):
+    """spd_factor: returns (Factor, info).  Raises on errors other than NOT_SPD unless check=False."""
+    lib = load()
+    pa, n, lda = _mat(A)
+    F = F or Factor()
+    info = C.c_int64()
+    st = lib.spd_factor(pa, n, lda, _prec(prec), C.byref(opts) if opts else None, _stream(),
+                        C.byref(F.h), C.byref(info))
+    if check and st not in (OK, ERR_NOT_SPD):
+        raise SPDError(st, "spd_factor")
+    return F, int(info.value), st
+
+
+def solve(F: Factor, B, X=None):
+    """spd_solve (Algorithm 1, line 2).  Returns X."""
+    torch = _torch()
+    n = F.query()["n"]
+    pb, ldb, m = _rhs(B, n)
+    if X is None:
+        X = torch.empty_like(B)
+    px, ldx, _ = _rhs(X, n, "X")
+    st = load().spd_solve(F.h, pb, ldb, m, px, ldx, _stream())
+    if st:
+        raise SPDError(st, "spd_solve")
+    return X
+
+
+def refine(F: Factor, A, B, X, opts: Opts | None = None) -> Report:
+    """spd_refine (Algorithm 1, lines 3-7), X updated in place; returns the Report."""
+    pa, n, lda = _mat(A)
+    pb, ldb, m = _rhs(B, n)
+    px, ldx, _ = _rhs(X, n, "X")
+    rep = Report()
+    load().spd_refine(F.h, pa, lda, pb, ldb, m, px, ldx, C.byref(opts) if opts else None, C.byref(rep),
+                      _stream())
+    return rep
+
+
+def posv(A, B, prec="fp32", opts: Opts | None = None, F: Factor | None = None, X=None):
+    """The whole of Algorithm 1: returns (X, Report, Factor)."""
+    torch = _torch()
+    pa, n, lda = _mat(A)
+    pb, ldb, m = _rhs(B, n)
+    if X is None:
+        X = torch.empty_like(B)
+    px, ldx, _ = _rhs(X, n, "X")
+    F = F or Factor()
+    rep = Report()
+    load().spd_posv(pa, n, lda, pb, ldb, m, px, ldx, _prec(prec), C.byref(opts) if opts else None,
+                    C.byref(rep), _stream(), C.byref(F.h))
+    return X, rep, F
+
+
+def residual(A, X, B, want_R=True):
+    """spd_residual: returns (R or None, eta as a list) -- binary64 residual and backward errors."""
+    import numpy as np
+    torch = _torch()
+    pa, n, lda = _mat(A)
+    pb, ldb, m = _rhs(B, n)
+    px, ldx, _ = _rhs(X, n, "X")
+    R = torch.empty_like(B) if want_R else None
+    pr, ldr = (_rhs(R, n, "R")[:2]) if want_R else (None, max(n, 1))
+    eta = np.zeros(m, dtype=np.float64)
+    st = load().spd_residual(pa, n, lda, px, ldx, pb, ldb, m, pr, ldr,
+                             eta.ctypes.data_as(C.c_void_p), _stream())
+    if st:
+        raise SPDError(st, "spd_residual")
+    return R, eta
+
+
+def export(F: Factor):
+    """Returns (L, d, mu): the factor of H = mu D A D as an (n, n) float64 tensor
+    in column-major storage (use L.T for the row-major view), and D's diagonal."""
+    torch = _torch()
+    n = F.query()["n"]
+    # allocate as (n, n) row-major; the library writes column-major, so the
+    # tensor holds L^T when read row-major.
+    Lt = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    d = torch.empty(n, dtype=torch.float64, device="cuda")
+    mu = C.c_double()
+    st = load().spd_factor_export(F.h, C.c_void_p(Lt.data_ptr()), max(n, 1), C.c_void_p(d.data_ptr()),
+                                  C.byref(mu), _stream())
+    if st:
+        raise SPDError(st, "spd_factor_export")
+    return Lt.T, d, mu.value
+
+
+K_UPDATE, K_RESIDUAL = 0, 1
+
+
+def profile_enable(on: bool = True):
+    load().spd_profile_enable(int(bool(on)))
+
+
+def profile_reset():
+    load().spd_profile_reset()
+
+
+def profile_query(kernel: int):
+    """(launches, total_ms, total_flops, total_bytes) for a kernel class."""
+    n, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+    st = load().spd_profile_query(int(kernel), C.byref(n), C.byref(ms), C.byref(fl), C.byref(by))
+    if st:
+        raise SPDError(st, "spd_profile_query")
+    return n.value, ms.value, fl.value, by.value
+
+
+def version() -> str:
+    return load().spd_version().decode()

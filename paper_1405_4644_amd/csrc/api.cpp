@@ -1,0 +1,736 @@
+// libspd host runtime and C ABI (see include/spd.h).
+//
+// Drivers for Algorithm 1 of the paper (Cholesky with mixed-precision
+// iterative refinement, Section 3.1): the blocked low-precision factorisation
+// with one panel of lookahead on a second stream, the substitutions, and the
+// binary64 refinement loop with its stopping/divergence rules and the
+// precision fallback chain (the convergence condition of Eq. (4) is what the
+// divergence test guards against).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "spd.h"
+
+#define SPD_TILE_H 128
+#define SPD_IB_H 32
+#define SPD_INFO_NONE_H 0x7fffffffffffffffULL
+
+struct spd_factor_s {
+    int device = 0;
+    int64_t n = 0, npad = 0;
+    int prec = -1;
+    int elem = 0;            // bytes per factor element (4 or 8)
+    size_t cap_L = 0;        // allocated bytes of L / W / Winv
+    void *L = nullptr;       // npad x npad, column-major, lower used
+    void *W = nullptr;       // nt blocks NB x NB: inverses of the diagonal blocks
+    void *Winv = nullptr;    // npad/32 blocks 32 x 32: inverses of the 32-wide diagonal sub-blocks
+    double *d = nullptr;     // n: equilibration
+    int64_t cap_d = 0;
+    double mu = 1.0;
+    unsigned long long *info_dev = nullptr;
+    unsigned long long *info_host = nullptr;  // pinned
+    // solve workspace
+    void *Y = nullptr, *Z = nullptr;
+    size_t cap_YZ = 0;
+    double *smax = nullptr;
+    int64_t cap_smax = 0;
+    // refinement workspace
+    double *R = nullptr;
+    size_t cap_R = 0;
+    double *P = nullptr;
+    size_t cap_P = 0;
+    double *norms = nullptr, *norms_host = nullptr;
+    int64_t cap_norms = 0;
+    hipStream_t side = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+// ---- optional kernel timing (spd_profile_*) ----
+struct ProfRec {
+    hipEvent_t a, b;
+    int kind;
+    double flops, bytes;
+};
+struct ProfTotals {
+    int64_t launches = 0;
+    double ms = 0, flops = 0, bytes = 0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+ProfTotals g_prof_tot[SPD_K_COUNT];
+
+// Returns an event recorded before the launch (or nullptr when disabled).
+hipEvent_t prof_begin(hipStream_t st)
+{
+    if (!g_prof_on) return nullptr;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    hipEventRecord(e, st);
+    return e;
+}
+
+void prof_end(hipEvent_t a, hipStream_t st, int kind, double flops, double bytes)
+{
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) != hipSuccess) {
+        hipEventDestroy(a);
+        return;
+    }
+    hipEventRecord(b, st);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_pending.push_back({a, b, kind, flops, bytes});
+}
+
+// algorithmic work of one trailing-update launch over tile columns [lo, hi)
+void update_work(int t, int lo, int hi, int nbk, int elem, double *flops, double *bytes)
+{
+    const double T = SPD_TILE_H;
+    double f = 0, b = 0;
+    for (int c = lo; c < hi; ++c) {
+        const double off = t - c - 1;  // off-diagonal tiles in this tile column
+        f += off * 2.0 * T * T * nbk + T * (T + 1) * nbk;
+        b += (off + 1) * (2.0 * T * T + 2.0 * T * nbk) * elem;
+    }
+    *flops = f;
+    *bytes = b;
+}
+
+spd_status map_err(hipError_t e)
+{
+    if (e == hipSuccess) return SPD_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SPD_ERR_OUT_OF_MEMORY;
+    return SPD_ERR_DEVICE;
+}
+
+#define HIP_TRY(x)                                   \
+    do {                                             \
+        hipError_t e_ = (x);                         \
+        if (e_ != hipSuccess) return map_err(e_);    \
+    } while (0)
+#define SPD_TRY(x)                                   \
+    do {                                             \
+        spd_status s_ = (x);                         \
+        if (s_ != SPD_OK) return s_;                 \
+    } while (0)
+
+spd_opts defaults()
+{
+    spd_opts o;
+    o.tol = 1e-14;
+    o.max_iter = 10;
+    o.fallback = 1;
+    o.equilibrate = 1;
+    o.theta = 0.1;
+    return o;
+}
+
+bool opts_valid(const spd_opts &o)
+{
+    return o.tol >= 0.0 && o.max_iter >= 0 && o.theta > 0.0 && o.theta <= 1.0;
+}
+
+// grow a device buffer (contents not preserved)
+spd_status grow(void **p, size_t *cap, size_t bytes, bool zero, hipStream_t st)
+{
+    if (*cap >= bytes && *p) return SPD_OK;
+    if (*p) {
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipFree(*p));
+        *p = nullptr;
+        *cap = 0;
+    }
+    HIP_TRY(hipMalloc(p, bytes ? bytes : 16));
+    *cap = bytes;
+    if (zero) HIP_TRY(hipMemsetAsync(*p, 0, bytes, st));
+    return SPD_OK;
+}
+
+spd_status ensure_stream_objs(spd_factor_t F)
+{
+    if (!F->side) HIP_TRY(hipStreamCreateWithFlags(&F->side, hipStreamNonBlocking));
+    for (auto &e : F->ev)
+        if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (!F->info_dev) HIP_TRY(hipMalloc(&F->info_dev, sizeof(unsigned long long)));
+    if (!F->info_host) HIP_TRY(hipHostMalloc(&F->info_host, sizeof(unsigned long long), hipHostMallocDefault));
+    return SPD_OK;
+}
+
+double fp16_scale(double theta)
+{
+    // largest power of two <= theta * 65504
+    int e;
+    std::frexp(theta * 65504.0, &e);
+    return std::ldexp(1.0, e - 1);
+}
+
+// ---------------------------------------------------------------------------
+// Blocked right-looking factorisation with one panel of lookahead:
+//   side stream: update of the next panel's columns, its diagonal factor and
+//                panel solve;
+//   main stream: update of the remaining trailing columns.
+template <typename T>
+spd_status factor_blocked(spd_factor_t F, hipStream_t st)
+{
+    const int64_t NB = SPD_NB, npad = F->npad, nt = npad / NB;
+    T *H = (T *)F->L;
+    T *Wi = (T *)F->Winv;
+    const int64_t wi_blk = (NB / SPD_IB_H) * SPD_IB_H * SPD_IB_H;
+    const int tcols = (int)(NB / SPD_TILE_H);
+    hipEvent_t evU = F->ev[0], evP = F->ev[1], evQ = F->ev[2];
+
+    spd::launch_potrf_diag<T>(H, npad, 0, Wi, F->info_dev, st);
+    spd::launch_trsm_panel<T>(H, npad, 0, NB, npad - NB, Wi, F->info_dev, st);
+    if (nt > 1) {
+        HIP_TRY(hipEventRecord(evP, st));
+        for (int64_t k = 0; k + 1 < nt; ++k) {
+            const int64_t k0 = k * NB, r0 = k0 + NB;
+            const int t = (int)((npad - r0) / SPD_TILE_H);
+            // lookahead: next panel on the side stream
+            HIP_TRY(hipStreamWaitEvent(F->side, evP, 0));
+            if (k > 0) HIP_TRY(hipStreamWaitEvent(F->side, evU, 0));
+            double fl, by;
+            hipEvent_t pa = prof_begin(F->side);
+            spd::launch_syrk_update<T>(H, npad, k0, (int)NB, r0, t, 0, tcols, F->info_dev, F->side);
+            if (pa) {
+                update_work(t, 0, tcols, (int)NB, (int)sizeof(T), &fl, &by);
+                prof_end(pa, F->side, SPD_K_UPDATE, fl, by);
+            }
+            spd::launch_potrf_diag<T>(H + r0 + r0 * npad, npad, r0, Wi + (k + 1) * wi_blk, F->info_dev, F->side);
+            spd::launch_trsm_panel<T>(H, npad, r0, r0 + NB, npad - r0 - NB, Wi + (k + 1) * wi_blk, F->info_dev,
+                                      F->side);
+            HIP_TRY(hipEventRecord(evQ, F->side));
+            // the rest of the trailing update on the main stream
+            HIP_TRY(hipStreamWaitEvent(st, evP, 0));
+            hipEvent_t pb = prof_begin(st);
+            spd::launch_syrk_update<T>(H, npad, k0, (int)NB, r0, t, tcols, t, F->info_dev, st);
+            if (pb) {
+                update_work(t, tcols, t, (int)NB, (int)sizeof(T), &fl, &by);
+                prof_end(pb, st, SPD_K_UPDATE, fl, by);
+            }
+            HIP_TRY(hipEventRecord(evU, st));
+            std::swap(evP, evQ);
+        }
+        HIP_TRY(hipStreamWaitEvent(st, evP, 0));
+    }
+    HIP_TRY(hipGetLastError());
+    spd::launch_trtri_blocks<T>(H, npad, nt, Wi, (T *)F->W, st);
+    HIP_TRY(hipGetLastError());
+    return SPD_OK;
+}
+
+spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, int prec, const spd_opts &o,
+                     hipStream_t st, int64_t *info)
+{
+    F->n = n;
+    F->prec = prec;
+    F->npad = ((n + SPD_NB - 1) / SPD_NB) * SPD_NB;
+    if (F->npad == 0) F->npad = SPD_NB;
+    F->elem = (prec == SPD_FP64) ? 8 : 4;
+    const int64_t npad = F->npad;
+    SPD_TRY(ensure_stream_objs(F));
+    // one allocation for L, W and Winv (all zeroed when (re)allocated)
+    const size_t bL = (size_t)npad * npad * F->elem;
+    const size_t bW = (size_t)npad * SPD_NB * F->elem;
+    const size_t bWi = (size_t)npad * SPD_IB_H * F->elem;
+    size_t cap = F->cap_L;
+    void *base = F->L;
+    SPD_TRY(grow(&base, &cap, bL + bW + bWi, true, st));
+    F->L = base;
+    F->cap_L = cap;
+    F->W = (char *)base + bL;
+    F->Winv = (char *)base + bL + bW;
+    size_t capd = (size_t)F->cap_d * sizeof(double);
+    SPD_TRY(grow((void **)&F->d, &capd, (size_t)std::max<int64_t>(n, 1) * sizeof(double), false, st));
+    F->cap_d = (int64_t)(capd / sizeof(double));
+
+    F->mu = (prec == SPD_FP16) ? fp16_scale(o.theta) : 1.0;
+    const int equil = (prec != SPD_FP64 && o.equilibrate) ? 1 : 0;
+    *F->info_host = SPD_INFO_NONE_H;
+    HIP_TRY(hipMemcpyAsync(F->info_dev, F->info_host, sizeof(unsigned long long), hipMemcpyHostToDevice, st));
+    if (n > 0) spd::launch_equil(A, lda, n, F->d, equil, st);
+    if (prec == SPD_FP64) {
+        spd::launch_convert<double>(A, lda, n, npad, F->d, 1.0, (double *)F->L, npad, st);
+        SPD_TRY(factor_blocked<double>(F, st));
+    } else {
+        spd::launch_convert<float>(A, lda, n, npad, F->d, F->mu, (float *)F->L, npad, st);
+        SPD_TRY(factor_blocked<float>(F, st));
+    }
+    HIP_TRY(hipMemcpyAsync(F->info_host, F->info_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const unsigned long long v = *F->info_host;
+    *info = (v == SPD_INFO_NONE_H) ? 0 : (int64_t)v;
+    return *info ? SPD_ERR_NOT_SPD : SPD_OK;
+}
+
+spd_status ensure_solve_ws(spd_factor_t F, int64_t m, hipStream_t st)
+{
+    const size_t b = (size_t)F->npad * m * F->elem;
+    size_t cap = F->cap_YZ;
+    void *base = F->Y;
+    SPD_TRY(grow(&base, &cap, 2 * b, false, st));
+    F->Y = base;
+    F->Z = (char *)base + F->npad * m * F->elem;  // Z follows Y for this m
+    F->cap_YZ = cap;
+    size_t capm = (size_t)F->cap_smax * sizeof(double);
+    SPD_TRY(grow((void **)&F->smax, &capm, (size_t)m * sizeof(double), false, st));
+    F->cap_smax = (int64_t)(capm / sizeof(double));
+    return SPD_OK;
+}
+
+// Low-precision solve of (D R / s) and X (+)= s mu D Y  (Algorithm 1, lines 2, 5, 6)
+template <typename T>
+void solve_apply(spd_factor_t F, const double *R, int64_t ldr, int64_t m, const double *smax, double *X, int64_t ldx,
+                 int accumulate, hipStream_t st)
+{
+    const int64_t npad = F->npad;
+    T *Y = (T *)F->Y;
+    T *Z = (T *)((char *)F->Y + npad * m * sizeof(T));
+    spd::launch_rhs_scale<T>(R, ldr, F->n, npad, (int)m, F->d, smax, Y, npad, st);
+    spd::launch_trsv_fwd<T>((const T *)F->L, npad, (const T *)F->W, npad, (int)m, Y, Z, npad, st);
+    spd::launch_trsv_bwd<T>((const T *)F->L, npad, (const T *)F->W, npad, (int)m, Z, Y, npad, st);
+    spd::launch_update_x<T>(X, ldx, F->n, (int)m, Y, npad, F->d, F->mu, smax, accumulate, st);
+}
+
+spd_status do_solve(spd_factor_t F, const double *B, int64_t ldb, int64_t m, double *X, int64_t ldx,
+                    hipStream_t st)
+{
+    if (F->n == 0 || m == 0) return SPD_OK;
+    SPD_TRY(ensure_solve_ws(F, m, st));
+    spd::launch_zero(F->smax, m, st);
+    spd::launch_rhs_max(B, ldb, F->n, (int)m, F->d, F->smax, st);
+    if (F->elem == 8)
+        solve_apply<double>(F, B, ldb, m, F->smax, X, ldx, 0, st);
+    else
+        solve_apply<float>(F, B, ldb, m, F->smax, X, ldx, 0, st);
+    HIP_TRY(hipGetLastError());
+    return SPD_OK;
+}
+
+spd_status ensure_refine_ws(spd_factor_t F, int64_t m, hipStream_t st)
+{
+    size_t cap = F->cap_R;
+    SPD_TRY(grow((void **)&F->R, &cap, (size_t)F->n * m * sizeof(double), false, st));
+    F->cap_R = cap;
+    cap = F->cap_P;
+    SPD_TRY(grow((void **)&F->P, &cap, (size_t)spd::resid_scratch(F->n, (int)m) * sizeof(double), false, st));
+    F->cap_P = cap;
+    const int64_t nn = 1 + 4 * m;
+    if (F->cap_norms < nn) {
+        if (F->norms) {
+            HIP_TRY(hipStreamSynchronize(st));
+            HIP_TRY(hipFree(F->norms));
+            HIP_TRY(hipHostFree(F->norms_host));
+            F->norms = F->norms_host = nullptr;
+        }
+        HIP_TRY(hipMalloc(&F->norms, nn * sizeof(double)));
+        HIP_TRY(hipHostMalloc(&F->norms_host, nn * sizeof(double), hipHostMallocDefault));
+        F->cap_norms = nn;
+    }
+    return SPD_OK;
+}
+
+int next_prec(int p) { return (p == SPD_BF16 || p == SPD_FP16) ? SPD_FP32 : SPD_FP64; }
+
+constexpr double ETA_FLOOR = 0x1p-51;  // 4u: relative forward error <= ~2 cond eta stays under 10 cond u
+
+// One refinement run at the handle's current precision, from the iterate in X.
+// Returns SPD_OK (converged) or SPD_ERR_NO_CONVERGENCE (diverged / out of
+// iterations); device errors propagate.
+spd_status refine_once(spd_factor_t F, const double *A, int64_t lda, const double *B, int64_t ldb, int64_t m,
+                       double *X, int64_t ldx, const spd_opts &o, spd_report *rep, hipStream_t st)
+{
+    const int64_t n = F->n;
+    SPD_TRY(ensure_solve_ws(F, m, st));
+    SPD_TRY(ensure_refine_ws(F, m, st));
+    const int64_t nn = 1 + 4 * m;
+    double *eta = new (std::nothrow) double[2 * m];
+    if (!eta) return SPD_ERR_OUT_OF_MEMORY;
+    double *prev = eta + m;
+    rep->iters_low = 1;  // the iterate came from one low-precision solve
+    rep->iters_high = 0;
+    double eta0 = 0.0, prev_worst = 0.0, anorm = 0.0;
+    int stalls = 0;
+    spd_status result = SPD_ERR_NO_CONVERGENCE;
+    for (;;) {
+        const int first = (rep->iters_high == 0);
+        spd::launch_zero(first ? F->norms : F->norms + 1, first ? nn : nn - 1, st);
+        hipEvent_t pr = prof_begin(st);
+        spd::launch_residual(A, lda, n, X, ldx, B, ldb, (int)m, F->R, n, F->d, F->norms, first, F->P, st);
+        if (pr)
+            prof_end(pr, st, SPD_K_RESIDUAL, 2.0 * n * n * m,
+                     8.0 * ((double)n * (n + 1) / 2 + 3.0 * n * m));
+        hipError_t e = hipMemcpyAsync(F->norms_host, F->norms, nn * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            delete[] eta;
+            return map_err(e);
+        }
+        rep->iters_high++;
+        if (first) anorm = F->norms_host[0];
+        bool finite = std::isfinite(anorm);
+        double worst = 0.0;
+        for (int64_t c = 0; c < m; ++c) {
+            const double rn = F->norms_host[1 + c], xn = F->norms_host[1 + m + c], bn = F->norms_host[1 + 2 * m + c];
+            const double den = anorm * xn + bn;
+            double v = (den > 0.0) ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+            if (!(rn == rn) || !(xn == xn)) v = NAN;
+            eta[c] = v;
+            if (!std::isfinite(v)) finite = false;
+            if (v > worst) worst = v;
+        }
+        rep->eta = finite ? worst : NAN;
+        if (!finite) break;                                   // diverged
+        if (worst <= ETA_FLOOR) { result = SPD_OK; break; }  // binary64 floor
+        if (rep->iters_high == 1) {
+            eta0 = worst;
+        } else {
+            if (worst <= o.tol && worst > 0.5 * prev_worst) { result = SPD_OK; break; }  // stalled inside tol
+            bool all_slow = true;
+            for (int64_t c = 0; c < m; ++c)
+                if (!(eta[c] > 0.9 * prev[c])) all_slow = false;
+            stalls = all_slow ? stalls + 1 : 0;
+            if (worst > o.tol && (worst > eta0 || stalls >= 2)) break;  // diverged / stagnated
+        }
+        if (rep->iters_low > o.max_iter) {
+            if (worst <= o.tol) result = SPD_OK;
+            break;
+        }
+        prev_worst = worst;
+        std::memcpy(prev, eta, m * sizeof(double));
+        // correction: Z = low-precision solve of D R / s, X += s mu D Z
+        const double *dmax = F->norms + 1 + 3 * m;
+        if (F->elem == 8)
+            solve_apply<double>(F, F->R, n, m, dmax, X, ldx, 1, st);
+        else
+            solve_apply<float>(F, F->R, n, m, dmax, X, ldx, 1, st);
+        e = hipGetLastError();
+        if (e != hipSuccess) {
+            delete[] eta;
+            return map_err(e);
+        }
+        rep->iters_low++;
+    }
+    delete[] eta;
+    return result;
+}
+
+bool valid_prec(int p) { return p >= SPD_BF16 && p <= SPD_FP64; }
+
+}  // namespace
+
+extern "C" {
+
+void spd_opts_default(spd_opts *o)
+{
+    if (o) *o = defaults();
+}
+
+const char *spd_status_str(spd_status s)
+{
+    switch (s) {
+    case SPD_OK: return "SPD_OK";
+    case SPD_ERR_INVALID_ARG: return "SPD_ERR_INVALID_ARG";
+    case SPD_ERR_NOT_SPD: return "SPD_ERR_NOT_SPD";
+    case SPD_ERR_NO_CONVERGENCE: return "SPD_ERR_NO_CONVERGENCE";
+    case SPD_ERR_DEVICE: return "SPD_ERR_DEVICE";
+    case SPD_ERR_OUT_OF_MEMORY: return "SPD_ERR_OUT_OF_MEMORY";
+    case SPD_ERR_UNSUPPORTED: return "SPD_ERR_UNSUPPORTED";
+    }
+    return "SPD_ERR_UNKNOWN";
+}
+
+const char *spd_version(void) { return "libspd 0.1 (gfx950)"; }
+
+void spd_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = on != 0;
+}
+
+void spd_profile_reset(void)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto &r : g_prof_pending) {
+        hipEventSynchronize(r.b);
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_prof_pending.clear();
+    for (auto &t : g_prof_tot) t = ProfTotals();
+}
+
+spd_status spd_profile_query(int kernel, int64_t *launches, double *total_ms, double *total_flops,
+                             double *total_bytes)
+{
+    if (kernel < 0 || kernel >= SPD_K_COUNT) return SPD_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto &r : g_prof_pending) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e == hipSuccess) {
+            ProfTotals &t = g_prof_tot[r.kind];
+            t.launches++;
+            t.ms += ms;
+            t.flops += r.flops;
+            t.bytes += r.bytes;
+        }
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_prof_pending.clear();
+    const ProfTotals &t = g_prof_tot[kernel];
+    if (launches) *launches = t.launches;
+    if (total_ms) *total_ms = t.ms;
+    if (total_flops) *total_flops = t.flops;
+    if (total_bytes) *total_bytes = t.bytes;
+    return SPD_OK;
+}
+
+spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec, const spd_opts *o, void *hip_stream,
+                      spd_factor_t *F, int64_t *info)
+{
+    if (!F || !info || n < 0 || lda < std::max<int64_t>(1, n) || (n > 0 && !A) || !valid_prec(prec))
+        return SPD_ERR_INVALID_ARG;
+    const spd_opts op = o ? *o : defaults();
+    if (!opts_valid(op)) return SPD_ERR_INVALID_ARG;
+    if (prec == SPD_BF16 || prec == SPD_FP16) return SPD_ERR_UNSUPPORTED;
+    *info = 0;
+    bool created = false;
+    if (!*F) {
+        *F = new (std::nothrow) spd_factor_s();
+        if (!*F) return SPD_ERR_OUT_OF_MEMORY;
+        created = true;
+        if (hipGetDevice(&(*F)->device) != hipSuccess) {
+            delete *F;
+            *F = nullptr;
+            return SPD_ERR_DEVICE;
+        }
+    }
+    spd_status s = do_factor(*F, A, n, lda, prec, op, (hipStream_t)hip_stream, info);
+    if (s != SPD_OK && s != SPD_ERR_NOT_SPD && created) {
+        spd_factor_destroy(*F);
+        *F = nullptr;
+    }
+    return s;
+}
+
+spd_status spd_solve(spd_factor_t F, const double *B, int64_t ldb, int64_t nrhs, double *X, int64_t ldx,
+                     void *hip_stream)
+{
+    if (!F || F->prec < 0 || nrhs < 0) return SPD_ERR_INVALID_ARG;
+    const int64_t n = F->n;
+    if (ldb < std::max<int64_t>(1, n) || ldx < std::max<int64_t>(1, n)) return SPD_ERR_INVALID_ARG;
+    if (n > 0 && nrhs > 0 && (!B || !X)) return SPD_ERR_INVALID_ARG;
+    return do_solve(F, B, ldb, nrhs, X, ldx, (hipStream_t)hip_stream);
+}
+
+spd_status spd_refine(spd_factor_t F, const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrhs,
+                      double *X, int64_t ldx, const spd_opts *o, spd_report *rep, void *hip_stream)
+{
+    if (!F || F->prec < 0 || !rep || nrhs < 0) return SPD_ERR_INVALID_ARG;
+    const int64_t n = F->n;
+    if (lda < std::max<int64_t>(1, n) || ldb < std::max<int64_t>(1, n) || ldx < std::max<int64_t>(1, n))
+        return SPD_ERR_INVALID_ARG;
+    if (n > 0 && nrhs > 0 && (!A || !B || !X)) return SPD_ERR_INVALID_ARG;
+    const spd_opts op = o ? *o : defaults();
+    if (!opts_valid(op)) return SPD_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::memset(rep, 0, sizeof(*rep));
+    rep->prec_used = F->prec;
+    if (n == 0 || nrhs == 0) {
+        rep->status = SPD_OK;
+        rep->eta = 0.0;
+        return SPD_OK;
+    }
+    for (;;) {
+        spd_status s = refine_once(F, A, lda, B, ldb, nrhs, X, ldx, op, rep, st);
+        rep->prec_used = F->prec;
+        if (s != SPD_ERR_NO_CONVERGENCE || !op.fallback || F->prec == SPD_FP64) {
+            rep->status = s;
+            return s;
+        }
+        // escalate: re-factor at the next precision and restart from solve(B)
+        rep->fallbacks++;
+        int64_t info = 0;
+        int p = next_prec(F->prec);
+        for (;;) {
+            s = do_factor(F, A, n, lda, p, op, st, &info);
+            if (s == SPD_ERR_NOT_SPD && p != SPD_FP64) {
+                rep->fallbacks++;
+                p = next_prec(p);
+                continue;
+            }
+            break;
+        }
+        rep->prec_used = F->prec;
+        rep->info = info;
+        if (s != SPD_OK) {
+            rep->status = s;
+            return s;
+        }
+        s = do_solve(F, B, ldb, nrhs, X, ldx, st);
+        if (s != SPD_OK) {
+            rep->status = s;
+            return s;
+        }
+    }
+}
+
+spd_status spd_posv(const double *A, int64_t n, int64_t lda, const double *B, int64_t ldb, int64_t nrhs, double *X,
+                    int64_t ldx, spd_prec prec, const spd_opts *o, spd_report *rep, void *hip_stream,
+                    spd_factor_t *F)
+{
+    if (!rep || !F) return SPD_ERR_INVALID_ARG;
+    std::memset(rep, 0, sizeof(*rep));
+    const spd_opts op = o ? *o : defaults();
+    if (!opts_valid(op) || !valid_prec(prec)) return SPD_ERR_INVALID_ARG;
+    int p = prec;
+    int fallbacks = 0;
+    int64_t info = 0;
+    spd_status s;
+    for (;;) {
+        s = spd_factor(A, n, lda, (spd_prec)p, &op, hip_stream, F, &info);
+        if (s == SPD_ERR_NOT_SPD && op.fallback && p != SPD_FP64) {
+            ++fallbacks;
+            p = next_prec(p);
+            continue;
+        }
+        break;
+    }
+    rep->info = info;
+    rep->prec_used = p;
+    rep->fallbacks = fallbacks;
+    if (s != SPD_OK) {
+        rep->status = s;
+        return s;
+    }
+    s = spd_solve(*F, B, ldb, nrhs, X, ldx, hip_stream);
+    if (s != SPD_OK) {
+        rep->status = s;
+        return s;
+    }
+    s = spd_refine(*F, A, lda, B, ldb, nrhs, X, ldx, &op, rep, hip_stream);
+    rep->fallbacks += fallbacks;
+    return s;
+}
+
+spd_status spd_residual(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx, const double *B,
+                        int64_t ldb, int64_t nrhs, double *R, int64_t ldr, double *eta, void *hip_stream)
+{
+    if (n < 0 || nrhs < 0 || lda < std::max<int64_t>(1, n) || ldx < std::max<int64_t>(1, n) ||
+        ldb < std::max<int64_t>(1, n) || (R && ldr < std::max<int64_t>(1, n)))
+        return SPD_ERR_INVALID_ARG;
+    if (n > 0 && nrhs > 0 && (!A || !X || !B)) return SPD_ERR_INVALID_ARG;
+    if (n == 0 || nrhs == 0) {
+        for (int64_t c = 0; eta && c < nrhs; ++c) eta[c] = 0.0;
+        return SPD_OK;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int64_t nn = 1 + 4 * nrhs;
+    const size_t bP = (size_t)spd::resid_scratch(n, (int)nrhs) * sizeof(double);
+    const size_t bR = R ? 0 : (size_t)n * nrhs * sizeof(double);
+    char *scratch = nullptr;
+    HIP_TRY(hipMalloc(&scratch, bP + bR + nn * sizeof(double)));
+    double *P = (double *)scratch;
+    double *Rw = R ? R : (double *)(scratch + bP);
+    const int64_t ldrw = R ? ldr : n;
+    double *norms = (double *)(scratch + bP + bR);
+    spd::launch_zero(norms, nn, st);
+    spd::launch_residual(A, lda, n, X, ldx, B, ldb, (int)nrhs, Rw, ldrw, nullptr, norms, 1, P, st);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && eta) {
+        double *h = new (std::nothrow) double[nn];
+        if (!h) {
+            hipStreamSynchronize(st);
+            hipFree(scratch);
+            return SPD_ERR_OUT_OF_MEMORY;
+        }
+        e = hipMemcpyAsync(h, norms, nn * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        for (int64_t c = 0; e == hipSuccess && c < nrhs; ++c) {
+            const double rn = h[1 + c], xn = h[1 + nrhs + c], bn = h[1 + 2 * nrhs + c];
+            const double den = h[0] * xn + bn;
+            double v = (den > 0.0) ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+            if (!(rn == rn) || !(xn == xn) || !(h[0] == h[0])) v = NAN;
+            eta[c] = v;
+        }
+        delete[] h;
+    } else if (e == hipSuccess) {
+        e = hipStreamSynchronize(st);
+    }
+    hipError_t e2 = hipFree(scratch);
+    if (e == hipSuccess) e = e2;
+    return map_err(e);
+}
+
+spd_status spd_solve_batched(int64_t batch, const int32_t *n, const int32_t *nrhs, const int64_t *a_off,
+                             const double *A, const int64_t *b_off, const double *B, double *X, spd_prec *prec,
+                             const spd_opts *o, spd_report *reps, void *hip_stream)
+{
+    (void)n; (void)nrhs; (void)a_off; (void)A; (void)b_off; (void)B; (void)X; (void)prec; (void)o; (void)reps;
+    (void)hip_stream;
+    if (batch < 0) return SPD_ERR_INVALID_ARG;
+    return SPD_ERR_UNSUPPORTED;
+}
+
+void spd_factor_destroy(spd_factor_t F)
+{
+    if (!F) return;
+    if (F->side) hipStreamSynchronize(F->side);
+    hipFree(F->L);
+    hipFree(F->d);
+    hipFree(F->Y);
+    hipFree(F->smax);
+    hipFree(F->R);
+    hipFree(F->P);
+    hipFree(F->norms);
+    hipFree(F->info_dev);
+    if (F->norms_host) hipHostFree(F->norms_host);
+    if (F->info_host) hipHostFree(F->info_host);
+    for (auto &e : F->ev)
+        if (e) hipEventDestroy(e);
+    if (F->side) hipStreamDestroy(F->side);
+    delete F;
+}
+
+spd_status spd_factor_query(spd_factor_t F, int64_t *n, int32_t *prec, int32_t *nb)
+{
+    if (!F) return SPD_ERR_INVALID_ARG;
+    if (n) *n = F->n;
+    if (prec) *prec = F->prec;
+    if (nb) *nb = SPD_NB;
+    return SPD_OK;
+}
+
+spd_status spd_factor_export(spd_factor_t F, double *Lout, int64_t ldl, double *dout, double *mu, void *hip_stream)
+{
+    if (!F || F->prec < 0) return SPD_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (Lout) {
+        if (ldl < std::max<int64_t>(1, F->n)) return SPD_ERR_INVALID_ARG;
+        if (F->elem == 8)
+            spd::launch_export<double>((const double *)F->L, F->npad, F->n, Lout, ldl, st);
+        else
+            spd::launch_export<float>((const float *)F->L, F->npad, F->n, Lout, ldl, st);
+    }
+    if (dout && F->n > 0)
+        HIP_TRY(hipMemcpyAsync(dout, F->d, F->n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (mu) *mu = F->mu;
+    HIP_TRY(hipGetLastError());
+    return SPD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// Host-side declarations shared by the libspd translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SPD_NB 256  // panel width of the blocked factorisation
+
+namespace spd {
+
+// --- factorisation (k_factor.hip) ---
+void launch_equil(const double *A, int64_t lda, int64_t n, double *d, int equil, hipStream_t st);
+template <typename T>
+void launch_convert(const double *A, int64_t lda, int64_t n, int64_t npad, const double *d, double mu, T *H,
+                    int64_t ldh, hipStream_t st);
+template <typename T>
+void launch_potrf_diag(T *Hkk, int64_t ld, int64_t col0, T *Winv, unsigned long long *info, hipStream_t st);
+template <typename T>
+void launch_trsm_panel(T *H, int64_t ld, int64_t k0, int64_t row0, int64_t nrows, const T *Winv,
+                       const unsigned long long *info, hipStream_t st);
+template <typename T>
+void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,
+                        const unsigned long long *info, hipStream_t st);
+template <typename T>
+void launch_trtri_blocks(const T *H, int64_t ld, int64_t nt, const T *Winv, T *W, hipStream_t st);
+
+// --- triangular solves and scaling (k_solve.hip) ---
+// smax[c] = max_i |d_i r_ic| over the n rows (zeroed by the caller first)
+void launch_rhs_max(const double *R, int64_t ldr, int64_t n, int m, const double *d, double *smax,
+                    hipStream_t st);
+// Y[i][c] = round_T(d_i r_ic / s_c) for i < n, 0 for n <= i < npad; s_c = pow2_ceil(smax[c])
+template <typename T>
+void launch_rhs_scale(const double *R, int64_t ldr, int64_t n, int64_t npad, int m, const double *d,
+                      const double *smax, T *Y, int64_t ldy, hipStream_t st);
+// Y <- L^{-1} Y (output in Z), then Z <- L^{-T} Z (output in Y); L and W as built by the factorisation
+template <typename T>
+void launch_trsv_fwd(const T *L, int64_t ld, const T *W, int64_t npad, int m, T *Y, T *Z, int64_t ldy,
+                     hipStream_t st);
+template <typename T>
+void launch_trsv_bwd(const T *L, int64_t ld, const T *W, int64_t npad, int m, T *Z, T *Y, int64_t ldy,
+                     hipStream_t st);
+// X[i][c] (+)= s_c mu d_i Y[i][c]
+template <typename T>
+void launch_update_x(double *X, int64_t ldx, int64_t n, int m, const T *Y, int64_t ldy, const double *d,
+                     double mu, const double *smax, int accumulate, hipStream_t st);
+// fill a double array with zeros (a kernel, not a memset node)
+void launch_zero(double *p, int64_t count, hipStream_t st);
+// Lout (binary64, n x n, column-major) <- lower triangle of the factor, zeros above
+template <typename T>
+void launch_export(const T *L, int64_t ld, int64_t n, double *Lout, int64_t ldo, hipStream_t st);
+
+// --- binary64 residual (k_resid.hip) ---
+// R = B - A X for the symmetric A (lower triangle read) and, per column c,
+// norms[1 + k m + c] for k = 0..3: max|r|, max|x|, max|b|, max|d r| (atomic
+// max; zero them first);
+// with want_anorm, norms[0] = ||A||_inf.  P is scratch of resid_scratch(n, m) doubles.
+int64_t resid_scratch(int64_t n, int m);
+void launch_residual(const double *A, int64_t lda, int64_t n, const double *X, int64_t ldx, const double *B,
+                     int64_t ldb, int m, double *R, int64_t ldr, const double *d, double *norms, int want_anorm,
+                     double *P, hipStream_t st);
+
+}  // namespace spd

@@ -1,0 +1,240 @@
+// Binary64 residual R = B - A X and the norms of the backward error
+// (Algorithm 1, lines 3 and 7: the "high precision" steps).
+//
+// A is symmetric with only its lower triangle stored.  Workgroup (I, s) owns
+// the 64-row block I and visits the 64-column blocks J = s, s + S, ...; each
+// 64 x 64 tile of the full symmetric matrix is formed in LDS from the lower
+// triangle (directly for J < I, transposed for J > I, mirrored for J == I)
+// and multiplied by the matching rows of X.  Per-(s, row) partial sums are
+// reduced in a fixed order by k_resid_reduce, so results are bitwise
+// reproducible run to run.  The same pass can accumulate sum_j |a_ij| for
+// ||A||_inf.
+#include "common.h"
+#include "internal.h"
+
+template <int MC, int RB, int CB, int JS>
+__global__ __launch_bounds__(256) void k_resid_partial(const double *__restrict__ A, int64_t lda, int64_t n,
+                                                       const double *__restrict__ X, int64_t ldx, int m, int c0, int S,
+                                                       double *__restrict__ P, double *__restrict__ Pabs, int want_abs)
+{
+    constexpr int RG = 64 / RB, CG = MC / CB;
+    static_assert(RG * CG * JS == 256, "thread layout");
+    constexpr int TS = 65;
+    __shared__ double Ts[64 * TS];
+    __shared__ double Xs[MC * 64];
+    const int tid = threadIdx.x;
+    const int rg = tid % RG, cg = (tid / RG) % CG, js = tid / (RG * CG);
+    const int I = blockIdx.x, s = blockIdx.y;
+    const int64_t i0 = (int64_t)I * 64;
+    const int nrb = (int)((n + 63) / 64);
+    double acc[RB][CB];
+    double aabs[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        aabs[r] = 0.0;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[r][c] = 0.0;
+    }
+    const bool do_abs = want_abs && cg == 0;
+    for (int J = s; J < nrb; J += S) {
+        const int64_t j0 = (int64_t)J * 64;
+        __syncthreads();
+        if (J < I) {
+            for (int idx = tid; idx < 4096; idx += 256) {
+                const int i = idx & 63, j = idx >> 6;
+                const int64_t gi = i0 + i, gj = j0 + j;
+                Ts[j * TS + i] = (gi < n && gj < n) ? A[gi + gj * lda] : 0.0;
+            }
+        } else if (J > I) {
+            for (int idx = tid; idx < 4096; idx += 256) {
+                const int j = idx & 63, i = idx >> 6;
+                const int64_t gi = i0 + i, gj = j0 + j;
+                Ts[j * TS + i] = (gi < n && gj < n) ? A[gj + gi * lda] : 0.0;
+            }
+        } else {
+            for (int idx = tid; idx < 4096; idx += 256) {
+                const int i = idx & 63, j = idx >> 6;
+                const int64_t gi = i0 + i, gj = j0 + j;
+                Ts[j * TS + i] = (i >= j && gi < n && gj < n) ? A[gi + gj * lda] : 0.0;
+            }
+            __syncthreads();
+            for (int idx = tid; idx < 4096; idx += 256) {
+                const int i = idx & 63, j = idx >> 6;
+                if (i < j)
+                    Ts[j * TS + i] = Ts[i * TS + j];
+            }
+        }
+        for (int idx = tid; idx < MC * 64; idx += 256) {
+            const int j = idx & 63, c = idx >> 6;
+            const int64_t gj = j0 + j;
+            Xs[c * 64 + j] = (gj < n && c0 + c < m) ? X[gj + (int64_t)(c0 + c) * ldx] : 0.0;
+        }
+        __syncthreads();
+        constexpr int JW = 64 / JS;
+#pragma unroll 4
+        for (int jj = 0; jj < JW; ++jj) {
+            const int j = js * JW + jj;
+            double a[RB], x[CB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) a[r] = Ts[j * TS + rg + RG * r];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) x[c] = Xs[(cg * CB + c) * 64 + j];
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) acc[r][c] = fma(a[r], x[c], acc[r][c]);
+            if (do_abs)
+#pragma unroll
+                for (int r = 0; r < RB; ++r) aabs[r] += fabs(a[r]);
+        }
+    }
+    // combine the JS partial sums (fixed order) and store
+    __syncthreads();
+    double *red = Ts;  // reuse: JS * MC * 64 <= 64 * TS doubles
+    if (JS > 1) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+                red[(js * MC + cg * CB + c) * 64 + rg + RG * r] = acc[r][c];
+    }
+    __shared__ double redabs[JS * 64];
+    if (do_abs)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) redabs[js * 64 + rg + RG * r] = aabs[r];
+    __syncthreads();
+    if (js == 0) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int i = rg + RG * r;
+            const int64_t gi = i0 + i;
+            if (gi >= n)
+                continue;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const int cc = cg * CB + c;
+                double v = acc[r][c];
+                for (int q = 1; q < JS; ++q)
+                    v += red[(q * MC + cc) * 64 + i];
+                if (c0 + cc < m)
+                    P[((int64_t)s * m + c0 + cc) * n + gi] = v;
+            }
+            if (do_abs) {
+                double v = aabs[r];
+                for (int q = 1; q < JS; ++q)
+                    v += redabs[q * 64 + i];
+                Pabs[(int64_t)s * n + gi] = v;
+            }
+        }
+    }
+}
+
+SPD_DEV double nanmax2(double a, double b) { return (a > b || a != a) ? a : b; }
+SPD_DEV double wave_max2(double v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v = nanmax2(v, __shfl_xor(v, off));
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_resid_reduce(const double *__restrict__ B, int64_t ldb,
+                                                      const double *__restrict__ X, int64_t ldx, int64_t n, int m,
+                                                      int S, const double *__restrict__ P,
+                                                      const double *__restrict__ Pabs, int want_abs,
+                                                      const double *__restrict__ d, double *__restrict__ R,
+                                                      int64_t ldr, double *norms)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    double vr = 0.0, vx = 0.0, vb = 0.0, vd = 0.0, va = 0.0;
+    if (i < n) {
+        double sum = 0.0;
+        for (int s = 0; s < S; ++s)
+            sum += P[((int64_t)s * m + c) * n + i];
+        const double b = B[i + c * ldb];
+        const double r = b - sum;
+        R[i + c * ldr] = r;
+        vr = fabs(r);
+        vx = fabs(X[i + c * ldx]);
+        vb = fabs(b);
+        vd = d ? fabs(d[i] * r) : vr;
+        if (want_abs && c == 0) {
+            double a = 0.0;
+            for (int s = 0; s < S; ++s)
+                a += Pabs[(int64_t)s * n + i];
+            va = a;
+        }
+    }
+    vr = wave_max2(vr);
+    vx = wave_max2(vx);
+    vb = wave_max2(vb);
+    vd = wave_max2(vd);
+    if (want_abs && c == 0)
+        va = wave_max2(va);
+    if ((threadIdx.x & 63) == 0) {
+        atomic_max_nonneg(norms + 1 + c, vr);
+        atomic_max_nonneg(norms + 1 + m + c, vx);
+        atomic_max_nonneg(norms + 1 + 2 * m + c, vb);
+        atomic_max_nonneg(norms + 1 + 3 * m + c, vd);
+        if (want_abs && c == 0)
+            atomic_max_nonneg(norms, va);
+    }
+}
+
+namespace spd {
+
+static int resid_splits(int64_t n)
+{
+    const int64_t nrb = (n + 63) / 64;
+    int64_t S = 2048 / (nrb > 0 ? nrb : 1);
+    if (S < 1) S = 1;
+    if (S > nrb) S = nrb;
+    if (S > 64) S = 64;
+    return (int)(S < 1 ? 1 : S);
+}
+
+int64_t resid_scratch(int64_t n, int m)
+{
+    const int S = resid_splits(n);
+    return (int64_t)S * n * (m + 1);
+}
+
+template <int MC, int RB, int CB, int JS>
+static void launch_partial(const double *A, int64_t lda, int64_t n, const double *X, int64_t ldx, int m, int c0,
+                           int S, double *P, double *Pabs, int want_abs, hipStream_t st)
+{
+    const unsigned nrb = (unsigned)((n + 63) / 64);
+    hipLaunchKernelGGL((k_resid_partial<MC, RB, CB, JS>), dim3(nrb, (unsigned)S), dim3(256), 0, st, A, lda, n, X,
+                       ldx, m, c0, S, P, Pabs, want_abs);
+}
+
+void launch_residual(const double *A, int64_t lda, int64_t n, const double *X, int64_t ldx, const double *B,
+                     int64_t ldb, int m, double *R, int64_t ldr, const double *d, double *norms, int want_anorm,
+                     double *P, hipStream_t st)
+{
+    if (n <= 0 || m <= 0) return;
+    const int S = resid_splits(n);
+    double *Pabs = P + (int64_t)S * n * m;
+    for (int c0 = 0; c0 < m; c0 += 64) {
+        const int mc = (m - c0 < 64) ? (m - c0) : 64;
+        const int wa = (want_anorm && c0 == 0) ? 1 : 0;
+        if (mc <= 1)
+            launch_partial<1, 1, 1, 4>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
+        else if (mc <= 2)
+            launch_partial<2, 1, 1, 2>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
+        else if (mc <= 4)
+            launch_partial<4, 1, 1, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
+        else if (mc <= 8)
+            launch_partial<8, 1, 2, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
+        else if (mc <= 16)
+            launch_partial<16, 2, 2, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
+        else if (mc <= 32)
+            launch_partial<32, 2, 4, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
+        else
+            launch_partial<64, 4, 4, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
+    }
+    hipLaunchKernelGGL(k_resid_reduce, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0, st, B, ldb, X,
+                       ldx, n, m, S, P, Pabs, want_anorm, d, R, ldr, norms);
+}
+
+}  // namespace spd

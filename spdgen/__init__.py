@@ -214,14 +214,13 @@ def covariance(n: int, d: float) -> np.ndarray:
 
 
 def indefinite(n: int, j0: int, seed: int = 7) -> np.ndarray:
-    """Symmetric A = M S M^T with M unit lower triangular (small random
-    off-diagonal entries, exactly representable) and S = diag(1,..,1,-1,1,..)
-    with the -1 at 1-based position j0.  The leading j0-1 pivots of the
-    Cholesky factorisation are exactly 1 and pivot j0 is exactly -1."""
+    """Symmetric A = M S M^T with M = I + N, N strictly lower triangular with
+    N(0, 1/(4n)) entries (so ||N|| is about 1/2 and M is well conditioned),
+    and S = diag(1,..,1,-1,1,..) with the -1 at 1-based position j0.  In exact
+    arithmetic the Cholesky pivots (Schur complements) are exactly the entries
+    of S: the leading j0-1 succeed with pivot 1 and column j0 has radicand -1."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    # entries are multiples of 1/8 in [-1/2, 1/2] so every product and sum in
-    # M S M^T is exact in binary64 for modest n.
-    M = np.tril(np.round(rng.uniform(-0.5, 0.5, (n, n)) * 8.0) / 8.0, -1) + np.eye(n)
+    M = np.eye(n) + np.tril(rng.standard_normal((n, n)) * (0.5 / np.sqrt(n)), -1)
     s = np.ones(n)
     s[j0 - 1] = -1.0
     A = (M * s[None, :]) @ M.T

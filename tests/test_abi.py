@@ -1,0 +1,95 @@
+"""The C-ABI library loads and exports every entry point include/spd.h declares;
+argument validation happens on the host before any device work (so these
+calls are safe without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spd.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"\b(spd_[a-z_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1405_4644_amd as spd
+    if not os.path.exists(spd.LIB_PATH):
+        pytest.fail("libspd.so is not built (python -m paper_1405_4644_amd.build)")
+    return spd.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("spd_factor", "spd_solve", "spd_refine", "spd_solve_batched", "spd_factor_destroy",
+                     "spd_status_str"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_symbol():
+    import paper_1405_4644_amd as spd
+    bound = {name for name, _, _ in spd._SIGS}
+    assert set(_declared()) == bound
+
+
+def test_status_strings(lib):
+    import paper_1405_4644_amd as spd
+    assert spd.status_str(0) == "SPD_OK"
+    assert spd.status_str(2) == "SPD_ERR_NOT_SPD"
+    assert spd.status_str(3) == "SPD_ERR_NO_CONVERGENCE"
+    assert spd.status_str(99) == "SPD_ERR_UNKNOWN"
+
+
+def test_defaults(lib):
+    import paper_1405_4644_amd as spd
+    o = spd.default_opts()
+    assert (o.tol, o.max_iter, o.fallback, o.equilibrate, o.theta) == (1e-14, 10, 1, 1, 0.1)
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    import paper_1405_4644_amd as spd
+    info = C.c_int64()
+    h = C.c_void_p()
+    fake = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.spd_factor(None, -1, 1, 2, None, None, C.byref(h), C.byref(info)) == spd.ERR_INVALID_ARG
+    assert lib.spd_factor(fake, 10, 5, 2, None, None, C.byref(h), C.byref(info)) == spd.ERR_INVALID_ARG  # lda < n
+    assert lib.spd_factor(None, 10, 10, 2, None, None, C.byref(h), C.byref(info)) == spd.ERR_INVALID_ARG  # A NULL
+    assert lib.spd_factor(fake, 10, 10, 7, None, None, C.byref(h), C.byref(info)) == spd.ERR_INVALID_ARG  # prec
+    assert lib.spd_factor(fake, 10, 10, 2, None, None, None, C.byref(info)) == spd.ERR_INVALID_ARG  # F NULL
+    bad = spd.default_opts(theta=0.0)
+    assert lib.spd_factor(fake, 10, 10, 2, C.byref(bad), None, C.byref(h), C.byref(info)) == spd.ERR_INVALID_ARG
+    bad = spd.default_opts(max_iter=-1)
+    assert lib.spd_factor(fake, 10, 10, 2, C.byref(bad), None, C.byref(h), C.byref(info)) == spd.ERR_INVALID_ARG
+    assert lib.spd_solve(None, fake, 10, 1, fake, 10, None) == spd.ERR_INVALID_ARG
+    rep = spd.Report()
+    assert lib.spd_refine(None, fake, 10, fake, 10, 1, fake, 10, None, C.byref(rep), None) == spd.ERR_INVALID_ARG
+    assert lib.spd_residual(fake, 10, 9, fake, 10, fake, 10, 1, None, 10, None, None) == spd.ERR_INVALID_ARG
+    assert lib.spd_residual(None, 10, 10, fake, 10, fake, 10, 1, None, 10, None, None) == spd.ERR_INVALID_ARG
+    assert lib.spd_solve_batched(-1, None, None, None, None, None, None, None, None, None, None,
+                                 None) == spd.ERR_INVALID_ARG
+    assert lib.spd_factor_query(None, None, None, None) == spd.ERR_INVALID_ARG
+    assert lib.spd_factor_export(None, None, 1, None, None, None) == spd.ERR_INVALID_ARG
+    lib.spd_factor_destroy(None)  # no-op
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    import paper_1405_4644_amd as spd
+    saved = spd._lib
+    try:
+        spd._lib = None
+        with pytest.raises(RuntimeError):
+            spd.load(str(tmp_path / "missing.so"))
+    finally:
+        spd._lib = saved

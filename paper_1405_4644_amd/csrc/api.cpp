@@ -28,6 +28,7 @@ struct spd_factor_s {
     int64_t n = 0, npad = 0;
     int prec = -1;
     int elem = 0;            // bytes per factor element (4 or 8)
+    int nb = 0;              // panel width
     size_t cap_L = 0;        // allocated bytes of L / W / Winv
     void *L = nullptr;       // npad x npad, column-major, lower used
     void *W = nullptr;       // nt blocks NB x NB: inverses of the diagonal blocks
@@ -42,6 +43,15 @@ struct spd_factor_s {
     size_t cap_YZ = 0;
     double *smax = nullptr;
     int64_t cap_smax = 0;
+    // persistent triangular solve state
+    void *tP = nullptr;          // partial products
+    size_t cap_tP = 0;
+    int *tctl = nullptr;         // work-queue head + per-row counters
+    int *tflags = nullptr;       // per-block-row ready flags (epochs)
+    int *terr = nullptr;         // sticky error flag (device)
+    int *terr_host = nullptr;    // pinned mirror
+    int64_t cap_tns = 0;
+    int epoch = 1;
     // refinement workspace
     double *R = nullptr;
     size_t cap_R = 0;
@@ -183,7 +193,7 @@ double fp16_scale(double theta)
 template <typename T>
 spd_status factor_blocked(spd_factor_t F, hipStream_t st)
 {
-    const int64_t NB = SPD_NB, npad = F->npad, nt = npad / NB;
+    const int64_t NB = spd::Panel<T>::NB, npad = F->npad, nt = npad / NB;
     T *H = (T *)F->L;
     T *Wi = (T *)F->Winv;
     const int64_t wi_blk = (NB / SPD_IB_H) * SPD_IB_H * SPD_IB_H;
@@ -202,7 +212,7 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
             if (k > 0) HIP_TRY(hipStreamWaitEvent(F->side, evU, 0));
             double fl, by;
             hipEvent_t pa = prof_begin(F->side);
-            spd::launch_syrk_update<T>(H, npad, k0, (int)NB, r0, t, 0, tcols, F->info_dev, F->side);
+            spd::launch_syrk_update<T>(H, npad, k0, (int)NB, r0, t, 0, tcols, F->info_dev, F->side, 1);
             if (pa) {
                 update_work(t, 0, tcols, (int)NB, (int)sizeof(T), &fl, &by);
                 prof_end(pa, F->side, SPD_K_UPDATE, fl, by);
@@ -235,14 +245,15 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
 {
     F->n = n;
     F->prec = prec;
-    F->npad = ((n + SPD_NB - 1) / SPD_NB) * SPD_NB;
-    if (F->npad == 0) F->npad = SPD_NB;
     F->elem = (prec == SPD_FP64) ? 8 : 4;
+    F->nb = (prec == SPD_FP64) ? spd::Panel<double>::NB : spd::Panel<float>::NB;
+    F->npad = ((n + F->nb - 1) / F->nb) * F->nb;
+    if (F->npad == 0) F->npad = F->nb;
     const int64_t npad = F->npad;
     SPD_TRY(ensure_stream_objs(F));
     // one allocation for L, W and Winv (all zeroed when (re)allocated)
     const size_t bL = (size_t)npad * npad * F->elem;
-    const size_t bW = (size_t)npad * SPD_NB * F->elem;
+    const size_t bW = (size_t)npad * F->nb * F->elem;
     const size_t bWi = (size_t)npad * SPD_IB_H * F->elem;
     size_t cap = F->cap_L;
     void *base = F->L;
@@ -274,8 +285,39 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
     return *info ? SPD_ERR_NOT_SPD : SPD_OK;
 }
 
+spd_status ensure_trsv_ws(spd_factor_t F, hipStream_t st)
+{
+    const int64_t ns = F->npad / spd::trsv_block(F->elem);
+    size_t cap = F->cap_tP;
+    SPD_TRY(grow(&F->tP, &cap, (size_t)std::max<int64_t>(spd::trsv_scratch_elems(F->npad, F->elem), 1) * F->elem,
+                 false, st));
+    F->cap_tP = cap;
+    if (F->cap_tns < ns) {
+        if (F->tctl) {
+            HIP_TRY(hipStreamSynchronize(st));
+            HIP_TRY(hipFree(F->tctl));
+            F->tctl = nullptr;
+        }
+        // ctl (ns + 1) and flags (ns) in one zeroed allocation
+        HIP_TRY(hipMalloc(&F->tctl, (2 * ns + 1) * sizeof(int)));
+        HIP_TRY(hipMemsetAsync(F->tctl, 0, (2 * ns + 1) * sizeof(int), st));
+        F->tflags = F->tctl + ns + 1;
+        F->cap_tns = ns;
+        F->epoch = 1;
+    } else {
+        F->tflags = F->tctl + F->cap_tns + 1;
+    }
+    if (!F->terr) {
+        HIP_TRY(hipMalloc(&F->terr, sizeof(int)));
+        HIP_TRY(hipMemsetAsync(F->terr, 0, sizeof(int), st));
+    }
+    if (!F->terr_host) HIP_TRY(hipHostMalloc(&F->terr_host, sizeof(int), hipHostMallocDefault));
+    return SPD_OK;
+}
+
 spd_status ensure_solve_ws(spd_factor_t F, int64_t m, hipStream_t st)
 {
+    SPD_TRY(ensure_trsv_ws(F, st));
     const size_t b = (size_t)F->npad * m * F->elem;
     size_t cap = F->cap_YZ;
     void *base = F->Y;
@@ -298,8 +340,8 @@ void solve_apply(spd_factor_t F, const double *R, int64_t ldr, int64_t m, const 
     T *Y = (T *)F->Y;
     T *Z = (T *)((char *)F->Y + npad * m * sizeof(T));
     spd::launch_rhs_scale<T>(R, ldr, F->n, npad, (int)m, F->d, smax, Y, npad, st);
-    spd::launch_trsv_fwd<T>((const T *)F->L, npad, (const T *)F->W, npad, (int)m, Y, Z, npad, st);
-    spd::launch_trsv_bwd<T>((const T *)F->L, npad, (const T *)F->W, npad, (int)m, Z, Y, npad, st);
+    F->epoch = spd::launch_trsv_persist<T>((const T *)F->L, npad, (const T *)F->W, F->nb, npad, (int)m, Y, Z, npad,
+                                           (T *)F->tP, F->tctl, F->tflags, F->epoch, F->terr, st);
     spd::launch_update_x<T>(X, ldx, F->n, (int)m, Y, npad, F->d, F->mu, smax, accumulate, st);
 }
 
@@ -372,10 +414,16 @@ spd_status refine_once(spd_factor_t F, const double *A, int64_t lda, const doubl
             prof_end(pr, st, SPD_K_RESIDUAL, 2.0 * n * n * m,
                      8.0 * ((double)n * (n + 1) / 2 + 3.0 * n * m));
         hipError_t e = hipMemcpyAsync(F->norms_host, F->norms, nn * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(F->terr_host, F->terr, sizeof(int), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
             delete[] eta;
             return map_err(e);
+        }
+        if (*F->terr_host) {  // a triangular-solve wait timed out
+            delete[] eta;
+            return SPD_ERR_DEVICE;
         }
         rep->iters_high++;
         if (first) anorm = F->norms_host[0];
@@ -698,6 +746,10 @@ void spd_factor_destroy(spd_factor_t F)
     hipFree(F->P);
     hipFree(F->norms);
     hipFree(F->info_dev);
+    hipFree(F->tP);
+    hipFree(F->tctl);
+    hipFree(F->terr);
+    if (F->terr_host) hipHostFree(F->terr_host);
     if (F->norms_host) hipHostFree(F->norms_host);
     if (F->info_host) hipHostFree(F->info_host);
     for (auto &e : F->ev)
@@ -711,7 +763,7 @@ spd_status spd_factor_query(spd_factor_t F, int64_t *n, int32_t *prec, int32_t *
     if (!F) return SPD_ERR_INVALID_ARG;
     if (n) *n = F->n;
     if (prec) *prec = F->prec;
-    if (nb) *nb = SPD_NB;
+    if (nb) *nb = F->nb;
     return SPD_OK;
 }
 

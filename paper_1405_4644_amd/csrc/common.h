@@ -69,6 +69,7 @@ template <> struct Frag<float> {
     static constexpr int K = 2;
     float v;
     SPD_DEV void load(const float *p, int ks, int lane) { v = p[(lane & 31) + (lane >> 5) * ks]; }
+    SPD_DEV void negate() { v = -v; }
 };
 template <> struct Frag<double> {
     static constexpr int K = 4;
@@ -79,6 +80,7 @@ template <> struct Frag<double> {
         v[0] = p[r + kk * ks];
         v[1] = p[16 + r + kk * ks];
     }
+    SPD_DEV void negate() { v[0] = -v[0]; v[1] = -v[1]; }
 };
 SPD_DEV void mma(Acc32<float> &acc, const Frag<float> &a, const Frag<float> &b) { acc.mma(a.v, b.v); }
 SPD_DEV void mma(Acc32<double> &acc, const Frag<double> &a, const Frag<double> &b) { acc.mma(a.v, b.v); }
@@ -94,6 +96,31 @@ SPD_DEV void mma_tile(Acc32<T> &acc, const T *pa, int aks, const T *pb, int bks,
         a.load(pa + (size_t)k * aks, aks, lane);
         b.load(pb + (size_t)k * bks, bks, lane);
         mma(acc, a, b);
+    }
+}
+
+// Cooperative copy of a ROWS x cols column-major block (leading dimension ld)
+// into LDS as dst[c * dld + r].  Each thread issues UNROLL global loads
+// before storing any of them, so load latency overlaps instead of
+// serialising on every element.  NT = threads taking part (tid < NT).
+template <typename T, int ROWS, int NT, int UNROLL>
+SPD_DEV void copy_g2s(T *dst, int dld, const T *__restrict__ src, int64_t ld, int cols, int tid)
+{
+    const int total = ROWS * cols;
+    for (int base = 0; base < total; base += NT * UNROLL) {
+        T v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int idx = base + u * NT + tid;
+            if (idx < total)
+                v[u] = src[(idx % ROWS) + (int64_t)(idx / ROWS) * ld];
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int idx = base + u * NT + tid;
+            if (idx < total)
+                dst[(idx / ROWS) * dld + (idx % ROWS)] = v[u];
+        }
     }
 }
 

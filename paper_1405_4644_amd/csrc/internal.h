@@ -3,9 +3,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define SPD_NB 256  // panel width of the blocked factorisation
-
 namespace spd {
+
+// Panel width of the blocked factorisation per factor type: 256 for binary32
+// (trailing update K = 256 keeps it MFMA-bound), 128 for binary64 (the
+// binary64 ridge is lower and the diagonal block then fits in registers).
+template <typename T> struct Panel;
+template <> struct Panel<float> { static constexpr int NB = 256; };
+template <> struct Panel<double> { static constexpr int NB = 128; };
 
 // --- factorisation (k_factor.hip) ---
 void launch_equil(const double *A, int64_t lda, int64_t n, double *d, int equil, hipStream_t st);
@@ -19,7 +24,7 @@ void launch_trsm_panel(T *H, int64_t ld, int64_t k0, int64_t row0, int64_t nrows
                        const unsigned long long *info, hipStream_t st);
 template <typename T>
 void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,
-                        const unsigned long long *info, hipStream_t st);
+                        const unsigned long long *info, hipStream_t st, int prio = 0);
 template <typename T>
 void launch_trtri_blocks(const T *H, int64_t ld, int64_t nt, const T *Winv, T *W, hipStream_t st);
 
@@ -31,13 +36,16 @@ void launch_rhs_max(const double *R, int64_t ldr, int64_t n, int m, const double
 template <typename T>
 void launch_rhs_scale(const double *R, int64_t ldr, int64_t n, int64_t npad, int m, const double *d,
                       const double *smax, T *Y, int64_t ldy, hipStream_t st);
-// Y <- L^{-1} Y (output in Z), then Z <- L^{-T} Z (output in Y); L and W as built by the factorisation
+// Persistent triangular solves (k_trsv.hip): forward Y -> Z then backward Z -> Y.
+// P: trsv_scratch_elems(npad, elem) elements; ctl: npad/trsv_block(elem) + 1 ints;
+// flags: npad/trsv_block(elem) ints, zeroed once at allocation; epoch strictly
+// increases across calls (returned); err: sticky int raised on a timed-out wait.
+#define TRSV_MC 8
+int trsv_block(int elem);
+int64_t trsv_scratch_elems(int64_t npad, int elem);
 template <typename T>
-void launch_trsv_fwd(const T *L, int64_t ld, const T *W, int64_t npad, int m, T *Y, T *Z, int64_t ldy,
-                     hipStream_t st);
-template <typename T>
-void launch_trsv_bwd(const T *L, int64_t ld, const T *W, int64_t npad, int m, T *Z, T *Y, int64_t ldy,
-                     hipStream_t st);
+int launch_trsv_persist(const T *L, int64_t ld, const T *W, int nbw, int64_t npad, int m, T *Y, T *Z, int64_t ldy,
+                        T *P, int *ctl, int *flags, int epoch, int *err, hipStream_t st);
 // X[i][c] (+)= s_c mu d_i Y[i][c]
 template <typename T>
 void launch_update_x(double *X, int64_t ldx, int64_t n, int m, const T *Y, int64_t ldy, const double *d,

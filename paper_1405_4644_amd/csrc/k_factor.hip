@@ -55,30 +55,73 @@ __global__ __launch_bounds__(256) void k_convert(const double *__restrict__ A, i
 }
 
 // ---------------------------------------------------------------------------
-// K2: Cholesky of one NB x NB diagonal block (one workgroup, 256 threads).
-// Strip s (columns c0 = 32 s .. c0+31, rows c0 .. NB-1) is loaded to LDS;
-// wave 0 factors its top 32 x 32 block in registers and inverts it; every
-// thread then solves one row below against that block; the strip is written
-// back and its outer product is subtracted from the rest of the block (MFMA).
+// Value of `v` held by lane `src` of the wavefront (src uniform).
+template <typename T> SPD_DEV T bcast(T v, int src);
+template <> SPD_DEV float bcast<float>(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+template <> SPD_DEV double bcast<double>(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ---------------------------------------------------------------------------
+// K2: Cholesky of one NB x NB diagonal block by one workgroup of 8 waves.
+// The lower triangle is held in registers as 32 x 32 MFMA accumulator tiles
+// (tile t of the row-major lower triangle belongs to wave t % 8).  For each
+// 32-wide strip s: the owners of tile column s spill it to LDS; wave 0
+// factors the top 32 x 32 block (lane r holds row r; values are broadcast
+// with readlane); every thread solves one row below against it; the strip is
+// stored to global memory; every wave subtracts the strip's outer product
+// from its remaining tiles with MFMA.  Finally waves 0..NB/32-1 each invert
+// one 32 x 32 diagonal sub-block (stored in Winv for the panel solve).
 // `info` receives min(1-based global column) of a non-positive pivot.
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_potrf_diag(T *__restrict__ Hkk, int64_t ld, int64_t col0,
+__global__ __launch_bounds__(512) void k_potrf_diag(T *__restrict__ Hkk, int64_t ld, int64_t col0,
                                                     T *__restrict__ Winv, unsigned long long *info)
 {
-    constexpr int IB = SPD_IB;
-    constexpr int SLD = NB + 1;
-    __shared__ T S[IB * SLD];
-    __shared__ T Wt[IB * (IB + 1)];
+    constexpr int IB = SPD_IB, NT = NB / IB, NTILES = NT * (NT + 1) / 2, NW = 8;
+    constexpr int SLOTS = (NTILES + NW - 1) / NW;
+    constexpr int SLD = NB + 1, DLD = IB + 1, CLD = IB + 4;
+    __shared__ T S[IB * SLD];          // strip: S[k * SLD + r], r = row offset from 32 s
+    __shared__ T Ld[NT][IB * DLD];     // factored 32 x 32 diagonal sub-blocks, row-major
+    __shared__ T Lc[IB * CLD];         // current one, column-major: Lc[t * CLD + c] = L[c][t]
+    __shared__ T Dinv[IB];             // 1 / L[t][t]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (*(volatile unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
         return;
+    __builtin_amdgcn_s_setprio(3);  // on the critical path of the factorisation
 
-    for (int s = 0; s < NB / IB; ++s) {
-        const int c0 = s * IB, rows = NB - c0;
-        for (int idx = tid; idx < rows * IB; idx += 256) {
-            const int r = idx % rows, j = idx / rows;
-            S[j * SLD + r] = Hkk[(c0 + r) + (int64_t)(c0 + j) * ld];
+    Acc32<T> acc[SLOTS];
+    int tI[SLOTS], tJ[SLOTS];
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+        const int t = wave + NW * q;
+        int ti = 0;
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        tI[q] = (t < NTILES) ? ti : -1;
+        tJ[q] = (t < NTILES) ? t - ti * (ti + 1) / 2 : -1;
+        // accumulator orientation: register j holds C[ti*32 + col(j)][tj*32 + row(j)]
+        if (t < NTILES) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                acc[q].set(j, Hkk[(tI[q] * IB + Acc32<T>::col(j, lane)) + (int64_t)(tJ[q] * IB + Acc32<T>::row(j, lane)) * ld]);
         }
+    }
+
+    for (int s = 0; s < NT; ++s) {
+        const int rows = NB - s * IB;
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q)
+            if (tJ[q] == s) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    S[Acc32<T>::row(j, lane) * SLD + (tI[q] - s) * IB + Acc32<T>::col(j, lane)] = acc[q].get(j);
+            }
         __syncthreads();
         if (wave == 0) {
             T v[IB];
@@ -88,149 +131,162 @@ __global__ __launch_bounds__(256) void k_potrf_diag(T *__restrict__ Hkk, int64_t
             bool failed = false;
 #pragma unroll
             for (int j = 0; j < IB; ++j) {
-                const T piv = __shfl(v[j], j);
+                const T piv = bcast(v[j], j);
                 if (!(piv > (T)0) && !failed) {
                     failed = true;
                     if (lane == 0)
-                        atomicMin(info, (unsigned long long)(col0 + c0 + j + 1));
+                        atomicMin(info, (unsigned long long)(col0 + s * IB + j + 1));
                 }
                 const T ljj = sqrt(piv);
+                const T rinv = (T)1 / ljj;
                 if (lane == j)
                     v[j] = ljj;
                 else if (lane > j)
-                    v[j] = v[j] / ljj;
+                    v[j] = v[j] * rinv;
 #pragma unroll
                 for (int k = j + 1; k < IB; ++k) {
-                    const T lkj = __shfl(v[j], k);
+                    const T lkj = bcast(v[j], k);
                     if (lane >= k)
                         v[k] -= v[j] * lkj;
                 }
+                if (lane == 0)
+                    Dinv[j] = rinv;
             }
             if (lane < IB) {
 #pragma unroll
-                for (int j = 0; j < IB; ++j)
-                    S[j * SLD + lane] = (j <= lane) ? v[j] : (T)0;
-            }
-            // inverse of the 32 x 32 factor, row `lane`: W L = I gives
-            // W[r][c] = (delta_rc - sum_{k=c+1..r} W[r][k] L[k][c]) / L[c][c]
-            T w[IB];
-#pragma unroll
-            for (int c = IB - 1; c >= 0; --c) {
-                const T lcc = S[c * SLD + c];
-                T acc = (c == lane) ? (T)1 : (T)0;
-#pragma unroll
-                for (int k = c + 1; k < IB; ++k)
-                    if (k <= lane)
-                        acc -= w[k] * S[c * SLD + k];
-                w[c] = (c <= lane) ? acc / lcc : (T)0;
-            }
-            if (lane < IB) {
-#pragma unroll
-                for (int c = 0; c < IB; ++c) {
-                    Wt[lane + c * (IB + 1)] = w[c];
-                    Winv[(size_t)s * IB * IB + lane + c * IB] = w[c];
+                for (int j = 0; j < IB; ++j) {
+                    const T x = (j <= lane) ? v[j] : (T)0;
+                    S[j * SLD + lane] = x;
+                    Ld[s][lane * DLD + j] = x;
+                    Lc[j * CLD + lane] = x;
                 }
             }
         }
         __syncthreads();
-        // rows below the top block: x = s_row * W_top^T
-        for (int r = IB + tid; r < rows; r += 256) {
-            T srow[IB];
+        // rows below the top block solve x L_top^T = s_r, column by column
+        // (right-looking: after x_t is final it updates every later x_c, so
+        // the 31 - t updates of a step are independent)
+        for (int r = IB + tid; r < rows; r += 512) {
+            T x[IB];
 #pragma unroll
             for (int t = 0; t < IB; ++t)
-                srow[t] = S[t * SLD + r];
+                x[t] = S[t * SLD + r];
 #pragma unroll
-            for (int c = 0; c < IB; ++c) {
-                T acc = (T)0;
+            for (int t = 0; t < IB; ++t) {
+                x[t] *= Dinv[t];
 #pragma unroll
-                for (int t = 0; t <= c; ++t)
-                    acc += srow[t] * Wt[c + t * (IB + 1)];
-                S[c * SLD + r] = acc;
+                for (int c = t + 1; c < IB; ++c)
+                    x[c] -= x[t] * Lc[t * CLD + c];
             }
+#pragma unroll
+            for (int t = 0; t < IB; ++t)
+                S[t * SLD + r] = x[t];
         }
         __syncthreads();
-        for (int idx = tid; idx < rows * IB; idx += 256) {
-            const int r = idx % rows, j = idx / rows;
-            Hkk[(c0 + r) + (int64_t)(c0 + j) * ld] = S[j * SLD + r];
+        for (int idx = tid; idx < IB * rows; idx += 512) {
+            const int j = idx / rows, r = idx - j * rows;
+            Hkk[(s * IB + r) + (int64_t)(s * IB + j) * ld] = S[j * SLD + r];
         }
-        // trailing update of the block: rows/cols [c0+IB, NB), 32 x 32 tiles
-        const int nt = (rows - IB) / 32;
-        const int ntiles = nt * (nt + 1) / 2;
-        for (int tIdx = wave; tIdx < ntiles; tIdx += 4) {
-            int ti = (int)((sqrtf(8.f * tIdx + 1.f) - 1.f) * 0.5f);
-            while (ti * (ti + 1) / 2 > tIdx) --ti;
-            while ((ti + 1) * (ti + 2) / 2 <= tIdx) ++ti;
-            const int tj = tIdx - ti * (ti + 1) / 2;
-            Acc32<T> acc;
-            acc.zero();
-            // transposed product: D[m][n] = sum_k S[tj-row m][k] S[ti-row n][k] = C[ti n][tj m]
-            mma_tile<T>(acc, &S[IB + tj * 32], SLD, &S[IB + ti * 32], SLD, IB, lane);
+        // trailing update of the owned tiles: D(ti,tj) -= L_tj L_ti^T
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int m = Acc32<T>::row(j, lane), nn = Acc32<T>::col(j, lane);
-                const int64_t gi = c0 + IB + ti * 32 + nn, gj = c0 + IB + tj * 32 + m;
-                Hkk[gi + gj * ld] -= acc.get(j);
+        for (int q = 0; q < SLOTS; ++q)
+            if (tJ[q] > s) {
+                const T *pa = &S[(tJ[q] - s) * IB];
+                const T *pb = &S[(tI[q] - s) * IB];
+#pragma unroll
+                for (int k = 0; k < IB; k += Frag<T>::K) {
+                    Frag<T> fa, fb;
+                    fa.load(pa + k * SLD, SLD, lane);
+                    fb.load(pb + k * SLD, SLD, lane);
+                    fa.negate();
+                    mma(acc[q], fa, fb);
+                }
             }
-        }
         __syncthreads();
+    }
+    // inverses of the 32 x 32 diagonal sub-blocks: lane r forms row r of
+    // W = L^{-1} from W L = I:  W[r][c] = (delta_rc - sum_{k>c} W[r][k] L[k][c]) / L[c][c]
+    if (wave < NT) {
+        const int r = lane & 31;
+        T v[IB], w[IB];
+#pragma unroll
+        for (int c = 0; c < IB; ++c)
+            v[c] = Ld[wave][r * DLD + c];
+#pragma unroll
+        for (int c = IB - 1; c >= 0; --c) {
+            T a = (c == r) ? (T)1 : (T)0;
+#pragma unroll
+            for (int k = c + 1; k < IB; ++k)
+                a -= w[k] * bcast(v[c], k);
+            w[c] = (c <= r) ? a / bcast(v[c], c) : (T)0;
+        }
+        if (lane < IB) {
+#pragma unroll
+            for (int c = 0; c < IB; ++c)
+                Winv[(size_t)wave * IB * IB + r + c * IB] = w[c];
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // K3: panel solve L_ik = H_ik L_kk^{-T}, in place, rows [row0, row0 + nrows).
-// Each wave owns 32 rows, kept in LDS; strip s: X_s -= X_{<s} L_{s,<s}^T
-// (MFMA), then X_s <- X_s W_s^T with W_s the inverse of the 32 x 32 diagonal
-// sub-block.  Waves are independent (no block barrier after the load).
-template <typename T, int NB, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_trsm_panel(T *__restrict__ H, int64_t ld, int64_t k0, int64_t row0,
-                                                           int64_t nrows, const T *__restrict__ Winv,
-                                                           const unsigned long long *info)
+// A workgroup of 2 waves owns 64 rows (32 per wave, kept in LDS).  Strip s:
+// the workgroup stages L_kk[32 s .. 32 s + 31][0 .. 32 s) and the 32 x 32
+// inverse W_s in LDS; each wave computes X_s -= X_{<s} L_{s,<s}^T (MFMA) and
+// then X_s <- X_s W_s^T (MFMA) and stores the strip.
+template <typename T, int NB>
+__global__ __launch_bounds__(128) void k_trsm_panel(T *__restrict__ H, int64_t ld, int64_t k0, int64_t row0,
+                                                    int64_t nrows, const T *__restrict__ Winv,
+                                                    const unsigned long long *info)
 {
     constexpr int IB = SPD_IB;
-    __shared__ T Xs[WAVES][NB * 32];
+    __shared__ T Xs[2][NB * 32];
+    __shared__ T Ls[NB * 32];     // Ls[k * 32 + m] = L_kk[32 s + m][k]
+    __shared__ T Ws[IB * IB];     // W_s column-major
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (*(volatile const unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
         return;
-    const int64_t rbase = row0 + ((int64_t)blockIdx.x * WAVES + wave) * 32;
-    if (rbase >= row0 + nrows)
-        return;  // whole wave idle; no block barriers follow
+    __builtin_amdgcn_s_setprio(3);  // on the critical path of the factorisation
+    const int64_t rbase = row0 + (int64_t)blockIdx.x * 64 + wave * 32;
+    const bool active = rbase < row0 + nrows;
     T *X = Xs[wave];
-    for (int idx = lane; idx < 32 * NB; idx += 64) {
-        const int m = idx & 31, k = idx >> 5;
-        X[k * 32 + m] = H[(rbase + m) + (k0 + k) * ld];
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+    if (active)
+        copy_g2s<T, 32, 64, 16>(X, 32, H + rbase + k0 * ld, ld, NB, lane);
     const T *Lkk = H + k0 + k0 * ld;
     for (int s = 0; s < NB / IB; ++s) {
-        Acc32<T> acc;
-        acc.zero();
-        // D[m][n] = sum_{k < 32 s} L_kk[32 s + m][k] X[n][k]  (= (X L_s^T)^T)
-        if (s > 0)
-            mma_tile<T>(acc, Lkk + 32 * s, (int)ld, X, 32, 32 * s, lane);
-        __builtin_amdgcn_wave_barrier();
+        __syncthreads();
+        copy_g2s<T, 32, 128, 8>(Ls, 32, Lkk + 32 * s, ld, IB * s, tid);
+        copy_g2s<T, 32, 128, 8>(Ws, IB, Winv + (size_t)s * IB * IB, IB, IB, tid);
+        __syncthreads();
+        if (active) {
+            Acc32<T> acc;
+            acc.zero();
+            // D[m][n] = sum_{k < 32 s} L_kk[32 s + m][k] X[n][k]
+            if (s > 0)
+                mma_tile<T>(acc, Ls, 32, X, 32, 32 * s, lane);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int m = Acc32<T>::row(j, lane), nn = Acc32<T>::col(j, lane);
-            X[(32 * s + m) * 32 + nn] -= acc.get(j);
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        // D2[m][n] = sum_t W_s[m][t] Y[n][t] = (Y W_s^T)[n][m]
-        Acc32<T> acc2;
-        acc2.zero();
-        mma_tile<T>(acc2, Winv + (size_t)s * IB * IB, IB, X + 32 * s * 32, 32, IB, lane);
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
+            for (int j = 0; j < 16; ++j) {
+                const int m = Acc32<T>::row(j, lane), nn = Acc32<T>::col(j, lane);
+                X[(32 * s + m) * 32 + nn] -= acc.get(j);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_wave_barrier();
+            // D2[m][n] = sum_t W_s[m][t] Y[n][t] = (Y W_s^T)[n][m]
+            Acc32<T> acc2;
+            acc2.zero();
+            mma_tile<T>(acc2, Ws, IB, X + 32 * s * 32, 32, IB, lane);
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int m = Acc32<T>::row(j, lane), nn = Acc32<T>::col(j, lane);
-            const T v = acc2.get(j);
-            X[(32 * s + m) * 32 + nn] = v;
-            H[(rbase + nn) + (k0 + 32 * s + m) * ld] = v;
+            for (int j = 0; j < 16; ++j) {
+                const int m = Acc32<T>::row(j, lane), nn = Acc32<T>::col(j, lane);
+                const T v = acc2.get(j);
+                X[(32 * s + m) * 32 + nn] = v;
+                H[(rbase + nn) + (k0 + 32 * s + m) * ld] = v;
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -270,7 +326,7 @@ template <> struct SyrkCfg<double> { static constexpr int KC = 16; };
 template <typename T>
 __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t ld, int64_t k0, int nbk, int64_t r0,
                                                      int t, int tj_lo, int tj_hi, int ntiles,
-                                                     const unsigned long long *info)
+                                                     const unsigned long long *info, int prio)
 {
     constexpr int KC = SyrkCfg<T>::KC;
     constexpr int LDT = SPD_TILE + 4;  // LDS column stride
@@ -279,6 +335,8 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (*(volatile const unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
         return;
+    if (prio)
+        __builtin_amdgcn_s_setprio(2);  // the lookahead part of the update
     const int per = gridDim.x / 8;
     const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (logical >= ntiles)
@@ -292,12 +350,19 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
     const T *pb = H + crow + k0 * ld;  // rows of tile ti (D columns = C rows)
     const int wm = wave >> 1, wn = wave & 1;
 
+    // The C tile is read once, up front, straight into the accumulators (so
+    // its latency overlaps the K loop); the MFMA operands are negated.
+    // Register j of tile (mi, ni) holds C[crow + 64 wn + 32 ni + col(j)][ccol + 64 wm + 32 mi + row(j)].
     Acc32<T> acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-            acc[a][b].zero();
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int m = Acc32<T>::row(j, lane), nn = Acc32<T>::col(j, lane);
+                acc[mi][ni].set(j, H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld]);
+            }
 
     // 128 rows x KC columns of each operand per chunk, 16-byte vector loads,
     // staged through registers so the next chunk's loads overlap the MFMAs.
@@ -305,35 +370,42 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
     constexpr int VEC = 16 / sizeof(T);
     constexpr int PER_COL = SPD_TILE / VEC;
     constexpr int NV = PER_COL * KC / 256;  // vectors per thread per operand
-    V ra[NV], rb[NV];
-    auto gload = [&](int kb) {
+    static_assert(NV == 4, "staging layout");
+    // per-thread staging slots: vector v covers column col_v, rows r_v..r_v+VEC-1
+    int soff[NV];
+    size_t goff[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const int idx = tid + 256 * v;
-            const int col = idx / PER_COL, r = (idx % PER_COL) * VEC;
-            const size_t go = (size_t)(kb + col) * ld + r;
-            ra[v] = *(const V *)&pa[go];
-            rb[v] = *(const V *)&pb[go];
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const int idx = tid + 256 * v;
-            const int col = idx / PER_COL, r = (idx % PER_COL) * VEC;
-            *(V *)&As[buf][col * LDT + r] = ra[v];
-            *(V *)&Bs[buf][col * LDT + r] = rb[v];
-        }
-    };
+    for (int v = 0; v < NV; ++v) {
+        const int idx = tid + 256 * v;
+        const int col = idx / PER_COL, r = (idx % PER_COL) * VEC;
+        soff[v] = col * LDT + r;
+        goff[v] = (size_t)col * ld + r;
+    }
+    V ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+#define SPD_GLOAD(kb)                                                       \
+    do {                                                                    \
+        const size_t o_ = (size_t)(kb) * ld;                                \
+        ra0 = *(const V *)&pa[o_ + goff[0]]; rb0 = *(const V *)&pb[o_ + goff[0]]; \
+        ra1 = *(const V *)&pa[o_ + goff[1]]; rb1 = *(const V *)&pb[o_ + goff[1]]; \
+        ra2 = *(const V *)&pa[o_ + goff[2]]; rb2 = *(const V *)&pb[o_ + goff[2]]; \
+        ra3 = *(const V *)&pa[o_ + goff[3]]; rb3 = *(const V *)&pb[o_ + goff[3]]; \
+    } while (0)
+#define SPD_SSTORE(buf)                                                     \
+    do {                                                                    \
+        *(V *)&As[buf][soff[0]] = ra0; *(V *)&Bs[buf][soff[0]] = rb0;       \
+        *(V *)&As[buf][soff[1]] = ra1; *(V *)&Bs[buf][soff[1]] = rb1;       \
+        *(V *)&As[buf][soff[2]] = ra2; *(V *)&Bs[buf][soff[2]] = rb2;       \
+        *(V *)&As[buf][soff[3]] = ra3; *(V *)&Bs[buf][soff[3]] = rb3;       \
+    } while (0)
 
-    gload(0);
-    sstore(0);
+    SPD_GLOAD(0);
+    SPD_SSTORE(0);
     __syncthreads();
     int buf = 0;
     for (int kb = 0; kb < nbk; kb += KC) {
-        const bool more = kb + KC < nbk;
-        if (more)
-            gload(kb + KC);
+        // prefetch the next chunk (the last iteration re-reads its own chunk)
+        const int kn = (kb + KC < nbk) ? kb + KC : kb;
+        SPD_GLOAD(kn);
         const T *a0 = &As[buf][64 * wm];
         const T *b0 = &Bs[buf][64 * wn];
 #pragma unroll
@@ -343,18 +415,20 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
             fa[1].load(a0 + 32 + k * LDT, LDT, lane);
             fb[0].load(b0 + k * LDT, LDT, lane);
             fb[1].load(b0 + 32 + k * LDT, LDT, lane);
+            fa[0].negate();
+            fa[1].negate();
 #pragma unroll
             for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
                 for (int ni = 0; ni < 2; ++ni)
                     mma(acc[mi][ni], fa[mi], fb[ni]);
         }
-        if (more)
-            sstore(buf ^ 1);
+        SPD_SSTORE(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
-    // epilogue: C[crow + 64 wn + 32 ni + n][ccol + 64 wm + 32 mi + m] -= D
+#undef SPD_GLOAD
+#undef SPD_SSTORE
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -362,8 +436,7 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const int m = Acc32<T>::row(j, lane), nn = Acc32<T>::col(j, lane);
-                T *p = H + (crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld;
-                *p -= acc[mi][ni].get(j);
+                H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld] = acc[mi][ni].get(j);
             }
 }
 
@@ -501,21 +574,18 @@ template void launch_convert<double>(const double *, int64_t, int64_t, int64_t, 
 template <typename T>
 void launch_potrf_diag(T *Hkk, int64_t ld, int64_t col0, T *Winv, unsigned long long *info, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_potrf_diag<T, SPD_NB>), dim3(1), dim3(256), 0, st, Hkk, ld, col0, Winv, info);
+    hipLaunchKernelGGL((k_potrf_diag<T, Panel<T>::NB>), dim3(1), dim3(512), 0, st, Hkk, ld, col0, Winv, info);
 }
 template void launch_potrf_diag<float>(float *, int64_t, int64_t, float *, unsigned long long *, hipStream_t);
 template void launch_potrf_diag<double>(double *, int64_t, int64_t, double *, unsigned long long *, hipStream_t);
-
-template <typename T> constexpr int trsm_waves() { return sizeof(T) == 4 ? 4 : 2; }
 
 template <typename T>
 void launch_trsm_panel(T *H, int64_t ld, int64_t k0, int64_t row0, int64_t nrows, const T *Winv,
                        const unsigned long long *info, hipStream_t st)
 {
     if (nrows <= 0) return;
-    constexpr int W = trsm_waves<T>();
-    const unsigned blocks = (unsigned)((nrows + 32 * W - 1) / (32 * W));
-    hipLaunchKernelGGL((k_trsm_panel<T, SPD_NB, W>), dim3(blocks), dim3(64 * W), 0, st, H, ld, k0, row0, nrows,
+    const unsigned blocks = (unsigned)((nrows + 63) / 64);
+    hipLaunchKernelGGL((k_trsm_panel<T, Panel<T>::NB>), dim3(blocks), dim3(128), 0, st, H, ld, k0, row0, nrows,
                        Winv, info);
 }
 template void launch_trsm_panel<float>(float *, int64_t, int64_t, int64_t, int64_t, const float *,
@@ -525,25 +595,26 @@ template void launch_trsm_panel<double>(double *, int64_t, int64_t, int64_t, int
 
 template <typename T>
 void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,
-                        const unsigned long long *info, hipStream_t st)
+                        const unsigned long long *info, hipStream_t st, int prio)
 {
     if (t <= 0 || tj_lo >= tj_hi) return;
     int64_t ntiles = 0;
     for (int c = tj_lo; c < tj_hi; ++c) ntiles += t - c;
     const int64_t grid = ((ntiles + 7) / 8) * 8;
     hipLaunchKernelGGL(k_syrk_update<T>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, k0, nbk, r0, t, tj_lo,
-                       tj_hi, (int)ntiles, info);
+                       tj_hi, (int)ntiles, info, prio);
 }
 template void launch_syrk_update<float>(float *, int64_t, int64_t, int, int64_t, int, int, int,
-                                        const unsigned long long *, hipStream_t);
+                                        const unsigned long long *, hipStream_t, int);
 template void launch_syrk_update<double>(double *, int64_t, int64_t, int, int64_t, int, int, int,
-                                         const unsigned long long *, hipStream_t);
+                                         const unsigned long long *, hipStream_t, int);
 
 template <typename T>
 void launch_trtri_blocks(const T *H, int64_t ld, int64_t nt, const T *Winv, T *W, hipStream_t st)
 {
     constexpr int WV = sizeof(T) == 4 ? 4 : 2;
-    hipLaunchKernelGGL((k_trtri_blocks<T, SPD_NB, WV>), dim3((unsigned)nt), dim3(64 * WV), 0, st, H, ld, Winv, W);
+    hipLaunchKernelGGL((k_trtri_blocks<T, Panel<T>::NB, WV>), dim3((unsigned)nt), dim3(64 * WV), 0, st, H, ld, Winv,
+                       W);
 }
 template void launch_trtri_blocks<float>(const float *, int64_t, int64_t, const float *, float *, hipStream_t);
 template void launch_trtri_blocks<double>(const double *, int64_t, int64_t, const double *, double *, hipStream_t);

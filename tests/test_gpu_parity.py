@@ -262,3 +262,28 @@ def test_separate_calls_match_posv(spd, orc):
     assert np.array_equal(host(X0), host(Xp))
     F.close()
     F2.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("n,m", [(640, 11), (400, 64), (1100, 3)])
+def test_posv_many_rhs(spd, orc, prec, n, m):
+    _say(f"posv {prec} n={n} m={m}")
+    cond = 1e3
+    s = spdgen.system(n, cond, m, config=0, index=3000 + n + m)
+    X, rep, F = spd.posv(dev(s.A), dev(s.Bt), prec=prec)
+    Xh = host(X)
+    F.close()
+    assert rep.status == 0, rep.as_dict()
+    assert np.all(orc.backward_error(s.A, Xh, s.Bt) <= 1e-14)
+    Xo, _ = orc.solve(s.A, s.Bt)
+    assert np.all(fwd_err(Xh, Xo) <= 10 * cond * U64)
+
+
+def test_solve_only_first_step_accuracy(spd, orc):
+    # Algorithm 1, line 2 alone with a binary64 factor: already binary64-accurate
+    s = spdgen.system(777, 1e4, 4, config=0, index=4000)
+    F, info, st = spd.factor(dev(s.A), "fp64")
+    X = host(spd.solve(F, dev(s.Bt)))
+    F.close()
+    Xo, _ = orc.solve(s.A, s.Bt)
+    assert np.all(fwd_err(X, Xo) <= 10 * 1e4 * U64)

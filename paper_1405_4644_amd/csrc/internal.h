@@ -5,11 +5,14 @@
 
 namespace spd {
 
-// Panel width of the blocked factorisation per factor type: 256 for binary32
-// (trailing update K = 256 keeps it MFMA-bound), 128 for binary64 (the
-// binary64 ridge is lower and the diagonal block then fits in registers).
+// Panel width of the blocked factorisation per factor type.  128 for both:
+// the diagonal-block factor is a chain of NB dependent column steps per
+// panel, and at NB = 128 the panel chain (diagonal factor + panel solve)
+// stays short enough for the lookahead to hide it behind the trailing
+// update, which is still MFMA-bound at K = 128 in binary32 (about 81 TFLOP/s
+// measured) and in binary64.
 template <typename T> struct Panel;
-template <> struct Panel<float> { static constexpr int NB = 256; };
+template <> struct Panel<float> { static constexpr int NB = 128; };
 template <> struct Panel<double> { static constexpr int NB = 128; };
 
 // --- factorisation (k_factor.hip) ---

@@ -69,28 +69,37 @@ template <> SPD_DEV double bcast<double>(double v, int src)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Square root and reciprocal for the diagonal factor: the hardware
+// approximations (about 1 ulp) for binary32, IEEE-correct for binary64.
+SPD_DEV float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+SPD_DEV float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+SPD_DEV double fast_sqrt(double x) { return sqrt(x); }
+SPD_DEV double fast_rcp(double x) { return 1.0 / x; }
+
 // ---------------------------------------------------------------------------
-// K2: Cholesky of one NB x NB diagonal block by one workgroup of 8 waves.
+// K2: Cholesky of one NB x NB diagonal block by one workgroup of 4 waves.
 // The lower triangle is held in registers as 32 x 32 MFMA accumulator tiles
-// (tile t of the row-major lower triangle belongs to wave t % 8).  For each
-// 32-wide strip s: the owners of tile column s spill it to LDS; wave 0
-// factors the top 32 x 32 block (lane r holds row r; values are broadcast
-// with readlane); every thread solves one row below against it; the strip is
-// stored to global memory; every wave subtracts the strip's outer product
-// from its remaining tiles with MFMA.  Finally waves 0..NB/32-1 each invert
-// one 32 x 32 diagonal sub-block (stored in Winv for the panel solve).
+// (tile t of the row-major lower triangle belongs to wave t % 4).  For each
+// 32-wide strip s (rows 32 s .. NB-1):
+//   1. the owners of tile column s spill it to LDS;
+//   2. the strip is factored column by column inside each wave, without
+//      block barriers: every wave holds its own copy of the 32 x 32 top
+//      block in lanes 0..31 and 32 of the rows below in lanes 32..63 (a
+//      second pass covers rows beyond 128), broadcasting column values
+//      between lanes with readlane;
+//   3. the strip is stored and every wave subtracts its outer product from
+//      its remaining tiles with MFMA.
+// Finally each 32 x 32 diagonal sub-block is inverted (for the panel solve).
 // `info` receives min(1-based global column) of a non-positive pivot.
 template <typename T, int NB>
-__global__ __launch_bounds__(512) void k_potrf_diag(T *__restrict__ Hkk, int64_t ld, int64_t col0,
+__global__ __launch_bounds__(256) void k_potrf_diag(T *__restrict__ Hkk, int64_t ld, int64_t col0,
                                                     T *__restrict__ Winv, unsigned long long *info)
 {
-    constexpr int IB = SPD_IB, NT = NB / IB, NTILES = NT * (NT + 1) / 2, NW = 8;
+    constexpr int IB = SPD_IB, NT = NB / IB, NTILES = NT * (NT + 1) / 2, NW = 4;
     constexpr int SLOTS = (NTILES + NW - 1) / NW;
-    constexpr int SLD = NB + 1, DLD = IB + 1, CLD = IB + 4;
-    __shared__ T S[IB * SLD];          // strip: S[k * SLD + r], r = row offset from 32 s
-    __shared__ T Ld[NT][IB * DLD];     // factored 32 x 32 diagonal sub-blocks, row-major
-    __shared__ T Lc[IB * CLD];         // current one, column-major: Lc[t * CLD + c] = L[c][t]
-    __shared__ T Dinv[IB];             // 1 / L[t][t]
+    constexpr int SLD = NB + 1, CLD = IB + 4;
+    __shared__ T S[IB * SLD];                     // strip: S[k * SLD + r], r = row offset from 32 s
+    __shared__ __align__(16) T Lc[NT][IB * CLD];  // factored 32 x 32 blocks, column-major: Lc[t*CLD + c] = L[c][t]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (*(volatile unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
         return;
@@ -123,69 +132,66 @@ __global__ __launch_bounds__(512) void k_potrf_diag(T *__restrict__ Hkk, int64_t
                     S[Acc32<T>::row(j, lane) * SLD + (tI[q] - s) * IB + Acc32<T>::col(j, lane)] = acc[q].get(j);
             }
         __syncthreads();
-        if (wave == 0) {
-            T v[IB];
-#pragma unroll
-            for (int j = 0; j < IB; ++j)
-                v[j] = (lane < IB && j <= lane) ? S[j * SLD + lane] : (T)0;
-            bool failed = false;
-#pragma unroll
-            for (int j = 0; j < IB; ++j) {
-                const T piv = bcast(v[j], j);
-                if (!(piv > (T)0) && !failed) {
-                    failed = true;
-                    if (lane == 0)
-                        atomicMin(info, (unsigned long long)(col0 + s * IB + j + 1));
+        // Strip factorisation without block barriers: lanes 0..31 of EVERY
+        // wave hold the 32 x 32 top block (row = lane) and factor it
+        // redundantly; lanes 32..63 of wave w carry rows below the top block
+        // through the same column operations (pass p: below-rows
+        // 128 p + 32 w .. +31; the second pass reuses the final top block).
+        // Column j: pivot from lane j, scale, L[k][j] broadcast from lane k
+        // (readlane), rank-1 update.  Entries above the diagonal in the top
+        // lanes are updated too but never read.
+        {
+            const int nbelow = rows - IB;
+            const int npass = nbelow > 128 ? 2 : 1;
+            T *lc = Lc[s];
+            for (int pass = 0; pass < npass; ++pass) {
+                int row;
+                if (lane < IB)
+                    row = lane;
+                else {
+                    const int bidx = pass * 128 + wave * 32 + (lane - IB);
+                    row = (bidx < nbelow) ? IB + bidx : -1;
                 }
-                const T ljj = sqrt(piv);
-                const T rinv = (T)1 / ljj;
-                if (lane == j)
-                    v[j] = ljj;
-                else if (lane > j)
-                    v[j] = v[j] * rinv;
+                T v[IB];
 #pragma unroll
-                for (int k = j + 1; k < IB; ++k) {
-                    const T lkj = bcast(v[j], k);
-                    if (lane >= k)
-                        v[k] -= v[j] * lkj;
-                }
-                if (lane == 0)
-                    Dinv[j] = rinv;
-            }
-            if (lane < IB) {
+                for (int k = 0; k < IB; ++k)
+                    v[k] = (row >= 0) ? S[k * SLD + row] : (T)0;
 #pragma unroll
                 for (int j = 0; j < IB; ++j) {
-                    const T x = (j <= lane) ? v[j] : (T)0;
-                    S[j * SLD + lane] = x;
-                    Ld[s][lane * DLD + j] = x;
-                    Lc[j * CLD + lane] = x;
+                    const T piv = bcast(v[j], j);
+                    if (pass == 0 && !(piv > (T)0) && wave == 0 && lane == 0)
+                        atomicMin(info, (unsigned long long)(col0 + s * IB + j + 1));
+                    // pass 0 factors; later passes find the final L_jj in lane j
+                    const T ljj = (pass == 0) ? fast_sqrt(piv) : piv;
+                    const T rinv = fast_rcp(ljj);
+                    const T sc = v[j] * rinv;
+                    const bool top = lane < IB;
+                    v[j] = (pass == 0) ? ((lane == j) ? ljj : sc) : (top ? v[j] : sc);
+                    // broadcast L[k][j] from lane k and apply the rank-1 update
+                    const T vj = v[j];
+                    const bool upd = (pass == 0) || lane >= IB;
+#pragma unroll
+                    for (int k = j + 1; k < IB; ++k) {
+                        const T lkj = bcast(vj, k);
+                        if (upd)
+                            v[k] -= vj * lkj;
+                    }
                 }
+                if (row >= 0 && (lane >= IB || (pass == 0 && wave == 0))) {
+#pragma unroll
+                    for (int k = 0; k < IB; ++k) {
+                        const T x = (row >= k) ? v[k] : (T)0;
+                        S[k * SLD + row] = x;
+                        if (row < IB)
+                            lc[k * CLD + row] = x;
+                    }
+                }
+                __syncthreads();
             }
         }
-        __syncthreads();
-        // rows below the top block solve x L_top^T = s_r, column by column
-        // (right-looking: after x_t is final it updates every later x_c, so
-        // the 31 - t updates of a step are independent)
-        for (int r = IB + tid; r < rows; r += 512) {
-            T x[IB];
-#pragma unroll
-            for (int t = 0; t < IB; ++t)
-                x[t] = S[t * SLD + r];
-#pragma unroll
-            for (int t = 0; t < IB; ++t) {
-                x[t] *= Dinv[t];
-#pragma unroll
-                for (int c = t + 1; c < IB; ++c)
-                    x[c] -= x[t] * Lc[t * CLD + c];
-            }
-#pragma unroll
-            for (int t = 0; t < IB; ++t)
-                S[t * SLD + r] = x[t];
-        }
-        __syncthreads();
-        for (int idx = tid; idx < IB * rows; idx += 512) {
-            const int j = idx / rows, r = idx - j * rows;
-            Hkk[(s * IB + r) + (int64_t)(s * IB + j) * ld] = S[j * SLD + r];
+        for (int idx = tid; idx < IB * rows; idx += 256) {
+            const int j = idx / rows, rr = idx - j * rows;
+            Hkk[(s * IB + rr) + (int64_t)(s * IB + j) * ld] = S[j * SLD + rr];
         }
         // trailing update of the owned tiles: D(ti,tj) -= L_tj L_ti^T
 #pragma unroll
@@ -206,24 +212,22 @@ __global__ __launch_bounds__(512) void k_potrf_diag(T *__restrict__ Hkk, int64_t
     }
     // inverses of the 32 x 32 diagonal sub-blocks: lane r forms row r of
     // W = L^{-1} from W L = I:  W[r][c] = (delta_rc - sum_{k>c} W[r][k] L[k][c]) / L[c][c]
-    if (wave < NT) {
-        const int r = lane & 31;
-        T v[IB], w[IB];
-#pragma unroll
-        for (int c = 0; c < IB; ++c)
-            v[c] = Ld[wave][r * DLD + c];
+    for (int b = wave; b < NT; b += NW) {
+        const int rr = lane & 31;
+        const T *lc = Lc[b];
+        T w[IB];
 #pragma unroll
         for (int c = IB - 1; c >= 0; --c) {
-            T a = (c == r) ? (T)1 : (T)0;
+            T a = (c == rr) ? (T)1 : (T)0;
 #pragma unroll
             for (int k = c + 1; k < IB; ++k)
-                a -= w[k] * bcast(v[c], k);
-            w[c] = (c <= r) ? a / bcast(v[c], c) : (T)0;
+                a -= w[k] * lc[c * CLD + k];
+            w[c] = (c <= rr) ? a / lc[c * CLD + c] : (T)0;
         }
         if (lane < IB) {
 #pragma unroll
             for (int c = 0; c < IB; ++c)
-                Winv[(size_t)wave * IB * IB + r + c * IB] = w[c];
+                Winv[(size_t)b * IB * IB + rr + c * IB] = w[c];
         }
     }
 }
@@ -574,7 +578,7 @@ template void launch_convert<double>(const double *, int64_t, int64_t, int64_t, 
 template <typename T>
 void launch_potrf_diag(T *Hkk, int64_t ld, int64_t col0, T *Winv, unsigned long long *info, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_potrf_diag<T, Panel<T>::NB>), dim3(1), dim3(512), 0, st, Hkk, ld, col0, Winv, info);
+    hipLaunchKernelGGL((k_potrf_diag<T, Panel<T>::NB>), dim3(1), dim3(256), 0, st, Hkk, ld, col0, Winv, info);
 }
 template void launch_potrf_diag<float>(float *, int64_t, int64_t, float *, unsigned long long *, hipStream_t);
 template void launch_potrf_diag<double>(double *, int64_t, int64_t, double *, unsigned long long *, hipStream_t);

@@ -49,11 +49,13 @@ typedef enum {
 } spd_status;
 
 /* Precision of the factorisation (the "low precision" of Algorithm 1).
- * BF16/FP16: the trailing-update operands are rounded to that format and
- * multiplied with binary32 accumulation, after symmetric diagonal
- * equilibration (and, for FP16, a power-of-two scale).  FP32: binary32
- * throughout.  FP64: plain binary64 Cholesky (the baseline and the last
- * fallback).  AUTO: chosen per system by the library (batched entry point). */
+ * BF16/FP16: after symmetric diagonal equilibration (and, for FP16, a
+ * power-of-two scale mu), each solved panel is rounded to nearest even in that
+ * format and the trailing update multiplies those operands with binary32
+ * accumulation; the diagonal blocks, panel solves and the stored factor stay
+ * binary32, and so do the triangular solves.  FP32: binary32 throughout.
+ * FP64: plain binary64 Cholesky (the baseline and the last fallback).  AUTO:
+ * chosen per system by the library (batched entry point). */
 typedef enum { SPD_BF16 = 0, SPD_FP16 = 1, SPD_FP32 = 2, SPD_FP64 = 3, SPD_AUTO = 4 } spd_prec;
 
 /* Options; passing NULL means the defaults shown. */

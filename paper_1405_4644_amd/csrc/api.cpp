@@ -36,6 +36,9 @@ struct spd_factor_s {
     double *d = nullptr;     // n: equilibration
     int64_t cap_d = 0;
     double mu = 1.0;
+    int half = HALF_NONE;    // operand rounding of the trailing update (BF16 / FP16 factors)
+    void *Lh = nullptr;      // two panel copies in that precision (npad x NB halves each)
+    size_t cap_Lh = 0;
     unsigned long long *info_dev = nullptr;
     unsigned long long *info_host = nullptr;  // pinned
     // solve workspace
@@ -104,14 +107,18 @@ void prof_end(hipEvent_t a, hipStream_t st, int kind, double flops, double bytes
 }
 
 // algorithmic work of one trailing-update launch over tile columns [lo, hi)
-void update_work(int t, int lo, int hi, int nbk, int elem, double *flops, double *bytes)
+// Algorithmic work of one trailing-update launch: flops of the lower tiles
+// (diagonal tiles count their lower half), bytes = each C tile read and
+// written once in the factor type (elem) plus its two operand panels
+// (op_elem bytes per element).
+void update_work(int t, int lo, int hi, int nbk, int elem, int op_elem, double *flops, double *bytes)
 {
     const double T = SPD_TILE_H;
     double f = 0, b = 0;
     for (int c = lo; c < hi; ++c) {
         const double off = t - c - 1;  // off-diagonal tiles in this tile column
         f += off * 2.0 * T * T * nbk + T * (T + 1) * nbk;
-        b += (off + 1) * (2.0 * T * T + 2.0 * T * nbk) * elem;
+        b += (off + 1) * (2.0 * T * T * elem + 2.0 * T * nbk * op_elem);
     }
     *flops = f;
     *bytes = b;
@@ -199,9 +206,23 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
     const int64_t wi_blk = (NB / SPD_IB_H) * SPD_IB_H * SPD_IB_H;
     const int tcols = (int)(NB / SPD_TILE_H);
     hipEvent_t evU = F->ev[0], evP = F->ev[1], evQ = F->ev[2];
+    // half-precision operand copies of panels k (even / odd), written by the
+    // panel solve and read by both parts of the update
+    const int half = (sizeof(T) == 4) ? F->half : HALF_NONE;
+    const int op_elem = half ? 2 : (int)sizeof(T);
+    auto lh = [&](int64_t k) -> void * {
+        return half ? (void *)((char *)F->Lh + (size_t)(k & 1) * npad * NB * 2) : nullptr;
+    };
+    auto update = [&](int64_t k, int t, int lo, int hi, hipStream_t s, int prio) {
+        const int64_t k0 = k * NB, r0 = k0 + NB;
+        if (half)
+            spd::launch_syrk_update_half((float *)H, npad, lh(k), half, r0, t, lo, hi, F->info_dev, s, prio);
+        else
+            spd::launch_syrk_update<T>(H, npad, k0, (int)NB, r0, t, lo, hi, F->info_dev, s, prio);
+    };
 
     spd::launch_potrf_diag<T>(H, npad, 0, Wi, F->info_dev, st);
-    spd::launch_trsm_panel<T>(H, npad, 0, NB, npad - NB, Wi, F->info_dev, st);
+    spd::launch_trsm_panel<T>(H, npad, 0, NB, npad - NB, Wi, F->info_dev, st, lh(0), half);
     if (nt > 1) {
         HIP_TRY(hipEventRecord(evP, st));
         for (int64_t k = 0; k + 1 < nt; ++k) {
@@ -212,21 +233,21 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
             if (k > 0) HIP_TRY(hipStreamWaitEvent(F->side, evU, 0));
             double fl, by;
             hipEvent_t pa = prof_begin(F->side);
-            spd::launch_syrk_update<T>(H, npad, k0, (int)NB, r0, t, 0, tcols, F->info_dev, F->side, 1);
+            update(k, t, 0, tcols, F->side, 1);
             if (pa) {
-                update_work(t, 0, tcols, (int)NB, (int)sizeof(T), &fl, &by);
+                update_work(t, 0, tcols, (int)NB, (int)sizeof(T), op_elem, &fl, &by);
                 prof_end(pa, F->side, SPD_K_UPDATE, fl, by);
             }
             spd::launch_potrf_diag<T>(H + r0 + r0 * npad, npad, r0, Wi + (k + 1) * wi_blk, F->info_dev, F->side);
             spd::launch_trsm_panel<T>(H, npad, r0, r0 + NB, npad - r0 - NB, Wi + (k + 1) * wi_blk, F->info_dev,
-                                      F->side);
+                                      F->side, lh(k + 1), half);
             HIP_TRY(hipEventRecord(evQ, F->side));
             // the rest of the trailing update on the main stream
             HIP_TRY(hipStreamWaitEvent(st, evP, 0));
             hipEvent_t pb = prof_begin(st);
-            spd::launch_syrk_update<T>(H, npad, k0, (int)NB, r0, t, tcols, t, F->info_dev, st);
+            update(k, t, tcols, t, st, 0);
             if (pb) {
-                update_work(t, tcols, t, (int)NB, (int)sizeof(T), &fl, &by);
+                update_work(t, tcols, t, (int)NB, (int)sizeof(T), op_elem, &fl, &by);
                 prof_end(pb, st, SPD_K_UPDATE, fl, by);
             }
             HIP_TRY(hipEventRecord(evU, st));
@@ -267,6 +288,12 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
     F->cap_d = (int64_t)(capd / sizeof(double));
 
     F->mu = (prec == SPD_FP16) ? fp16_scale(o.theta) : 1.0;
+    F->half = (prec == SPD_FP16) ? HALF_F16 : (prec == SPD_BF16) ? HALF_BF16 : HALF_NONE;
+    if (F->half) {
+        size_t caph = F->cap_Lh;
+        SPD_TRY(grow(&F->Lh, &caph, (size_t)2 * npad * F->nb * 2, false, st));
+        F->cap_Lh = caph;
+    }
     const int equil = (prec != SPD_FP64 && o.equilibrate) ? 1 : 0;
     *F->info_host = SPD_INFO_NONE_H;
     HIP_TRY(hipMemcpyAsync(F->info_dev, F->info_host, sizeof(unsigned long long), hipMemcpyHostToDevice, st));
@@ -554,7 +581,6 @@ spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec, co
         return SPD_ERR_INVALID_ARG;
     const spd_opts op = o ? *o : defaults();
     if (!opts_valid(op)) return SPD_ERR_INVALID_ARG;
-    if (prec == SPD_BF16 || prec == SPD_FP16) return SPD_ERR_UNSUPPORTED;
     *info = 0;
     bool created = false;
     if (!*F) {
@@ -739,6 +765,7 @@ void spd_factor_destroy(spd_factor_t F)
     if (!F) return;
     if (F->side) hipStreamSynchronize(F->side);
     hipFree(F->L);
+    hipFree(F->Lh);
     hipFree(F->d);
     hipFree(F->Y);
     hipFree(F->smax);

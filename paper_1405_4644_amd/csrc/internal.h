@@ -3,6 +3,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Operand rounding of the trailing update: none (binary32 / binary64
+// operands), binary16 or bfloat16 (binary32 accumulation).
+enum spd_half_kind { HALF_NONE = 0, HALF_F16 = 1, HALF_BF16 = 2 };
+
 namespace spd {
 
 // Panel width of the blocked factorisation per factor type.  128 for both:
@@ -22,12 +26,19 @@ void launch_convert(const double *A, int64_t lda, int64_t n, int64_t npad, const
                     int64_t ldh, hipStream_t st);
 template <typename T>
 void launch_potrf_diag(T *Hkk, int64_t ld, int64_t col0, T *Winv, unsigned long long *info, hipStream_t st);
+// With half != HALF_NONE (binary32 only) the solved rows are also written,
+// rounded to nearest even, to Lh (nrows x NB halves, fragment layout of
+// launch_syrk_update_half).
 template <typename T>
 void launch_trsm_panel(T *H, int64_t ld, int64_t k0, int64_t row0, int64_t nrows, const T *Winv,
-                       const unsigned long long *info, hipStream_t st);
+                       const unsigned long long *info, hipStream_t st, void *Lh = nullptr, int half = HALF_NONE);
 template <typename T>
 void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,
                         const unsigned long long *info, hipStream_t st, int prio = 0);
+// Trailing update with binary16 / bfloat16 operands from the panel copy Lh
+// (rows r0.. of the panel, K = 128), binary32 accumulation into H.
+void launch_syrk_update_half(float *H, int64_t ld, const void *Lh, int half, int64_t r0, int t, int tj_lo,
+                             int tj_hi, const unsigned long long *info, hipStream_t st, int prio = 0);
 template <typename T>
 void launch_trtri_blocks(const T *H, int64_t ld, int64_t nt, const T *Winv, T *W, hipStream_t st);
 

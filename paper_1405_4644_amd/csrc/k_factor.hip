@@ -16,6 +16,22 @@
 #include "internal.h"
 #include <type_traits>
 
+// Operand types of the half-precision trailing update.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <int HK> struct HalfT;
+template <> struct HalfT<HALF_F16> {
+    using E = _Float16;
+    using V8 = halfx8;
+    static SPD_DEV V8 neg(V8 v) { return __builtin_bit_cast(V8, __builtin_bit_cast(u32x4, v) ^ 0x80008000u); }
+    static SPD_DEV floatx16 mma(V8 a, V8 b, floatx16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0); }
+};
+template <> struct HalfT<HALF_BF16> {
+    using E = __bf16;
+    using V8 = bf16x8;
+    static SPD_DEV V8 neg(V8 v) { return __builtin_bit_cast(V8, __builtin_bit_cast(u32x4, v) ^ 0x80008000u); }
+    static SPD_DEV floatx16 mma(V8 a, V8 b, floatx16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+};
+
 // ---------------------------------------------------------------------------
 // K1a: equilibration vector d_i = a_ii^{-1/2} (1 where a_ii <= 0 or not
 // equilibrating; a non-positive diagonal then surfaces as a breakdown).
@@ -238,10 +254,10 @@ __global__ __launch_bounds__(256) void k_potrf_diag(T *__restrict__ Hkk, int64_t
 // the workgroup stages L_kk[32 s .. 32 s + 31][0 .. 32 s) and the 32 x 32
 // inverse W_s in LDS; each wave computes X_s -= X_{<s} L_{s,<s}^T (MFMA) and
 // then X_s <- X_s W_s^T (MFMA) and stores the strip.
-template <typename T, int NB>
+template <typename T, int NB, int HK>
 __global__ __launch_bounds__(128) void k_trsm_panel(T *__restrict__ H, int64_t ld, int64_t k0, int64_t row0,
                                                     int64_t nrows, const T *__restrict__ Winv,
-                                                    const unsigned long long *info)
+                                                    const unsigned long long *info, void *__restrict__ Lh)
 {
     constexpr int IB = SPD_IB;
     __shared__ T Xs[2][NB * 32];
@@ -290,6 +306,23 @@ __global__ __launch_bounds__(128) void k_trsm_panel(T *__restrict__ H, int64_t l
             }
             __builtin_amdgcn_s_waitcnt(0);
             __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if constexpr (HK != HALF_NONE) {
+        // the same 32 rows rounded to binary16 / bfloat16 (round to nearest
+        // even), in the fragment layout of the half-precision update
+        if (active) {
+            using V8 = typename HalfT<HK>::V8;
+            V8 *dst = (V8 *)Lh + (size_t)((rbase - row0) / 32) * (NB / 16) * 64;
+            const int rr = lane & 31, kh = lane >> 5;
+#pragma unroll
+            for (int ks = 0; ks < NB / 16; ++ks) {
+                V8 v;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    v[i] = (typename HalfT<HK>::E)X[(16 * ks + 8 * kh + i) * 32 + rr];
+                dst[ks * 64 + lane] = v;
+            }
         }
     }
 }
@@ -445,6 +478,81 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+// K4, half-precision operands: H_ij -= round(L_ik) round(L_jk)^T with
+// binary16 or bfloat16 operands and binary32 accumulation
+// (v_mfma_f32_32x32x16_{f16,bf16}), K = NB = 128.  The operand panel is the
+// fragment-layout copy written by the panel solve: row r (relative to the
+// first trailing row), column k lives at
+//   ((r/32) (NB/16) + k/16) * 512 + (32 ((k%16)/8) + r%32) * 8 + k%8,
+// so every fragment load is one contiguous 1 KiB per wave.  The C tile is the
+// only HBM traffic that scales with the tile count: 64 KiB in, 64 KiB out.
+template <int HK>
+__global__ __launch_bounds__(256) void k_syrk_update_h(float *__restrict__ H, int64_t ld,
+                                                       const void *__restrict__ Lh, int64_t r0, int t, int tj_lo,
+                                                       int tj_hi, int ntiles, const unsigned long long *info,
+                                                       int prio)
+{
+    using V8 = typename HalfT<HK>::V8;
+    constexpr int KS = 128 / 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (*(volatile const unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
+        return;
+    if (prio)
+        __builtin_amdgcn_s_setprio(2);
+    const int per = gridDim.x / 8;
+    const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (logical >= ntiles)
+        return;
+    int ti, tj;
+    decode_tile(logical, t, tj_lo, tj_hi, ti, tj);
+    if (ti < 0)
+        return;
+    const int64_t crow = r0 + (int64_t)ti * SPD_TILE, ccol = r0 + (int64_t)tj * SPD_TILE;
+    const int wm = wave >> 1, wn = wave & 1;
+    const V8 *lh = (const V8 *)Lh;
+    // A operand: rows of tile tj (C columns); B operand: rows of tile ti (C rows)
+    const V8 *pa0 = lh + (size_t)(4 * tj + 2 * wm) * KS * 64 + lane;
+    const V8 *pb0 = lh + (size_t)(4 * ti + 2 * wn) * KS * 64 + lane;
+    V8 fa[KS][2], fb[KS][2];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            fa[ks][q] = pa0[(q * KS + ks) * 64];
+            fb[ks][q] = pb0[(q * KS + ks) * 64];
+        }
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int m = Acc32<float>::row(j, lane), nn = Acc32<float>::col(j, lane);
+                acc[mi][ni][j] = H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld];
+            }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) {
+            const V8 na = HalfT<HK>::neg(fa[ks][mi]);
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni)
+                acc[mi][ni] = HalfT<HK>::mma(na, fb[ks][ni], acc[mi][ni]);
+        }
+    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int m = Acc32<float>::row(j, lane), nn = Acc32<float>::col(j, lane);
+                H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld] = acc[mi][ni][j];
+            }
+}
+
+// ---------------------------------------------------------------------------
 // K5 (post-factorisation): W_k = L_kk^{-1} for every diagonal block, one
 // workgroup per block.  A wave owns block columns j (32 wide): W_jj is the
 // stored 32 x 32 inverse and, going down,
@@ -585,17 +693,45 @@ template void launch_potrf_diag<double>(double *, int64_t, int64_t, double *, un
 
 template <typename T>
 void launch_trsm_panel(T *H, int64_t ld, int64_t k0, int64_t row0, int64_t nrows, const T *Winv,
-                       const unsigned long long *info, hipStream_t st)
+                       const unsigned long long *info, hipStream_t st, void *Lh, int half)
 {
     if (nrows <= 0) return;
     const unsigned blocks = (unsigned)((nrows + 63) / 64);
-    hipLaunchKernelGGL((k_trsm_panel<T, Panel<T>::NB>), dim3(blocks), dim3(128), 0, st, H, ld, k0, row0, nrows,
-                       Winv, info);
+    constexpr int NB = Panel<T>::NB;
+    if constexpr (sizeof(T) == 4) {
+        if (half == HALF_F16) {
+            hipLaunchKernelGGL((k_trsm_panel<T, NB, HALF_F16>), dim3(blocks), dim3(128), 0, st, H, ld, k0, row0,
+                               nrows, Winv, info, Lh);
+            return;
+        }
+        if (half == HALF_BF16) {
+            hipLaunchKernelGGL((k_trsm_panel<T, NB, HALF_BF16>), dim3(blocks), dim3(128), 0, st, H, ld, k0, row0,
+                               nrows, Winv, info, Lh);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_trsm_panel<T, NB, HALF_NONE>), dim3(blocks), dim3(128), 0, st, H, ld, k0, row0, nrows,
+                       Winv, info, nullptr);
 }
 template void launch_trsm_panel<float>(float *, int64_t, int64_t, int64_t, int64_t, const float *,
-                                       const unsigned long long *, hipStream_t);
+                                       const unsigned long long *, hipStream_t, void *, int);
 template void launch_trsm_panel<double>(double *, int64_t, int64_t, int64_t, int64_t, const double *,
-                                        const unsigned long long *, hipStream_t);
+                                        const unsigned long long *, hipStream_t, void *, int);
+
+void launch_syrk_update_half(float *H, int64_t ld, const void *Lh, int half, int64_t r0, int t, int tj_lo,
+                             int tj_hi, const unsigned long long *info, hipStream_t st, int prio)
+{
+    if (t <= 0 || tj_lo >= tj_hi) return;
+    int64_t ntiles = 0;
+    for (int c = tj_lo; c < tj_hi; ++c) ntiles += t - c;
+    const int64_t grid = ((ntiles + 7) / 8) * 8;
+    if (half == HALF_F16)
+        hipLaunchKernelGGL(k_syrk_update_h<HALF_F16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh, r0, t,
+                           tj_lo, tj_hi, (int)ntiles, info, prio);
+    else
+        hipLaunchKernelGGL(k_syrk_update_h<HALF_BF16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh, r0, t,
+                           tj_lo, tj_hi, (int)ntiles, info, prio);
+}
 
 template <typename T>
 void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,

@@ -46,15 +46,17 @@ struct spd_factor_s {
     size_t cap_YZ = 0;
     double *smax = nullptr;
     int64_t cap_smax = 0;
-    // persistent triangular solve state
+    // triangular solve state
+    void *WB = nullptr;          // inverses of the big diagonal blocks
+    size_t cap_WB = 0;
+    void *Tb = nullptr;          // scratch of their construction
+    size_t cap_Tb = 0;
     void *tP = nullptr;          // partial products
     size_t cap_tP = 0;
     int *tctl = nullptr;         // work-queue head + per-row counters
-    int *tflags = nullptr;       // per-block-row ready flags (epochs)
+    int cap_tctl = 0;
     int *terr = nullptr;         // sticky error flag (device)
     int *terr_host = nullptr;    // pinned mirror
-    int64_t cap_tns = 0;
-    int epoch = 1;
     // refinement workspace
     double *R = nullptr;
     size_t cap_R = 0;
@@ -257,6 +259,7 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
     }
     HIP_TRY(hipGetLastError());
     spd::launch_trtri_blocks<T>(H, npad, nt, Wi, (T *)F->W, st);
+    spd::launch_build_winv<T>(H, npad, npad, (const T *)F->W, (T *)F->WB, (T *)F->Tb, st);
     HIP_TRY(hipGetLastError());
     return SPD_OK;
 }
@@ -283,6 +286,12 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
     F->cap_L = cap;
     F->W = (char *)base + bL;
     F->Winv = (char *)base + bL + bW;
+    size_t capw = F->cap_WB;
+    SPD_TRY(grow(&F->WB, &capw, (size_t)spd::solve_winv_elems(npad) * F->elem, true, st));
+    F->cap_WB = capw;
+    size_t capt = F->cap_Tb;
+    SPD_TRY(grow(&F->Tb, &capt, (size_t)spd::solve_tmp_elems(npad) * F->elem, false, st));
+    F->cap_Tb = capt;
     size_t capd = (size_t)F->cap_d * sizeof(double);
     SPD_TRY(grow((void **)&F->d, &capd, (size_t)std::max<int64_t>(n, 1) * sizeof(double), false, st));
     F->cap_d = (int64_t)(capd / sizeof(double));
@@ -314,25 +323,18 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
 
 spd_status ensure_trsv_ws(spd_factor_t F, hipStream_t st)
 {
-    const int64_t ns = F->npad / spd::trsv_block(F->elem);
     size_t cap = F->cap_tP;
-    SPD_TRY(grow(&F->tP, &cap, (size_t)std::max<int64_t>(spd::trsv_scratch_elems(F->npad, F->elem), 1) * F->elem,
-                 false, st));
+    SPD_TRY(grow(&F->tP, &cap, (size_t)spd::trsv_scratch_elems(F->npad) * F->elem, false, st));
     F->cap_tP = cap;
-    if (F->cap_tns < ns) {
+    const int nctl = spd::trsv_ctl_ints(F->npad);
+    if (F->cap_tctl < nctl) {
         if (F->tctl) {
             HIP_TRY(hipStreamSynchronize(st));
             HIP_TRY(hipFree(F->tctl));
             F->tctl = nullptr;
         }
-        // ctl (ns + 1) and flags (ns) in one zeroed allocation
-        HIP_TRY(hipMalloc(&F->tctl, (2 * ns + 1) * sizeof(int)));
-        HIP_TRY(hipMemsetAsync(F->tctl, 0, (2 * ns + 1) * sizeof(int), st));
-        F->tflags = F->tctl + ns + 1;
-        F->cap_tns = ns;
-        F->epoch = 1;
-    } else {
-        F->tflags = F->tctl + F->cap_tns + 1;
+        HIP_TRY(hipMalloc(&F->tctl, nctl * sizeof(int)));
+        F->cap_tctl = nctl;
     }
     if (!F->terr) {
         HIP_TRY(hipMalloc(&F->terr, sizeof(int)));
@@ -367,8 +369,8 @@ void solve_apply(spd_factor_t F, const double *R, int64_t ldr, int64_t m, const 
     T *Y = (T *)F->Y;
     T *Z = (T *)((char *)F->Y + npad * m * sizeof(T));
     spd::launch_rhs_scale<T>(R, ldr, F->n, npad, (int)m, F->d, smax, Y, npad, st);
-    F->epoch = spd::launch_trsv_persist<T>((const T *)F->L, npad, (const T *)F->W, F->nb, npad, (int)m, Y, Z, npad,
-                                           (T *)F->tP, F->tctl, F->tflags, F->epoch, F->terr, st);
+    spd::launch_trsv<T>((const T *)F->L, npad, (const T *)F->WB, npad, (int)m, Y, Z, npad, (T *)F->tP, F->tctl,
+                        F->terr, st);
     spd::launch_update_x<T>(X, ldx, F->n, (int)m, Y, npad, F->d, F->mu, smax, accumulate, st);
 }
 
@@ -773,6 +775,8 @@ void spd_factor_destroy(spd_factor_t F)
     hipFree(F->P);
     hipFree(F->norms);
     hipFree(F->info_dev);
+    hipFree(F->WB);
+    hipFree(F->Tb);
     hipFree(F->tP);
     hipFree(F->tctl);
     hipFree(F->terr);

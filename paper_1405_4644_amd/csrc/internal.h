@@ -50,16 +50,26 @@ void launch_rhs_max(const double *R, int64_t ldr, int64_t n, int m, const double
 template <typename T>
 void launch_rhs_scale(const double *R, int64_t ldr, int64_t n, int64_t npad, int m, const double *d,
                       const double *smax, T *Y, int64_t ldy, hipStream_t st);
-// Persistent triangular solves (k_trsv.hip): forward Y -> Z then backward Z -> Y.
-// P: trsv_scratch_elems(npad, elem) elements; ctl: npad/trsv_block(elem) + 1 ints;
-// flags: npad/trsv_block(elem) ints, zeroed once at allocation; epoch strictly
-// increases across calls (returned); err: sticky int raised on a timed-out wait.
-#define TRSV_MC 8
-int trsv_block(int elem);
-int64_t trsv_scratch_elems(int64_t npad, int elem);
+// Triangular solves (k_trsv.hip), blocked by big diagonal blocks of
+// solve_nbs(npad) rows whose inverses WB (solve_winv_elems(npad) elements)
+// are built once per factorisation from L and the 128-wide block inverses
+// W128, with solve_tmp_elems(npad) elements of scratch Tb.
+int solve_nbs(int64_t npad);
+int solve_nblocks(int64_t npad);
+int64_t solve_winv_elems(int64_t npad);
+int64_t solve_tmp_elems(int64_t npad);
 template <typename T>
-int launch_trsv_persist(const T *L, int64_t ld, const T *W, int nbw, int64_t npad, int m, T *Y, T *Z, int64_t ldy,
-                        T *P, int *ctl, int *flags, int epoch, int *err, hipStream_t st);
+void launch_build_winv(const T *L, int64_t ld, int64_t npad, const T *W128, T *WB, T *Tb, hipStream_t st);
+// Forward Y -> Z then backward Z -> Y for m right-hand sides (TRSV_MC per
+// launch).  P: trsv_scratch_elems(npad) elements; ctl: trsv_ctl_ints(npad)
+// ints (zeroed by the launches themselves); err: sticky int raised on a
+// timed-out wait.
+#define TRSV_MC 8
+int64_t trsv_scratch_elems(int64_t npad);
+int trsv_ctl_ints(int64_t npad);
+template <typename T>
+void launch_trsv(const T *L, int64_t ld, const T *WB, int64_t npad, int m, T *Y, T *Z, int64_t ldy, T *P, int *ctl,
+                 int *err, hipStream_t st);
 // X[i][c] (+)= s_c mu d_i Y[i][c]
 template <typename T>
 void launch_update_x(double *X, int64_t ldx, int64_t n, int m, const T *Y, int64_t ldy, const double *d,

@@ -1,18 +1,25 @@
-// Triangular solves with the low-precision factor in one persistent launch
-// per direction (Eq. (3): forward L y = b, backward L^T x = y).
+// Triangular solves with the low-precision factor (Eq. (3): forward L y = b,
+// backward L^T x = y), blocked by big diagonal blocks of NBS (1024) rows.
 //
-// The factor is cut into SB x SB blocks (ns = npad / SB block rows).  The
-// forward solve needs z_k = W_kk (b_k - sum_{j<k} L_kj z_j), W_kk = L_kk^{-1}
-// (the diagonal blocks of the stored per-panel inverses).  Work items:
-//   item 0          : z_0 = W_00 b_0
-//   item (k, j), j<k: P_kj = L_kj z_j ; the item with j = k-1 is "designated":
-//                     it also waits for the other partials of row k, forms
-//                     z_k = W_kk (b_k - sum_j P_kj) and publishes z_k.
-// Items are handed out by an atomic counter in column-major order of the
-// strictly lower block triangle, which is a topological order: every item
-// waits only on items handed out before it, so progress does not depend on
-// how many workgroups are resident.  The backward solve is the mirror image
-// with transposed blocks (x_k = W_kk^T (y_k - sum_{j>k} L_jk^T x_j)).
+// Set-up, once per factorisation: W_k = L_kk^{-1} for every big diagonal
+// block, built from the 128-wide block inverses by repeated doubling,
+//   [W11 0; W21 W22] with W21 = -W22 (L21 W11),
+// two batched MFMA products per doubling level.
+//
+// Solve, one persistent launch per direction.  With K big blocks the forward
+// solve is z_k = W_k (b_k - sum_{j<k} L_kj z_j).  It is cut into tasks of R
+// rows (32 binary32 / 16 binary64):
+//   U(j, i, c): P_ij[c] = L_ij[rows c] z_j          (j < i)
+//   Z(i, c)   : z_i[c]  = W_i[rows c] (b_i - sum_j P_ij)
+// handed out by an atomic counter row by row (U(0, i), ..., U(i-1, i), Z(i)),
+// which is a topological order: every task waits only on tasks handed out
+// before it, so progress never depends on how many workgroups are resident.
+// A task loads its matrix block into registers before it waits, so the wait
+// hides the load.  Z(i) sums the partials of blocks j <= i-2 (finished a step
+// earlier) before it waits for the newest ones, U(i-1, i), so the critical
+// path per big block is one Z and one U task.  Partials are summed in a fixed
+// order: results do not depend on timing.  The backward solve is the mirror
+// image with transposed blocks (x_k = W_k^T (y_k - sum_{j>k} L_jk^T x_j)).
 //
 // Waits are bounded: after ~1 s without progress a workgroup raises the
 // error flag and leaves; every other waiter sees the flag and leaves too.
@@ -20,10 +27,11 @@
 #include "internal.h"
 
 #define TRSV_TIMEOUT_TICKS 100000000ULL  // wall_clock64 runs at 100 MHz on gfx9
+#define TRSV_NBS 1024                    // big diagonal block
 
 // thread 0 only: wait until *addr >= want, or give up.  The polling loads are
 // relaxed agent-scope atomics (coherent loads that do not invalidate the
-// caches); the caller issues one acquire fence after a successful wait.
+// caches); one acquire fence follows a successful wait.
 SPD_DEV bool wait_ge(int *addr, int want, int *err)
 {
     const unsigned long long t0 = wall_clock64();
@@ -40,180 +48,395 @@ SPD_DEV bool wait_ge(int *addr, int want, int *err)
     return true;
 }
 
-// every thread: make this workgroup's global stores complete, then thread 0
-// publishes with one release operation
-SPD_DEV void publish_barrier()
+// ---------------------------------------------------------------------------
+// Big-block inverses.
+// WB holds K blocks of nbs x nbs (column-major, leading dimension nbs); block
+// k covers rows [k nbs, k nbs + s_k), s_k = min(nbs, npad - k nbs).
+__global__ __launch_bounds__(256) void k_inv_init_f(const float *__restrict__ W128, int64_t npad, int nbs,
+                                                    float *__restrict__ WB)
 {
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    // one workgroup per 128-block b: WB_kb[128 i + r][128 i + c] = W128_b[r][c]
+    const int64_t b = blockIdx.x, g = b * 128, kb = g / nbs, i = (g - kb * nbs) / 128;
+    float *dst = WB + kb * nbs * nbs + 128 * i + 128 * i * nbs;
+    const float *src = W128 + b * 128 * 128;
+    for (int idx = threadIdx.x; idx < 128 * 128; idx += 256)
+        dst[(idx % 128) + (int64_t)(idx / 128) * nbs] = src[idx];
+}
+__global__ __launch_bounds__(256) void k_inv_init_d(const double *__restrict__ W128, int64_t npad, int nbs,
+                                                    double *__restrict__ WB)
+{
+    const int64_t b = blockIdx.x, g = b * 128, kb = g / nbs, i = (g - kb * nbs) / 128;
+    double *dst = WB + kb * nbs * nbs + 128 * i + 128 * i * nbs;
+    const double *src = W128 + b * 128 * 128;
+    for (int idx = threadIdx.x; idx < 128 * 128; idx += 256)
+        dst[(idx % 128) + (int64_t)(idx / 128) * nbs] = src[idx];
 }
 
-// item q >= 1 -> (r, c), r > c, column-major over the strictly lower triangle of ns x ns
-SPD_DEV void decode_item(int q, int ns, int &r, int &c)
+// One doubling level of width s.  Workgroup (x, y, z): output tile (x, y) of
+// pair p of big block kb (z = kb * ppb + p); the pair is [a0, a1) + [a1, b1)
+// inside the block.  PHASE 1: Tk = L21 W11 (W11 lower: k >= 128 y);
+// PHASE 2: W21 = -W22 Tk (W22 lower: k < 128 (x + 1)).  128 x 128 tiles on
+// MFMA, computed transposed so that each lane stores contiguous rows.
+template <typename T, int PHASE>
+__global__ __launch_bounds__(256) void k_inv_merge(const T *__restrict__ L, int64_t ld, int64_t npad,
+                                                   T *__restrict__ WB, int nbs, int s, T *__restrict__ Tb)
 {
-    // prefix(c) = c (2 ns - 1 - c) / 2 items precede column c
-    const double b = 2.0 * ns - 1.0;
-    int j = (int)((b - sqrt(b * b - 8.0 * q)) * 0.5);
-    if (j < 0) j = 0;
-    while (j > 0 && (long long)j * (2 * ns - 1 - j) / 2 > q) --j;
-    while ((long long)(j + 1) * (2 * ns - 2 - j) / 2 <= q) ++j;
-    c = j;
-    r = j + 1 + (q - (int)((long long)j * (2 * ns - 1 - j) / 2));
-}
-
-// Stage an SB x SB block (column-major source, leading dimension ld) into LDS
-// as Ms[c * (SB + 1) + r] = M[r][c].
-template <typename T, int SB>
-SPD_DEV void stage(T *Ms, const T *src, int64_t ld, int tid)
-{
-    copy_g2s<T, SB, 256, 16>(Ms, SB + 1, src, ld, SB, tid);
-}
-
-// out[i] = sum_t M(i, t) v[t] for the MC columns of v (vs[cc][t]); M in LDS.
-// TRANS: M(i, t) = Ms^T, i.e. out = M^T v.  Result for row i is returned to
-// the thread with (tid % SB) == i and tid < SB (others get garbage).
-template <typename T, int SB, int MC, bool TRANS>
-SPD_DEV void block_gemv(const T *Ms, const T (*vs)[SB], T (*red)[MC][SB], T out[MC], int tid)
-{
-    constexpr int PARTS = 256 / SB, SPAN = SB / PARTS;
-    const int i = tid % SB, part = tid / SB;
-    T acc[MC];
-#pragma unroll
-    for (int cc = 0; cc < MC; ++cc) acc[cc] = (T)0;
-#pragma unroll 8
-    for (int tt = 0; tt < SPAN; ++tt) {
-        const int t = part * SPAN + tt;
-        const T a = TRANS ? Ms[i * (SB + 1) + t] : Ms[t * (SB + 1) + i];
-#pragma unroll
-        for (int cc = 0; cc < MC; ++cc) acc[cc] += a * vs[cc][t];
+    constexpr int KC = sizeof(T) == 4 ? 32 : 16;
+    constexpr int LDA = 128 + 4, LDB = KC + 1;
+    __shared__ T As[KC * LDA];   // As[k * LDA + m]
+    __shared__ T Bs[128 * LDB];  // Bs[n * LDB + k]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ppb = (nbs + 2 * s - 1) / (2 * s);
+    const int kb = blockIdx.z / ppb, p = blockIdx.z % ppb;
+    const int64_t o = (int64_t)kb * nbs;
+    const int sk = (int)((npad - o) < nbs ? (npad - o) : nbs);
+    const int a0 = 2 * p * s, a1 = a0 + s, b1 = (a0 + 2 * s < sk) ? a0 + 2 * s : sk;
+    if (a1 >= sk)
+        return;
+    const int M = b1 - a1;
+    const int m0 = blockIdx.x * 128, n0 = blockIdx.y * 128;
+    if (m0 >= M)
+        return;
+    T *Wk = WB + (int64_t)kb * nbs * nbs;
+    T *Tk = Tb + (int64_t)blockIdx.z * s * s;
+    const T *A, *B;
+    T *Cp;
+    int64_t lda, ldb, ldc;
+    int kbeg, kend;
+    T alpha;
+    if (PHASE == 1) {
+        A = L + (o + a1) + (o + a0) * ld;
+        lda = ld;
+        B = Wk + a0 + (int64_t)a0 * nbs;
+        ldb = nbs;
+        Cp = Tk;
+        ldc = s;
+        kbeg = n0;
+        kend = s;
+        alpha = (T)1;
+    } else {
+        A = Wk + a1 + (int64_t)a1 * nbs;
+        lda = nbs;
+        B = Tk;
+        ldb = s;
+        Cp = Wk + a1 + (int64_t)a0 * nbs;
+        ldc = nbs;
+        kbeg = 0;
+        kend = (m0 + 128 < M) ? m0 + 128 : M;
+        alpha = (T)-1;
     }
+    const int wn = wave >> 1, wm = wave & 1;
+    Acc32<T> acc[2][2];
 #pragma unroll
-    for (int cc = 0; cc < MC; ++cc) red[part][cc][i] = acc[cc];
-    __syncthreads();
-    if (tid < SB) {
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int cc = 0; cc < MC; ++cc) {
-            T s = red[0][cc][i];
+        for (int b = 0; b < 2; ++b) acc[a][b].zero();
+    for (int k0 = kbeg; k0 < kend; k0 += KC) {
+        __syncthreads();
+        copy_g2s<T, 128, 256, 8>(As, LDA, A + m0 + (int64_t)k0 * lda, lda, KC, tid);
+        copy_g2s<T, KC, 256, 8>(Bs, LDB, B + k0 + (int64_t)n0 * ldb, ldb, 128, tid);
+        __syncthreads();
 #pragma unroll
-            for (int p = 1; p < PARTS; ++p) s += red[p][cc][i];
-            out[cc] = s;
+        for (int kk = 0; kk < KC; kk += Frag<T>::K) {
+            if constexpr (sizeof(T) == 4) {
+                float fa[2], fb[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    fa[q] = Bs[(64 * wn + 32 * q + (lane & 31)) * LDB + kk + (lane >> 5)];
+                    fb[q] = As[(kk + (lane >> 5)) * LDA + 64 * wm + 32 * q + (lane & 31)];
+                }
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi) acc[ni][mi].mma(fa[ni], fb[mi]);
+            } else {
+                double fa[2][2], fb[2][2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        fa[q][h] = Bs[(64 * wn + 32 * q + 16 * h + (lane & 15)) * LDB + kk + (lane >> 4)];
+                        fb[q][h] = As[(kk + (lane >> 4)) * LDA + 64 * wm + 32 * q + 16 * h + (lane & 15)];
+                    }
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+                    for (int mi = 0; mi < 2; ++mi) acc[ni][mi].mma(fa[ni], fb[mi]);
+            }
         }
     }
+    // register j of acc[ni][mi]: n = 64 wn + 32 ni + row(j), m = 64 wm + 32 mi + col(j)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int n = 64 * wn + 32 * ni + Acc32<T>::row(j, lane);
+                const int m = 64 * wm + 32 * mi + Acc32<T>::col(j, lane);
+                Cp[(m0 + m) + (int64_t)(n0 + n) * ldc] = alpha * acc[ni][mi].get(j);
+            }
 }
 
-template <typename T, int SB, int MC, bool FWD>
-__global__ __launch_bounds__(256) void k_trsv_persist(const T *__restrict__ L, int64_t ld, const T *__restrict__ W,
-                                                      int nbw, int ns, const T *__restrict__ Yin,
-                                                      T *__restrict__ Zout, int64_t ldy, int c0, int m,
-                                                      T *__restrict__ P, int *ctl, int *flags, int epoch,
-                                                      int *err)
+// ---------------------------------------------------------------------------
+// Register-resident block times vector.
+//   FWD (rows form):  out[r] = sum_c M[r][c] v[c], R rows, columns [0, ncols)
+//   BWD (cols form):  out[c] = sum_r M[r][c] v[r0 + r], R columns, rows [0, nrows)
+// M is column-major (leading dimension ld).  VEC elements per 16-byte load;
+// R = 8 VEC; every thread holds E = NBS / 32 vectors.
+template <typename T> struct VecOf;
+template <> struct VecOf<float> { using V = float4; static constexpr int N = 4; };
+template <> struct VecOf<double> { using V = double2; static constexpr int N = 2; };
+
+template <typename T>
+SPD_DEV T vget(const typename VecOf<T>::V &v, int r)
 {
-    __shared__ T Ms[SB * (SB + 1)];
-    __shared__ T Ws[SB * (SB + 1)];
-    __shared__ T vs[MC][SB];
-    __shared__ T red[256 / SB][MC][SB];
-    __shared__ int s_item, s_ok;
+    if constexpr (sizeof(T) == 4)
+        return r == 0 ? v.x : r == 1 ? v.y : r == 2 ? v.z : v.w;
+    else
+        return r == 0 ? v.x : v.y;
+}
+
+template <typename T, int MC, bool FWD, int NBS>
+struct BlockVec {
+    using V = typename VecOf<T>::V;
+    static constexpr int VEC = VecOf<T>::N;
+    static constexpr int R = 8 * VEC;      // rows (FWD) / columns (BWD) per task
+    static constexpr int E = NBS / 32;     // vectors per thread
+    static constexpr int TPC = 256 / R;    // BWD: threads per column
+    V m[E];
+
+    // FWD: thread t covers rows VEC (t % 8) .. +VEC of columns t / 8 + 32 e.
+    // BWD: thread t covers column t / TPC, rows VEC (t % TPC) + 32 e .. +VEC.
+    SPD_DEV void load(const T *base, int64_t ld, int len, int tid)
+    {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if constexpr (FWD) {
+                const int col = tid / 8 + 32 * e;
+                if (col < len)
+                    m[e] = *(const V *)(base + VEC * (tid % 8) + (int64_t)col * ld);
+            } else {
+                const int row = VEC * (tid % TPC) + 32 * e;
+                if (row < len)
+                    m[e] = *(const V *)(base + row + (int64_t)(tid / TPC) * ld);
+            }
+        }
+    }
+
+    // out[r][cc] for r < R (valid in thread tid < R * MC as (tid % R, tid / R)
+    // for FWD; in the thread with tid % TPC == 0 for column tid / TPC for BWD)
+    SPD_DEV void apply(const T (*vs)[NBS], int len, int r0, T (*red)[R][MC], T out[MC], int tid)
+    {
+        const int lane = tid & 63, wave = tid >> 6;
+        if constexpr (FWD) {
+            T acc[VEC][MC];
+#pragma unroll
+            for (int r = 0; r < VEC; ++r)
+#pragma unroll
+                for (int cc = 0; cc < MC; ++cc) acc[r][cc] = (T)0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int col = tid / 8 + 32 * e;
+                if (col < len) {
+#pragma unroll
+                    for (int cc = 0; cc < MC; ++cc) {
+                        const T x = vs[cc][col];
+#pragma unroll
+                        for (int r = 0; r < VEC; ++r) acc[r][cc] += vget<T>(m[e], r) * x;
+                    }
+                }
+            }
+            // sum over the 8 column groups of this wave (lane bits 3..5), then over waves
+#pragma unroll
+            for (int sh = 8; sh < 64; sh <<= 1)
+#pragma unroll
+                for (int r = 0; r < VEC; ++r)
+#pragma unroll
+                    for (int cc = 0; cc < MC; ++cc) acc[r][cc] += __shfl_xor(acc[r][cc], sh);
+            if (lane < 8) {
+#pragma unroll
+                for (int r = 0; r < VEC; ++r)
+#pragma unroll
+                    for (int cc = 0; cc < MC; ++cc) red[wave][VEC * lane + r][cc] = acc[r][cc];
+            }
+            __syncthreads();
+            if (tid < R * MC) {
+                const int r = tid % R, cc = tid / R;
+                out[0] = ((red[0][r][cc] + red[1][r][cc]) + red[2][r][cc]) + red[3][r][cc];
+            }
+        } else {
+            T acc[MC];
+#pragma unroll
+            for (int cc = 0; cc < MC; ++cc) acc[cc] = (T)0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int row = VEC * (tid % TPC) + 32 * e;
+                if (row < len) {
+#pragma unroll
+                    for (int r = 0; r < VEC; ++r) {
+                        const T a = vget<T>(m[e], r);
+#pragma unroll
+                        for (int cc = 0; cc < MC; ++cc) acc[cc] += a * vs[cc][r0 + row + r];
+                    }
+                }
+            }
+#pragma unroll
+            for (int sh = 1; sh < TPC; sh <<= 1)
+#pragma unroll
+                for (int cc = 0; cc < MC; ++cc) acc[cc] += __shfl_xor(acc[cc], sh);
+#pragma unroll
+            for (int cc = 0; cc < MC; ++cc) out[cc] = acc[cc];
+        }
+    }
+};
+
+// geometry of big block k
+SPD_DEV void big_block(int64_t npad, int nbs, int k, int64_t &o, int &sz)
+{
+    o = (int64_t)k * nbs;
+    sz = (int)((npad - o) < nbs ? (npad - o) : nbs);
+}
+
+template <typename T, int MC, bool FWD>
+__global__ __launch_bounds__(256) void k_trsv_blk(const T *__restrict__ L, int64_t ld, const T *__restrict__ WB,
+                                                  int64_t npad, int nbs, int K, const T *__restrict__ Yin,
+                                                  T *__restrict__ Zout, int64_t ldy, int c0, int m,
+                                                  T *__restrict__ P, int *ctl, int *err)
+{
+    constexpr int NBS = TRSV_NBS;
+    using BV = BlockVec<T, MC, FWD, NBS>;
+    constexpr int R = BV::R;
+    __shared__ T vs[MC][NBS];
+    __shared__ T red[4][R][MC];
+    __shared__ int s_task, s_ok;
     const int tid = threadIdx.x;
-    int *qhead = ctl, *cnt = ctl + 1;
-    const int total = 1 + ns * (ns - 1) / 2;
+    int *qhead = ctl, *cntA = ctl + 1, *cntB = ctl + 1 + K, *cntZ = ctl + 1 + 2 * K;
     const int mc = min(MC, m - c0);
+    BV bv;
 
     for (;;) {
         if (tid == 0)
-            s_item = atomicAdd(qhead, 1);
+            s_task = atomicAdd(qhead, 1);
         __syncthreads();
-        const int q = s_item;
-        if (q >= total)
+        int rem = s_task;
+        // decode: row pi holds (pi + 1) nc tasks: U(0..pi-1, pi, c) then Z(pi, c)
+        int pi = 0, nc = 0;
+        for (; pi < K; ++pi) {
+            int64_t oo;
+            int ss;
+            big_block(npad, nbs, FWD ? pi : K - 1 - pi, oo, ss);
+            nc = ss / R;
+            if (rem < (pi + 1) * nc)
+                break;
+            rem -= (pi + 1) * nc;
+        }
+        if (pi >= K)
             return;
-        // (row, col) of the item in the solve's own orientation
-        int k, j;  // k: block row being accumulated; j: block whose solution is consumed
-        bool diag_only = (q == 0), designated;
-        if (diag_only) {
-            k = FWD ? 0 : ns - 1;
-            j = -1;
-            designated = true;
+        const int pj = rem / nc, c = rem % nc;
+        const bool ztask = (pj == pi);
+        const int ki = FWD ? pi : K - 1 - pi, kj = FWD ? pj : K - 1 - pj;
+        int64_t oi, oj;
+        int si, sj;
+        big_block(npad, nbs, ki, oi, si);
+        big_block(npad, nbs, kj, oj, sj);
+        T *Pbase = P + ((int64_t)pi * (pi - 1) / 2) * NBS * MC;  // partials of row pi
+        const T *Wk = WB + (int64_t)ki * nbs * nbs;
+
+        // The task's matrix block, loaded before any wait:
+        //   U: the block of L coupling ki and kj (entries c R .. +R of block ki);
+        //   Z: rows (FWD) / columns (BWD) c R .. +R of W_ki.
+        // Vector range it needs: U [0, sj); Z FWD [0, (c+1) R), BWD [c R, si).
+        const T *mb;
+        int64_t mld;
+        int lo, hi;
+        if (!ztask) {
+            mb = FWD ? L + (oi + c * R) + oj * ld : L + oj + (oi + c * R) * ld;
+            mld = ld;
+            lo = 0;
+            hi = sj;
         } else {
-            int r, c;
-            decode_item(q - 1, ns, r, c);
-            k = FWD ? r : ns - 1 - r;
-            j = FWD ? c : ns - 1 - c;
-            designated = FWD ? (j == k - 1) : (j == k + 1);
+            mb = FWD ? Wk + c * R : Wk + c * R + (int64_t)(c * R) * nbs;
+            mld = nbs;
+            lo = FWD ? 0 : c * R;
+            hi = FWD ? (c + 1) * R : si;
         }
-        // prefetch: the off-diagonal block and, for a designated item, W_kk
-        if (!diag_only) {
-            // forward: L_kj (rows k, cols j); backward: L_jk (rows j, cols k), used transposed
-            const T *src = FWD ? L + (int64_t)k * SB + (int64_t)j * SB * ld : L + (int64_t)j * SB + (int64_t)k * SB * ld;
-            stage<T, SB>(Ms, src, ld, tid);
-        }
-        if (designated) {
-            const int64_t g = (int64_t)k * SB, b = g / nbw, o = g - b * nbw;
-            stage<T, SB>(Ws, W + b * nbw * nbw + o + o * nbw, nbw, tid);
-        }
-        const int pk = FWD ? k : ns - 1 - k;  // row index in the forward-style triangle
-        const int others = (diag_only || !designated) ? 0 : pk - 1;
-        // a designated item first collects the other partials of its row
-        // (usually ready long before the newest block), in a fixed order
-        T psum[MC];
-#pragma unroll
-        for (int cc = 0; cc < MC; ++cc) psum[cc] = (T)0;
-        if (others > 0) {
+        bv.load(mb, mld, hi - lo, tid);
+
+        if (!ztask) {
             if (tid == 0)
-                s_ok = wait_ge(&cnt[k], others, err) ? 1 : 0;
+                s_ok = wait_ge(&cntZ[pj], sj / R, err) ? 1 : 0;
             __syncthreads();
             if (!s_ok)
                 return;
-            if (tid < SB) {
-                const T *pp = P + ((int64_t)pk * (pk - 1) / 2) * MC * SB + tid;
-                for (int pj = 0; pj < others; ++pj)
-#pragma unroll
-                    for (int cc = 0; cc < MC; ++cc) psum[cc] += pp[(int64_t)pj * MC * SB + cc * SB];
+            for (int idx = tid; idx < MC * NBS; idx += 256) {
+                const int t = idx % NBS, cc = idx / NBS;
+                if (t < sj)
+                    vs[cc][t] = (cc < mc) ? Zout[(oj + t) + (int64_t)(c0 + cc) * ldy] : (T)0;
             }
-        }
-        T own[MC];
-#pragma unroll
-        for (int cc = 0; cc < MC; ++cc) own[cc] = (T)0;
-        if (!diag_only) {
-            if (tid == 0)
-                s_ok = wait_ge(&flags[j], epoch, err) ? 1 : 0;
-            __syncthreads();
-            if (!s_ok)
-                return;
-            for (int idx = tid; idx < MC * SB; idx += 256) {
-                const int t = idx % SB, cc = idx / SB;
-                vs[cc][t] = (cc < mc) ? Zout[((int64_t)j * SB + t) + (int64_t)(c0 + cc) * ldy] : (T)0;
+        } else {
+            if (pi >= 2) {
+                if (tid == 0)
+                    s_ok = wait_ge(&cntA[pi], (pi - 1) * nc, err) ? 1 : 0;
+                __syncthreads();
+                if (!s_ok)
+                    return;
             }
-            __syncthreads();
-            block_gemv<T, SB, MC, !FWD>(Ms, vs, red, own, tid);
-        }
-        if (!designated) {
-            const int pj = FWD ? j : ns - 1 - j;
-            T *pp = P + ((int64_t)pk * (pk - 1) / 2 + pj) * MC * SB;
-            if (tid < SB)
-#pragma unroll
-                for (int cc = 0; cc < MC; ++cc) pp[cc * SB + tid] = own[cc];
-            publish_barrier();
-            if (tid == 0)
-                __hip_atomic_fetch_add(&cnt[k], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            continue;
-        }
-        __syncthreads();  // red[] and vs[] reuse below
-        if (tid < SB) {
-            // v = y_k - (sum of the other partials + own)
-#pragma unroll
-            for (int cc = 0; cc < MC; ++cc) {
-                const T y = (cc < mc) ? Yin[((int64_t)k * SB + tid) + (int64_t)(c0 + cc) * ldy] : (T)0;
-                vs[cc][tid] = y - (psum[cc] + own[cc]);
+            // v = y - (sum of the partials of blocks finished a step ago), fixed order
+            for (int idx = tid; idx < MC * NBS; idx += 256) {
+                const int t = idx % NBS, cc = idx / NBS;
+                if (t >= lo && t < hi) {
+                    T sA = (T)0;
+                    for (int q = 0; q + 1 < pi; ++q) sA += Pbase[(int64_t)q * NBS * MC + cc * NBS + t];
+                    vs[cc][t] = (cc < mc) ? Yin[(oi + t) + (int64_t)(c0 + cc) * ldy] - sA : (T)0;
+                }
+            }
+            if (pi >= 1) {
+                if (tid == 0)
+                    s_ok = wait_ge(&cntB[pi], nc, err) ? 1 : 0;
+                __syncthreads();
+                if (!s_ok)
+                    return;
+                const T *pB = Pbase + (int64_t)(pi - 1) * NBS * MC;
+                for (int idx = tid; idx < MC * NBS; idx += 256) {
+                    const int t = idx % NBS, cc = idx / NBS;
+                    if (t >= lo && t < hi)
+                        vs[cc][t] -= pB[cc * NBS + t];
+                }
             }
         }
         __syncthreads();
-        T z[MC];
-        block_gemv<T, SB, MC, !FWD>(Ws, vs, red, z, tid);
-        if (tid < SB)
-            for (int cc = 0; cc < mc; ++cc)
-                Zout[((int64_t)k * SB + tid) + (int64_t)(c0 + cc) * ldy] = z[cc];
-        publish_barrier();
-        if (tid == 0)
-            __hip_atomic_store(&flags[k], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        T out[MC];
+        bv.apply(vs, hi - lo, lo, red, out, tid);
+
+        // results: U -> partial P_{pi,pj}; Z -> solution entries of block ki
+        T *dst;
+        int64_t dcol;
+        int nvalid;
+        if (!ztask) {
+            dst = Pbase + (int64_t)pj * NBS * MC + c * R;
+            dcol = NBS;
+            nvalid = MC;
+        } else {
+            dst = Zout + oi + c * R + (int64_t)c0 * ldy;
+            dcol = ldy;
+            nvalid = mc;
+        }
+        if (FWD) {
+            if (tid < R * MC && tid / R < nvalid)
+                dst[tid % R + (tid / R) * dcol] = out[0];
+        } else if (tid % BV::TPC == 0) {
+#pragma unroll
+            for (int cc = 0; cc < MC; ++cc)
+                if (cc < nvalid)
+                    dst[tid / BV::TPC + cc * dcol] = out[cc];
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+            int *ctr = ztask ? &cntZ[pi] : (pj == pi - 1 ? &cntB[pi] : &cntA[pi]);
+            __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -226,57 +449,95 @@ __global__ void k_zero_int(int *p, int count)
 
 namespace spd {
 
-template <typename T> struct SolveBlk;
-template <> struct SolveBlk<float> { static constexpr int SB = 128; };
-template <> struct SolveBlk<double> { static constexpr int SB = 64; };
+int solve_nbs(int64_t npad) { return (int)(npad < TRSV_NBS ? npad : TRSV_NBS); }
+int solve_nblocks(int64_t npad) { return (int)((npad + solve_nbs(npad) - 1) / solve_nbs(npad)); }
 
-int trsv_block(int elem) { return elem == 4 ? SolveBlk<float>::SB : SolveBlk<double>::SB; }
-
-int64_t trsv_scratch_elems(int64_t npad, int elem)
+int64_t solve_winv_elems(int64_t npad)
 {
-    const int64_t ns = npad / trsv_block(elem);
-    return ns * (ns - 1) / 2 * TRSV_MC * trsv_block(elem);
+    const int64_t nbs = solve_nbs(npad);
+    return solve_nblocks(npad) * nbs * nbs;
 }
 
-template <typename T, bool FWD>
-static int launch_dir(const T *L, int64_t ld, const T *W, int nbw, int64_t npad, int m, const T *Yin, T *Zout,
-                      int64_t ldy, T *P, int *ctl, int *flags, int epoch, int *err, hipStream_t st)
+int64_t solve_tmp_elems(int64_t npad)
 {
-    constexpr int SB = SolveBlk<T>::SB;
-    const int ns = (int)(npad / SB);
-    const int total = 1 + ns * (ns - 1) / 2;
-    const int grid = total < 256 ? total : 256;  // one workgroup per CU fits the LDS budget
+    const int nbs = solve_nbs(npad), K = solve_nblocks(npad);
+    int64_t mx = 1;
+    for (int s = 128; s < nbs; s *= 2) {
+        const int64_t ppb = (nbs + 2 * s - 1) / (2 * s);
+        mx = std::max<int64_t>(mx, K * ppb * (int64_t)s * s);
+    }
+    return mx;
+}
+
+int64_t trsv_scratch_elems(int64_t npad)
+{
+    const int64_t K = solve_nblocks(npad);
+    return std::max<int64_t>(K * (K - 1) / 2, 1) * TRSV_NBS * TRSV_MC;
+}
+
+int trsv_ctl_ints(int64_t npad) { return 1 + 3 * solve_nblocks(npad); }
+
+template <typename T>
+void launch_build_winv(const T *L, int64_t ld, int64_t npad, const T *W128, T *WB, T *Tb, hipStream_t st)
+{
+    const int nbs = solve_nbs(npad), K = solve_nblocks(npad);
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL(k_inv_init_f, dim3((unsigned)(npad / 128)), dim3(256), 0, st, W128, npad, nbs, WB);
+    else
+        hipLaunchKernelGGL(k_inv_init_d, dim3((unsigned)(npad / 128)), dim3(256), 0, st, W128, npad, nbs, WB);
+    for (int s = 128; s < nbs; s *= 2) {
+        const int ppb = (nbs + 2 * s - 1) / (2 * s);
+        const dim3 grid((unsigned)(s / 128), (unsigned)(s / 128), (unsigned)(K * ppb));
+        hipLaunchKernelGGL((k_inv_merge<T, 1>), grid, dim3(256), 0, st, L, ld, npad, WB, nbs, s, Tb);
+        hipLaunchKernelGGL((k_inv_merge<T, 2>), grid, dim3(256), 0, st, L, ld, npad, WB, nbs, s, Tb);
+    }
+}
+template void launch_build_winv<float>(const float *, int64_t, int64_t, const float *, float *, float *,
+                                       hipStream_t);
+template void launch_build_winv<double>(const double *, int64_t, int64_t, const double *, double *, double *,
+                                        hipStream_t);
+
+template <typename T, bool FWD>
+static void launch_dir(const T *L, int64_t ld, const T *WB, int64_t npad, int m, const T *Yin, T *Zout,
+                       int64_t ldy, T *P, int *ctl, int *err, hipStream_t st)
+{
+    const int nbs = solve_nbs(npad), K = solve_nblocks(npad);
+    constexpr int R = 8 * VecOf<T>::N;
+    int64_t total = 0;
+    for (int p = 0; p < K; ++p) {
+        const int64_t o = (int64_t)p * nbs, sz = std::min<int64_t>(nbs, npad - o);
+        total += (p + 1) * (sz / R);
+    }
+    const int grid = (int)std::min<int64_t>(total, 512);
+    const int nctl = trsv_ctl_ints(npad);
     for (int c0 = 0; c0 < m; c0 += TRSV_MC) {
-        hipLaunchKernelGGL(k_zero_int, dim3((ns + 1 + 255) / 256), dim3(256), 0, st, ctl, ns + 1);
+        hipLaunchKernelGGL(k_zero_int, dim3((nctl + 255) / 256), dim3(256), 0, st, ctl, nctl);
         const int mc = m - c0;
         if (mc == 1)
-            hipLaunchKernelGGL((k_trsv_persist<T, SB, 1, FWD>), dim3(grid), dim3(256), 0, st, L, ld, W, nbw, ns, Yin,
-                               Zout, ldy, c0, m, P, ctl, flags, epoch, err);
+            hipLaunchKernelGGL((k_trsv_blk<T, 1, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K, Yin,
+                               Zout, ldy, c0, m, P, ctl, err);
         else if (mc == 2)
-            hipLaunchKernelGGL((k_trsv_persist<T, SB, 2, FWD>), dim3(grid), dim3(256), 0, st, L, ld, W, nbw, ns, Yin,
-                               Zout, ldy, c0, m, P, ctl, flags, epoch, err);
+            hipLaunchKernelGGL((k_trsv_blk<T, 2, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K, Yin,
+                               Zout, ldy, c0, m, P, ctl, err);
         else if (mc <= 4)
-            hipLaunchKernelGGL((k_trsv_persist<T, SB, 4, FWD>), dim3(grid), dim3(256), 0, st, L, ld, W, nbw, ns, Yin,
-                               Zout, ldy, c0, m, P, ctl, flags, epoch, err);
+            hipLaunchKernelGGL((k_trsv_blk<T, 4, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K, Yin,
+                               Zout, ldy, c0, m, P, ctl, err);
         else
-            hipLaunchKernelGGL((k_trsv_persist<T, SB, TRSV_MC, FWD>), dim3(grid), dim3(256), 0, st, L, ld, W, nbw,
-                               ns, Yin, Zout, ldy, c0, m, P, ctl, flags, epoch, err);
-        ++epoch;
+            hipLaunchKernelGGL((k_trsv_blk<T, TRSV_MC, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K,
+                               Yin, Zout, ldy, c0, m, P, ctl, err);
     }
-    return epoch;
 }
 
 template <typename T>
-int launch_trsv_persist(const T *L, int64_t ld, const T *W, int nbw, int64_t npad, int m, T *Y, T *Z, int64_t ldy,
-                        T *P, int *ctl, int *flags, int epoch, int *err, hipStream_t st)
+void launch_trsv(const T *L, int64_t ld, const T *WB, int64_t npad, int m, T *Y, T *Z, int64_t ldy, T *P, int *ctl,
+                 int *err, hipStream_t st)
 {
-    epoch = launch_dir<T, true>(L, ld, W, nbw, npad, m, Y, Z, ldy, P, ctl, flags, epoch, err, st);
-    epoch = launch_dir<T, false>(L, ld, W, nbw, npad, m, Z, Y, ldy, P, ctl, flags, epoch, err, st);
-    return epoch;
+    launch_dir<T, true>(L, ld, WB, npad, m, Y, Z, ldy, P, ctl, err, st);
+    launch_dir<T, false>(L, ld, WB, npad, m, Z, Y, ldy, P, ctl, err, st);
 }
-template int launch_trsv_persist<float>(const float *, int64_t, const float *, int, int64_t, int, float *, float *,
-                                        int64_t, float *, int *, int *, int, int *, hipStream_t);
-template int launch_trsv_persist<double>(const double *, int64_t, const double *, int, int64_t, int, double *,
-                                         double *, int64_t, double *, int *, int *, int, int *, hipStream_t);
+template void launch_trsv<float>(const float *, int64_t, const float *, int64_t, int, float *, float *, int64_t,
+                                 float *, int *, int *, hipStream_t);
+template void launch_trsv<double>(const double *, int64_t, const double *, int64_t, int, double *, double *, int64_t,
+                                  double *, int *, int *, hipStream_t);
 
 }  // namespace spd

@@ -11,6 +11,7 @@
 // ||A||_inf.
 #include "common.h"
 #include "internal.h"
+#include <algorithm>
 
 template <int MC, int RB, int CB, int JS>
 __global__ __launch_bounds__(256) void k_resid_partial(const double *__restrict__ A, int64_t lda, int64_t n,
@@ -129,6 +130,112 @@ __global__ __launch_bounds__(256) void k_resid_partial(const double *__restrict_
     }
 }
 
+// Single pass over the lower triangle for a few right-hand sides.  Workgroup
+// (J, q) walks tiles I = J + q CH .. of the 64-column strip J (contiguous in
+// memory); wave w holds columns 16 w .. 16 w + 15 of the tile, lane l its row
+// l.  Each stored a_ij (i > j) serves twice: a_ij x_j for row i (a row partial
+// per tile, RP[I][J]) and a_ij x_i for row j (accumulated over the chunk in
+// registers, CP[J][q]); a diagonal tile uses its lower triangle only (the
+// diagonal once).  k_resid_sym_reduce then sums, per row of block I,
+// RP[I][0..I] and CP[I][0..Q) in that fixed order.  With want_abs an extra
+// "column" c = MC carries |a_ij| (row sums of |A|).
+#define RSYM_CH 16
+template <int MC, bool WA>
+__global__ __launch_bounds__(256) void k_resid_sym(const double *__restrict__ A, int64_t lda, int64_t n,
+                                                   const double *__restrict__ X, int64_t ldx, int m, int Q,
+                                                   double *__restrict__ RP, double *__restrict__ CP)
+{
+    constexpr int NC = MC + 1;  // partial "columns" in the layout: MC right-hand sides + |A|
+    constexpr int NA = WA ? NC : MC;  // the ones this variant computes
+    constexpr bool want_abs = WA;
+    __shared__ double xs[MC][64];
+    __shared__ double red[4][NA][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int J = blockIdx.x, q = blockIdx.y;
+    const int nrb = (int)((n + 63) / 64);
+    const int I0 = J + q * RSYM_CH, I1 = min(I0 + RSYM_CH, nrb);
+    if (I0 >= nrb)
+        return;
+    const int64_t j0 = (int64_t)J * 64;
+    // x of the strip's columns, for the row partials
+    for (int idx = threadIdx.x; idx < MC * 64; idx += 256) {
+        const int c = idx / 64, j = idx % 64;
+        xs[c][j] = (j0 + j < n && c < m) ? X[(j0 + j) + (int64_t)c * ldx] : 0.0;
+    }
+    __syncthreads();
+    double cacc[16][NA];
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj)
+#pragma unroll
+        for (int c = 0; c < NA; ++c) cacc[jj][c] = 0.0;
+    // tile loads run one tile ahead of the arithmetic
+    double an[16];
+    auto load_tile = [&](int I) {
+        const int64_t gi = (int64_t)I * 64 + lane;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const int64_t gj = j0 + 16 * w + jj;
+            an[jj] = (gi < n && gj < n) ? A[gi + gj * lda] : 0.0;
+        }
+    };
+    load_tile(I0);
+    for (int I = I0; I < I1; ++I) {
+        const int64_t gi = (int64_t)I * 64 + lane;
+        double a[16];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) a[jj] = an[jj];
+        if (I + 1 < I1)
+            load_tile(I + 1);
+        if (I == J) {
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj)
+                if (lane < 16 * w + jj)
+                    a[jj] = 0.0;
+        }
+        double xi[MC];
+#pragma unroll
+        for (int c = 0; c < MC; ++c) xi[c] = (gi < n && c < m) ? X[gi + (int64_t)c * ldx] : 0.0;
+        double racc[NA];
+#pragma unroll
+        for (int c = 0; c < NA; ++c) racc[c] = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const bool strict = (I != J) || (lane > 16 * w + jj);
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+                racc[c] = fma(a[jj], xs[c][16 * w + jj], racc[c]);
+                if (strict)
+                    cacc[jj][c] = fma(a[jj], xi[c], cacc[jj][c]);
+            }
+            if constexpr (WA) {
+                racc[NA - 1] += fabs(a[jj]);
+                if (strict)
+                    cacc[jj][NA - 1] += fabs(a[jj]);
+            }
+        }
+        // row partial of tile (I, J): sum over the 4 waves in order
+#pragma unroll
+        for (int c = 0; c < NA; ++c) red[w][c][lane] = racc[c];
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < NA * 64; idx += 256) {
+            const int c = idx / 64, i = idx % 64;
+            RP[(((int64_t)I * nrb + J) * NC + c) * 64 + i] = ((red[0][c][i] + red[1][c][i]) + red[2][c][i]) + red[3][c][i];
+        }
+        __syncthreads();
+    }
+    // column partials: reduce each column's 64 lanes (fixed butterfly order)
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj)
+#pragma unroll
+        for (int c = 0; c < NA; ++c) {
+            double v = cacc[jj][c];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0)
+                CP[(((int64_t)J * Q + q) * NC + c) * 64 + 16 * w + jj] = v;
+        }
+}
+
 SPD_DEV double nanmax2(double a, double b) { return (a > b || a != a) ? a : b; }
 SPD_DEV double wave_max2(double v)
 {
@@ -181,6 +288,60 @@ __global__ __launch_bounds__(256) void k_resid_reduce(const double *__restrict__
     }
 }
 
+// R = B - (sum_J RP[I][J] + sum_q CP[I][q]) and the norms (as k_resid_reduce)
+template <int MC>
+__global__ __launch_bounds__(256) void k_resid_sym_reduce(const double *__restrict__ B, int64_t ldb,
+                                                          const double *__restrict__ X, int64_t ldx, int64_t n, int m,
+                                                          int Q, const double *__restrict__ RP,
+                                                          const double *__restrict__ CP, int want_abs,
+                                                          const double *__restrict__ d, double *__restrict__ R,
+                                                          int64_t ldr, double *norms)
+{
+    constexpr int NC = MC + 1;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    const int nrb = (int)((n + 63) / 64);
+    double vr = 0.0, vx = 0.0, vb = 0.0, vd = 0.0, va = 0.0;
+    if (i < n) {
+        const int I = (int)(i / 64), il = (int)(i % 64);
+        double y = 0.0, ya = 0.0;
+        for (int J = 0; J <= I; ++J) {
+            y += RP[(((int64_t)I * nrb + J) * NC + c) * 64 + il];
+            if (want_abs && c == 0)
+                ya += RP[(((int64_t)I * nrb + J) * NC + MC) * 64 + il];
+        }
+        for (int q = 0; q < Q; ++q) {
+            if (I + q * RSYM_CH >= nrb)
+                break;
+            y += CP[(((int64_t)I * Q + q) * NC + c) * 64 + il];
+            if (want_abs && c == 0)
+                ya += CP[(((int64_t)I * Q + q) * NC + MC) * 64 + il];
+        }
+        const double b = B[i + c * ldb];
+        const double r = b - y;
+        R[i + c * ldr] = r;
+        vr = fabs(r);
+        vx = fabs(X[i + c * ldx]);
+        vb = fabs(b);
+        vd = d ? fabs(d[i] * r) : vr;
+        va = ya;
+    }
+    vr = wave_max2(vr);
+    vx = wave_max2(vx);
+    vb = wave_max2(vb);
+    vd = wave_max2(vd);
+    if (want_abs && c == 0)
+        va = wave_max2(va);
+    if ((threadIdx.x & 63) == 0) {
+        atomic_max_nonneg(norms + 1 + c, vr);
+        atomic_max_nonneg(norms + 1 + m + c, vx);
+        atomic_max_nonneg(norms + 1 + 2 * m + c, vb);
+        atomic_max_nonneg(norms + 1 + 3 * m + c, vd);
+        if (want_abs && c == 0)
+            atomic_max_nonneg(norms, va);
+    }
+}
+
 namespace spd {
 
 static int resid_splits(int64_t n)
@@ -193,10 +354,18 @@ static int resid_splits(int64_t n)
     return (int)(S < 1 ? 1 : S);
 }
 
+#define RSYM_MAX_M 2
+static int rsym_mc(int m) { return m <= 1 ? 1 : 2; }
+
 int64_t resid_scratch(int64_t n, int m)
 {
     const int S = resid_splits(n);
-    return (int64_t)S * n * (m + 1);
+    int64_t need = (int64_t)S * n * (m + 1);
+    if (m <= RSYM_MAX_M) {
+        const int64_t nrb = (n + 63) / 64, Q = (nrb + RSYM_CH - 1) / RSYM_CH, nc = rsym_mc(m) + 1;
+        need = std::max<int64_t>(need, (nrb * nrb + nrb * Q) * nc * 64);
+    }
+    return need;
 }
 
 template <int MC, int RB, int CB, int JS>
@@ -213,6 +382,27 @@ void launch_residual(const double *A, int64_t lda, int64_t n, const double *X, i
                      double *P, hipStream_t st)
 {
     if (n <= 0 || m <= 0) return;
+    if (m <= RSYM_MAX_M) {
+        const int nrb = (int)((n + 63) / 64), Q = (nrb + RSYM_CH - 1) / RSYM_CH, mc = rsym_mc(m);
+        double *RP = P, *CP = P + (int64_t)nrb * nrb * (mc + 1) * 64;
+        const dim3 g((unsigned)nrb, (unsigned)Q), gr((unsigned)((n + 255) / 256), (unsigned)m);
+        if (mc == 1) {
+            if (want_anorm)
+                hipLaunchKernelGGL((k_resid_sym<1, true>), g, dim3(256), 0, st, A, lda, n, X, ldx, m, Q, RP, CP);
+            else
+                hipLaunchKernelGGL((k_resid_sym<1, false>), g, dim3(256), 0, st, A, lda, n, X, ldx, m, Q, RP, CP);
+            hipLaunchKernelGGL(k_resid_sym_reduce<1>, gr, dim3(256), 0, st, B, ldb, X, ldx, n, m, Q, RP, CP,
+                               want_anorm, d, R, ldr, norms);
+        } else {
+            if (want_anorm)
+                hipLaunchKernelGGL((k_resid_sym<2, true>), g, dim3(256), 0, st, A, lda, n, X, ldx, m, Q, RP, CP);
+            else
+                hipLaunchKernelGGL((k_resid_sym<2, false>), g, dim3(256), 0, st, A, lda, n, X, ldx, m, Q, RP, CP);
+            hipLaunchKernelGGL(k_resid_sym_reduce<2>, gr, dim3(256), 0, st, B, ldb, X, ldx, n, m, Q, RP, CP,
+                               want_anorm, d, R, ldr, norms);
+        }
+        return;
+    }
     const int S = resid_splits(n);
     double *Pabs = P + (int64_t)S * n * m;
     for (int c0 = 0; c0 < m; c0 += 64) {

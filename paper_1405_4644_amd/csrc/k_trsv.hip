@@ -11,9 +11,10 @@
 // rows (32 binary32 / 16 binary64):
 //   U(j, i, c): P_ij[c] = L_ij[rows c] z_j          (j < i)
 //   Z(i, c)   : z_i[c]  = W_i[rows c] (b_i - sum_j P_ij)
-// handed out by an atomic counter row by row (U(0, i), ..., U(i-1, i), Z(i)),
-// which is a topological order: every task waits only on tasks handed out
-// before it, so progress never depends on how many workgroups are resident.
+// handed out by an atomic counter column by column (Z(j), U(j, j+1), ...,
+// U(j, K-1)), which is a topological order: every task waits only on tasks
+// handed out before it, so progress never depends on how many workgroups are
+// resident, and the bandwidth-bound U tasks run well ahead of the chain.
 // A task loads its matrix block into registers before it waits, so the wait
 // hides the load.  Z(i) sums the partials of blocks j <= i-2 (finished a step
 // earlier) before it waits for the newest ones, U(i-1, i), so the critical
@@ -314,26 +315,53 @@ __global__ __launch_bounds__(256) void k_trsv_blk(const T *__restrict__ L, int64
     int *qhead = ctl, *cntA = ctl + 1, *cntB = ctl + 1 + K, *cntZ = ctl + 1 + 2 * K;
     const int mc = min(MC, m - c0);
     BV bv;
+    // Blocks in processing order p (FWD: block p; BWD: block K-1-p); only
+    // block K-1 may be shorter than nbs.
+    const int slast = (int)(npad - (int64_t)(K - 1) * nbs);
+    auto proc_size = [&](int p) -> int { return (FWD ? p == K - 1 : p == 0) ? slast : nbs; };
+    auto rows_before = [&](int p) -> int64_t {
+        return FWD ? (int64_t)p * nbs : (p == 0 ? 0 : slast + (int64_t)(p - 1) * nbs);
+    };
+    auto proc_locate = [&](int64_t pos, int &p, int &off) {
+        if (FWD) {
+            p = (int)(pos / nbs);
+            off = (int)(pos - (int64_t)p * nbs);
+        } else if (pos < slast) {
+            p = 0;
+            off = (int)pos;
+        } else {
+            p = 1 + (int)((pos - slast) / nbs);
+            off = (int)((pos - slast) % nbs);
+        }
+    };
 
     for (;;) {
         if (tid == 0)
             s_task = atomicAdd(qhead, 1);
         __syncthreads();
-        int rem = s_task;
-        // decode: row pi holds (pi + 1) nc tasks: U(0..pi-1, pi, c) then Z(pi, c)
-        int pi = 0, nc = 0;
-        for (; pi < K; ++pi) {
-            int64_t oo;
-            int ss;
-            big_block(npad, nbs, FWD ? pi : K - 1 - pi, oo, ss);
-            nc = ss / R;
-            if (rem < (pi + 1) * nc)
+        // decode, column by column in processing order: column pj holds
+        // Z(pj, 0..) followed by U(pj, pi, 0..) for the blocks pi after it
+        int rem = s_task, pj = 0;
+        for (; pj < K; ++pj) {
+            const int cnt = (int)((npad - rows_before(pj)) / R);
+            if (rem < cnt)
                 break;
-            rem -= (pi + 1) * nc;
+            rem -= cnt;
         }
-        if (pi >= K)
+        if (pj >= K)
             return;
-        const int pj = rem / nc, c = rem % nc;
+        int pi, c;
+        const int ncj = proc_size(pj) / R;
+        if (rem < ncj) {
+            pi = pj;
+            c = rem;
+        } else {
+            const int64_t pos = rows_before(pj) + proc_size(pj) + (int64_t)(rem - ncj) * R;
+            int off;
+            proc_locate(pos, pi, off);
+            c = off / R;
+        }
+        const int nc = proc_size(pi) / R;
         const bool ztask = (pj == pi);
         const int ki = FWD ? pi : K - 1 - pi, kj = FWD ? pj : K - 1 - pj;
         int64_t oi, oj;

@@ -134,19 +134,37 @@ spd_status spd_posv(const double *A, int64_t n, int64_t lda, const double *B, in
 spd_status spd_residual(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx, const double *B,
                         int64_t ldb, int64_t nrhs, double *R, int64_t ldr, double *eta, void *hip_stream);
 
-/* Many independent systems (Eq. (2) per system) in one persistent launch.
- * Device arrays of length `batch`: n[s], nrhs[s], a_off[s] (offset of system
- * s's matrix in A, in elements; leading dimension n[s]), b_off[s] (offset of
- * its right-hand sides in B and of its solution in X; leading dimension
- * n[s]); prec[s] is the requested precision on input (AUTO allowed) and the
- * one used on output; reps[s] is written (device memory).  No host
- * synchronisation; graph-capturable after a first uncaptured call with the
- * same batch. Returns SPD_OK when every system converged, else the first
- * failing status. */
+/* Limits of the batched entry point (per system). */
+#define SPD_BATCH_NMAX 512
+#define SPD_BATCH_MAXRHS 8
+
+/* Many independent systems (Eq. (2) per system), each taken through all of
+ * Algorithm 1 (with the fallback chain) in one persistent launch, one
+ * workgroup per system, largest systems first.  Device arrays of length
+ * `batch`: n[s] (0..SPD_BATCH_NMAX), nrhs[s] (0..SPD_BATCH_MAXRHS),
+ * a_off[s] (offset of system s's matrix in A, in elements; column-major,
+ * leading dimension n[s], lower triangle read), b_off[s] (offset of its
+ * right-hand sides in B and of its solution in X; leading dimension n[s]);
+ * prec[s] is the requested precision on input (AUTO: FP32) and the one used
+ * on output; reps[s] (device memory) receives each system's report, with
+ * SPD_ERR_INVALID_ARG for a system outside the limits.
+ * The first call for a given batch size allocates the workspace (about 2.3 MB
+ * per workgroup of the persistent grid), picks the launch shape by timing the
+ * candidates on this very batch (the results are those of the last, chosen,
+ * run) and synchronises the stream.  Later calls with the same batch size
+ * allocate nothing and never synchronise the host, so they can be captured in
+ * a graph; under capture without such a first call the status is
+ * SPD_ERR_UNSUPPORTED.  Per-system outcomes are only in reps (the returned
+ * status covers the arguments and the launch). */
 spd_status spd_solve_batched(int64_t batch, const int32_t *n, const int32_t *nrhs,
                              const int64_t *a_off, const double *A, const int64_t *b_off,
                              const double *B, double *X, spd_prec *prec, const spd_opts *o,
                              spd_report *reps, void *hip_stream);
+
+/* Launch shape the batched solver chose for this batch size on the current
+ * device (workgroups of the persistent grid, waves per workgroup);
+ * SPD_ERR_INVALID_ARG if no call with that batch size has been made yet. */
+spd_status spd_batched_config(int64_t batch, int32_t *grid, int32_t *waves);
 
 /* Release every device buffer the handle owns.  NULL is ignored. */
 void spd_factor_destroy(spd_factor_t F);

@@ -61,6 +61,7 @@ _SIGS = [
                            C.POINTER(Report), _vp, C.POINTER(_vp)]),
     ("spd_residual", C.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _vp]),
     ("spd_solve_batched", C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Opts), _vp, _vp]),
+    ("spd_batched_config", C.c_int, [_i64, C.POINTER(_i32), C.POINTER(_i32)]),
     ("spd_factor_destroy", None, [_vp]),
     ("spd_factor_query", C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32)]),
     ("spd_factor_export", C.c_int, [_vp, _vp, _i64, _vp, C.POINTER(_f64), _vp]),
@@ -276,6 +277,67 @@ def profile_query(kernel: int):
     if st:
         raise SPDError(st, "spd_profile_query")
     return n.value, ms.value, fl.value, by.value
+
+
+# spd_report as laid out in device memory (batched reports)
+REPORT_DTYPE = None
+
+
+def _report_dtype():
+    import numpy as np
+    global REPORT_DTYPE
+    if REPORT_DTYPE is None:
+        REPORT_DTYPE = np.dtype({"names": [f for f, _ in Report._fields_],
+                                 "formats": ["<i4", "<i4", "<i4", "<i4", "<i4", "<i8", "<f8"],
+                                 "offsets": [getattr(Report, f).offset for f, _ in Report._fields_],
+                                 "itemsize": C.sizeof(Report)})
+    return REPORT_DTYPE
+
+
+class Batch:
+    """Device arrays of a packed batch: n, nrhs (int32), a_off, b_off (int64),
+    A (float64, system s column-major n x n at a_off[s]), B and X (float64,
+    n x m column-major at b_off[s]), prec (int32, in/out), reps (raw reports)."""
+
+    def __init__(self, n, nrhs, a_off, A, b_off, B, X=None, prec="fp32"):
+        torch = _torch()
+        self.n, self.nrhs, self.a_off, self.b_off, self.A, self.B = n, nrhs, a_off, b_off, A, B
+        for t, name, dt in ((n, "n", torch.int32), (nrhs, "nrhs", torch.int32), (a_off, "a_off", torch.int64),
+                            (b_off, "b_off", torch.int64), (A, "A", torch.float64), (B, "B", torch.float64)):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                raise TypeError(f"{name} must be a contiguous {dt} CUDA tensor")
+        self.batch = int(n.numel())
+        self.X = torch.zeros_like(B) if X is None else X
+        if isinstance(prec, torch.Tensor):
+            self.prec = prec
+        else:
+            self.prec = torch.full((self.batch,), _prec(prec), dtype=torch.int32, device=n.device)
+        self.reps = torch.zeros((max(self.batch, 1), C.sizeof(Report)), dtype=torch.uint8, device=n.device)
+
+    def reports(self):
+        import numpy as np
+        raw = self.reps[:self.batch].cpu().numpy()
+        return np.frombuffer(raw.tobytes(), dtype=_report_dtype())
+
+
+def solve_batched(bt: Batch, opts: Opts | None = None, check=True) -> int:
+    """Every system of the batch through Algorithm 1 in one persistent launch
+    (asynchronous; the first call for a batch size also autotunes and
+    synchronises).  Per-system outcomes: bt.reports(), bt.prec."""
+    st = load().spd_solve_batched(bt.batch, C.c_void_p(bt.n.data_ptr()), C.c_void_p(bt.nrhs.data_ptr()),
+                                  C.c_void_p(bt.a_off.data_ptr()), C.c_void_p(bt.A.data_ptr()),
+                                  C.c_void_p(bt.b_off.data_ptr()), C.c_void_p(bt.B.data_ptr()),
+                                  C.c_void_p(bt.X.data_ptr()), C.c_void_p(bt.prec.data_ptr()),
+                                  C.byref(opts) if opts else None, C.c_void_p(bt.reps.data_ptr()), _stream())
+    if check and st != OK:
+        raise SPDError(st, "spd_solve_batched")
+    return st
+
+
+def batched_config(batch: int):
+    g, w = _i32(), _i32()
+    st = load().spd_batched_config(int(batch), C.byref(g), C.byref(w))
+    return (g.value, w.value) if st == OK else None
 
 
 def version() -> str:

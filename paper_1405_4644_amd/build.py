@@ -21,7 +21,7 @@ INC = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libspd.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["k_factor.hip", "k_solve.hip", "k_trsv.hip", "k_resid.hip", "api.cpp"]
+SOURCES = ["k_factor.hip", "k_solve.hip", "k_trsv.hip", "k_resid.hip", "k_batch.hip", "api.cpp"]
 
 
 def _hipcc() -> str:
@@ -49,7 +49,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]

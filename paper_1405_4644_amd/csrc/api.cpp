@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -505,6 +506,23 @@ spd_status refine_once(spd_factor_t F, const double *A, int64_t lda, const doubl
 
 bool valid_prec(int p) { return p >= SPD_BF16 && p <= SPD_FP64; }
 
+// ---- batched solver state (per device; kept until the process ends) ----
+constexpr int kMaxDevices = 64;
+constexpr int kBatchMaxGrid = 1024;
+// launch shapes tried by the autotuner: {workgroups, waves per workgroup}
+constexpr int kBatchCandidates[][2] = {{256, 4}, {512, 4}, {1024, 4}, {256, 8}, {512, 8}};
+struct BatchEntry {
+    int32_t *order = nullptr;  // work order (and, after it, the queue counter)
+    int *queue = nullptr;
+    int grid = 256, waves = 4;
+};
+struct BatchCtx {
+    void *ws = nullptr;
+    std::map<int64_t, BatchEntry> per_batch;
+};
+std::mutex g_batch_mu;
+BatchCtx g_batch[kMaxDevices];
+
 }  // namespace
 
 extern "C" {
@@ -756,10 +774,110 @@ spd_status spd_solve_batched(int64_t batch, const int32_t *n, const int32_t *nrh
                              const double *A, const int64_t *b_off, const double *B, double *X, spd_prec *prec,
                              const spd_opts *o, spd_report *reps, void *hip_stream)
 {
-    (void)n; (void)nrhs; (void)a_off; (void)A; (void)b_off; (void)B; (void)X; (void)prec; (void)o; (void)reps;
-    (void)hip_stream;
     if (batch < 0) return SPD_ERR_INVALID_ARG;
-    return SPD_ERR_UNSUPPORTED;
+    if (batch == 0) return SPD_OK;
+    if (!n || !nrhs || !a_off || !A || !b_off || !B || !X || !prec || !reps) return SPD_ERR_INVALID_ARG;
+    if (batch > (int64_t)INT32_MAX) return SPD_ERR_INVALID_ARG;
+    const spd_opts op = o ? *o : defaults();
+    if (!opts_valid(op)) return SPD_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return SPD_ERR_DEVICE;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cs));
+    const bool capturing = (cs != hipStreamCaptureStatusNone);
+
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    BatchCtx &c = g_batch[dev];
+    auto it = c.per_batch.find(batch);
+    if (it == c.per_batch.end() && capturing) return SPD_ERR_UNSUPPORTED;
+    if (!c.ws) {
+        // every candidate's grid fits; never freed, so captured graphs stay valid
+        const size_t bytes = (size_t)kBatchMaxGrid * spd::batch_ws_stride();
+        HIP_TRY(hipMalloc(&c.ws, bytes));
+    }
+    spd::BatchLaunch l;
+    l.batch = batch;
+    l.n = n;
+    l.nrhs = nrhs;
+    l.a_off = a_off;
+    l.b_off = b_off;
+    l.A = A;
+    l.B = B;
+    l.X = X;
+    l.prec = (int32_t *)prec;
+    l.reps = reps;
+    l.tol = op.tol;
+    l.mu16 = fp16_scale(op.theta);
+    l.max_iter = op.max_iter;
+    l.fallback = op.fallback;
+    l.equilibrate = op.equilibrate;
+    l.ws = c.ws;
+    if (it == c.per_batch.end()) {
+        BatchEntry e;
+        HIP_TRY(hipMalloc(&e.order, (size_t)batch * sizeof(int32_t) + 256));
+        e.queue = (int *)((char *)e.order + (size_t)batch * sizeof(int32_t) + 128);
+        // autotune: time every launch shape on this batch, keep the fastest;
+        // the requested precisions are restored before each run (prec is in/out)
+        int32_t *saved = nullptr;
+        HIP_TRY(hipMalloc(&saved, (size_t)batch * sizeof(int32_t)));
+        HIP_TRY(hipMemcpyAsync(saved, prec, (size_t)batch * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        hipEvent_t ea, eb;
+        HIP_TRY(hipEventCreate(&ea));
+        HIP_TRY(hipEventCreate(&eb));
+        float best = 1e30f;
+        hipError_t err = hipSuccess;
+        for (const auto &cand : kBatchCandidates) {
+            l.grid = (int)std::min<int64_t>(cand[0], batch);
+            l.waves = cand[1];
+            l.order = e.order;
+            l.queue = e.queue;
+            if (err == hipSuccess)
+                err = hipMemcpyAsync(prec, saved, (size_t)batch * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+            if (err == hipSuccess) err = hipEventRecord(ea, st);
+            if (err == hipSuccess) err = spd::launch_batch(l, st);
+            if (err == hipSuccess) err = hipEventRecord(eb, st);
+            if (err == hipSuccess) err = hipEventSynchronize(eb);
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, ea, eb);
+            if (err == hipSuccess && ms < best) {
+                best = ms;
+                e.grid = l.grid;
+                e.waves = l.waves;
+            }
+        }
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(prec, saved, (size_t)batch * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+        if (err == hipSuccess) err = hipStreamSynchronize(st);
+        hipEventDestroy(ea);
+        hipEventDestroy(eb);
+        hipFree(saved);
+        if (err != hipSuccess) {
+            hipFree(e.order);
+            return map_err(err);
+        }
+        it = c.per_batch.emplace(batch, e).first;
+    }
+    l.grid = it->second.grid;
+    l.waves = it->second.waves;
+    l.order = it->second.order;
+    l.queue = it->second.queue;
+    HIP_TRY(spd::launch_batch(l, st));
+    return SPD_OK;
+}
+
+spd_status spd_batched_config(int64_t batch, int32_t *grid, int32_t *waves)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return SPD_ERR_DEVICE;
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    auto it = g_batch[dev].per_batch.find(batch);
+    if (it == g_batch[dev].per_batch.end()) return SPD_ERR_INVALID_ARG;
+    if (grid) *grid = it->second.grid;
+    if (waves) *waves = it->second.waves;
+    return SPD_OK;
 }
 
 void spd_factor_destroy(spd_factor_t F)

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <spd.h>
+
 // Operand rounding of the trailing update: none (binary32 / binary64
 // operands), binary16 or bfloat16 (binary32 accumulation).
 enum spd_half_kind { HALF_NONE = 0, HALF_F16 = 1, HALF_BF16 = 2 };
@@ -89,5 +91,24 @@ int64_t resid_scratch(int64_t n, int m);
 void launch_residual(const double *A, int64_t lda, int64_t n, const double *X, int64_t ldx, const double *B,
                      int64_t ldb, int m, double *R, int64_t ldr, const double *d, double *norms, int want_anorm,
                      double *P, hipStream_t st);
+
+// --- batched solver (k_batch.hip) ---
+struct BatchLaunch {
+    int64_t batch;
+    const int32_t *n, *nrhs;
+    const int64_t *a_off, *b_off;
+    const double *A, *B;
+    double *X;
+    int32_t *prec;
+    spd_report *reps;
+    double tol, mu16;
+    int max_iter, fallback, equilibrate;
+    int32_t *order;  // batch entries of scratch
+    int *queue;      // one int of scratch
+    void *ws;        // grid * batch_ws_stride() bytes
+    int grid, waves;
+};
+int64_t batch_ws_stride();
+hipError_t launch_batch(const BatchLaunch &l, hipStream_t st);
 
 }  // namespace spd

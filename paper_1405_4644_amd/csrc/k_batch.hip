@@ -1,0 +1,692 @@
+// Batched solver: many independent SPD systems A_s X_s = B_s (Eq. (2) per
+// system) in one persistent launch, each system taken through all of
+// Algorithm 1 by one workgroup:
+//   equilibrate and round (mu D A D), blocked Cholesky in the factor's
+//   precision (32-wide panels; trailing update on MFMA, with binary16 /
+//   bfloat16 rounded operands for the half formats), triangular solves with
+//   the 32 x 32 diagonal-block inverses, binary64 residual and backward error,
+//   correction loop with the same stopping, divergence and fallback rules as
+//   the single-system path (BF16/FP16 -> FP32 -> FP64).
+// Systems are handed out by an atomic counter in decreasing order of n
+// (counting sort on the device), so the largest start first.  Each workgroup
+// owns a fixed slice of workspace (factor, inverses, d, residual): a call
+// allocates nothing once the workspace exists, and never synchronises the
+// host, so it can be captured in a graph.
+#include <spd.h>
+
+#include "common.h"
+#include "internal.h"
+
+#define BNB 32  // panel and tile width
+
+struct BatchArgs {
+    int64_t batch;
+    const int32_t *n, *nrhs;
+    const int64_t *a_off, *b_off;
+    const double *A, *B;
+    double *X;
+    int32_t *prec;
+    spd_report *reps;
+    double tol, mu16;
+    int max_iter, fallback, equilibrate;
+    const int32_t *order;
+    int *queue;
+    char *ws;
+    int64_t ws_stride;
+};
+
+// workspace slice of one workgroup
+struct BatchWs {
+    void *L;      // np x np factor (binary32 or binary64), column-major
+    void *Winv;   // np/32 blocks of 32 x 32 inverses of the diagonal blocks
+    double *d;    // equilibration
+    double *R;    // n x m residual
+};
+
+SPD_DEV BatchWs batch_ws(const BatchArgs &a)
+{
+    char *p = a.ws + (int64_t)blockIdx.x * a.ws_stride;
+    BatchWs w;
+    w.L = p;
+    p += (int64_t)SPD_BATCH_NMAX * SPD_BATCH_NMAX * 8;
+    w.Winv = p;
+    p += (int64_t)SPD_BATCH_NMAX * BNB * 8;
+    w.d = (double *)p;
+    p += (int64_t)SPD_BATCH_NMAX * 8;
+    w.R = (double *)p;
+    return w;
+}
+
+SPD_DEV double b_nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
+
+// shared state of the workgroup
+struct BatchSmem {
+    double ys[SPD_BATCH_MAXRHS * SPD_BATCH_NMAX];  // solve vectors (factor type)
+    double Lk[BNB * (BNB + 1)];                    // inverse of the diagonal block
+    double ts[SPD_BATCH_MAXRHS * BNB];
+    double red[16][4 * SPD_BATCH_MAXRHS + 1];
+    double norms[1 + 4 * SPD_BATCH_MAXRHS];
+    double smax[SPD_BATCH_MAXRHS];
+    int info;
+};
+
+template <typename T>
+SPD_DEV T round_half(T v, int half)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (half == HALF_F16)
+            return (float)(_Float16)v;
+        if (half == HALF_BF16)
+            return (float)(__bf16)v;
+    }
+    return v;
+}
+
+// value of v in lane src (src uniform); binary64 as two 32-bit halves
+SPD_DEV float rl(float v, int src) { return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src)); }
+SPD_DEV double rl(double v, int src)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ---------------------------------------------------------------------------
+// H = round(mu D A D) (lower), identity padding up to np; d (binary64).
+template <typename T>
+SPD_DEV void b_convert(const double *A, int n, int np, double *d, double mu, int equil, T *L, int nthr)
+{
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n; i += nthr) {
+        const double a = A[i + (int64_t)i * n];
+        d[i] = (equil && a > 0.0) ? 1.0 / sqrt(a) : 1.0;
+    }
+    __syncthreads();
+    for (int64_t idx = tid; idx < (int64_t)np * np; idx += nthr) {
+        const int i = (int)(idx % np), j = (int)(idx / np);
+        if (j > i)
+            continue;
+        T v;
+        if (i < n && j < n)
+            v = (T)(((mu * d[i]) * A[i + (int64_t)j * n]) * d[j]);
+        else
+            v = (i == j) ? (T)1 : (T)0;
+        L[i + (int64_t)j * np] = v;
+    }
+    __syncthreads();
+}
+
+// Factor the 32 x 32 diagonal block at (k0, k0) in one wavefront (lane r
+// holds row r; right-looking, one column per step, broadcasts by readlane)
+// and form its inverse W (lane c builds column c:
+// W[r][c] = (delta_rc - sum_{q<r} L[r][q] W[q][c]) / L[r][r]) into Ws
+// (Ws[c * 33 + r]) and Wg (column-major).  Returns the 1-based failing column
+// of the block, 0 on success.  A function of its own so that its registers
+// are allocated apart from the rest of the factorisation.
+template <typename T>
+__device__ __attribute__((noinline)) int b_diag(T *L, int np, int k0, T *Ws, T *Wg)
+{
+    const int lane = threadIdx.x & 63;
+    T row[BNB];
+#pragma unroll
+    for (int c = 0; c < BNB; ++c)
+        row[c] = (lane < BNB && c <= lane) ? L[(k0 + lane) + (int64_t)(k0 + c) * np] : (T)0;
+#pragma unroll
+    for (int j = 0; j < BNB; ++j) {
+        const T p = rl(row[j], j);
+        if (!(p > (T)0))
+            return j + 1;
+        const T ljj = sqrt(p);
+        if (lane == j)
+            row[j] = ljj;
+        else if (lane > j)
+            row[j] = row[j] / ljj;
+#pragma unroll
+        for (int c = j + 1; c < BNB; ++c) {
+            const T lcj = rl(row[j], c);
+            row[c] -= row[j] * lcj;
+        }
+    }
+    T w[BNB];
+#pragma unroll
+    for (int r = 0; r < BNB; ++r) {
+        T sacc = (lane == r) ? (T)1 : (T)0;
+#pragma unroll
+        for (int q = 0; q < r; ++q) sacc -= rl(row[q], r) * w[q];
+        w[r] = sacc / rl(row[r], r);
+    }
+    if (lane < BNB) {
+#pragma unroll
+        for (int c = 0; c < BNB; ++c)
+            if (c <= lane)
+                L[(k0 + lane) + (int64_t)(k0 + c) * np] = row[c];
+#pragma unroll
+        for (int r = 0; r < BNB; ++r) {
+            const T v = (r < lane) ? (T)0 : w[r];
+            Ws[lane * (BNB + 1) + r] = v;
+            Wg[r + lane * BNB] = v;
+        }
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Blocked right-looking Cholesky of the np x np lower matrix in L.  Returns
+// the 1-based failing column (0 on success); Winv receives the inverses of
+// the 32 x 32 diagonal blocks.  With half != HALF_NONE the trailing-update
+// operands are rounded to that format (binary32 accumulation).
+template <typename T, int WAVES>
+SPD_DEV int b_factor(T *L, int np, T *Winv, int half, BatchSmem &sm)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nb = np / BNB;
+    T *Ws = (T *)sm.Lk;  // inverse of the diagonal block: Ws[c * 33 + r] = W[r][c]
+    for (int kb = 0; kb < nb; ++kb) {
+        const int k0 = kb * BNB;
+        if (wave == 0) {
+            const int bad = b_diag<T>(L, np, k0, Ws, Winv + (int64_t)kb * BNB * BNB);
+            if (lane == 0)
+                sm.info = bad ? k0 + bad : 0;
+        }
+        __syncthreads();
+        if (sm.info)
+            return sm.info;
+        // panel: L_ik = H_ik W^T for the row blocks below, one 32 x 32 block per wave
+        for (int I = kb + 1 + wave; I < nb; I += WAVES) {
+            Acc32<T> acc;
+            acc.zero();
+            // D[c][r] = sum_q W[c][q] H[r][q]
+            mma_tile<T>(acc, Ws, BNB + 1, L + (int64_t)I * BNB + (int64_t)k0 * np, np, BNB, lane);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int c = Acc32<T>::row(j, lane), r = Acc32<T>::col(j, lane);
+                L[((int64_t)I * BNB + r) + (int64_t)(k0 + c) * np] = acc.get(j);
+            }
+        }
+        __syncthreads();
+        // trailing update of the lower tiles (I, J), kb < J <= I
+        const int t = nb - kb - 1, ntile = t * (t + 1) / 2;
+        for (int q = wave; q < ntile; q += WAVES) {
+            int I = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+            while (I * (I + 1) / 2 > q) --I;
+            while ((I + 1) * (I + 2) / 2 <= q) ++I;
+            const int J = q - I * (I + 1) / 2;
+            const int gI = kb + 1 + I, gJ = kb + 1 + J;
+            T *C = L + (int64_t)gI * BNB + (int64_t)gJ * BNB * np;
+            Acc32<T> acc;
+            // register j: column Acc32::row(j) of the tile, row Acc32::col(j)
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                acc.set(j, C[Acc32<T>::col(j, lane) + (int64_t)Acc32<T>::row(j, lane) * np]);
+            const T *pJ = L + (int64_t)gJ * BNB + (int64_t)k0 * np;
+            const T *pI = L + (int64_t)gI * BNB + (int64_t)k0 * np;
+#pragma unroll 4
+            for (int kk = 0; kk < BNB; kk += Frag<T>::K) {
+                Frag<T> fa, fb;
+                fa.load(pJ + (int64_t)kk * np, np, lane);
+                fb.load(pI + (int64_t)kk * np, np, lane);
+                if constexpr (sizeof(T) == 4) {
+                    if (half) {
+                        fa.v = round_half(fa.v, half);
+                        fb.v = round_half(fb.v, half);
+                    }
+                }
+                fa.negate();
+                mma(acc, fa, fb);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                C[Acc32<T>::col(j, lane) + (int64_t)Acc32<T>::row(j, lane) * np] = acc.get(j);
+        }
+        __syncthreads();
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// X (+)= s mu D L^{-T} L^{-1} round(D R / s) for m right-hand sides; the
+// scales s_c = pow2_ceil(smax[c]) (smax in shared memory).
+template <typename T>
+SPD_DEV void b_solve(const T *L, const T *Winv, int n, int np, int m, const double *R, const double *d, double mu,
+                     double *X, int accumulate, BatchSmem &sm, int nthr)
+{
+    const int tid = threadIdx.x;
+    const int nb = np / BNB;
+    T *ys = (T *)sm.ys;  // ys[c * NMAX + i]
+    constexpr int NM = SPD_BATCH_NMAX;
+    for (int idx = tid; idx < m * np; idx += nthr) {
+        const int c = idx / np, i = idx % np;
+        const double s = pow2_ceil(sm.smax[c]);
+        ys[c * NM + i] = (i < n) ? (T)(d[i] * R[i + (int64_t)c * n] / s) : (T)0;
+    }
+    __syncthreads();
+    // forward: z_k = W_k y_k, then y_below -= L_below,k z_k
+    for (int kb = 0; kb < nb; ++kb) {
+        const int k0 = kb * BNB;
+        const T *W = Winv + (int64_t)kb * BNB * BNB;
+        T z = (T)0;
+        if (tid < BNB * m) {
+            const int r = tid % BNB, c = tid / BNB;
+            for (int q = 0; q <= r; ++q) z += W[r + q * BNB] * ys[c * NM + k0 + q];
+        }
+        __syncthreads();
+        if (tid < BNB * m)
+            ys[(tid / BNB) * NM + k0 + tid % BNB] = z;
+        __syncthreads();
+        const int rows = np - k0 - BNB;
+        for (int idx = tid; idx < rows * m; idx += nthr) {
+            const int i = k0 + BNB + idx % rows, c = idx / rows;
+            T s = (T)0;
+#pragma unroll 8
+            for (int q = 0; q < BNB; ++q) s += L[i + (int64_t)(k0 + q) * np] * ys[c * NM + k0 + q];
+            ys[c * NM + i] -= s;
+        }
+        __syncthreads();
+    }
+    // backward: x_k = W_k^T (y_k - L_below,k^T x_below)
+    T *ts = (T *)sm.ts;
+    for (int kb = nb - 1; kb >= 0; --kb) {
+        const int k0 = kb * BNB;
+        const T *W = Winv + (int64_t)kb * BNB * BNB;
+        if (tid < BNB * m) {
+            const int q = tid % BNB, c = tid / BNB;
+            T s = (T)0;
+            for (int i = k0 + BNB; i < np; ++i) s += L[i + (int64_t)(k0 + q) * np] * ys[c * NM + i];
+            ts[c * BNB + q] = s;
+        }
+        __syncthreads();
+        T x = (T)0;
+        if (tid < BNB * m) {
+            const int r = tid % BNB, c = tid / BNB;
+            for (int q = r; q < BNB; ++q) x += W[q + r * BNB] * (ys[c * NM + k0 + q] - ts[c * BNB + q]);
+        }
+        __syncthreads();
+        if (tid < BNB * m)
+            ys[(tid / BNB) * NM + k0 + tid % BNB] = x;
+        __syncthreads();
+    }
+    for (int idx = tid; idx < m * n; idx += nthr) {
+        const int c = idx / n, i = idx % n;
+        const double s = pow2_ceil(sm.smax[c]);
+        const double z = ((s * mu) * d[i]) * (double)ys[c * NM + i];
+        double *px = X + i + (int64_t)c * n;
+        *px = accumulate ? *px + z : z;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// R = B - A X (binary64, A symmetric from its lower triangle) and the norms:
+// norms[1 + k m + c], k = 0..3: max|r|, max|x|, max|b|, max|d r|; with
+// want_anorm also norms[0] = ||A||_inf.  Rows: sum_{j <= i} a_ij x_j by
+// thread; columns: sum_{i > j} a_ij x_i by wave; then r = b - (row + col).
+template <int WAVES>
+SPD_DEV void b_residual(const double *A, int n, int m, const double *X, const double *B, const double *d, double *R,
+                        int want_anorm, BatchSmem &sm)
+{
+    constexpr int NT = WAVES * 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int MR = SPD_BATCH_MAXRHS;
+    double *abs_rows = (double *)sm.ys;  // row sums of |A| (binary64 scratch, n entries)
+    for (int i = tid; i < n; i += NT) {
+        double acc[MR], aa = 0.0;
+#pragma unroll
+        for (int c = 0; c < MR; ++c) acc[c] = 0.0;
+        for (int j = 0; j <= i; ++j) {
+            const double a = A[i + (int64_t)j * n];
+#pragma unroll
+            for (int c = 0; c < MR; ++c)
+                if (c < m)
+                    acc[c] = fma(a, X[j + (int64_t)c * n], acc[c]);
+            aa += fabs(a);
+        }
+#pragma unroll
+        for (int c = 0; c < MR; ++c)
+            if (c < m)
+                R[i + (int64_t)c * n] = acc[c];
+        if (want_anorm)
+            abs_rows[i] = aa;
+    }
+    __syncthreads();
+    for (int j = wave; j < n; j += WAVES) {
+        double acc[MR], aa = 0.0;
+#pragma unroll
+        for (int c = 0; c < MR; ++c) acc[c] = 0.0;
+        for (int i = j + 1 + lane; i < n; i += 64) {
+            const double a = A[i + (int64_t)j * n];
+#pragma unroll
+            for (int c = 0; c < MR; ++c)
+                if (c < m)
+                    acc[c] = fma(a, X[i + (int64_t)c * n], acc[c]);
+            aa += fabs(a);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+            for (int c = 0; c < MR; ++c) acc[c] += __shfl_xor(acc[c], off);
+            aa += __shfl_xor(aa, off);
+        }
+        if (lane == 0) {
+            for (int c = 0; c < m; ++c) {
+                const double y = R[j + (int64_t)c * n] + acc[c];
+                R[j + (int64_t)c * n] = B[j + (int64_t)c * n] - y;
+            }
+            if (want_anorm)
+                abs_rows[j] += aa;
+        }
+    }
+    __syncthreads();
+    // maxima (NaN propagates), per column, then ||A||_inf
+    double v[4 * MR + 1];
+#pragma unroll
+    for (int k = 0; k < 4 * MR + 1; ++k) v[k] = 0.0;
+    for (int i = tid; i < n; i += NT) {
+#pragma unroll
+        for (int c = 0; c < MR; ++c)
+            if (c < m) {
+                const double r = R[i + (int64_t)c * n];
+                v[c] = b_nanmax(v[c], fabs(r));
+                v[MR + c] = b_nanmax(v[MR + c], fabs(X[i + (int64_t)c * n]));
+                v[2 * MR + c] = b_nanmax(v[2 * MR + c], fabs(B[i + (int64_t)c * n]));
+                v[3 * MR + c] = b_nanmax(v[3 * MR + c], fabs(d[i] * r));
+            }
+        if (want_anorm)
+            v[4 * MR] = b_nanmax(v[4 * MR], abs_rows[i]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4 * MR + 1; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] = b_nanmax(v[k], __shfl_xor(v[k], off));
+        if (lane == 0)
+            sm.red[wave][k] = v[k];
+    }
+    __syncthreads();
+    if (tid < 4 * MR + 1) {
+        double x = 0.0;
+        for (int w = 0; w < WAVES; ++w) x = b_nanmax(x, sm.red[w][tid]);
+        const int k = tid / MR, c = tid % MR;
+        if (tid == 4 * MR) {
+            if (want_anorm)
+                sm.norms[0] = x;
+        } else if (c < m) {
+            sm.norms[1 + k * m + c] = x;
+        }
+    }
+    __syncthreads();
+}
+
+SPD_DEV int b_next_prec(int p) { return (p == SPD_BF16 || p == SPD_FP16) ? SPD_FP32 : SPD_FP64; }
+
+// Refinement at the precision of the current factor (T), from the iterate in
+// X; same rules as the single-system path.  Returns SPD_OK or
+// SPD_ERR_NO_CONVERGENCE and fills the iteration counts and eta.
+template <typename T, int WAVES>
+SPD_DEV int b_refine(const BatchArgs &a, const double *A, const double *B, double *X, int n, int np, int m,
+                     const BatchWs &w, double mu, spd_report &rep, BatchSmem &sm)
+{
+    constexpr double FLOOR = 0x1p-51;
+    rep.iters_low = 1;
+    rep.iters_high = 0;
+    constexpr int MR = SPD_BATCH_MAXRHS;
+    double eta0 = 0.0, prev_worst = 0.0, anorm = 0.0;
+    double eta[MR], prev[MR];  // identical in every thread
+    int stalls = 0;
+    for (;;) {
+        const int first = (rep.iters_high == 0);
+        b_residual<WAVES>(A, n, m, X, B, w.d, w.R, first, sm);
+        rep.iters_high++;
+        if (first)
+            anorm = sm.norms[0];
+        bool finite = isfinite(anorm);
+        double worst = 0.0;
+#pragma unroll
+        for (int c = 0; c < MR; ++c) {
+            if (c >= m)
+                break;
+            const double rn = sm.norms[1 + c], xn = sm.norms[1 + m + c], bn = sm.norms[1 + 2 * m + c];
+            const double den = anorm * xn + bn;
+            double v = (den > 0.0) ? rn / den : (rn > 0.0 ? __builtin_inf() : 0.0);
+            if (!(rn == rn) || !(xn == xn))
+                v = __builtin_nan("");
+            eta[c] = v;
+            if (!isfinite(v))
+                finite = false;
+            if (v > worst)
+                worst = v;
+        }
+        rep.eta = finite ? worst : __builtin_nan("");
+        if (!finite)
+            return SPD_ERR_NO_CONVERGENCE;
+        if (worst <= FLOOR)
+            return SPD_OK;
+        if (rep.iters_high == 1) {
+            eta0 = worst;
+        } else {
+            if (worst <= a.tol && worst > 0.5 * prev_worst)
+                return SPD_OK;
+            bool all_slow = true;
+#pragma unroll
+            for (int c = 0; c < MR; ++c)
+                if (c < m && !(eta[c] > 0.9 * prev[c]))
+                    all_slow = false;
+            stalls = all_slow ? stalls + 1 : 0;
+            if (worst > a.tol && (worst > eta0 || stalls >= 2))
+                return SPD_ERR_NO_CONVERGENCE;
+        }
+        if (rep.iters_low > a.max_iter)
+            return worst <= a.tol ? SPD_OK : SPD_ERR_NO_CONVERGENCE;
+        prev_worst = worst;
+#pragma unroll
+        for (int c = 0; c < MR; ++c) prev[c] = eta[c];
+        __syncthreads();
+        if (threadIdx.x < m)
+            sm.smax[threadIdx.x] = sm.norms[1 + 3 * m + threadIdx.x];
+        __syncthreads();
+        b_solve<T>((const T *)w.L, (const T *)w.Winv, n, np, m, w.R, w.d, mu, X, 1, sm, WAVES * 64);
+        rep.iters_low++;
+    }
+}
+
+// Factor at precision p (with the fallback chain on breakdown when enabled);
+// returns the 1-based failing column of the last attempt (0 = success).
+template <int WAVES>
+SPD_DEV int b_factor_at(const BatchArgs &a, const double *A, int n, int np, const BatchWs &w, int &p,
+                        int &fallbacks, double &mu, BatchSmem &sm)
+{
+    for (;;) {
+        int info;
+        if (p == SPD_FP64) {
+            mu = 1.0;
+            b_convert<double>(A, n, np, w.d, 1.0, 0, (double *)w.L, WAVES * 64);
+            info = b_factor<double, WAVES>((double *)w.L, np, (double *)w.Winv, HALF_NONE, sm);
+        } else {
+            mu = (p == SPD_FP16) ? a.mu16 : 1.0;
+            b_convert<float>(A, n, np, w.d, mu, a.equilibrate, (float *)w.L, WAVES * 64);
+            const int half = (p == SPD_FP16) ? HALF_F16 : (p == SPD_BF16) ? HALF_BF16 : HALF_NONE;
+            info = b_factor<float, WAVES>((float *)w.L, np, (float *)w.Winv, half, sm);
+        }
+        if (info && a.fallback && p != SPD_FP64) {
+            ++fallbacks;
+            p = b_next_prec(p);
+            continue;
+        }
+        return info;
+    }
+}
+
+template <int WAVES>
+SPD_DEV void b_system(const BatchArgs &a, int64_t s, BatchSmem &sm)
+{
+    const int n = a.n[s], m = a.nrhs[s];
+    spd_report rep;
+    rep.status = SPD_OK;
+    rep.prec_used = a.prec[s];
+    rep.iters_low = rep.iters_high = rep.fallbacks = 0;
+    rep.info = 0;
+    rep.eta = 0.0;
+    int p = a.prec[s];
+    if (p == SPD_AUTO)
+        p = SPD_FP32;
+    if (n < 0 || m < 0 || n > SPD_BATCH_NMAX || m > SPD_BATCH_MAXRHS || p < SPD_BF16 || p > SPD_FP64) {
+        rep.status = SPD_ERR_INVALID_ARG;
+    } else if (n > 0 && m > 0) {
+        const double *A = a.A + a.a_off[s];
+        const double *B = a.B + a.b_off[s];
+        double *X = a.X + a.b_off[s];
+        const int np = ((n + BNB - 1) / BNB) * BNB;
+        const BatchWs w = batch_ws(a);
+        double mu = 1.0;
+        int info = b_factor_at<WAVES>(a, A, n, np, w, p, rep.fallbacks, mu, sm);
+        rep.info = info;
+        rep.prec_used = p;
+        int status = info ? SPD_ERR_NOT_SPD : SPD_OK;
+        // first solve from B (smax = max |d b|), then refinement with fallback
+        bool need_solve = (status == SPD_OK);
+        while (status == SPD_OK && need_solve) {
+            // smax from B
+            double v[SPD_BATCH_MAXRHS];
+#pragma unroll
+            for (int c = 0; c < SPD_BATCH_MAXRHS; ++c) v[c] = 0.0;
+            for (int i = threadIdx.x; i < n; i += WAVES * 64)
+#pragma unroll
+                for (int c = 0; c < SPD_BATCH_MAXRHS; ++c)
+                    if (c < m)
+                        v[c] = b_nanmax(v[c], fabs(w.d[i] * B[i + (int64_t)c * n]));
+#pragma unroll
+            for (int c = 0; c < SPD_BATCH_MAXRHS; ++c) {
+                for (int off = 32; off > 0; off >>= 1) v[c] = b_nanmax(v[c], __shfl_xor(v[c], off));
+                if ((threadIdx.x & 63) == 0)
+                    sm.red[threadIdx.x >> 6][c] = v[c];
+            }
+            __syncthreads();
+            if (threadIdx.x < m) {
+                double x = 0.0;
+                for (int q = 0; q < WAVES; ++q) x = b_nanmax(x, sm.red[q][threadIdx.x]);
+                sm.smax[threadIdx.x] = x;
+            }
+            __syncthreads();
+            int r;
+            if (p == SPD_FP64) {
+                b_solve<double>((const double *)w.L, (const double *)w.Winv, n, np, m, B, w.d, mu, X, 0, sm,
+                                WAVES * 64);
+                r = b_refine<double, WAVES>(a, A, B, X, n, np, m, w, mu, rep, sm);
+            } else {
+                b_solve<float>((const float *)w.L, (const float *)w.Winv, n, np, m, B, w.d, mu, X, 0, sm,
+                               WAVES * 64);
+                r = b_refine<float, WAVES>(a, A, B, X, n, np, m, w, mu, rep, sm);
+            }
+            need_solve = false;
+            if (r == SPD_ERR_NO_CONVERGENCE && a.fallback && p != SPD_FP64) {
+                rep.fallbacks++;
+                p = b_next_prec(p);
+                info = b_factor_at<WAVES>(a, A, n, np, w, p, rep.fallbacks, mu, sm);
+                rep.info = info;
+                rep.prec_used = p;
+                if (info)
+                    status = SPD_ERR_NOT_SPD;
+                else
+                    need_solve = true;
+            } else {
+                status = r;
+            }
+        }
+        rep.status = status;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.reps[s] = rep;
+        a.prec[s] = rep.prec_used;
+    }
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_batch(BatchArgs a)
+{
+    __shared__ BatchSmem sm;
+    __shared__ int s_q;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_q = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int64_t q = s_q;
+        if (q >= a.batch)
+            return;
+        b_system<WAVES>(a, a.order[q], sm);
+        __syncthreads();
+    }
+}
+
+// Order of work: systems sorted by decreasing n (counting sort, one
+// workgroup); also clears the work-queue counter.
+__global__ __launch_bounds__(1024) void k_batch_order(int64_t batch, const int32_t *__restrict__ n,
+                                                      int32_t *__restrict__ order, int *queue)
+{
+    constexpr int NBIN = SPD_BATCH_NMAX + 1;
+    __shared__ int hist[NBIN], start[NBIN];
+    const int tid = threadIdx.x;
+    for (int b = tid; b < NBIN; b += 1024) hist[b] = 0;
+    __syncthreads();
+    for (int64_t s = tid; s < batch; s += 1024) {
+        int v = n[s];
+        v = (v < 0 || v > SPD_BATCH_NMAX) ? 0 : v;
+        atomicAdd(&hist[SPD_BATCH_NMAX - v], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int b = 0; b < NBIN; ++b) {
+            start[b] = acc;
+            acc += hist[b];
+        }
+        *queue = 0;
+    }
+    __syncthreads();
+    for (int64_t s = tid; s < batch; s += 1024) {
+        int v = n[s];
+        v = (v < 0 || v > SPD_BATCH_NMAX) ? 0 : v;
+        const int pos = atomicAdd(&start[SPD_BATCH_NMAX - v], 1);
+        order[pos] = (int32_t)s;
+    }
+}
+
+namespace spd {
+
+int64_t batch_ws_stride()
+{
+    int64_t b = (int64_t)SPD_BATCH_NMAX * SPD_BATCH_NMAX * 8 + (int64_t)SPD_BATCH_NMAX * BNB * 8 +
+                (int64_t)SPD_BATCH_NMAX * 8 + (int64_t)SPD_BATCH_NMAX * SPD_BATCH_MAXRHS * 8;
+    return (b + 255) / 256 * 256;
+}
+
+hipError_t launch_batch(const BatchLaunch &l, hipStream_t st)
+{
+    BatchArgs a;
+    a.batch = l.batch;
+    a.n = l.n;
+    a.nrhs = l.nrhs;
+    a.a_off = l.a_off;
+    a.b_off = l.b_off;
+    a.A = l.A;
+    a.B = l.B;
+    a.X = l.X;
+    a.prec = l.prec;
+    a.reps = l.reps;
+    a.tol = l.tol;
+    a.mu16 = l.mu16;
+    a.max_iter = l.max_iter;
+    a.fallback = l.fallback;
+    a.equilibrate = l.equilibrate;
+    a.order = l.order;
+    a.queue = l.queue;
+    a.ws = (char *)l.ws;
+    a.ws_stride = batch_ws_stride();
+    hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, st, l.batch, l.n, l.order, l.queue);
+    if (l.waves == 8)
+        hipLaunchKernelGGL(k_batch<8>, dim3((unsigned)l.grid), dim3(512), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_batch<4>, dim3((unsigned)l.grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace spd

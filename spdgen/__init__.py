@@ -238,6 +238,50 @@ def batch_shapes(batch: int, config: int = 3, nmin: int = 32, nmax: int = 512,
     return [(int(a), float(b), int(c)) for a, b, c in zip(ns, conds, ms)]
 
 
+@dataclass
+class PackedBatch:
+    """A batch of systems packed for the batched entry point: A_s column-major
+    n_s x n_s at a_off[s], B_s / Xt_s column-major n_s x m_s at b_off[s]."""
+    n: np.ndarray
+    m: np.ndarray
+    cond: np.ndarray
+    a_off: np.ndarray
+    b_off: np.ndarray
+    A: object
+    B: object
+    Xt: object
+
+
+def packed_batch(shapes, config: int = 3, first_index: int = 0, backend: str = "numpy", device=None) -> PackedBatch:
+    """Generate every system of `shapes` ((n, cond, m) per system, e.g. from
+    batch_shapes) with the single-system recipe and pack them."""
+    ns = np.array([s[0] for s in shapes], dtype=np.int32)
+    ms = np.array([s[2] for s in shapes], dtype=np.int32)
+    conds = np.array([s[1] for s in shapes], dtype=np.float64)
+    a_off = np.zeros(len(shapes), dtype=np.int64)
+    b_off = np.zeros(len(shapes), dtype=np.int64)
+    if len(shapes):
+        a_off[1:] = np.cumsum(ns.astype(np.int64) ** 2)[:-1]
+        b_off[1:] = np.cumsum(ns.astype(np.int64) * ms)[:-1]
+    na = int((ns.astype(np.int64) ** 2).sum())
+    nbx = int((ns.astype(np.int64) * ms).sum())
+    if backend == "torch":
+        import torch
+        A = torch.empty(na, dtype=torch.float64, device=device)
+        B = torch.empty(nbx, dtype=torch.float64, device=device)
+        Xt = torch.empty(nbx, dtype=torch.float64, device=device)
+    else:
+        A, B, Xt = np.empty(na), np.empty(nbx), np.empty(nbx)
+    for s, (n, cond, m) in enumerate(shapes):
+        sy = system(n, cond, m, config=config, index=first_index + s, backend=backend, device=device)
+        # row-major (m, n) right-hand sides are column-major n x m already;
+        # A is symmetric, so its row-major bytes are its column-major bytes
+        A[a_off[s]:a_off[s] + n * n] = sy.A.reshape(-1)
+        B[b_off[s]:b_off[s] + n * m] = sy.Bt.reshape(-1)
+        Xt[b_off[s]:b_off[s] + n * m] = sy.Xt.reshape(-1)
+    return PackedBatch(ns, ms, conds, a_off, b_off, A, B, Xt)
+
+
 def sha256(arr) -> str:
     if not isinstance(arr, np.ndarray):
         arr = arr.detach().cpu().numpy()

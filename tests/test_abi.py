@@ -79,6 +79,10 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.spd_residual(None, 10, 10, fake, 10, fake, 10, 1, None, 10, None, None) == spd.ERR_INVALID_ARG
     assert lib.spd_solve_batched(-1, None, None, None, None, None, None, None, None, None, None,
                                  None) == spd.ERR_INVALID_ARG
+    assert lib.spd_solve_batched(0, None, None, None, None, None, None, None, None, None, None, None) == spd.OK
+    # non-empty batch with a missing array: rejected before any device work
+    assert lib.spd_solve_batched(3, fake, fake, fake, fake, None, fake, fake, fake, None, fake,
+                                 None) == spd.ERR_INVALID_ARG
     assert lib.spd_factor_query(None, None, None, None) == spd.ERR_INVALID_ARG
     assert lib.spd_factor_export(None, None, 1, None, None, None) == spd.ERR_INVALID_ARG
     lib.spd_factor_destroy(None)  # no-op

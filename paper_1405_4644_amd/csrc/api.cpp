@@ -510,7 +510,7 @@ bool valid_prec(int p) { return p >= SPD_BF16 && p <= SPD_FP64; }
 constexpr int kMaxDevices = 64;
 constexpr int kBatchMaxGrid = 1024;
 // launch shapes tried by the autotuner: {workgroups, waves per workgroup}
-constexpr int kBatchCandidates[][2] = {{256, 4}, {512, 4}, {1024, 4}, {256, 8}, {512, 8}};
+constexpr int kBatchCandidates[][2] = {{256, 4}, {512, 4}, {1024, 4}};
 struct BatchEntry {
     int32_t *order = nullptr;  // work order (and, after it, the queue counter)
     int *queue = nullptr;

@@ -67,6 +67,9 @@ struct BatchSmem {
     double red[16][4 * SPD_BATCH_MAXRHS + 1];
     double norms[1 + 4 * SPD_BATCH_MAXRHS];
     double smax[SPD_BATCH_MAXRHS];
+    double arow[SPD_BATCH_NMAX];  // row sums of |A|
+    double csum[SPD_BATCH_MAXRHS * SPD_BATCH_NMAX];  // residual: column-pass sums
+    double cabs[SPD_BATCH_NMAX];
     int info;
 };
 
@@ -103,16 +106,17 @@ SPD_DEV void b_convert(const double *A, int n, int np, double *d, double mu, int
         d[i] = (equil && a > 0.0) ? 1.0 / sqrt(a) : 1.0;
     }
     __syncthreads();
-    for (int64_t idx = tid; idx < (int64_t)np * np; idx += nthr) {
-        const int i = (int)(idx % np), j = (int)(idx / np);
-        if (j > i)
-            continue;
-        T v;
-        if (i < n && j < n)
-            v = (T)(((mu * d[i]) * A[i + (int64_t)j * n]) * d[j]);
-        else
-            v = (i == j) ? (T)1 : (T)0;
-        L[i + (int64_t)j * np] = v;
+    const int lane = tid & 63, wave = tid >> 6, nw = nthr / 64;
+    for (int j = wave; j < np; j += nw) {
+        const double dj = (j < n) ? d[j] : 0.0;
+        for (int i = j + lane; i < np; i += 64) {
+            T v;
+            if (i < n && j < n)
+                v = (T)(((mu * d[i]) * A[i + (int64_t)j * n]) * dj);
+            else
+                v = (i == j) ? (T)1 : (T)0;
+            L[i + (int64_t)j * np] = v;
+        }
     }
     __syncthreads();
 }
@@ -246,16 +250,19 @@ SPD_DEV int b_factor(T *L, int np, T *Winv, int half, BatchSmem &sm)
 
 // ---------------------------------------------------------------------------
 // X (+)= s mu D L^{-T} L^{-1} round(D R / s) for m right-hand sides; the
-// scales s_c = pow2_ceil(smax[c]) (smax in shared memory).
-template <typename T>
+// scales s_c = pow2_ceil(smax[c]) (smax in shared memory).  Every global
+// read is coalesced across lanes and issued in batches (no loop carries a
+// load-to-use dependency).
+template <typename T, int WAVES>
 SPD_DEV void b_solve(const T *L, const T *Winv, int n, int np, int m, const double *R, const double *d, double mu,
-                     double *X, int accumulate, BatchSmem &sm, int nthr)
+                     double *X, int accumulate, BatchSmem &sm)
 {
-    const int tid = threadIdx.x;
+    constexpr int NT = WAVES * 64, MR = SPD_BATCH_MAXRHS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nb = np / BNB;
     T *ys = (T *)sm.ys;  // ys[c * NMAX + i]
     constexpr int NM = SPD_BATCH_NMAX;
-    for (int idx = tid; idx < m * np; idx += nthr) {
+    for (int idx = tid; idx < m * np; idx += NT) {
         const int c = idx / np, i = idx % np;
         const double s = pow2_ceil(sm.smax[c]);
         ys[c * NM + i] = (i < n) ? (T)(d[i] * R[i + (int64_t)c * n] / s) : (T)0;
@@ -268,45 +275,88 @@ SPD_DEV void b_solve(const T *L, const T *Winv, int n, int np, int m, const doub
         T z = (T)0;
         if (tid < BNB * m) {
             const int r = tid % BNB, c = tid / BNB;
-            for (int q = 0; q <= r; ++q) z += W[r + q * BNB] * ys[c * NM + k0 + q];
+            T wv[BNB];
+#pragma unroll
+            for (int q = 0; q < BNB; ++q) wv[q] = W[r + q * BNB];
+#pragma unroll
+            for (int q = 0; q < BNB; ++q) z += wv[q] * ys[c * NM + k0 + q];  // W is zero above its diagonal
         }
         __syncthreads();
         if (tid < BNB * m)
             ys[(tid / BNB) * NM + k0 + tid % BNB] = z;
         __syncthreads();
-        const int rows = np - k0 - BNB;
-        for (int idx = tid; idx < rows * m; idx += nthr) {
-            const int i = k0 + BNB + idx % rows, c = idx / rows;
-            T s = (T)0;
-#pragma unroll 8
-            for (int q = 0; q < BNB; ++q) s += L[i + (int64_t)(k0 + q) * np] * ys[c * NM + k0 + q];
-            ys[c * NM + i] -= s;
+        for (int i = k0 + BNB + tid; i < np; i += NT) {
+            T lv[BNB];
+#pragma unroll
+            for (int q = 0; q < BNB; ++q) lv[q] = L[i + (int64_t)(k0 + q) * np];
+#pragma unroll
+            for (int c = 0; c < MR; ++c) {
+                if (c < m) {
+                    T sacc = (T)0;
+#pragma unroll
+                    for (int q = 0; q < BNB; ++q) sacc += lv[q] * ys[c * NM + k0 + q];
+                    ys[c * NM + i] -= sacc;
+                }
+            }
         }
         __syncthreads();
     }
-    // backward: x_k = W_k^T (y_k - L_below,k^T x_below)
+    // backward: x_k = W_k^T (y_k - L_below,k^T x_below); the column sums by
+    // wave (lanes over rows), one column q at a time
     T *ts = (T *)sm.ts;
     for (int kb = nb - 1; kb >= 0; --kb) {
-        const int k0 = kb * BNB;
+        const int k0 = kb * BNB, r0 = k0 + BNB;
         const T *W = Winv + (int64_t)kb * BNB * BNB;
-        if (tid < BNB * m) {
-            const int q = tid % BNB, c = tid / BNB;
-            T s = (T)0;
-            for (int i = k0 + BNB; i < np; ++i) s += L[i + (int64_t)(k0 + q) * np] * ys[c * NM + i];
-            ts[c * BNB + q] = s;
+        for (int q = wave; q < BNB; q += WAVES) {
+            T acc[MR];
+#pragma unroll
+            for (int c = 0; c < MR; ++c) acc[c] = (T)0;
+            const T *col = L + (int64_t)(k0 + q) * np;
+            for (int i0 = r0; i0 < np; i0 += 4 * 64) {
+                T lv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + 64 * u + lane;
+                    lv[u] = (i < np) ? col[i] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 + 64 * u + lane;
+                    if (i < np) {
+#pragma unroll
+                        for (int c = 0; c < MR; ++c)
+                            if (c < m)
+                                acc[c] += lv[u] * ys[c * NM + i];
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < MR; ++c) {
+                if (c < m) {
+                    T v = acc[c];
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                    if (lane == 0)
+                        ts[c * BNB + q] = v;
+                }
+            }
         }
         __syncthreads();
         T x = (T)0;
         if (tid < BNB * m) {
             const int r = tid % BNB, c = tid / BNB;
-            for (int q = r; q < BNB; ++q) x += W[q + r * BNB] * (ys[c * NM + k0 + q] - ts[c * BNB + q]);
+            T wv[BNB];
+#pragma unroll
+            for (int q = 0; q < BNB; ++q) wv[q] = W[q + r * BNB];
+#pragma unroll
+            for (int q = 0; q < BNB; ++q) x += wv[q] * (ys[c * NM + k0 + q] - ts[c * BNB + q]);
         }
         __syncthreads();
         if (tid < BNB * m)
             ys[(tid / BNB) * NM + k0 + tid % BNB] = x;
         __syncthreads();
     }
-    for (int idx = tid; idx < m * n; idx += nthr) {
+    for (int idx = tid; idx < m * n; idx += NT) {
         const int c = idx / n, i = idx % n;
         const double s = pow2_ceil(sm.smax[c]);
         const double z = ((s * mu) * d[i]) * (double)ys[c * NM + i];
@@ -319,63 +369,121 @@ SPD_DEV void b_solve(const T *L, const T *Winv, int n, int np, int m, const doub
 // ---------------------------------------------------------------------------
 // R = B - A X (binary64, A symmetric from its lower triangle) and the norms:
 // norms[1 + k m + c], k = 0..3: max|r|, max|x|, max|b|, max|d r|; with
-// want_anorm also norms[0] = ||A||_inf.  Rows: sum_{j <= i} a_ij x_j by
-// thread; columns: sum_{i > j} a_ij x_i by wave; then r = b - (row + col).
+// want_anorm also norms[0] = ||A||_inf.  X is staged in shared memory.
+// Rows: sum_{j <= i} a_ij x_j, lanes over rows, 16 columns per batch of
+// loads with the next batch in flight; columns: sum_{i > j} a_ij x_i, lane =
+// column, each lane streaming down its column (the second read of A comes
+// from the cache); r = b - (row + col).
 template <int WAVES>
 SPD_DEV void b_residual(const double *A, int n, int m, const double *X, const double *B, const double *d, double *R,
                         int want_anorm, BatchSmem &sm)
 {
-    constexpr int NT = WAVES * 64;
+    constexpr int NT = WAVES * 64, NM = SPD_BATCH_NMAX;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int MR = SPD_BATCH_MAXRHS;
-    double *abs_rows = (double *)sm.ys;  // row sums of |A| (binary64 scratch, n entries)
-    for (int i = tid; i < n; i += NT) {
-        double acc[MR], aa = 0.0;
-#pragma unroll
-        for (int c = 0; c < MR; ++c) acc[c] = 0.0;
-        for (int j = 0; j <= i; ++j) {
-            const double a = A[i + (int64_t)j * n];
-#pragma unroll
-            for (int c = 0; c < MR; ++c)
-                if (c < m)
-                    acc[c] = fma(a, X[j + (int64_t)c * n], acc[c]);
-            aa += fabs(a);
-        }
-#pragma unroll
-        for (int c = 0; c < MR; ++c)
-            if (c < m)
-                R[i + (int64_t)c * n] = acc[c];
-        if (want_anorm)
-            abs_rows[i] = aa;
+    double *xs = sm.ys;  // xs[c * NMAX + j]
+    double *abs_rows = sm.arow;
+    for (int idx = tid; idx < m * n; idx += NT) {
+        const int c = idx / n, j = idx % n;
+        xs[c * NM + j] = X[j + (int64_t)c * n];
     }
     __syncthreads();
-    for (int j = wave; j < n; j += WAVES) {
+    // row pass: 32-column chunks, the next chunk's loads in flight while the
+    // current one is used
+    constexpr int CH = 16;
+    for (int i0 = wave * 64; i0 < n; i0 += NT) {
+        const int i = i0 + lane;
+        const int jmax = min(i0 + 63, n - 1);
         double acc[MR], aa = 0.0;
 #pragma unroll
         for (int c = 0; c < MR; ++c) acc[c] = 0.0;
-        for (int i = j + 1 + lane; i < n; i += 64) {
-            const double a = A[i + (int64_t)j * n];
+        double a[CH], an[CH];
+        auto load = [&](double *dst, int j0) {
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int j = j0 + u;
+                dst[u] = (i < n && j <= i) ? A[i + (int64_t)j * n] : 0.0;
+            }
+        };
+        load(a, 0);
+        for (int j0 = 0; j0 <= jmax; j0 += CH) {
+            if (j0 + CH <= jmax)
+                load(an, j0 + CH);
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int j = min(j0 + u, n - 1);
+#pragma unroll
+                for (int c = 0; c < MR; ++c)
+                    if (c < m)
+                        acc[c] = fma(a[u], xs[c * NM + j], acc[c]);
+                if (want_anorm)
+                    aa += fabs(a[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) a[u] = an[u];
+        }
+        if (i < n) {
 #pragma unroll
             for (int c = 0; c < MR; ++c)
                 if (c < m)
-                    acc[c] = fma(a, X[i + (int64_t)c * n], acc[c]);
-            aa += fabs(a);
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-            for (int c = 0; c < MR; ++c) acc[c] += __shfl_xor(acc[c], off);
-            aa += __shfl_xor(aa, off);
-        }
-        if (lane == 0) {
-            for (int c = 0; c < m; ++c) {
-                const double y = R[j + (int64_t)c * n] + acc[c];
-                R[j + (int64_t)c * n] = B[j + (int64_t)c * n] - y;
-            }
+                    R[i + (int64_t)c * n] = acc[c];
             if (want_anorm)
-                abs_rows[j] += aa;
+                abs_rows[i] = aa;
         }
     }
+    __syncthreads();
+    // column pass: lane = column (64 columns per wavefront), each lane walks
+    // down its own column (contiguous), 16 rows per batch of loads with the
+    // next batch in flight; no cross-lane reduction
+    for (int j0 = wave * 64; j0 < n; j0 += NT) {
+        const int j = j0 + lane;
+        double acc[MR], aa = 0.0;
+#pragma unroll
+        for (int c = 0; c < MR; ++c) acc[c] = 0.0;
+        double a[CH], an[CH];
+        auto load = [&](double *dst, int i0) {
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int i = i0 + u;
+                dst[u] = (j < n && i > j && i < n) ? A[i + (int64_t)j * n] : 0.0;
+            }
+        };
+        const int ibeg = j0 + 1;
+        load(a, ibeg);
+        for (int i0 = ibeg; i0 < n; i0 += CH) {
+            if (i0 + CH < n)
+                load(an, i0 + CH);
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int i = min(i0 + u, n - 1);
+#pragma unroll
+                for (int c = 0; c < MR; ++c)
+                    if (c < m)
+                        acc[c] = fma(a[u], xs[c * NM + i], acc[c]);
+                if (want_anorm)
+                    aa += fabs(a[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) a[u] = an[u];
+        }
+        if (j < n) {
+#pragma unroll
+            for (int c = 0; c < MR; ++c)
+                if (c < m)
+                    sm.csum[c * NM + j] = acc[c];
+            if (want_anorm)
+                sm.cabs[j] = aa;
+        }
+    }
+    __syncthreads();
+    // r = b - (row + column sums)
+    for (int idx = tid; idx < m * n; idx += NT) {
+        const int c = idx / n, i = idx % n;
+        const double y = R[i + (int64_t)c * n] + sm.csum[c * NM + i];
+        R[i + (int64_t)c * n] = B[i + (int64_t)c * n] - y;
+    }
+    if (want_anorm)
+        for (int i = tid; i < n; i += NT) abs_rows[i] += sm.cabs[i];
     __syncthreads();
     // maxima (NaN propagates), per column, then ||A||_inf
     double v[4 * MR + 1];
@@ -387,7 +495,7 @@ SPD_DEV void b_residual(const double *A, int n, int m, const double *X, const do
             if (c < m) {
                 const double r = R[i + (int64_t)c * n];
                 v[c] = b_nanmax(v[c], fabs(r));
-                v[MR + c] = b_nanmax(v[MR + c], fabs(X[i + (int64_t)c * n]));
+                v[MR + c] = b_nanmax(v[MR + c], fabs(xs[c * NM + i]));
                 v[2 * MR + c] = b_nanmax(v[2 * MR + c], fabs(B[i + (int64_t)c * n]));
                 v[3 * MR + c] = b_nanmax(v[3 * MR + c], fabs(d[i] * r));
             }
@@ -396,6 +504,10 @@ SPD_DEV void b_residual(const double *A, int n, int m, const double *X, const do
     }
 #pragma unroll
     for (int k = 0; k < 4 * MR + 1; ++k) {
+        if (k < 4 * MR && (k % MR) >= m)
+            continue;
+        if (k == 4 * MR && !want_anorm)
+            continue;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v[k] = b_nanmax(v[k], __shfl_xor(v[k], off));
         if (lane == 0)
@@ -403,13 +515,16 @@ SPD_DEV void b_residual(const double *A, int n, int m, const double *X, const do
     }
     __syncthreads();
     if (tid < 4 * MR + 1) {
-        double x = 0.0;
-        for (int w = 0; w < WAVES; ++w) x = b_nanmax(x, sm.red[w][tid]);
         const int k = tid / MR, c = tid % MR;
         if (tid == 4 * MR) {
-            if (want_anorm)
+            if (want_anorm) {
+                double x = 0.0;
+                for (int w = 0; w < WAVES; ++w) x = b_nanmax(x, sm.red[w][tid]);
                 sm.norms[0] = x;
+            }
         } else if (c < m) {
+            double x = 0.0;
+            for (int w = 0; w < WAVES; ++w) x = b_nanmax(x, sm.red[w][tid]);
             sm.norms[1 + k * m + c] = x;
         }
     }
@@ -483,7 +598,7 @@ SPD_DEV int b_refine(const BatchArgs &a, const double *A, const double *B, doubl
         if (threadIdx.x < m)
             sm.smax[threadIdx.x] = sm.norms[1 + 3 * m + threadIdx.x];
         __syncthreads();
-        b_solve<T>((const T *)w.L, (const T *)w.Winv, n, np, m, w.R, w.d, mu, X, 1, sm, WAVES * 64);
+        b_solve<T, WAVES>((const T *)w.L, (const T *)w.Winv, n, np, m, w.R, w.d, mu, X, 1, sm);
         rep.iters_low++;
     }
 }
@@ -568,12 +683,11 @@ SPD_DEV void b_system(const BatchArgs &a, int64_t s, BatchSmem &sm)
             __syncthreads();
             int r;
             if (p == SPD_FP64) {
-                b_solve<double>((const double *)w.L, (const double *)w.Winv, n, np, m, B, w.d, mu, X, 0, sm,
-                                WAVES * 64);
+                b_solve<double, WAVES>((const double *)w.L, (const double *)w.Winv, n, np, m, B, w.d, mu, X, 0,
+                                       sm);
                 r = b_refine<double, WAVES>(a, A, B, X, n, np, m, w, mu, rep, sm);
             } else {
-                b_solve<float>((const float *)w.L, (const float *)w.Winv, n, np, m, B, w.d, mu, X, 0, sm,
-                               WAVES * 64);
+                b_solve<float, WAVES>((const float *)w.L, (const float *)w.Winv, n, np, m, B, w.d, mu, X, 0, sm);
                 r = b_refine<float, WAVES>(a, A, B, X, n, np, m, w, mu, rep, sm);
             }
             need_solve = false;
@@ -682,10 +796,8 @@ hipError_t launch_batch(const BatchLaunch &l, hipStream_t st)
     a.ws = (char *)l.ws;
     a.ws_stride = batch_ws_stride();
     hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, st, l.batch, l.n, l.order, l.queue);
-    if (l.waves == 8)
-        hipLaunchKernelGGL(k_batch<8>, dim3((unsigned)l.grid), dim3(512), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_batch<4>, dim3((unsigned)l.grid), dim3(256), 0, st, a);
+    (void)l.waves;  // four wavefronts per workgroup (larger workgroups spill)
+    hipLaunchKernelGGL(k_batch<4>, dim3((unsigned)l.grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

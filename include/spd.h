@@ -161,6 +161,58 @@ spd_status spd_solve_batched(int64_t batch, const int32_t *n, const int32_t *nrh
                              const double *B, double *X, spd_prec *prec, const spd_opts *o,
                              spd_report *reps, void *hip_stream);
 
+/* spd_solve_batched that also writes ticks[s] (device, int64): the
+ * wall-clock ticks (100 MHz) that system s took, from its first step
+ * (including the picker for SPD_AUTO) to its report. */
+spd_status spd_solve_batched_timed(int64_t batch, const int32_t *n, const int32_t *nrhs,
+                                   const int64_t *a_off, const double *A, const int64_t *b_off,
+                                   const double *B, double *X, spd_prec *prec, const spd_opts *o,
+                                   spd_report *reps, int64_t *ticks, void *hip_stream);
+
+/* ---- Learned precision picker (not in the paper: it chooses the precision
+ * Algorithm 1 runs in, per system, for SPD_AUTO in the batched solver; FP64
+ * stays the fallback).  A perceptron 16 -> 64 -> 64 -> 4 (ReLU, softmax over
+ * BF16, FP16, FP32, FP64), binary32 parameters as one flat vector of
+ * SPD_PICKER_NPARAM: W1 (64 x 16), b1 (64), W2 (64 x 64), b2 (64), W3 (4 x 64),
+ * b3 (4), matrices row-major [out][in].  Features (16 per system, binary64
+ * arithmetic, stored binary32), with d_i = a_ii^{-1/2} (1 where a_ii <= 0),
+ * H = D A D, r_i = sum_{j != i} |h_ij| and theta the Ritz values of four
+ * Lanczos steps on H from (1, ..., 1)/sqrt(n) (no reorthogonalisation; stop
+ * when beta <= 1e-12 max(|alpha|, 1)):
+ *   log2(n)/9, m/8, spread, mean and std of log10 a_ii (/6, /6, /3),
+ *   log10(1 + max r)/3, log10(1 + mean r)/3, share of rows with r < 1,
+ *   clip(1 - max r, -10, 1)/10, log10 theta_max/3, log10 max(theta_min, 1e-16)/6,
+ *   log10(theta_max / max(theta_min, 1e-16))/6, max off-diagonal |h|,
+ *   log10(||H||_F / sqrt(n))/3, last beta / theta_max (0 after an early stop),
+ *   (theta_2 - theta_1)/(theta_max - theta_1) (0 with fewer than 3 values). */
+#define SPD_PICKER_NFEAT 16
+#define SPD_PICKER_NPARAM 5508
+
+/* Parameters (device pointer, copied) used by SPD_AUTO from now on on the
+ * current device; NULL switches the picker off (AUTO then means FP32). */
+spd_status spd_picker_set(const float *params, void *hip_stream);
+
+/* Features of every system of a packed batch (layout as spd_solve_batched):
+ * feat (device) receives batch x 16 floats, row-major; systems outside
+ * 1 <= n <= SPD_BATCH_NMAX get zeros. */
+spd_status spd_picker_features(int64_t batch, const int32_t *n, const int32_t *nrhs,
+                               const int64_t *a_off, const double *A, float *feat, void *hip_stream);
+
+/* Logits (device, N x 4) of the perceptron for samples X (device, N x 16). */
+spd_status spd_mlp_forward(const float *params, const float *X, int64_t N, float *logits,
+                           void *hip_stream);
+
+/* Gradient (device, SPD_PICKER_NPARAM) of the mean softmax cross-entropy
+ * over the N samples with labels y (device, int32 in 0..3), and the loss
+ * (device scalar, or NULL).  Sums over samples in a fixed order.  Allocates
+ * (and synchronises) when N grows past the largest N seen. */
+spd_status spd_mlp_grad(const float *params, const float *X, const int32_t *y, int64_t N,
+                        float *grad, float *loss, void *hip_stream);
+
+/* One Adam step (step >= 1; bias-corrected moments m, v, updated in place). */
+spd_status spd_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t count,
+                        int32_t step, float lr, float beta1, float beta2, float eps, void *hip_stream);
+
 /* Launch shape the batched solver chose for this batch size on the current
  * device (workgroups of the persistent grid, waves per workgroup);
  * SPD_ERR_INVALID_ARG if no call with that batch size has been made yet. */

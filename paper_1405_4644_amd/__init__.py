@@ -62,6 +62,13 @@ _SIGS = [
     ("spd_residual", C.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _vp]),
     ("spd_solve_batched", C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Opts), _vp, _vp]),
     ("spd_batched_config", C.c_int, [_i64, C.POINTER(_i32), C.POINTER(_i32)]),
+    ("spd_solve_batched_timed", C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Opts), _vp, _vp,
+                                          _vp]),
+    ("spd_picker_set", C.c_int, [_vp, _vp]),
+    ("spd_picker_features", C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    ("spd_mlp_forward", C.c_int, [_vp, _vp, _i64, _vp, _vp]),
+    ("spd_mlp_grad", C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    ("spd_mlp_adam", C.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
     ("spd_factor_destroy", None, [_vp]),
     ("spd_factor_query", C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32)]),
     ("spd_factor_export", C.c_int, [_vp, _vp, _i64, _vp, C.POINTER(_f64), _vp]),
@@ -320,18 +327,92 @@ class Batch:
         return np.frombuffer(raw.tobytes(), dtype=_report_dtype())
 
 
-def solve_batched(bt: Batch, opts: Opts | None = None, check=True) -> int:
+def solve_batched(bt: Batch, opts: Opts | None = None, check=True, ticks=None) -> int:
     """Every system of the batch through Algorithm 1 in one persistent launch
     (asynchronous; the first call for a batch size also autotunes and
-    synchronises).  Per-system outcomes: bt.reports(), bt.prec."""
-    st = load().spd_solve_batched(bt.batch, C.c_void_p(bt.n.data_ptr()), C.c_void_p(bt.nrhs.data_ptr()),
-                                  C.c_void_p(bt.a_off.data_ptr()), C.c_void_p(bt.A.data_ptr()),
-                                  C.c_void_p(bt.b_off.data_ptr()), C.c_void_p(bt.B.data_ptr()),
-                                  C.c_void_p(bt.X.data_ptr()), C.c_void_p(bt.prec.data_ptr()),
-                                  C.byref(opts) if opts else None, C.c_void_p(bt.reps.data_ptr()), _stream())
+    synchronises).  Per-system outcomes: bt.reports(), bt.prec; with `ticks`
+    (int64 CUDA tensor of batch entries) also each system's wall-clock ticks."""
+    args = (bt.batch, C.c_void_p(bt.n.data_ptr()), C.c_void_p(bt.nrhs.data_ptr()),
+            C.c_void_p(bt.a_off.data_ptr()), C.c_void_p(bt.A.data_ptr()),
+            C.c_void_p(bt.b_off.data_ptr()), C.c_void_p(bt.B.data_ptr()),
+            C.c_void_p(bt.X.data_ptr()), C.c_void_p(bt.prec.data_ptr()),
+            C.byref(opts) if opts else None, C.c_void_p(bt.reps.data_ptr()))
+    if ticks is None:
+        st = load().spd_solve_batched(*args, _stream())
+    else:
+        st = load().spd_solve_batched_timed(*args, C.c_void_p(ticks.data_ptr()), _stream())
     if check and st != OK:
         raise SPDError(st, "spd_solve_batched")
     return st
+
+
+# ---- learned precision picker --------------------------------------------------
+PICKER_NFEAT, PICKER_NPARAM = 16, 5508
+
+
+def _f32(t, name, numel=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements")
+
+
+def picker_set(params=None):
+    """Use these perceptron parameters for SPD_AUTO (None: switch the picker off)."""
+    if params is None:
+        st = load().spd_picker_set(None, _stream())
+    else:
+        _f32(params, "params", PICKER_NPARAM)
+        st = load().spd_picker_set(C.c_void_p(params.data_ptr()), _stream())
+    if st != OK:
+        raise SPDError(st, "spd_picker_set")
+
+
+def picker_features(bt: Batch):
+    torch = _torch()
+    feat = torch.empty((bt.batch, PICKER_NFEAT), dtype=torch.float32, device=bt.n.device)
+    st = load().spd_picker_features(bt.batch, C.c_void_p(bt.n.data_ptr()), C.c_void_p(bt.nrhs.data_ptr()),
+                                    C.c_void_p(bt.a_off.data_ptr()), C.c_void_p(bt.A.data_ptr()),
+                                    C.c_void_p(feat.data_ptr()), _stream())
+    if st != OK:
+        raise SPDError(st, "spd_picker_features")
+    return feat
+
+
+def mlp_forward(params, X):
+    torch = _torch()
+    _f32(params, "params", PICKER_NPARAM)
+    _f32(X, "X")
+    out = torch.empty((X.shape[0], 4), dtype=torch.float32, device=X.device)
+    st = load().spd_mlp_forward(C.c_void_p(params.data_ptr()), C.c_void_p(X.data_ptr()), X.shape[0],
+                                C.c_void_p(out.data_ptr()), _stream())
+    if st != OK:
+        raise SPDError(st, "spd_mlp_forward")
+    return out
+
+
+def mlp_grad(params, X, y):
+    """(gradient, loss) of the mean cross-entropy; both CUDA tensors."""
+    torch = _torch()
+    _f32(params, "params", PICKER_NPARAM)
+    _f32(X, "X")
+    if y.dtype != torch.int32 or not y.is_cuda:
+        raise TypeError("y must be an int32 CUDA tensor")
+    g = torch.empty(PICKER_NPARAM, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    st = load().spd_mlp_grad(C.c_void_p(params.data_ptr()), C.c_void_p(X.data_ptr()), C.c_void_p(y.data_ptr()),
+                             X.shape[0], C.c_void_p(g.data_ptr()), C.c_void_p(loss.data_ptr()), _stream())
+    if st != OK:
+        raise SPDError(st, "spd_mlp_grad")
+    return g, loss
+
+
+def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    st = load().spd_mlp_adam(C.c_void_p(params.data_ptr()), C.c_void_p(grad.data_ptr()), C.c_void_p(m.data_ptr()),
+                             C.c_void_p(v.data_ptr()), params.numel(), int(step), lr, beta1, beta2, eps, _stream())
+    if st != OK:
+        raise SPDError(st, "spd_mlp_adam")
 
 
 def batched_config(batch: int):

@@ -519,6 +519,10 @@ struct BatchEntry {
 struct BatchCtx {
     void *ws = nullptr;
     std::map<int64_t, BatchEntry> per_batch;
+    float *picker = nullptr;  // perceptron parameters (device), kept until the process ends
+    bool picker_on = false;
+    float *mlp_scratch = nullptr;  // gradient partials of spd_mlp_grad
+    size_t cap_mlp = 0;
 };
 std::mutex g_batch_mu;
 BatchCtx g_batch[kMaxDevices];
@@ -770,9 +774,9 @@ spd_status spd_residual(const double *A, int64_t n, int64_t lda, const double *X
     return map_err(e);
 }
 
-spd_status spd_solve_batched(int64_t batch, const int32_t *n, const int32_t *nrhs, const int64_t *a_off,
-                             const double *A, const int64_t *b_off, const double *B, double *X, spd_prec *prec,
-                             const spd_opts *o, spd_report *reps, void *hip_stream)
+static spd_status solve_batched_impl(int64_t batch, const int32_t *n, const int32_t *nrhs, const int64_t *a_off,
+                              const double *A, const int64_t *b_off, const double *B, double *X, spd_prec *prec,
+                              const spd_opts *o, spd_report *reps, void *hip_stream, int64_t *ticks)
 {
     if (batch < 0) return SPD_ERR_INVALID_ARG;
     if (batch == 0) return SPD_OK;
@@ -814,6 +818,8 @@ spd_status spd_solve_batched(int64_t batch, const int32_t *n, const int32_t *nrh
     l.fallback = op.fallback;
     l.equilibrate = op.equilibrate;
     l.ws = c.ws;
+    l.picker = c.picker_on ? c.picker : nullptr;
+    l.ticks = ticks;
     if (it == c.per_batch.end()) {
         BatchEntry e;
         HIP_TRY(hipMalloc(&e.order, (size_t)batch * sizeof(int32_t) + 256));
@@ -864,6 +870,87 @@ spd_status spd_solve_batched(int64_t batch, const int32_t *n, const int32_t *nrh
     l.order = it->second.order;
     l.queue = it->second.queue;
     HIP_TRY(spd::launch_batch(l, st));
+    return SPD_OK;
+}
+
+spd_status spd_solve_batched(int64_t batch, const int32_t *n, const int32_t *nrhs, const int64_t *a_off,
+                             const double *A, const int64_t *b_off, const double *B, double *X, spd_prec *prec,
+                             const spd_opts *o, spd_report *reps, void *hip_stream)
+{
+    return solve_batched_impl(batch, n, nrhs, a_off, A, b_off, B, X, prec, o, reps, hip_stream, nullptr);
+}
+
+spd_status spd_solve_batched_timed(int64_t batch, const int32_t *n, const int32_t *nrhs, const int64_t *a_off,
+                                   const double *A, const int64_t *b_off, const double *B, double *X, spd_prec *prec,
+                                   const spd_opts *o, spd_report *reps, int64_t *ticks, void *hip_stream)
+{
+    if (!ticks && batch > 0) return SPD_ERR_INVALID_ARG;
+    return solve_batched_impl(batch, n, nrhs, a_off, A, b_off, B, X, prec, o, reps, hip_stream, ticks);
+}
+
+spd_status spd_picker_set(const float *params, void *hip_stream)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return SPD_ERR_DEVICE;
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    BatchCtx &c = g_batch[dev];
+    if (!params) {
+        c.picker_on = false;
+        return SPD_OK;
+    }
+    if (!c.picker) HIP_TRY(hipMalloc(&c.picker, SPD_PICKER_NPARAM * sizeof(float)));
+    HIP_TRY(hipMemcpyAsync(c.picker, params, SPD_PICKER_NPARAM * sizeof(float), hipMemcpyDeviceToDevice,
+                           (hipStream_t)hip_stream));
+    c.picker_on = true;
+    return SPD_OK;
+}
+
+spd_status spd_picker_features(int64_t batch, const int32_t *n, const int32_t *nrhs, const int64_t *a_off,
+                               const double *A, float *feat, void *hip_stream)
+{
+    if (batch < 0) return SPD_ERR_INVALID_ARG;
+    if (batch == 0) return SPD_OK;
+    if (!n || !nrhs || !a_off || !A || !feat) return SPD_ERR_INVALID_ARG;
+    spd::launch_features(batch, n, nrhs, a_off, A, feat, (hipStream_t)hip_stream);
+    HIP_TRY(hipGetLastError());
+    return SPD_OK;
+}
+
+spd_status spd_mlp_forward(const float *params, const float *X, int64_t N, float *logits, void *hip_stream)
+{
+    if (N < 0 || (N > 0 && (!params || !X || !logits))) return SPD_ERR_INVALID_ARG;
+    spd::launch_mlp_forward(params, X, N, logits, (hipStream_t)hip_stream);
+    HIP_TRY(hipGetLastError());
+    return SPD_OK;
+}
+
+spd_status spd_mlp_grad(const float *params, const float *X, const int32_t *y, int64_t N, float *grad,
+                        float *loss, void *hip_stream)
+{
+    if (N <= 0 || !params || !X || !y || !grad) return SPD_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return SPD_ERR_DEVICE;
+    std::lock_guard<std::mutex> g(g_batch_mu);
+    BatchCtx &c = g_batch[dev];
+    void *p = c.mlp_scratch;
+    size_t cap = c.cap_mlp;
+    SPD_TRY(grow(&p, &cap, (size_t)spd::mlp_grad_scratch(N) * sizeof(float), false, st));
+    c.mlp_scratch = (float *)p;
+    c.cap_mlp = cap;
+    spd::launch_mlp_grad(params, X, y, N, grad, loss, c.mlp_scratch, st);
+    HIP_TRY(hipGetLastError());
+    return SPD_OK;
+}
+
+spd_status spd_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t count, int32_t step, float lr,
+                        float beta1, float beta2, float eps, void *hip_stream)
+{
+    if (count < 0 || step < 1 || (count > 0 && (!params || !grad || !m || !v))) return SPD_ERR_INVALID_ARG;
+    spd::launch_adam(params, grad, m, v, count, step, lr, beta1, beta2, eps, (hipStream_t)hip_stream);
+    HIP_TRY(hipGetLastError());
     return SPD_OK;
 }
 

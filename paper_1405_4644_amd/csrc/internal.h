@@ -107,8 +107,21 @@ struct BatchLaunch {
     int *queue;      // one int of scratch
     void *ws;        // grid * batch_ws_stride() bytes
     int grid, waves;
+    const float *picker = nullptr;  // perceptron parameters for SPD_AUTO, or NULL
+    int64_t *ticks = nullptr;       // per-system wall-clock ticks, or NULL
 };
 int64_t batch_ws_stride();
 hipError_t launch_batch(const BatchLaunch &l, hipStream_t st);
+// picker features of every system (16 floats each)
+void launch_features(int64_t batch, const int32_t *n, const int32_t *nrhs, const int64_t *a_off, const double *A,
+                     float *feat, hipStream_t st);
+// perceptron training kernels (k_picker.hip); parameters as in spd.h
+#define PICK_NPARAM 5508
+void launch_mlp_forward(const float *P, const float *X, int64_t N, float *logits, hipStream_t st);
+int64_t mlp_grad_scratch(int64_t N);
+void launch_mlp_grad(const float *P, const float *X, const int32_t *y, int64_t N, float *grad, float *loss,
+                     float *scratch, hipStream_t st);
+void launch_adam(float *P, const float *g, float *m, float *v, int64_t count, int step, float lr, float b1, float b2,
+                 float eps, hipStream_t st);
 
 }  // namespace spd

@@ -18,6 +18,11 @@
 #include "internal.h"
 
 #define BNB 32  // panel and tile width
+// precision picker: 16 features -> 64 -> 64 -> 4 classes (BF16, FP16, FP32, FP64)
+#define PICK_NFEAT 16
+#define PICK_NH 64
+#define PICK_NCLS 4
+#define PICK_LANCZOS 4
 
 struct BatchArgs {
     int64_t batch;
@@ -33,6 +38,8 @@ struct BatchArgs {
     int *queue;
     char *ws;
     int64_t ws_stride;
+    const float *picker;  // perceptron parameters for SPD_AUTO (NULL: binary32)
+    int64_t *ticks;       // optional: wall-clock ticks of each system's solve
 };
 
 // workspace slice of one workgroup
@@ -70,6 +77,9 @@ struct BatchSmem {
     double arow[SPD_BATCH_NMAX];  // row sums of |A|
     double csum[SPD_BATCH_MAXRHS * SPD_BATCH_NMAX];  // residual: column-pass sums
     double cabs[SPD_BATCH_NMAX];
+    float feat[PICK_NFEAT];
+    float hid[2][PICK_NH];
+    float logit[PICK_NCLS];
     int info;
 };
 
@@ -531,6 +541,300 @@ SPD_DEV void b_residual(const double *A, int n, int m, const double *X, const do
     __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Precision picker (a project addition around Algorithm 1: which precision to
+// run it in).  Features of one system, in binary64, by the workgroup:
+// d_i = a_ii^{-1/2} (1 where a_ii <= 0), H = D A D, r_i = sum_{j != i} |h_ij|;
+// four Lanczos steps on H from (1, ..., 1)/sqrt(n) without
+// reorthogonalisation (stopping early when beta <= 1e-12 max(|alpha|, 1));
+// theta = eigenvalues of the tridiagonal (bisection on Sturm counts).
+//   f0 log2(n)/9, f1 m/8, f2..f4 spread/mean/std of log10 a_ii (/6, /6, /3),
+//   f5 log10(1 + max r)/3, f6 log10(1 + mean r)/3, f7 share of rows r < 1,
+//   f8 clip(1 - max r, -10, 1)/10, f9 log10 theta_max/3,
+//   f10 log10 max(theta_min, 1e-16)/6, f11 log10(theta_max/max(theta_min, 1e-16))/6,
+//   f12 max off-diagonal |h_ij|, f13 log10(||H||_F/sqrt(n))/3,
+//   f14 last beta/theta_max (0 after an early stop),
+//   f15 (theta_2 - theta_1)/(theta_max - theta_1) (0 with fewer than 3 values).
+
+// block reduction of NV values per thread, fixed order (wave butterflies,
+// then waves in order); op 0 = sum, 1 = max, 2 = min.  Result in every thread.
+template <int WAVES, int NV>
+SPD_DEV void b_reduce(double v[NV], const int op[NV], BatchSmem &sm)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(v[k], off);
+            v[k] = op[k] == 0 ? v[k] + o : op[k] == 1 ? fmax(v[k], o) : fmin(v[k], o);
+        }
+        if (lane == 0)
+            sm.red[wave][k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = sm.red[0][k];
+        for (int w = 1; w < WAVES; ++w) {
+            const double o = sm.red[w][k];
+            x = op[k] == 0 ? x + o : op[k] == 1 ? fmax(x, o) : fmin(x, o);
+        }
+        v[k] = x;
+    }
+    __syncthreads();
+}
+
+// y = H v (v, y in shared memory), H = D A D from the lower triangle of A.
+// With first: rs[i] = r_i, and per thread the partial max off-diagonal |h|
+// and sum of h^2 (each stored element once, off-diagonal ones counted twice).
+template <int WAVES>
+SPD_DEV void b_hv(const double *A, int n, const double *d, const double *v, double *y, double *rs, bool first,
+                  double &hmax, double &fro, BatchSmem &sm)
+{
+    constexpr int NT = WAVES * 64, CH = 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *ycol = sm.csum, *rcol = sm.cabs;
+    // rows: sum_{j <= i} h_ij v_j
+    for (int i0 = wave * 64; i0 < n; i0 += NT) {
+        const int i = i0 + lane;
+        const int jmax = min(i0 + 63, n - 1);
+        const double di = (i < n) ? d[i] : 0.0;
+        double acc = 0.0, ra = 0.0;
+        for (int j0 = 0; j0 <= jmax; j0 += CH) {
+            double a[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int j = j0 + u;
+                a[u] = (i < n && j <= i) ? A[i + (int64_t)j * n] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int j = min(j0 + u, n - 1);
+                const double h = (di * a[u]) * d[j];
+                acc = fma(h, v[j], acc);
+                if (first && i < n && j0 + u < i) {
+                    ra += fabs(h);
+                    hmax = fmax(hmax, fabs(h));
+                    fro += 2.0 * h * h;
+                } else if (first && i < n && j0 + u == i) {
+                    fro += h * h;
+                }
+            }
+        }
+        if (i < n) {
+            y[i] = acc;
+            if (first)
+                rs[i] = ra;
+        }
+    }
+    // columns: lane = column, sum_{i > j} h_ij v_i
+    for (int j0 = wave * 64; j0 < n; j0 += NT) {
+        const int j = j0 + lane;
+        const double dj = (j < n) ? d[j] : 0.0;
+        double acc = 0.0, ca = 0.0;
+        for (int i0 = j0 + 1; i0 < n; i0 += CH) {
+            double a[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int i = i0 + u;
+                a[u] = (j < n && i > j && i < n) ? A[i + (int64_t)j * n] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int i = min(i0 + u, n - 1);
+                const double h = (d[i] * a[u]) * dj;
+                acc = fma(h, v[i], acc);
+                if (first)
+                    ca += fabs(h);
+            }
+        }
+        if (j < n) {
+            ycol[j] = acc;
+            if (first)
+                rcol[j] = ca;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) {
+        y[i] += ycol[i];
+        if (first)
+            rs[i] += rcol[i];
+    }
+    __syncthreads();
+}
+
+// eigenvalues (ascending) of the k x k symmetric tridiagonal (al, be), k <= 4
+SPD_DEV int sturm_below(const double *al, const double *be, int k, double x)
+{
+    int c = 0;
+    double q = al[0] - x;
+    if (q < 0)
+        ++c;
+    for (int i = 1; i < k; ++i) {
+        if (q == 0.0)
+            q = 1e-300;
+        q = (al[i] - x) - be[i - 1] * be[i - 1] / q;
+        if (q < 0)
+            ++c;
+    }
+    return c;
+}
+
+template <int WAVES>
+SPD_DEV void b_features(const double *A, int n, int m, BatchSmem &sm)
+{
+    constexpr int NT = WAVES * 64, NM = SPD_BATCH_NMAX, K = PICK_LANCZOS;
+    const int tid = threadIdx.x;
+    double *d = sm.arow;
+    double *v = sm.ys, *vp = sm.ys + NM, *w = sm.ys + 2 * NM, *rs = sm.ys + 3 * NM;
+    // diagonal statistics
+    double st[4] = {0.0, -1e300, 1e300, 0.0};  // sum, max, min of log10|a_ii|
+    const int ops3[3] = {0, 1, 2};
+    for (int i = tid; i < n; i += NT) {
+        const double a = A[i + (int64_t)i * n];
+        d[i] = (a > 0.0) ? 1.0 / sqrt(a) : 1.0;
+        const double la = log10(fmax(fabs(a), 1e-300));
+        st[0] += la;
+        st[1] = fmax(st[1], la);
+        st[2] = fmin(st[2], la);
+        v[i] = 1.0 / sqrt((double)n);
+        vp[i] = 0.0;
+    }
+    b_reduce<WAVES, 3>(st, ops3, sm);
+    const double mean_la = st[0] / n;
+    double sq[1] = {0.0};
+    const int ops1[1] = {0};
+    for (int i = tid; i < n; i += NT) {
+        const double la = log10(fmax(fabs(A[i + (int64_t)i * n]), 1e-300)) - mean_la;
+        sq[0] += la * la;
+    }
+    b_reduce<WAVES, 1>(sq, ops1, sm);
+    // Lanczos; the first product also yields the Gershgorin radii and |H| stats
+    double al[K], be[K];
+    int k = 0;
+    bool early = false;
+    double hmax = 0.0, fro = 0.0;
+    double bprev = 0.0;
+    for (int j = 0; j < K; ++j) {
+        b_hv<WAVES>(A, n, d, v, w, rs, j == 0, hmax, fro, sm);
+        double a1[1] = {0.0};
+        for (int i = tid; i < n; i += NT) a1[0] += w[i] * v[i];
+        b_reduce<WAVES, 1>(a1, ops1, sm);
+        const double alpha = a1[0];
+        double b2[1] = {0.0};
+        for (int i = tid; i < n; i += NT) {
+            const double x = (w[i] - alpha * v[i]) - bprev * vp[i];
+            w[i] = x;
+            b2[0] += x * x;
+        }
+        b_reduce<WAVES, 1>(b2, ops1, sm);
+        const double beta = sqrt(b2[0]);
+        al[j] = alpha;
+        k = j + 1;
+        if (j == K - 1) {
+            be[j] = beta;
+            break;
+        }
+        if (beta <= 1e-12 * fmax(fabs(alpha), 1.0)) {
+            be[j] = 0.0;
+            early = true;
+            break;
+        }
+        be[j] = beta;
+        for (int i = tid; i < n; i += NT) {
+            vp[i] = v[i];
+            v[i] = w[i] / beta;
+        }
+        bprev = beta;
+        __syncthreads();
+    }
+    // Gershgorin statistics of H and the |H| statistics (first product)
+    double gs[5] = {-1e300, 0.0, 0.0, hmax, fro};  // max r, sum r, count r < 1, max |h|, ||H||_F^2
+    const int ops5[5] = {1, 0, 0, 1, 0};
+    for (int i = tid; i < n; i += NT) {
+        gs[0] = fmax(gs[0], rs[i]);
+        gs[1] += rs[i];
+        gs[2] += (rs[i] < 1.0) ? 1.0 : 0.0;
+    }
+    b_reduce<WAVES, 5>(gs, ops5, sm);
+    if (tid == 0) {
+        // Ritz values by bisection
+        double lo = al[0], hi = al[0];
+        for (int i = 0; i < k; ++i) {
+            const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i + 1 < k ? fabs(be[i]) : 0.0);
+            lo = fmin(lo, al[i] - r);
+            hi = fmax(hi, al[i] + r);
+        }
+        double th[K];
+        for (int q = 0; q < k; ++q) {
+            double a = lo, b = hi;
+            for (int it = 0; it < 200; ++it) {
+                const double mid = 0.5 * (a + b);
+                if (mid <= a || mid >= b)
+                    break;
+                if (sturm_below(al, be, k, mid) > q)
+                    b = mid;
+                else
+                    a = mid;
+            }
+            th[q] = 0.5 * (a + b);
+        }
+        const double tmin = th[0], tmax = th[k - 1];
+        double f[PICK_NFEAT];
+        f[0] = log2((double)n) / 9.0;
+        f[1] = m / 8.0;
+        f[2] = (st[1] - st[2]) / 6.0;
+        f[3] = mean_la / 6.0;
+        f[4] = sqrt(sq[0] / n) / 3.0;
+        f[5] = log10(1.0 + gs[0]) / 3.0;
+        f[6] = log10(1.0 + gs[1] / n) / 3.0;
+        f[7] = gs[2] / n;
+        f[8] = fmin(fmax(1.0 - gs[0], -10.0), 1.0) / 10.0;
+        f[9] = log10(tmax) / 3.0;
+        f[10] = log10(fmax(tmin, 1e-16)) / 6.0;
+        f[11] = log10(tmax / fmax(tmin, 1e-16)) / 6.0;
+        f[12] = (n > 1) ? gs[3] : 0.0;
+        f[13] = log10(sqrt(gs[4]) / sqrt((double)n)) / 3.0;
+        f[14] = early ? 0.0 : be[k - 1] / tmax;
+        f[15] = (k >= 3 && tmax > th[0]) ? (th[1] - th[0]) / (tmax - th[0]) : 0.0;
+        for (int q = 0; q < PICK_NFEAT; ++q) sm.feat[q] = (float)f[q];
+    }
+    __syncthreads();
+}
+
+// the perceptron on sm.feat: class with the largest logit (the first on ties)
+SPD_DEV int b_pick(const float *P, BatchSmem &sm)
+{
+    const float *W1 = P, *b1 = W1 + PICK_NH * PICK_NFEAT, *W2 = b1 + PICK_NH, *b2 = W2 + PICK_NH * PICK_NH,
+                *W3 = b2 + PICK_NH, *b3 = W3 + PICK_NCLS * PICK_NH;
+    const int t = threadIdx.x;
+    if (t < PICK_NH) {
+        float z = b1[t];
+        for (int k = 0; k < PICK_NFEAT; ++k) z += W1[t * PICK_NFEAT + k] * sm.feat[k];
+        sm.hid[0][t] = fmaxf(z, 0.0f);
+    }
+    __syncthreads();
+    if (t < PICK_NH) {
+        float z = b2[t];
+        for (int k = 0; k < PICK_NH; ++k) z += W2[t * PICK_NH + k] * sm.hid[0][k];
+        sm.hid[1][t] = fmaxf(z, 0.0f);
+    }
+    __syncthreads();
+    if (t < PICK_NCLS) {
+        float z = b3[t];
+        for (int k = 0; k < PICK_NH; ++k) z += W3[t * PICK_NH + k] * sm.hid[1][k];
+        sm.logit[t] = z;
+    }
+    __syncthreads();
+    int best = 0;
+    for (int c = 1; c < PICK_NCLS; ++c)
+        if (sm.logit[c] > sm.logit[best])
+            best = c;
+    __syncthreads();
+    return best;
+}
+
 SPD_DEV int b_next_prec(int p) { return (p == SPD_BF16 || p == SPD_FP16) ? SPD_FP32 : SPD_FP64; }
 
 // Refinement at the precision of the current factor (T), from the iterate in
@@ -640,10 +944,17 @@ SPD_DEV void b_system(const BatchArgs &a, int64_t s, BatchSmem &sm)
     rep.iters_low = rep.iters_high = rep.fallbacks = 0;
     rep.info = 0;
     rep.eta = 0.0;
+    const unsigned long long t0 = wall_clock64();
     int p = a.prec[s];
-    if (p == SPD_AUTO)
+    const bool sizes_ok = n >= 0 && m >= 0 && n <= SPD_BATCH_NMAX && m <= SPD_BATCH_MAXRHS;
+    if (p == SPD_AUTO) {
         p = SPD_FP32;
-    if (n < 0 || m < 0 || n > SPD_BATCH_NMAX || m > SPD_BATCH_MAXRHS || p < SPD_BF16 || p > SPD_FP64) {
+        if (a.picker && sizes_ok && n > 0 && m > 0) {
+            b_features<WAVES>(a.A + a.a_off[s], n, m, sm);
+            p = b_pick(a.picker, sm);
+        }
+    }
+    if (!sizes_ok || p < SPD_BF16 || p > SPD_FP64) {
         rep.status = SPD_ERR_INVALID_ARG;
     } else if (n > 0 && m > 0) {
         const double *A = a.A + a.a_off[s];
@@ -711,6 +1022,8 @@ SPD_DEV void b_system(const BatchArgs &a, int64_t s, BatchSmem &sm)
     if (threadIdx.x == 0) {
         a.reps[s] = rep;
         a.prec[s] = rep.prec_used;
+        if (a.ticks)
+            a.ticks[s] = (int64_t)(wall_clock64() - t0);
     }
 }
 
@@ -727,6 +1040,25 @@ __global__ __launch_bounds__(WAVES * 64) void k_batch(BatchArgs a)
         if (q >= a.batch)
             return;
         b_system<WAVES>(a, a.order[q], sm);
+        __syncthreads();
+    }
+}
+
+// Features of every system (one workgroup each), for training the picker.
+__global__ __launch_bounds__(256) void k_features(int64_t batch, const int32_t *__restrict__ n,
+                                                  const int32_t *__restrict__ nrhs, const int64_t *__restrict__ a_off,
+                                                  const double *__restrict__ A, float *__restrict__ feat)
+{
+    __shared__ BatchSmem sm;
+    for (int64_t s = blockIdx.x; s < batch; s += gridDim.x) {
+        const int ns = n[s], ms = nrhs[s];
+        if (ns >= 1 && ns <= SPD_BATCH_NMAX) {
+            b_features<4>(A + a_off[s], ns, ms, sm);
+            if (threadIdx.x < PICK_NFEAT)
+                feat[s * PICK_NFEAT + threadIdx.x] = sm.feat[threadIdx.x];
+        } else if (threadIdx.x < PICK_NFEAT) {
+            feat[s * PICK_NFEAT + threadIdx.x] = 0.0f;
+        }
         __syncthreads();
     }
 }
@@ -795,10 +1127,20 @@ hipError_t launch_batch(const BatchLaunch &l, hipStream_t st)
     a.queue = l.queue;
     a.ws = (char *)l.ws;
     a.ws_stride = batch_ws_stride();
+    a.picker = l.picker;
+    a.ticks = l.ticks;
     hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, st, l.batch, l.n, l.order, l.queue);
     (void)l.waves;  // four wavefronts per workgroup (larger workgroups spill)
     hipLaunchKernelGGL(k_batch<4>, dim3((unsigned)l.grid), dim3(256), 0, st, a);
     return hipGetLastError();
+}
+
+void launch_features(int64_t batch, const int32_t *n, const int32_t *nrhs, const int64_t *a_off, const double *A,
+                     float *feat, hipStream_t st)
+{
+    if (batch <= 0) return;
+    const unsigned grid = (unsigned)(batch < 2048 ? batch : 2048);
+    hipLaunchKernelGGL(k_features, dim3(grid), dim3(256), 0, st, batch, n, nrhs, a_off, A, feat);
 }
 
 }  // namespace spd

@@ -1,0 +1,142 @@
+"""GPU parity of the precision picker's kernels against the picker oracle:
+features (binary64 on both sides, stored binary32 by the GPU: |diff| <=
+2e-6 max(1, |f|)), perceptron logits (binary32 vs binary64: 1e-5 relative to
+the logit scale), gradient and loss (binary32 sums over the samples:
+1e-4 of the largest gradient entry), Adam steps (1e-6 relative); the batched
+solver's SPD_AUTO choice equals the oracle network's argmax on the oracle
+features wherever the top two logits differ by more than 1e-3; and a
+training run on the GPU kernels fits a separable problem."""
+import sys
+
+import numpy as np
+import pytest
+
+import spdgen
+from oracle import picker as pk
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cuda(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _batch(spd, pb, prec="fp32"):
+    import torch
+    return spd.Batch(_cuda(pb.n, torch.int32), _cuda(pb.m, torch.int32), _cuda(pb.a_off, torch.int64),
+                     _cuda(pb.A, torch.float64), _cuda(pb.b_off, torch.int64), _cuda(pb.B, torch.float64), prec=prec)
+
+
+def _matrices(pb):
+    for s in range(len(pb.n)):
+        n = int(pb.n[s])
+        yield pb.A[pb.a_off[s]:pb.a_off[s] + n * n].reshape(n, n), int(pb.m[s])
+
+
+def test_features_match_oracle(spd):
+    shapes = [(1, 1e1, 1), (2, 1e2, 2), (6, 1e1, 1), (40, 1e1, 3), (33, 1e3, 1), (100, 1e5, 8), (257, 1e2, 2),
+              (512, 1e6, 1), (64, 1e4, 4)]
+    pb = spdgen.packed_batch(shapes, config=3, first_index=7000)
+    # special structure: 2 x tridiagonal (exact H), identity, a diagonal matrix
+    n = 6
+    pb.A[pb.a_off[2]:pb.a_off[2] + n * n] = (2.0 * spdgen.tridiag(n)).reshape(-1)
+    pb.A[pb.a_off[3]:pb.a_off[3] + 1600] = np.eye(40).reshape(-1)
+    pb.A[pb.a_off[8]:pb.a_off[8] + 64 * 64] = np.diag(np.logspace(0, 3, 64)).reshape(-1)
+    bt = _batch(spd, pb)
+    f = spd.picker_features(bt).cpu().numpy()
+    for s, (A, m) in enumerate(_matrices(pb)):
+        fo = pk.features(A, m)
+        err = np.abs(f[s] - fo)
+        _say(s, shapes[s][:2], "max |diff|", err.max())
+        assert np.all(err <= 2e-6 * np.maximum(1.0, np.abs(fo))), (s, f[s], fo)
+
+
+def _params(seed, scale=0.3):
+    return np.random.Generator(np.random.PCG64(seed)).normal(0, scale, pk.NPARAM)
+
+
+def test_mlp_forward_matches_oracle(spd):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(3))
+    X = rng.normal(0, 1, (1000, 16))
+    p = _params(4)
+    z = spd.mlp_forward(_cuda(p, torch.float32), _cuda(X, torch.float32)).cpu().numpy()
+    zo = pk.mlp_forward(p.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64))
+    scale = max(1.0, np.abs(zo).max())
+    assert np.abs(z - zo).max() <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("N", [777, 64, 5])
+def test_mlp_grad_matches_oracle(spd, N):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(N))
+    X = rng.normal(0, 1, (N, 16)).astype(np.float32).astype(np.float64)
+    y = rng.integers(0, 4, N)
+    p = _params(5).astype(np.float32).astype(np.float64)
+    g, loss = spd.mlp_grad(_cuda(p, torch.float32), _cuda(X, torch.float32), _cuda(y, torch.int32))
+    g = g.cpu().numpy()
+    lo, go = pk.mlp_loss_grad(p, X, y)
+    _say(N, "loss", float(loss.item()), lo, "max |dg|", np.abs(g - go).max(), "max |g|", np.abs(go).max())
+    assert abs(float(loss.item()) - lo) <= 1e-5 * max(1.0, lo)
+    assert np.abs(g - go).max() <= 1e-4 * np.abs(go).max() + 1e-7
+
+
+def test_adam_matches_oracle(spd):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(9))
+    p = rng.normal(0, 1, pk.NPARAM)
+    m = np.zeros(pk.NPARAM)
+    v = np.zeros(pk.NPARAM)
+    pt, mt, vt = (_cuda(a, torch.float32) for a in (p, m, v))
+    for t in range(1, 6):
+        g = rng.normal(0, 1e-2, pk.NPARAM)
+        p, m, v = pk.adam_step(p, g, m, v, t, lr=1e-3)
+        spd.mlp_adam(pt, _cuda(g, torch.float32), mt, vt, t, lr=1e-3)
+    assert np.allclose(pt.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+    assert np.allclose(vt.cpu().numpy(), v, rtol=1e-4, atol=1e-12)
+
+
+def test_training_on_gpu_fits_separable_problem(spd):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(11))
+    X = rng.normal(0, 1, (4096, 16))
+    y = np.argmax(X[:, :4] + 0.5 * X[:, 4:8], axis=1)
+    Xt, yt = _cuda(X, torch.float32), _cuda(y, torch.int32)
+    p = _cuda(_params(12, 0.2), torch.float32)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    losses = []
+    for t in range(1, 301):
+        g, loss = spd.mlp_grad(p, Xt, yt)
+        spd.mlp_adam(p, g, m, v, t, lr=3e-3)
+        if t % 50 == 0:
+            losses.append(float(loss.item()))
+    acc = float((spd.mlp_forward(p, Xt).argmax(dim=1) == yt.long()).float().mean())
+    _say("losses", losses, "train accuracy", acc)
+    assert losses[-1] < 0.5 * losses[0] and acc > 0.9
+
+
+def test_auto_picks_oracle_argmax(spd):
+    import torch
+    shapes = [(40 + 30 * k, 10 ** (1 + 0.5 * k), 1 + k % 3) for k in range(10)]
+    pb = spdgen.packed_batch(shapes, config=3, first_index=8000)
+    p = _params(21, 0.5)
+    spd.picker_set(_cuda(p, torch.float32))
+    try:
+        bt = _batch(spd, pb, prec="auto")
+        spd.solve_batched(bt, spd.default_opts(fallback=0))
+        used = bt.prec.cpu().numpy()
+    finally:
+        spd.picker_set(None)
+    p32 = p.astype(np.float32).astype(np.float64)
+    for s, (A, m) in enumerate(_matrices(pb)):
+        z = pk.mlp_forward(p32, pk.features(A, m).astype(np.float32).astype(np.float64)[None, :])[0]
+        top = np.sort(z)[::-1]
+        if top[0] - top[1] > 1e-3:
+            assert used[s] == int(np.argmax(z)), (s, used[s], z)

@@ -369,6 +369,21 @@ def picker_set(params=None):
         raise SPDError(st, "spd_picker_set")
 
 
+PICKER_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "picker_weights.npz")
+
+
+def picker_load(path: str | None = None):
+    """Load trained perceptron parameters (default: the ones trained by
+    paper_1405_4644_amd.picker_train and shipped with the package) and use
+    them for SPD_AUTO; returns the parameter tensor."""
+    import numpy as np
+    torch = _torch()
+    with np.load(path or PICKER_WEIGHTS, allow_pickle=False) as z:
+        params = torch.from_numpy(np.ascontiguousarray(z["params"], dtype=np.float32)).cuda()
+    picker_set(params)
+    return params
+
+
 def picker_features(bt: Batch):
     torch = _torch()
     feat = torch.empty((bt.batch, PICKER_NFEAT), dtype=torch.float32, device=bt.n.device)

@@ -140,3 +140,47 @@ def test_auto_picks_oracle_argmax(spd):
         top = np.sort(z)[::-1]
         if top[0] - top[1] > 1e-3:
             assert used[s] == int(np.argmax(z)), (s, used[s], z)
+
+
+def test_trained_picker_gains_over_fixed_fp32(spd):
+    """The shipped network against the method without it (always FP32 with the
+    fallback chain) on held-out systems of the batched workload's distribution:
+    picks judged against the measured outcome table (label rule of the
+    oracle), cost = measured device time of the picked run (plus the FP64 run
+    when a pick fails).  Gain: parity unpinned (the paper has no picker)."""
+    import os
+    import torch
+    if not os.path.exists(spd.PICKER_WEIGHTS):
+        pytest.skip("no trained picker shipped")
+    shapes = spdgen.batch_shapes(4096, config=3)[:384]
+    pb = spdgen.packed_batch(shapes, config=3, backend="torch", device="cuda")
+    bt = spd.Batch(_cuda(pb.n, torch.int32), _cuda(pb.m, torch.int32), _cuda(pb.a_off, torch.int64), pb.A,
+                   _cuda(pb.b_off, torch.int64), pb.B, prec="fp32")
+    tk = torch.zeros(bt.batch, dtype=torch.int64, device="cuda")
+    nofb = spd.default_opts(fallback=0)
+    conv = np.zeros((bt.batch, 4), dtype=bool)
+    ticks = np.zeros((bt.batch, 4))
+    for k, p in enumerate(("bf16", "fp16", "fp32", "fp64")):
+        bt.prec.fill_(spd.PREC[p])
+        spd.solve_batched(bt, nofb, ticks=tk)
+        conv[:, k] = bt.reports()["status"] == 0
+        ticks[:, k] = tk.cpu().numpy()
+    labels = np.array([pk.label(conv[s], ticks[s]) for s in range(bt.batch)])
+    spd.picker_load()
+    try:
+        bt.prec.fill_(spd.PREC["auto"])
+        spd.solve_batched(bt, nofb)
+        picks = bt.prec.cpu().numpy()
+        bt.prec.fill_(spd.PREC["auto"])
+        spd.solve_batched(bt)  # with the fallback chain: everything converges
+        assert np.all(bt.reports()["status"] == 0)
+    finally:
+        spd.picker_set(None)
+    idx = np.arange(bt.batch)
+    cost = lambda pick: (ticks[idx, pick] + np.where(conv[idx, pick], 0.0, ticks[:, 3])).sum()
+    mispick = float(np.mean(picks != labels))
+    ratio = cost(picks) / cost(np.full(bt.batch, 2))
+    _say("labels", np.bincount(labels, minlength=4), "picks", np.bincount(picks, minlength=4),
+         "mispick rate", mispick, "cost vs fixed FP32", ratio)
+    assert mispick <= 0.1
+    assert ratio < 0.95

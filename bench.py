@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -78,6 +80,71 @@ def cpu_baseline_leg(args, A_dev, X_dev, B_dev):
              "eta_lower_bound_rows": eta_rows})
 
 
+def batched_leg(args, spd, spdgen, torch):
+    """The many-small-systems workload: 4096 SPD systems, n ~ U{32..512},
+    cond ~ 10^U(1, 6), 1..8 right-hand sides, each through Algorithm 1 in one
+    persistent launch: FP32 (+ FP64 refinement), FP64 in the same kernel, the
+    shipped picker (AUTO), and a host loop of single-system FP64 solves."""
+    t0 = time.perf_counter()
+    shapes = spdgen.batch_shapes(args.batch, config=3)
+    pb = spdgen.packed_batch(shapes, config=3, backend="torch", device="cuda")
+    tt = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dt).cuda()
+    bt = spd.Batch(tt(pb.n, torch.int32), tt(pb.m, torch.int32), tt(pb.a_off, torch.int64), pb.A,
+                   tt(pb.b_off, torch.int64), pb.B, prec="fp32")
+    torch.cuda.synchronize()
+    log(f"batched: generated {args.batch} systems in {time.perf_counter() - t0:.1f} s")
+    flops = float(sum(algo_flops(n, m) for n, _, m in shapes))
+
+    def timed(prec, picker=False, reps=5):
+        if picker:
+            spd.picker_load()
+        try:
+            bt.prec.fill_(spd.PREC[prec])
+            spd.solve_batched(bt)  # warm (first call: workspace + launch shape)
+            ts = []
+            for _ in range(reps):
+                bt.prec.fill_(spd.PREC[prec])
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                spd.solve_batched(bt)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+        finally:
+            if picker:
+                spd.picker_set(None)
+        r = bt.reports()
+        return {"ms": float(np.median(ts)) * 1e3, "all_ok": bool((r["status"] == 0).all()),
+                "iters_low_mean": float(r["iters_low"].mean()),
+                "prec_used": np.bincount(r["prec_used"], minlength=4).tolist(),
+                "eff_TFLOPs": flops / float(np.median(ts)) / 1e12}
+
+    out = {"workload": f"{args.batch} SPD systems, n ~ U{{32..512}}, cond ~ 10^U(1,6), 1..8 RHS",
+           "fp32": timed("fp32"), "fp64_same_kernel": timed("fp64")}
+    import os as _os
+    if _os.path.exists(spd.PICKER_WEIGHTS):
+        out["auto_picker"] = timed("auto", picker=True)
+    out["launch_shape"] = spd.batched_config(args.batch)
+    # host loop of single-system FP64 solves over a bounded sample, scaled
+    k = min(args.batch, args.loop_sample)
+    F = spd.Factor()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for s in range(k):
+        n, m = int(pb.n[s]), int(pb.m[s])
+        A = pb.A[pb.a_off[s]:pb.a_off[s] + n * n].view(n, n)
+        B = pb.B[pb.b_off[s]:pb.b_off[s] + n * m].view(m, n)
+        spd.posv(A, B, prec="fp64", F=F)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    F.close()
+    out["fp64_host_loop"] = {"ms": dt * 1e3 * args.batch / k, "sample_systems": k,
+                             "note": "spd_posv(FP64) per system in a host loop, time scaled to the batch"}
+    out["speedup_fp32_vs_loop"] = out["fp64_host_loop"]["ms"] / out["fp32"]["ms"]
+    log(f"batched: fp32 {out['fp32']['ms']:.2f} ms, fp64 {out['fp64_same_kernel']['ms']:.2f} ms, "
+        f"loop {out['fp64_host_loop']['ms']:.1f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +157,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the binary64 baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=8192)
+    ap.add_argument("--no-batched", action="store_true", help="skip the many-small-systems leg")
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--loop-sample", type=int, default=512)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -151,6 +221,8 @@ def main():
                 "status": rep64.status}
         log(f"fp64: {dt64 * 1e3:.2f} ms/solve, eta {rep64.eta:.2e}")
 
+    batched = None if args.no_batched else batched_leg(args, spd, spdgen, torch)
+
     cpu = None
     ocheck = None
     if not args.no_cpu_baseline:
@@ -186,6 +258,7 @@ def main():
                      "fwd_err_vs_xtrue": fwd, "fwd_bound_10cond_u": fwd_bound, "oracle_rows": ocheck},
         "fp64_baseline": fp64,
         "speedup_vs_fp64": (fp64["ms_per_step"] / (dt * 1e3)) if fp64 else None,
+        "batched": batched,
         "residual_kernel": {"launches": res[0], "avg_ms": res[1] / max(res[0], 1),
                             "achieved_GBs": (res[3] / res[1] / 1e6) if res[1] > 0 else None,
                             "hbm_peak_GBs": HBM_PEAK_GBS},

@@ -80,6 +80,24 @@ def cpu_baseline_leg(args, A_dev, X_dev, B_dev):
              "eta_lower_bound_rows": eta_rows})
 
 
+def measured_traffic(prec):
+    """HBM bytes per launch of the update kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when
+    there is none for this precision or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"pmc_k_syrk_update_{prec}_n16384.json")  # written from rocprofv3 --pmc runs
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_1405_4644_amd", "csrc", "k_factor.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def batched_leg(args, spd, spdgen, torch):
     """The many-small-systems workload: 4096 SPD systems, n ~ U{32..512},
     cond ~ 10^U(1, 6), 1..8 right-hand sides, each through Algorithm 1 in one
@@ -160,6 +178,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the many-small-systems leg")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--loop-sample", type=int, default=512)
+    ap.add_argument("--input", choices=["logspaced", "dominant"], default="logspaced",
+                    help="logspaced: Q diag(lambda) Q^T (the workload); dominant: (R + R^T)/2 + n I with R ~ U(-1, 1), "
+                         "same sizes, no QR (for hardware-counter runs, whose traffic does not depend on the values)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes 3 times (calibrates HBM counters) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -170,6 +193,15 @@ def main():
 
     import torch
 
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": args.calibrate_copy, "copies": 3}), flush=True)
+        return
+
     import paper_1405_4644_amd as spd
     import spdgen
 
@@ -178,7 +210,13 @@ def main():
     n, m, cond = args.n, args.nrhs, args.cond
     t0 = time.perf_counter()
     sg, sx = spdgen.seeds(1, 0)
-    A = spdgen.logspaced(n, cond, sg, backend="torch", device="cuda")
+    if args.input == "dominant":
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(sg)
+        A = torch.rand(n, n, dtype=torch.float64, device="cuda", generator=gen) * 2.0 - 1.0
+        A = 0.5 * (A + A.T) + n * torch.eye(n, dtype=torch.float64, device="cuda")
+    else:
+        A = spdgen.logspaced(n, cond, sg, backend="torch", device="cuda")
     Xt = spdgen.rhs(n, m, sx, backend="torch", device="cuda")
     B = spdgen.accurate_product(A, Xt)
     torch.cuda.synchronize()
@@ -229,6 +267,7 @@ def main():
         cpu, ocheck = cpu_baseline_leg(args, A, X, B)
 
     launches, ms, fl, by = upd
+    traffic = measured_traffic(args.prec)
     achieved = fl / ms / 1e9 if ms > 0 else 0.0  # TFLOP/s
     peak = PEAK_TFLOPS[args.prec]
     out = {
@@ -248,7 +287,7 @@ def main():
                                f"orthogonal Q), {m} RHS, {args.prec} factor + binary64 refinement",
                    "n": n, "nrhs": m, "cond": cond, "prec": args.prec},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
                      "kernel": "k_syrk_update<float>" if args.prec == "fp32" else "k_syrk_update",
                      "launches": launches, "avg_launch_ms": ms / max(launches, 1),
                      "flops_per_launch": fl / max(launches, 1),

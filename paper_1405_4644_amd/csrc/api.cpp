@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -38,6 +39,8 @@ struct spd_factor_s {
     int64_t cap_d = 0;
     double mu = 1.0;
     int half = HALF_NONE;    // operand rounding of the trailing update (BF16 / FP16 factors)
+    int group = 4;           // panels per trailing-update group (SPD_GROUP overrides)
+    int upd_slots = 0;       // cap on the main-stream update's workgroups (SPD_UPD_SLOTS; 0: one per tile)
     void *Lh = nullptr;      // two panel copies in that precision (npad x NB halves each)
     size_t cap_Lh = 0;
     unsigned long long *info_dev = nullptr;
@@ -207,54 +210,76 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
     T *H = (T *)F->L;
     T *Wi = (T *)F->Winv;
     const int64_t wi_blk = (NB / SPD_IB_H) * SPD_IB_H * SPD_IB_H;
-    const int tcols = (int)(NB / SPD_TILE_H);
-    hipEvent_t evU = F->ev[0], evP = F->ev[1], evQ = F->ev[2];
-    // half-precision operand copies of panels k (even / odd), written by the
-    // panel solve and read by both parts of the update
+    hipEvent_t evU = F->ev[0], evP = F->ev[1];
+    // Panels are factored one by one (NB wide) but the trailing update is
+    // applied per group of G panels (K = G NB), which halves the C-tile
+    // traffic per flop at G = 2.  Lookahead is one group.
     const int half = (sizeof(T) == 4) ? F->half : HALF_NONE;
+    const int64_t G = half ? std::min<int64_t>(F->group, 2) : F->group;
+    const int64_t ng = (nt + G - 1) / G;
     const int op_elem = half ? 2 : (int)sizeof(T);
+    // half-precision operand copies of panels k mod 4 (two groups), written by
+    // the panel solve and read by the updates
     auto lh = [&](int64_t k) -> void * {
-        return half ? (void *)((char *)F->Lh + (size_t)(k & 1) * npad * NB * 2) : nullptr;
+        return half ? (void *)((char *)F->Lh + (size_t)(k & 3) * npad * NB * 2) : nullptr;
     };
-    auto update = [&](int64_t k, int t, int lo, int hi, hipStream_t s, int prio) {
-        const int64_t k0 = k * NB, r0 = k0 + NB;
-        if (half)
-            spd::launch_syrk_update_half((float *)H, npad, lh(k), half, r0, t, lo, hi, F->info_dev, s, prio);
-        else
-            spd::launch_syrk_update<T>(H, npad, k0, (int)NB, r0, t, lo, hi, F->info_dev, s, prio);
+    // H -= L_{.,[p0,p1)} L_{.,[p0,p1)}^T on tile columns [lo, hi) of the
+    // region starting at row/column r0
+    // the main stream's updates use at most F->upd_slots workgroups (looping
+    // over tiles), so that the panel chain always finds free slots
+    auto update = [&](int64_t p0, int64_t p1, int64_t r0, int lo, int hi, hipStream_t s, int prio) {
+        const int cap = (s == st) ? F->upd_slots : 0;
+        const int t = (int)((npad - r0) / SPD_TILE_H);
+        if (t <= 0 || lo >= hi) return;
+        hipEvent_t pe = prof_begin(s);
+        if (half) {
+            // copy of panel p starts at row (p + 1) NB
+            const int sk0 = (int)((r0 - (p0 + 1) * NB) / SPD_IB_H);
+            const void *l1 = (p1 - p0 > 1) ? lh(p0 + 1) : nullptr;
+            const int sk1 = (p1 - p0 > 1) ? (int)((r0 - (p0 + 2) * NB) / SPD_IB_H) : 0;
+            spd::launch_syrk_update_half((float *)H, npad, lh(p0), sk0, l1, sk1, half, r0, t, lo, hi, F->info_dev, s,
+                                         prio, cap);
+        } else {
+            spd::launch_syrk_update<T>(H, npad, p0 * NB, (int)((p1 - p0) * NB), r0, t, lo, hi, F->info_dev, s, prio,
+                                       cap);
+        }
+        if (pe) {
+            double fl, by;
+            update_work(t, lo, hi, (int)((p1 - p0) * NB), (int)sizeof(T), op_elem, &fl, &by);
+            prof_end(pe, s, SPD_K_UPDATE, fl, by);
+        }
+    };
+    // the panel chain of group g: factor each panel, solve the rows below it,
+    // and update the group's remaining panels with it
+    auto chain = [&](int64_t g, hipStream_t s) {
+        const int64_t p1 = std::min<int64_t>((g + 1) * G, nt);
+        for (int64_t k = g * G; k < p1; ++k) {
+            const int64_t r = k * NB;
+            spd::launch_potrf_diag<T>(H + r + r * npad, npad, r, Wi + k * wi_blk, F->info_dev, s);
+            spd::launch_trsm_panel<T>(H, npad, r, r + NB, npad - r - NB, Wi + k * wi_blk, F->info_dev, s, lh(k),
+                                      half);
+            if (k + 1 < p1) update(k, k + 1, r + NB, 0, (int)((p1 - k - 1) * (NB / SPD_TILE_H)), s, 1);
+        }
     };
 
-    spd::launch_potrf_diag<T>(H, npad, 0, Wi, F->info_dev, st);
-    spd::launch_trsm_panel<T>(H, npad, 0, NB, npad - NB, Wi, F->info_dev, st, lh(0), half);
-    if (nt > 1) {
+    // Main stream, per group g: wait for its panels, update the next group's
+    // columns first (the whole GPU, recorded as evU), then the rest.  Side
+    // stream: after evU, the next group's panel chain (recorded as evP), which
+    // overlaps the main stream's update of the rest.
+    chain(0, st);
+    if (ng > 1) {
         HIP_TRY(hipEventRecord(evP, st));
-        for (int64_t k = 0; k + 1 < nt; ++k) {
-            const int64_t k0 = k * NB, r0 = k0 + NB;
+        for (int64_t g = 0; g + 1 < ng; ++g) {
+            const int64_t p0 = g * G, p1 = std::min<int64_t>(p0 + G, nt), r0 = p1 * NB;
+            const int next = (int)((std::min<int64_t>(p1 + G, nt) - p1) * (NB / SPD_TILE_H));
             const int t = (int)((npad - r0) / SPD_TILE_H);
-            // lookahead: next panel on the side stream
-            HIP_TRY(hipStreamWaitEvent(F->side, evP, 0));
-            if (k > 0) HIP_TRY(hipStreamWaitEvent(F->side, evU, 0));
-            double fl, by;
-            hipEvent_t pa = prof_begin(F->side);
-            update(k, t, 0, tcols, F->side, 1);
-            if (pa) {
-                update_work(t, 0, tcols, (int)NB, (int)sizeof(T), op_elem, &fl, &by);
-                prof_end(pa, F->side, SPD_K_UPDATE, fl, by);
-            }
-            spd::launch_potrf_diag<T>(H + r0 + r0 * npad, npad, r0, Wi + (k + 1) * wi_blk, F->info_dev, F->side);
-            spd::launch_trsm_panel<T>(H, npad, r0, r0 + NB, npad - r0 - NB, Wi + (k + 1) * wi_blk, F->info_dev,
-                                      F->side, lh(k + 1), half);
-            HIP_TRY(hipEventRecord(evQ, F->side));
-            // the rest of the trailing update on the main stream
             HIP_TRY(hipStreamWaitEvent(st, evP, 0));
-            hipEvent_t pb = prof_begin(st);
-            update(k, t, tcols, t, st, 0);
-            if (pb) {
-                update_work(t, tcols, t, (int)NB, (int)sizeof(T), op_elem, &fl, &by);
-                prof_end(pb, st, SPD_K_UPDATE, fl, by);
-            }
+            update(p0, p1, r0, 0, next, st, 1);
             HIP_TRY(hipEventRecord(evU, st));
-            std::swap(evP, evQ);
+            HIP_TRY(hipStreamWaitEvent(F->side, evU, 0));
+            chain(g + 1, F->side);
+            HIP_TRY(hipEventRecord(evP, F->side));
+            update(p0, p1, r0, next, t, st, 0);
         }
         HIP_TRY(hipStreamWaitEvent(st, evP, 0));
     }
@@ -301,7 +326,7 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
     F->half = (prec == SPD_FP16) ? HALF_F16 : (prec == SPD_BF16) ? HALF_BF16 : HALF_NONE;
     if (F->half) {
         size_t caph = F->cap_Lh;
-        SPD_TRY(grow(&F->Lh, &caph, (size_t)2 * npad * F->nb * 2, false, st));
+        SPD_TRY(grow(&F->Lh, &caph, (size_t)4 * npad * F->nb * 2, false, st));
         F->cap_Lh = caph;
     }
     const int equil = (prec != SPD_FP64 && o.equilibrate) ? 1 : 0;
@@ -611,6 +636,8 @@ spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec, co
         *F = new (std::nothrow) spd_factor_s();
         if (!*F) return SPD_ERR_OUT_OF_MEMORY;
         created = true;
+        if (const char *e = std::getenv("SPD_GROUP")) (*F)->group = std::max(1, std::min(8, std::atoi(e)));
+        if (const char *e = std::getenv("SPD_UPD_SLOTS")) (*F)->upd_slots = std::max(0, std::atoi(e));
         if (hipGetDevice(&(*F)->device) != hipSuccess) {
             delete *F;
             *F = nullptr;

@@ -36,11 +36,14 @@ void launch_trsm_panel(T *H, int64_t ld, int64_t k0, int64_t row0, int64_t nrows
                        const unsigned long long *info, hipStream_t st, void *Lh = nullptr, int half = HALF_NONE);
 template <typename T>
 void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,
-                        const unsigned long long *info, hipStream_t st, int prio = 0);
-// Trailing update with binary16 / bfloat16 operands from the panel copy Lh
-// (rows r0.. of the panel, K = 128), binary32 accumulation into H.
-void launch_syrk_update_half(float *H, int64_t ld, const void *Lh, int half, int64_t r0, int t, int tj_lo,
-                             int tj_hi, const unsigned long long *info, hipStream_t st, int prio = 0);
+                        const unsigned long long *info, hipStream_t st, int prio = 0, int max_grid = 0);
+// Trailing update with binary16 / bfloat16 operands from the panel copies
+// Lh0 and (if not NULL) Lh1, K = 128 each, binary32 accumulation into H; in
+// copy p, skip_p 32-row blocks precede row r0.
+void launch_syrk_update_half(float *H, int64_t ld, const void *Lh0, int skip0, const void *Lh1, int skip1, int half,
+                             int64_t r0, int t, int tj_lo, int tj_hi, const unsigned long long *info, hipStream_t st,
+                             int prio = 0, int max_grid = 0);
+// max_grid > 0 caps the workgroups (multiple of 8); they then loop over tiles
 template <typename T>
 void launch_trtri_blocks(const T *H, int64_t ld, int64_t nt, const T *Winv, T *W, hipStream_t st);
 

@@ -374,14 +374,18 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
         return;
     if (prio)
         __builtin_amdgcn_s_setprio(2);  // the lookahead part of the update
-    const int per = gridDim.x / 8;
-    const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    // tiles of XCD x (blocks are dispatched round-robin over the 8 XCDs) are
+    // the contiguous range [x chunk, (x + 1) chunk); a grid smaller than the
+    // tile count loops (persistent), leaving compute-unit slots free
+    const int per = gridDim.x / 8, chunk = (ntiles + 7) / 8;
+    for (int it = blockIdx.x / 8; it < chunk; it += per) {
+    const int logical = (blockIdx.x % 8) * chunk + it;
     if (logical >= ntiles)
-        return;
+        break;
     int ti, tj;
     decode_tile(logical, t, tj_lo, tj_hi, ti, tj);
     if (ti < 0)
-        return;
+        break;
     const int64_t crow = r0 + (int64_t)ti * SPD_TILE, ccol = r0 + (int64_t)tj * SPD_TILE;
     const T *pa = H + ccol + k0 * ld;  // rows of tile tj (D rows = C columns)
     const T *pb = H + crow + k0 * ld;  // rows of tile ti (D columns = C rows)
@@ -443,6 +447,9 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
         // prefetch the next chunk (the last iteration re-reads its own chunk)
         const int kn = (kb + KC < nbk) ? kb + KC : kb;
         SPD_GLOAD(kn);
+        // keep the next chunk's loads here, ahead of the MFMAs (the scheduler
+        // would otherwise sink them to their LDS stores and expose their latency)
+        __builtin_amdgcn_sched_barrier(0);
         const T *a0 = &As[buf][64 * wm];
         const T *b0 = &Bs[buf][64 * wn];
 #pragma unroll
@@ -460,6 +467,7 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
                 for (int ni = 0; ni < 2; ++ni)
                     mma(acc[mi][ni], fa[mi], fb[ni]);
         }
+        __builtin_amdgcn_sched_barrier(0);
         SPD_SSTORE(buf ^ 1);
         __syncthreads();
         buf ^= 1;
@@ -475,12 +483,14 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
                 const int m = Acc32<T>::row(j, lane), nn = Acc32<T>::col(j, lane);
                 H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld] = acc[mi][ni].get(j);
             }
+    __syncthreads();  // shared memory is reused by the next tile
+    }
 }
 
 // ---------------------------------------------------------------------------
 // K4, half-precision operands: H_ij -= round(L_ik) round(L_jk)^T with
 // binary16 or bfloat16 operands and binary32 accumulation
-// (v_mfma_f32_32x32x16_{f16,bf16}), K = NB = 128.  The operand panel is the
+// (v_mfma_f32_32x32x16_{f16,bf16}), one or two panels of K = 128.  The operand panel is the
 // fragment-layout copy written by the panel solve: row r (relative to the
 // first trailing row), column k lives at
 //   ((r/32) (NB/16) + k/16) * 512 + (32 ((k%16)/8) + r%32) * 8 + k%8,
@@ -488,9 +498,10 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
 // only HBM traffic that scales with the tile count: 64 KiB in, 64 KiB out.
 template <int HK>
 __global__ __launch_bounds__(256) void k_syrk_update_h(float *__restrict__ H, int64_t ld,
-                                                       const void *__restrict__ Lh, int64_t r0, int t, int tj_lo,
-                                                       int tj_hi, int ntiles, const unsigned long long *info,
-                                                       int prio)
+                                                       const void *__restrict__ Lh0, int skip0,
+                                                       const void *__restrict__ Lh1, int skip1, int64_t r0, int t,
+                                                       int tj_lo, int tj_hi, int ntiles,
+                                                       const unsigned long long *info, int prio)
 {
     using V8 = typename HalfT<HK>::V8;
     constexpr int KS = 128 / 16;
@@ -499,28 +510,20 @@ __global__ __launch_bounds__(256) void k_syrk_update_h(float *__restrict__ H, in
         return;
     if (prio)
         __builtin_amdgcn_s_setprio(2);
-    const int per = gridDim.x / 8;
-    const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    // tiles of XCD x (blocks are dispatched round-robin over the 8 XCDs) are
+    // the contiguous range [x chunk, (x + 1) chunk); a grid smaller than the
+    // tile count loops (persistent), leaving compute-unit slots free
+    const int per = gridDim.x / 8, chunk = (ntiles + 7) / 8;
+    for (int it = blockIdx.x / 8; it < chunk; it += per) {
+    const int logical = (blockIdx.x % 8) * chunk + it;
     if (logical >= ntiles)
-        return;
+        break;
     int ti, tj;
     decode_tile(logical, t, tj_lo, tj_hi, ti, tj);
     if (ti < 0)
-        return;
+        break;
     const int64_t crow = r0 + (int64_t)ti * SPD_TILE, ccol = r0 + (int64_t)tj * SPD_TILE;
     const int wm = wave >> 1, wn = wave & 1;
-    const V8 *lh = (const V8 *)Lh;
-    // A operand: rows of tile tj (C columns); B operand: rows of tile ti (C rows)
-    const V8 *pa0 = lh + (size_t)(4 * tj + 2 * wm) * KS * 64 + lane;
-    const V8 *pb0 = lh + (size_t)(4 * ti + 2 * wn) * KS * 64 + lane;
-    V8 fa[KS][2], fb[KS][2];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            fa[ks][q] = pa0[(q * KS + ks) * 64];
-            fb[ks][q] = pb0[(q * KS + ks) * 64];
-        }
     floatx16 acc[2][2];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
@@ -531,14 +534,35 @@ __global__ __launch_bounds__(256) void k_syrk_update_h(float *__restrict__ H, in
                 const int m = Acc32<float>::row(j, lane), nn = Acc32<float>::col(j, lane);
                 acc[mi][ni][j] = H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld];
             }
+    // one or two panels (K = 128 each); `skip` 32-row blocks precede row r0
+    // in a panel's copy
+    for (int pnl = 0; pnl < 2; ++pnl) {
+        const V8 *lh = (const V8 *)(pnl == 0 ? Lh0 : Lh1);
+        if (!lh)
+            break;
+        const int skip = pnl == 0 ? skip0 : skip1;
+        // A operand: rows of tile tj (C columns); B operand: rows of tile ti (C rows)
+        const V8 *pa0 = lh + (size_t)(skip + 4 * tj + 2 * wm) * KS * 64 + lane;
+        const V8 *pb0 = lh + (size_t)(skip + 4 * ti + 2 * wn) * KS * 64 + lane;
+        V8 fa[KS][2], fb[KS][2];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
+        for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
-            const V8 na = HalfT<HK>::neg(fa[ks][mi]);
+            for (int q = 0; q < 2; ++q) {
+                fa[ks][q] = pa0[(q * KS + ks) * 64];
+                fb[ks][q] = pb0[(q * KS + ks) * 64];
+            }
+        // all operand loads in flight before the first MFMA
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni)
-                acc[mi][ni] = HalfT<HK>::mma(na, fb[ks][ni], acc[mi][ni]);
+        for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi) {
+                const V8 na = HalfT<HK>::neg(fa[ks][mi]);
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = HalfT<HK>::mma(na, fb[ks][ni], acc[mi][ni]);
+            }
         }
     }
 #pragma unroll
@@ -550,6 +574,7 @@ __global__ __launch_bounds__(256) void k_syrk_update_h(float *__restrict__ H, in
                 const int m = Acc32<float>::row(j, lane), nn = Acc32<float>::col(j, lane);
                 H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld] = acc[mi][ni][j];
             }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -718,36 +743,39 @@ template void launch_trsm_panel<float>(float *, int64_t, int64_t, int64_t, int64
 template void launch_trsm_panel<double>(double *, int64_t, int64_t, int64_t, int64_t, const double *,
                                         const unsigned long long *, hipStream_t, void *, int);
 
-void launch_syrk_update_half(float *H, int64_t ld, const void *Lh, int half, int64_t r0, int t, int tj_lo,
-                             int tj_hi, const unsigned long long *info, hipStream_t st, int prio)
+void launch_syrk_update_half(float *H, int64_t ld, const void *Lh0, int skip0, const void *Lh1, int skip1, int half,
+                             int64_t r0, int t, int tj_lo, int tj_hi, const unsigned long long *info, hipStream_t st,
+                             int prio, int max_grid)
 {
     if (t <= 0 || tj_lo >= tj_hi) return;
     int64_t ntiles = 0;
     for (int c = tj_lo; c < tj_hi; ++c) ntiles += t - c;
-    const int64_t grid = ((ntiles + 7) / 8) * 8;
+    int64_t grid = ((ntiles + 7) / 8) * 8;
+    if (max_grid > 0 && grid > max_grid) grid = (max_grid / 8) * 8;
     if (half == HALF_F16)
-        hipLaunchKernelGGL(k_syrk_update_h<HALF_F16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh, r0, t,
-                           tj_lo, tj_hi, (int)ntiles, info, prio);
+        hipLaunchKernelGGL(k_syrk_update_h<HALF_F16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh0, skip0,
+                           Lh1, skip1, r0, t, tj_lo, tj_hi, (int)ntiles, info, prio);
     else
-        hipLaunchKernelGGL(k_syrk_update_h<HALF_BF16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh, r0, t,
-                           tj_lo, tj_hi, (int)ntiles, info, prio);
+        hipLaunchKernelGGL(k_syrk_update_h<HALF_BF16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh0, skip0,
+                           Lh1, skip1, r0, t, tj_lo, tj_hi, (int)ntiles, info, prio);
 }
 
 template <typename T>
 void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,
-                        const unsigned long long *info, hipStream_t st, int prio)
+                        const unsigned long long *info, hipStream_t st, int prio, int max_grid)
 {
     if (t <= 0 || tj_lo >= tj_hi) return;
     int64_t ntiles = 0;
     for (int c = tj_lo; c < tj_hi; ++c) ntiles += t - c;
-    const int64_t grid = ((ntiles + 7) / 8) * 8;
+    int64_t grid = ((ntiles + 7) / 8) * 8;
+    if (max_grid > 0 && grid > max_grid) grid = (max_grid / 8) * 8;
     hipLaunchKernelGGL(k_syrk_update<T>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, k0, nbk, r0, t, tj_lo,
                        tj_hi, (int)ntiles, info, prio);
 }
 template void launch_syrk_update<float>(float *, int64_t, int64_t, int, int64_t, int, int, int,
-                                        const unsigned long long *, hipStream_t, int);
+                                        const unsigned long long *, hipStream_t, int, int);
 template void launch_syrk_update<double>(double *, int64_t, int64_t, int, int64_t, int, int, int,
-                                         const unsigned long long *, hipStream_t, int);
+                                         const unsigned long long *, hipStream_t, int, int);
 
 template <typename T>
 void launch_trtri_blocks(const T *H, int64_t ld, int64_t nt, const T *Winv, T *W, hipStream_t st)

@@ -328,6 +328,270 @@ __global__ __launch_bounds__(128) void k_trsm_panel(T *__restrict__ H, int64_t l
 }
 
 // ---------------------------------------------------------------------------
+// K2, binary32: the same factor with every column step as an MFMA rank-1
+// update held in registers.  The 32 x 32 accumulator layout of
+// v_mfma_f32_32x32x2f32 (register jj of lane l: row 8(jj/4) + 4(l/32) + jj%4,
+// column l%32) puts row j of a tile in register 4(j/8) + j%4 of the 32 lanes
+// of half h = (j/4)%2, which is exactly where the MFMA takes a column vector
+// for k-slot h.  Tiles are held transposed (T[m][n] = C[n][m]), so column j
+// of a tile needs no data movement: one readlane for the pivot, one
+// reciprocal square root, then
+//     top    -= x x^T        (diagonal tile, every wave keeps a copy)
+//     below  -= x x_b^T      (one tile below the diagonal per wave)
+//     Binv   -= x w^T        (the wave without a below tile: forward
+//                             substitution L W = I for W = L^{-1}, w = row j of W)
+// with x = column j of L.  Columns are saved in the same layout, so L and W
+// come out ready to store.  One barrier pair per 32-wide strip; the trailing
+// tiles are updated from LDS as in the generic kernel.
+__global__ __launch_bounds__(256) void k_potrf_f32(float *__restrict__ Hkk, int64_t ld, int64_t col0,
+                                                  float *__restrict__ Winv, unsigned long long *info)
+{
+    constexpr int NB = 128, IB = SPD_IB, NT = NB / IB, NTILES = NT * (NT + 1) / 2, NW = 4;
+    constexpr int SLOTS = (NTILES + NW - 1) / NW;
+    constexpr int SLD = NB + 1;
+    using A = Acc32<float>;
+    // S: the strip, S[k * SLD + r] = C[32 s + r][32 s + k], overwritten by
+    // the factored strip; SW: W_s = L_ss^{-1}, SW[j * SLD + c] = W[j][c];
+    // SD: scratch target of lanes with nothing to keep
+    __shared__ float S[IB * SLD];
+    __shared__ float SW[IB * SLD];
+    __shared__ float SD[IB * SLD];
+    __shared__ float SP[IB];  // the strip's pivots
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (*(volatile unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
+        return;
+    __builtin_amdgcn_s_setprio(3);  // on the critical path of the factorisation
+
+    A acc[SLOTS];
+    int tI[SLOTS], tJ[SLOTS];
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+        const int t = wave + NW * q;
+        int ti = 0;
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        tI[q] = (t < NTILES) ? ti : -1;
+        tJ[q] = (t < NTILES) ? t - ti * (ti + 1) / 2 : -1;
+        if (t < NTILES) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                acc[q].set(j, Hkk[(tI[q] * IB + A::col(j, lane)) + (int64_t)(tJ[q] * IB + A::row(j, lane)) * ld]);
+        }
+    }
+    // per-lane selectors of the two k-slots (lane halves)
+    const float hs[2] = {(lane < 32) ? 1.0f : 0.0f, (lane < 32) ? 0.0f : 1.0f};
+    const float nhs[2] = {-hs[0], -hs[1]};
+    const int r = lane & 31;
+    for (int s = 0; s < NT; ++s) {
+        const int nbelow = NT - 1 - s;
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q)
+            if (tJ[q] == s) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    S[A::row(j, lane) * SLD + (tI[q] - s) * IB + A::col(j, lane)] = acc[q].get(j);
+            }
+        lds_barrier();
+        // top: the diagonal tile, symmetrised from its lower triangle;
+        // sec: below tile s+1+wave, or the identity (wave NW-1), or nothing
+        const bool has_below = wave < nbelow, has_inv = wave == NW - 1;
+        floatx16 top, sec;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int m = A::row(j, lane), n = A::col(j, lane);
+            top[j] = (n >= m) ? S[m * SLD + n] : S[n * SLD + m];
+            sec[j] = has_below ? S[m * SLD + (1 + wave) * IB + n] : ((has_inv && m == n) ? 1.0f : 0.0f);
+        }
+        lds_barrier();  // the strip is overwritten below
+        // Column j.  The k-slot selector zeroes the other half exactly; in
+        // rows above j of the tile, x picks up rounding residue of entries
+        // already eliminated -- it only touches columns (and rows of W) that
+        // are final, and those rows are not stored.  (Above the diagonal W
+        // stays exactly zero.)  Each column of L and row of W goes to shared
+        // memory as it is formed; lanes of the other half, and waves with
+        // nothing to keep, write to SD instead, so the addresses are one
+        // base per half plus a constant offset per column.
+        float *xb[2], *yb[2];
+        {
+            float *ycol = has_inv ? SW : (has_below ? &S[(1 + wave) * IB] : SD);
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const bool mine = (lane >> 5) == hh;
+                xb[hh] = (mine && wave == 0) ? &S[r] : &SD[r];
+                yb[hh] = mine ? ycol + r : &SD[r];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < IB; ++j) {
+            const int h = (j >> 2) & 1, jj = 4 * (j >> 3) + (j & 3);
+            const float t = top[jj];
+            const float p = bcast(t, 32 * h + j);
+            SP[j] = p;  // the same value from every lane; checked after the strip
+            const float ri = __builtin_amdgcn_rsqf(p);
+            const float rih = ri * hs[h], nrih = ri * nhs[h];
+            const float x = t * rih, xn = t * nrih;
+            const float y = sec[jj] * rih;
+            top = __builtin_amdgcn_mfma_f32_32x32x2f32(xn, x, top, 0, 0, 0);
+            sec = __builtin_amdgcn_mfma_f32_32x32x2f32(xn, y, sec, 0, 0, 0);
+            xb[h][j * SLD] = x;  // rows above j: masked when stored
+            yb[h][j * SLD] = y;
+        }
+
+        lds_barrier();
+        // the factored strip (rows 32 s .. NB-1) and W_s to global memory
+        if (wave == 0) {
+            const unsigned long long badm = __ballot(lane < IB && !(SP[lane & 31] > 0.0f));
+            if (badm && lane == 0)
+                atomicMin(info, (unsigned long long)(col0 + s * IB + __builtin_ctzll(badm) + 1));
+        }
+        const int rows = NB - s * IB;
+        for (int c = wave; c < IB; c += NW)
+            for (int rr = lane; rr < rows; rr += 64)
+                Hkk[(s * IB + rr) + (int64_t)(s * IB + c) * ld] = (rr < c) ? 0.0f : S[c * SLD + rr];
+        for (int c = wave; c < IB; c += NW)
+            if (lane < IB)  // Winv column-major: W[lane][c]
+                Winv[(size_t)s * IB * IB + lane + c * IB] = SW[lane * SLD + c];
+        // trailing update of the owned tiles: D(ti,tj) -= L_tj L_ti^T
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q)
+            if (tJ[q] > s) {
+                const float *pa = &S[(tJ[q] - s) * IB];
+                const float *pb = &S[(tI[q] - s) * IB];
+#pragma unroll
+                for (int k = 0; k < IB; k += Frag<float>::K) {
+                    Frag<float> fa, fb;
+                    fa.load(pa + k * SLD, SLD, lane);
+                    fb.load(pb + k * SLD, SLD, lane);
+                    fa.negate();
+                    mma(acc[q], fa, fb);
+                }
+            }
+        lds_barrier();  // S is refilled by the next strip
+    }
+}
+// ---------------------------------------------------------------------------
+// K3, binary32: panel solve Y = X L_kk^{-T} with the rows in registers.
+// Each wave owns 16 rows as the transposed block Y^T (128 x 16) in eight
+// v_mfma_f32_16x16x4f32 accumulators: register q of lane l of block b holds
+// Y[l%16][16 b + 4 (l/16) + q].  The MFMA's k-slots are a free summation
+// order, so k-step q of a 16-column block pairs slot u = l/16 with column
+// 16 b + 4 u + q -- which is register q of block b in that lane: a solved
+// block is its own MFMA operand, no transposition or LDS round trip.
+// Strip s (columns 32 s .. 32 s + 31, blocks 2s and 2s+1):
+//     Z   = X_s - sum_{t<s} Y_t L_st^T
+//     Y_s = Z W_s^T                 (W_s = L_ss^{-1}, from the diagonal factor)
+// L_st and W_s are staged once per workgroup in LDS, row-major, so that
+// each operand fetch is one 16-byte read of four consecutive k.
+template <int HK>
+__global__ __launch_bounds__(256) void k_trsm_f32(float *__restrict__ H, int64_t ld, int64_t k0, int64_t row0,
+                                                 int64_t nrows, const float *__restrict__ Winv,
+                                                 const unsigned long long *info, void *__restrict__ Lh)
+{
+    constexpr int NB = 128, IB = SPD_IB, PL = IB + 4;
+    constexpr int NLB = 6, NBLK = NLB + 4;  // L_st for t < s (s(s-1)/2 + t), then W_0..W_3
+    __shared__ __align__(16) float Bs[NBLK][IB * PL];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (*(volatile const unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
+        return;
+    __builtin_amdgcn_s_setprio(3);  // on the critical path of the factorisation
+    const int64_t rw = row0 + (int64_t)blockIdx.x * 64 + wave * 16 + (lane & 15);
+    const bool valid = rw < row0 + nrows;
+    const int u = lane >> 4, c4 = 4 * u;
+    // the rows, transposed into the accumulators
+    floatx4 acc[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            acc[b][q] = valid ? H[rw + (k0 + 16 * b + c4 + q) * ld] : 0.0f;
+    // stage the operands: element (r, c) of block blk at Bs[blk][r * PL + c]
+    const float *Lkk = H + k0 + k0 * ld;
+    for (int base = 0; base < NBLK * IB * IB; base += 256 * 8) {
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int idx = base + i * 256 + tid;
+            const int blk = idx >> 10, e = idx & 1023, c = e >> 5, rr = e & 31;
+            if (blk < NLB) {
+                const int sb = blk < 1 ? 1 : (blk < 3 ? 2 : 3);
+                const int tb = blk - sb * (sb - 1) / 2;
+                v[i] = Lkk[(IB * sb + rr) + (int64_t)(IB * tb + c) * ld];
+            } else {
+                v[i] = Winv[(size_t)(blk - NLB) * IB * IB + rr + c * IB];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int idx = base + i * 256 + tid;
+            const int blk = idx >> 10, e = idx & 1023, c = e >> 5, rr = e & 31;
+            Bs[blk][rr * PL + c] = v[i];
+        }
+    }
+    __syncthreads();
+    const int rl = lane & 15;
+#pragma unroll
+    for (int s = 0; s < NB / IB; ++s) {
+        // Z: blocks 2s, 2s+1 minus the solved blocks 2t, 2t+1 (t < s) times L_st^T
+#pragma unroll
+        for (int t = 0; t < s; ++t) {
+            const float *Lb = Bs[s * (s - 1) / 2 + t];
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    const floatx4 a = *(const floatx4 *)&Lb[(16 * o + rl) * PL + 16 * bb + c4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc[2 * s + o] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[q], acc[2 * t + bb][q],
+                                                                              acc[2 * s + o], 0, 0, 0);
+                }
+        }
+        // Y_s = Z W_s^T (W_s lower triangular: block o needs k-blocks kb <= o)
+        const float *Wb = Bs[NLB + s];
+        floatx4 y[2];
+        y[0] = floatx4{0.f, 0.f, 0.f, 0.f};
+        y[1] = y[0];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int o = kb; o < 2; ++o) {
+                const floatx4 a = *(const floatx4 *)&Wb[(16 * o + rl) * PL + 16 * kb + c4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    y[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], acc[2 * s + kb][q], y[o], 0, 0, 0);
+            }
+        acc[2 * s] = y[0];
+        acc[2 * s + 1] = y[1];
+        if (valid) {
+#pragma unroll
+            for (int o = 0; o < 2; ++o)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    H[rw + (k0 + IB * s + 16 * o + c4 + q) * ld] = y[o][q];
+        }
+    }
+    if constexpr (HK != HALF_NONE) {
+        // the rows rounded to binary16 / bfloat16 (nearest even) in the
+        // fragment layout of the half-precision update: element (r, k) at
+        // ((r/32)(NB/16) + k/16) 512 + (32 ((k%16)/8) + r%32) 8 + k%8; the
+        // four columns of a lane are consecutive there
+        if (valid) {
+            using E = typename HalfT<HK>::E;
+            typedef E E4 __attribute__((ext_vector_type(4)));
+            const int64_t rr = rw - row0;
+            E *dst = (E *)Lh + (size_t)((rr >> 5) * (NB / 16)) * 512 + (32 * (u >> 1) + (rr & 31)) * 8 + 4 * (u & 1);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                E4 v;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    v[q] = (E)acc[b][q];
+                *(E4 *)(dst + (size_t)b * 512) = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // K4: trailing update H_ij -= L_ik L_jk^T on 128 x 128 lower tiles (MFMA).
 // Tiles are numbered over the lower triangle of the trailing region (t tiles
 // per side) restricted to tile columns [tj_lo, tj_hi); block indices are
@@ -357,8 +621,16 @@ SPD_DEV void decode_tile(int b, int t, int tj_lo, int tj_hi, int &ti, int &tj)
 }
 
 template <typename T> struct SyrkCfg;
-template <> struct SyrkCfg<float> { static constexpr int KC = 32; };
-template <> struct SyrkCfg<double> { static constexpr int KC = 16; };
+template <> struct SyrkCfg<float> {
+    static constexpr int KC = 32;
+    using Acc = Acc32x4;
+    using Fr = Frag4f;
+};
+template <> struct SyrkCfg<double> {
+    static constexpr int KC = 16;
+    using Acc = Acc32<double>;
+    using Fr = Frag<double>;
+};
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t ld, int64_t k0, int nbk, int64_t r0,
@@ -366,6 +638,8 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
                                                      const unsigned long long *info, int prio)
 {
     constexpr int KC = SyrkCfg<T>::KC;
+    using AccT = typename SyrkCfg<T>::Acc;
+    using FragT = typename SyrkCfg<T>::Fr;
     constexpr int LDT = SPD_TILE + 4;  // LDS column stride
     __shared__ T As[2][KC * LDT];
     __shared__ T Bs[2][KC * LDT];
@@ -394,14 +668,14 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
     // The C tile is read once, up front, straight into the accumulators (so
     // its latency overlaps the K loop); the MFMA operands are negated.
     // Register j of tile (mi, ni) holds C[crow + 64 wn + 32 ni + col(j)][ccol + 64 wm + 32 mi + row(j)].
-    Acc32<T> acc[2][2];
+    AccT acc[2][2];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                const int m = Acc32<T>::row(j, lane), nn = Acc32<T>::col(j, lane);
+                const int m = AccT::row(j, lane), nn = AccT::col(j, lane);
                 acc[mi][ni].set(j, H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld]);
             }
 
@@ -453,8 +727,8 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
         const T *a0 = &As[buf][64 * wm];
         const T *b0 = &Bs[buf][64 * wn];
 #pragma unroll
-        for (int k = 0; k < KC; k += Frag<T>::K) {
-            Frag<T> fa[2], fb[2];
+        for (int k = 0; k < KC; k += FragT::K) {
+            FragT fa[2], fb[2];
             fa[0].load(a0 + k * LDT, LDT, lane);
             fa[1].load(a0 + 32 + k * LDT, LDT, lane);
             fb[0].load(b0 + k * LDT, LDT, lane);
@@ -480,7 +754,7 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
         for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                const int m = Acc32<T>::row(j, lane), nn = Acc32<T>::col(j, lane);
+                const int m = AccT::row(j, lane), nn = AccT::col(j, lane);
                 H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld] = acc[mi][ni].get(j);
             }
     __syncthreads();  // shared memory is reused by the next tile
@@ -711,7 +985,10 @@ template void launch_convert<double>(const double *, int64_t, int64_t, int64_t, 
 template <typename T>
 void launch_potrf_diag(T *Hkk, int64_t ld, int64_t col0, T *Winv, unsigned long long *info, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_potrf_diag<T, Panel<T>::NB>), dim3(1), dim3(256), 0, st, Hkk, ld, col0, Winv, info);
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL(k_potrf_f32, dim3(1), dim3(256), 0, st, Hkk, ld, col0, Winv, info);
+    else
+        hipLaunchKernelGGL((k_potrf_diag<T, Panel<T>::NB>), dim3(1), dim3(256), 0, st, Hkk, ld, col0, Winv, info);
 }
 template void launch_potrf_diag<float>(float *, int64_t, int64_t, float *, unsigned long long *, hipStream_t);
 template void launch_potrf_diag<double>(double *, int64_t, int64_t, double *, unsigned long long *, hipStream_t);
@@ -724,19 +1001,20 @@ void launch_trsm_panel(T *H, int64_t ld, int64_t k0, int64_t row0, int64_t nrows
     const unsigned blocks = (unsigned)((nrows + 63) / 64);
     constexpr int NB = Panel<T>::NB;
     if constexpr (sizeof(T) == 4) {
-        if (half == HALF_F16) {
-            hipLaunchKernelGGL((k_trsm_panel<T, NB, HALF_F16>), dim3(blocks), dim3(128), 0, st, H, ld, k0, row0,
-                               nrows, Winv, info, Lh);
-            return;
-        }
-        if (half == HALF_BF16) {
-            hipLaunchKernelGGL((k_trsm_panel<T, NB, HALF_BF16>), dim3(blocks), dim3(128), 0, st, H, ld, k0, row0,
-                               nrows, Winv, info, Lh);
-            return;
-        }
+        static_assert(NB == 128, "binary32 panel solve is written for 128 columns");
+        if (half == HALF_F16)
+            hipLaunchKernelGGL(k_trsm_f32<HALF_F16>, dim3(blocks), dim3(256), 0, st, H, ld, k0, row0, nrows, Winv,
+                               info, Lh);
+        else if (half == HALF_BF16)
+            hipLaunchKernelGGL(k_trsm_f32<HALF_BF16>, dim3(blocks), dim3(256), 0, st, H, ld, k0, row0, nrows, Winv,
+                               info, Lh);
+        else
+            hipLaunchKernelGGL(k_trsm_f32<HALF_NONE>, dim3(blocks), dim3(256), 0, st, H, ld, k0, row0, nrows, Winv,
+                               info, nullptr);
+    } else {
+        hipLaunchKernelGGL((k_trsm_panel<T, NB, HALF_NONE>), dim3(blocks), dim3(128), 0, st, H, ld, k0, row0, nrows,
+                           Winv, info, nullptr);
     }
-    hipLaunchKernelGGL((k_trsm_panel<T, NB, HALF_NONE>), dim3(blocks), dim3(128), 0, st, H, ld, k0, row0, nrows,
-                       Winv, info, nullptr);
 }
 template void launch_trsm_panel<float>(float *, int64_t, int64_t, int64_t, int64_t, const float *,
                                        const unsigned long long *, hipStream_t, void *, int);

@@ -14,6 +14,7 @@
 // diagonal block (consumed by the triangular solves).
 #include "common.h"
 #include "internal.h"
+#include <cstdlib>
 #include <type_traits>
 
 // Operand types of the half-precision trailing update.
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(128) void k_trsm_panel(T *__restrict__ H, int64_t l
 // with x = column j of L.  Columns are saved in the same layout, so L and W
 // come out ready to store.  One barrier pair per 32-wide strip; the trailing
 // tiles are updated from LDS as in the generic kernel.
-__global__ __launch_bounds__(256) void k_potrf_f32(float *__restrict__ Hkk, int64_t ld, int64_t col0,
+__global__ __launch_bounds__(256, 2) void k_potrf_f32(float *__restrict__ Hkk, int64_t ld, int64_t col0,
                                                   float *__restrict__ Winv, unsigned long long *info)
 {
     constexpr int NB = 128, IB = SPD_IB, NT = NB / IB, NTILES = NT * (NT + 1) / 2, NW = 4;
@@ -420,22 +421,35 @@ __global__ __launch_bounds__(256) void k_potrf_f32(float *__restrict__ Hkk, int6
                 yb[hh] = mine ? ycol + r : &SD[r];
             }
         }
+        // The update of sec by column j is issued one step late, after the
+        // next pivot has been read: a read of an MFMA result waits for every
+        // MFMA in flight, so issuing it right behind the diagonal tile's
+        // update would put it on the pivot chain.
+        float xn_prev = 0.0f, rih_prev = 0.0f;
 #pragma unroll
-        for (int j = 0; j < IB; ++j) {
+        for (int j = 0; j <= IB; ++j) {
             const int h = (j >> 2) & 1, jj = 4 * (j >> 3) + (j & 3);
-            const float t = top[jj];
+            const float t = (j < IB) ? top[jj] : 0.0f;
+            if (j > 0) {
+                const int hp = ((j - 1) >> 2) & 1, jp = 4 * ((j - 1) >> 3) + ((j - 1) & 3);
+                const float y = sec[jp] * rih_prev;
+                __builtin_amdgcn_sched_barrier(0);
+                sec = __builtin_amdgcn_mfma_f32_32x32x2f32(xn_prev, y, sec, 0, 0, 0);
+                yb[hp][(j - 1) * SLD] = y;
+            }
+            if (j == IB)
+                break;
+            __builtin_amdgcn_sched_barrier(0);
             const float p = bcast(t, 32 * h + j);
             SP[j] = p;  // the same value from every lane; checked after the strip
             const float ri = __builtin_amdgcn_rsqf(p);
             const float rih = ri * hs[h], nrih = ri * nhs[h];
             const float x = t * rih, xn = t * nrih;
-            const float y = sec[jj] * rih;
             top = __builtin_amdgcn_mfma_f32_32x32x2f32(xn, x, top, 0, 0, 0);
-            sec = __builtin_amdgcn_mfma_f32_32x32x2f32(xn, y, sec, 0, 0, 0);
             xb[h][j * SLD] = x;  // rows above j: masked when stored
-            yb[h][j * SLD] = y;
+            xn_prev = xn;
+            rih_prev = rih;
         }
-
         lds_barrier();
         // the factored strip (rows 32 s .. NB-1) and W_s to global memory
         if (wave == 0) {
@@ -443,13 +457,33 @@ __global__ __launch_bounds__(256) void k_potrf_f32(float *__restrict__ Hkk, int6
             if (badm && lane == 0)
                 atomicMin(info, (unsigned long long)(col0 + s * IB + __builtin_ctzll(badm) + 1));
         }
-        const int rows = NB - s * IB;
-        for (int c = wave; c < IB; c += NW)
-            for (int rr = lane; rr < rows; rr += 64)
-                Hkk[(s * IB + rr) + (int64_t)(s * IB + c) * ld] = (rr < c) ? 0.0f : S[c * SLD + rr];
-        for (int c = wave; c < IB; c += NW)
-            if (lane < IB)  // Winv column-major: W[lane][c]
-                Winv[(size_t)s * IB * IB + lane + c * IB] = SW[lane * SLD + c];
+        {
+            // wave w stores columns w, w+4, ... of the strip (rows 32 s .. NB-1) and of W_s
+            const int rows = NB - s * IB;
+            float v[8][2], w[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int c = wave + NW * i;
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    const int rr = lane + 64 * h2;
+                    v[i][h2] = (rr < rows) ? ((rr < c) ? 0.0f : S[c * SLD + rr]) : 0.0f;
+                }
+                w[i] = SW[(lane & 31) * SLD + c];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int c = wave + NW * i;
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    const int rr = lane + 64 * h2;
+                    if (rr < rows)
+                        Hkk[(s * IB + rr) + (int64_t)(s * IB + c) * ld] = v[i][h2];
+                }
+                if (lane < IB)  // Winv column-major: W[lane][c]
+                    Winv[(size_t)s * IB * IB + lane + c * IB] = w[i];
+            }
+        }
         // trailing update of the owned tiles: D(ti,tj) -= L_tj L_ti^T
 #pragma unroll
         for (int q = 0; q < SLOTS; ++q)
@@ -594,12 +628,14 @@ __global__ __launch_bounds__(256) void k_trsm_f32(float *__restrict__ H, int64_t
 // ---------------------------------------------------------------------------
 // K4: trailing update H_ij -= L_ik L_jk^T on 128 x 128 lower tiles (MFMA).
 // Tiles are numbered over the lower triangle of the trailing region (t tiles
-// per side) restricted to tile columns [tj_lo, tj_hi); block indices are
-// remapped so that consecutive tiles land on the same XCD (blocks are
-// dispatched round-robin over the 8 XCDs).
+// per side) restricted to tile columns [tj_lo, tj_hi): a range that stops
+// short of the last tile column (or spans at most four) is walked column by
+// column, a range reaching it as the lower triangle from (tj_lo, tj_lo) row
+// by row.  Block indices are remapped so that consecutive tiles land on the
+// same XCD (blocks are dispatched round-robin over the 8 XCDs).
 SPD_DEV void decode_tile(int b, int t, int tj_lo, int tj_hi, int &ti, int &tj)
 {
-    if (tj_hi - tj_lo <= 4) {
+    if (tj_hi < t || tj_hi - tj_lo <= 4) {
         for (int c = tj_lo; c < tj_hi; ++c) {
             const int cnt = t - c;
             if (b < cnt) {
@@ -758,6 +794,137 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
                 H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld] = acc[mi][ni].get(j);
             }
     __syncthreads();  // shared memory is reused by the next tile
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K4, binary32: the same update written for v_mfma_f32_16x16x4f32, on TS x TS
+// tiles (TS = 128, or 64 when a launch has too few 128-tiles to fill the
+// chip).  Each wave owns a TS/2 x TS/2 block of D = C^T as NB x NB 16 x 16
+// accumulators holding -C (the sign is applied once on load and once on
+// store, so the K loop only multiplies and adds).  Shared memory holds 32
+// columns of each operand as [k][row] with TS floats per k and the row index
+// XOR-ed with 16 (k % 4): a fragment read (lane l: row 16 b + l%16, k = 4 s +
+// l/16) then touches 64 distinct banks, and the 16-byte staging stores stay
+// contiguous.  Tiles are counted in TS units over the lower triangle of the
+// trailing region (t tiles per side), tile columns [tj_lo, tj_hi).
+template <int TS>
+__global__ __launch_bounds__(256, 2) void k_syrk_update_f32(float *__restrict__ H, int64_t ld, int64_t k0, int nbk,
+                                                           int64_t r0, int t, int tj_lo, int tj_hi, int ntiles,
+                                                           const unsigned long long *info, int prio)
+{
+    constexpr int KC = 32, NB = TS / 32, NV = TS / 32;  // 16-blocks per wave side; staged float4 per thread
+    __shared__ __align__(16) float As[2][KC * TS];
+    __shared__ __align__(16) float Bs[2][KC * TS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (*(volatile const unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
+        return;
+    if (prio)
+        __builtin_amdgcn_s_setprio(2);  // the lookahead part of the update
+    const int wm = wave >> 1, wn = wave & 1, r = lane & 15, u = lane >> 4;
+    const int ldi = (int)ld;  // offsets within a tile row block of <= 512 columns fit in 32 bits
+    // staging: thread covers rows 4 (tid % (TS/4)) .. +3 of columns tid / (TS/4) + (1024/TS) v
+    constexpr int TPC = TS / 4, CSTEP = 256 / TPC;
+    const int scol = tid / TPC, srow = (tid % TPC) * 4;
+    const int goff = scol * ldi + srow;
+    const int soff = scol * TS + (srow ^ (16 * (scol & 3)));  // CSTEP is a multiple of 4: col % 4 fixed
+    // fragment offsets: row 16 b + r of the wave's TS/2 rows, k-slot u (+ 4 s TS for k-step s)
+    int fa[NB], fb[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        fa[b] = u * TS + (((TS / 2) * wm + 16 * b) ^ (16 * u)) + r;
+        fb[b] = u * TS + (((TS / 2) * wn + 16 * b) ^ (16 * u)) + r;
+    }
+    const int coff = r + 4 * u * ldi;
+    const int per = gridDim.x / 8, chunk = (ntiles + 7) / 8;
+    for (int it = blockIdx.x / 8; it < chunk; it += per) {
+        const int logical = (blockIdx.x % 8) * chunk + it;
+        if (logical >= ntiles)
+            break;
+        int ti, tj;
+        decode_tile(logical, t, tj_lo, tj_hi, ti, tj);
+        if (ti < 0)
+            break;
+        const int64_t crow = r0 + (int64_t)ti * TS, ccol = r0 + (int64_t)tj * TS;
+        const float *pa = H + ccol + k0 * ld;  // rows of tile tj (D rows = C columns)
+        const float *pb = H + crow + k0 * ld;  // rows of tile ti (D columns = C rows)
+        // register q of block (mi, ni): -C[crow + TS/2 wn + 16 ni + r][ccol + TS/2 wm + 16 mi + 4 u + q]
+        float *cu = H + (crow + (TS / 2) * wn) + (ccol + (TS / 2) * wm) * ld;
+        floatx4 c[NB][NB];
+#pragma unroll
+        for (int mi = 0; mi < NB; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < NB; ++ni)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    c[mi][ni][q] = -cu[coff + 16 * ni + (16 * mi + q) * ldi];
+        // staging registers (named, not an array, so that they stay registers)
+        float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+#define SPD_GL(o)                                                                         \
+    do {                                                                                  \
+        ra0 = *(const float4 *)&pa[(o) + goff];                                           \
+        rb0 = *(const float4 *)&pb[(o) + goff];                                           \
+        ra1 = *(const float4 *)&pa[(o) + goff + CSTEP * ldi];                             \
+        rb1 = *(const float4 *)&pb[(o) + goff + CSTEP * ldi];                             \
+        if constexpr (NV > 2) {                                                           \
+            ra2 = *(const float4 *)&pa[(o) + goff + 2 * CSTEP * ldi];                     \
+            rb2 = *(const float4 *)&pb[(o) + goff + 2 * CSTEP * ldi];                     \
+            ra3 = *(const float4 *)&pa[(o) + goff + 3 * CSTEP * ldi];                     \
+            rb3 = *(const float4 *)&pb[(o) + goff + 3 * CSTEP * ldi];                     \
+        }                                                                                 \
+    } while (0)
+#define SPD_SS(bf)                                                                        \
+    do {                                                                                  \
+        *(float4 *)&As[bf][soff] = ra0;                                                   \
+        *(float4 *)&Bs[bf][soff] = rb0;                                                   \
+        *(float4 *)&As[bf][soff + CSTEP * TS] = ra1;                                      \
+        *(float4 *)&Bs[bf][soff + CSTEP * TS] = rb1;                                      \
+        if constexpr (NV > 2) {                                                           \
+            *(float4 *)&As[bf][soff + 2 * CSTEP * TS] = ra2;                              \
+            *(float4 *)&Bs[bf][soff + 2 * CSTEP * TS] = rb2;                              \
+            *(float4 *)&As[bf][soff + 3 * CSTEP * TS] = ra3;                              \
+            *(float4 *)&Bs[bf][soff + 3 * CSTEP * TS] = rb3;                              \
+        }                                                                                 \
+    } while (0)
+        static_assert(NV == 2 || NV == 4, "staging layout");
+        SPD_GL(0);
+        SPD_SS(0);
+        lds_barrier();
+        int buf = 0;
+        for (int kb = 0; kb < nbk; kb += KC) {
+            // prefetch the next chunk (the last iteration re-reads its own chunk)
+            const int o = ((kb + KC < nbk) ? kb + KC : kb) * ldi;
+            SPD_GL(o);
+            __builtin_amdgcn_sched_barrier(0);
+            const float *A0 = As[buf], *B0 = Bs[buf];
+#pragma unroll
+            for (int ks = 0; ks < KC / 4; ++ks) {
+                float a[NB], b[NB];
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    a[i] = A0[4 * ks * TS + fa[i]];
+                    b[i] = B0[4 * ks * TS + fb[i]];
+                }
+#pragma unroll
+                for (int mi = 0; mi < NB; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < NB; ++ni)
+                        c[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], c[mi][ni], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            SPD_SS(buf ^ 1);
+            lds_barrier();
+            buf ^= 1;
+        }
+#undef SPD_GL
+#undef SPD_SS
+#pragma unroll
+        for (int mi = 0; mi < NB; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < NB; ++ni)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    cu[coff + 16 * ni + (16 * mi + q) * ldi] = -c[mi][ni][q];
     }
 }
 
@@ -1038,6 +1205,17 @@ void launch_syrk_update_half(float *H, int64_t ld, const void *Lh0, int skip0, c
                            Lh1, skip1, r0, t, tj_lo, tj_hi, (int)ntiles, info, prio);
 }
 
+// Below this many 128-tiles a binary32 update runs on 64-tiles (SPD_SMALL_TILES overrides).
+static int small_update_tiles()
+{
+    static const int v = [] {
+        const char *e = std::getenv("SPD_SMALL_TILES");
+        return e ? std::atoi(e) : 512;
+    }();
+    return v;
+}
+#define kSmallUpdateTiles small_update_tiles()
+
 template <typename T>
 void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,
                         const unsigned long long *info, hipStream_t st, int prio, int max_grid)
@@ -1047,8 +1225,22 @@ void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t
     for (int c = tj_lo; c < tj_hi; ++c) ntiles += t - c;
     int64_t grid = ((ntiles + 7) / 8) * 8;
     if (max_grid > 0 && grid > max_grid) grid = (max_grid / 8) * 8;
-    hipLaunchKernelGGL(k_syrk_update<T>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, k0, nbk, r0, t, tj_lo,
-                       tj_hi, (int)ntiles, info, prio);
+    if constexpr (sizeof(T) == 4) {
+        if (ntiles < kSmallUpdateTiles && max_grid == 0) {
+            // too few 128-tiles for the chip: 64-tiles, four times as many workgroups
+            const int t2 = 2 * t, lo2 = 2 * tj_lo, hi2 = 2 * tj_hi;
+            int64_t n2 = 0;
+            for (int c = lo2; c < hi2; ++c) n2 += t2 - c;
+            const int64_t g2 = ((n2 + 7) / 8) * 8;
+            hipLaunchKernelGGL(k_syrk_update_f32<64>, dim3((unsigned)g2), dim3(256), 0, st, H, ld, k0, nbk, r0, t2,
+                               lo2, hi2, (int)n2, info, prio);
+        } else {
+            hipLaunchKernelGGL(k_syrk_update_f32<128>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, k0, nbk, r0,
+                               t, tj_lo, tj_hi, (int)ntiles, info, prio);
+        }
+    } else
+        hipLaunchKernelGGL(k_syrk_update<T>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, k0, nbk, r0, t, tj_lo,
+                           tj_hi, (int)ntiles, info, prio);
 }
 template void launch_syrk_update<float>(float *, int64_t, int64_t, int, int64_t, int, int, int,
                                         const unsigned long long *, hipStream_t, int, int);

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_resid_partial(const double *__restrict_
 // per tile, RP[I][J]) and a_ij x_i for row j (accumulated over the chunk in
 // registers, CP[J][q]); a diagonal tile uses its lower triangle only (the
 // diagonal once).  k_resid_sym_reduce then sums, per row of block I,
-// RP[I][0..I] and CP[I][0..Q) in that fixed order.  With want_abs an extra
+// RP[I][0..I] (as four interleaved sums) and CP[I][0..Q), in a fixed order.  With want_abs an extra
 // "column" c = MC carries |a_ij| (row sums of |A|).
 #define RSYM_CH 16
 template <int MC, bool WA>
@@ -288,7 +288,10 @@ __global__ __launch_bounds__(256) void k_resid_reduce(const double *__restrict__
     }
 }
 
-// R = B - (sum_J RP[I][J] + sum_q CP[I][q]) and the norms (as k_resid_reduce)
+// R = B - (sum_J RP[I][J] + sum_q CP[I][q]) and the norms (as k_resid_reduce).
+// Workgroup (I, c): 64 rows of block I, four waves; wave p sums the partials
+// J = p, p + 4, ... (loads issued four at a time), and the four sums are
+// added in the fixed order (s0 + s1) + (s2 + s3), then the column partials.
 template <int MC>
 __global__ __launch_bounds__(256) void k_resid_sym_reduce(const double *__restrict__ B, int64_t ldb,
                                                           const double *__restrict__ X, int64_t ldx, int64_t n, int m,
@@ -298,23 +301,46 @@ __global__ __launch_bounds__(256) void k_resid_sym_reduce(const double *__restri
                                                           int64_t ldr, double *norms)
 {
     constexpr int NC = MC + 1;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int c = blockIdx.y;
+    __shared__ double part[2][4][64];
+    const int il = threadIdx.x & 63, p = threadIdx.x >> 6;
+    const int I = blockIdx.x, c = blockIdx.y;
     const int nrb = (int)((n + 63) / 64);
+    const bool wa = want_abs && c == 0;
+    {
+        const double *rp = RP + ((int64_t)I * nrb * NC + c) * 64 + il;
+        const double *ra = RP + ((int64_t)I * nrb * NC + MC) * 64 + il;
+        const int64_t st = (int64_t)NC * 64;  // stride between consecutive J
+        double y = 0.0, ya = 0.0;
+        int J = p;
+        for (; J + 12 <= I; J += 16) {
+            const double v0 = rp[J * st], v1 = rp[(J + 4) * st], v2 = rp[(J + 8) * st], v3 = rp[(J + 12) * st];
+            if (wa) {
+                const double a0 = ra[J * st], a1 = ra[(J + 4) * st], a2 = ra[(J + 8) * st], a3 = ra[(J + 12) * st];
+                ya = (((ya + a0) + a1) + a2) + a3;
+            }
+            y = (((y + v0) + v1) + v2) + v3;
+        }
+        for (; J <= I; J += 4) {
+            y += rp[J * st];
+            if (wa)
+                ya += ra[J * st];
+        }
+        part[0][p][il] = y;
+        part[1][p][il] = ya;
+    }
+    __syncthreads();
+    if (p != 0)
+        return;
+    const int64_t i = (int64_t)I * 64 + il;
     double vr = 0.0, vx = 0.0, vb = 0.0, vd = 0.0, va = 0.0;
     if (i < n) {
-        const int I = (int)(i / 64), il = (int)(i % 64);
-        double y = 0.0, ya = 0.0;
-        for (int J = 0; J <= I; ++J) {
-            y += RP[(((int64_t)I * nrb + J) * NC + c) * 64 + il];
-            if (want_abs && c == 0)
-                ya += RP[(((int64_t)I * nrb + J) * NC + MC) * 64 + il];
-        }
+        double y = (part[0][0][il] + part[0][1][il]) + (part[0][2][il] + part[0][3][il]);
+        double ya = (part[1][0][il] + part[1][1][il]) + (part[1][2][il] + part[1][3][il]);
         for (int q = 0; q < Q; ++q) {
             if (I + q * RSYM_CH >= nrb)
                 break;
             y += CP[(((int64_t)I * Q + q) * NC + c) * 64 + il];
-            if (want_abs && c == 0)
+            if (wa)
                 ya += CP[(((int64_t)I * Q + q) * NC + MC) * 64 + il];
         }
         const double b = B[i + c * ldb];
@@ -330,14 +356,14 @@ __global__ __launch_bounds__(256) void k_resid_sym_reduce(const double *__restri
     vx = wave_max2(vx);
     vb = wave_max2(vb);
     vd = wave_max2(vd);
-    if (want_abs && c == 0)
+    if (wa)
         va = wave_max2(va);
-    if ((threadIdx.x & 63) == 0) {
+    if (il == 0) {
         atomic_max_nonneg(norms + 1 + c, vr);
         atomic_max_nonneg(norms + 1 + m + c, vx);
         atomic_max_nonneg(norms + 1 + 2 * m + c, vb);
         atomic_max_nonneg(norms + 1 + 3 * m + c, vd);
-        if (want_abs && c == 0)
+        if (wa)
             atomic_max_nonneg(norms, va);
     }
 }
@@ -385,7 +411,7 @@ void launch_residual(const double *A, int64_t lda, int64_t n, const double *X, i
     if (m <= RSYM_MAX_M) {
         const int nrb = (int)((n + 63) / 64), Q = (nrb + RSYM_CH - 1) / RSYM_CH, mc = rsym_mc(m);
         double *RP = P, *CP = P + (int64_t)nrb * nrb * (mc + 1) * 64;
-        const dim3 g((unsigned)nrb, (unsigned)Q), gr((unsigned)((n + 255) / 256), (unsigned)m);
+        const dim3 g((unsigned)nrb, (unsigned)Q), gr((unsigned)nrb, (unsigned)m);
         if (mc == 1) {
             if (want_anorm)
                 hipLaunchKernelGGL((k_resid_sym<1, true>), g, dim3(256), 0, st, A, lda, n, X, ldx, m, Q, RP, CP);

@@ -90,7 +90,7 @@ def measured_traffic(prec):
         return None
     with open(path) as f:
         rec = json.load(f)
-    src = os.path.join(ROOT, "paper_1405_4644_amd", "csrc", "k_factor.hip")
+    src = os.path.join(ROOT, "paper_1405_4644_amd", "csrc", "k_update.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     if rec.get("source_sha256") != sha:

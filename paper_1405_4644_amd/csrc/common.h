@@ -84,43 +84,6 @@ template <> struct Frag<double> {
 };
 SPD_DEV void mma(Acc32<float> &acc, const Frag<float> &a, const Frag<float> &b) { acc.mma(a.v, b.v); }
 
-// A 32x32 binary32 tile as 2x2 blocks of v_mfma_f32_16x16x4f32 (lane l
-// supplies A[l%16][k0 + l/16] and B[l%16][k0 + l/16]; register j of a block
-// holds C[4*(l/16) + j][l%16], checked on the device).  Sixteen independent
-// accumulators per 64x64 wave tile keep the matrix pipe busy where the four
-// 32x32x2 chains of Acc32<float> cannot.
-struct Acc32x4 {
-    floatx4 v[2][2];
-    SPD_DEV void zero() {
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b)
-                for (int j = 0; j < 4; ++j) v[a][b][j] = 0.f;
-    }
-    SPD_DEV void mma(const float a[2], const float b[2]) {
-        for (int mi = 0; mi < 2; ++mi)
-            for (int ni = 0; ni < 2; ++ni)
-                v[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], v[mi][ni], 0, 0, 0);
-    }
-    // flattened register index j in [0,16): mi = j/8, ni = (j/4)%2, r = j%4
-    static SPD_DEV int row(int j, int l) { return 16 * (j / 8) + 4 * (l / 16) + (j % 4); }
-    static SPD_DEV int col(int j, int l) { return 16 * ((j / 4) % 2) + l % 16; }
-    static constexpr int NREG = 16;
-    SPD_DEV float get(int j) const { return v[j / 8][(j / 4) % 2][j % 4]; }
-    SPD_DEV void set(int j, float x) { v[j / 8][(j / 4) % 2][j % 4] = x; }
-};
-// k-step 4 fragment for Acc32x4: rows l%16 and 16 + l%16, column k0 + l/16
-struct Frag4f {
-    static constexpr int K = 4;
-    float v[2];
-    SPD_DEV void load(const float *p, int ks, int lane)
-    {
-        const int r = lane & 15, kk = lane >> 4;
-        v[0] = p[r + kk * ks];
-        v[1] = p[16 + r + kk * ks];
-    }
-    SPD_DEV void negate() { v[0] = -v[0]; v[1] = -v[1]; }
-};
-SPD_DEV void mma(Acc32x4 &acc, const Frag4f &a, const Frag4f &b) { acc.mma(a.v, b.v); }
 SPD_DEV void mma(Acc32<double> &acc, const Frag<double> &a, const Frag<double> &b) { acc.mma(a.v, b.v); }
 
 // acc += A(32 x kc) * B(32 x kc)^T with A(r,k) = pa[r + k*aks], B(r,k) = pb[r + k*bks];

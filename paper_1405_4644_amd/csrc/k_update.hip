@@ -1,0 +1,464 @@
+// Trailing update of the blocked factorisation: Algorithm 1, line 1 (the
+// Schur complement update of the low-precision Cholesky factor),
+//   H_ij -= L_ik L_jk^T   for the lower tiles of the trailing region,
+// on MFMA: binary32 (k_syrk_update_f32), binary64 (k_syrk_update<double>),
+// and binary16 / bfloat16 operands with binary32 accumulation
+// (k_syrk_update_h).  Launched by the factorisation driver per group of
+// panels (K = G NB) and within a group for its remaining panels.
+#include "common.h"
+#include "internal.h"
+#include "half_ops.h"
+#include <cstdlib>
+#include <type_traits>
+
+// ---------------------------------------------------------------------------
+// K4: trailing update H_ij -= L_ik L_jk^T on 128 x 128 lower tiles (MFMA).
+// Tiles are numbered over the lower triangle of the trailing region (t tiles
+// per side) restricted to tile columns [tj_lo, tj_hi): a range that stops
+// short of the last tile column (or spans at most four) is walked column by
+// column, a range reaching it as the lower triangle from (tj_lo, tj_lo) row
+// by row.  Block indices are remapped so that consecutive tiles land on the
+// same XCD (blocks are dispatched round-robin over the 8 XCDs).
+SPD_DEV void decode_tile(int b, int t, int tj_lo, int tj_hi, int &ti, int &tj)
+{
+    if (tj_hi < t || tj_hi - tj_lo <= 4) {
+        for (int c = tj_lo; c < tj_hi; ++c) {
+            const int cnt = t - c;
+            if (b < cnt) {
+                ti = c + b;
+                tj = c;
+                return;
+            }
+            b -= cnt;
+        }
+        ti = tj = -1;
+        return;
+    }
+    // lower triangle of the sub-block starting at tile (tj_lo, tj_lo), row-major
+    int r = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while (r * (r + 1) / 2 > b) --r;
+    while ((r + 1) * (r + 2) / 2 <= b) ++r;
+    ti = tj_lo + r;
+    tj = tj_lo + (b - r * (r + 1) / 2);
+}
+
+// binary64 (binary32 has its own kernel below)
+template <typename T> struct SyrkCfg;
+template <> struct SyrkCfg<double> {
+    static constexpr int KC = 16;
+    using Acc = Acc32<double>;
+    using Fr = Frag<double>;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t ld, int64_t k0, int nbk, int64_t r0,
+                                                     int t, int tj_lo, int tj_hi, int ntiles,
+                                                     const unsigned long long *info, int prio)
+{
+    constexpr int KC = SyrkCfg<T>::KC;
+    using AccT = typename SyrkCfg<T>::Acc;
+    using FragT = typename SyrkCfg<T>::Fr;
+    constexpr int LDT = SPD_TILE + 4;  // LDS column stride
+    __shared__ T As[2][KC * LDT];
+    __shared__ T Bs[2][KC * LDT];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (*(volatile const unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
+        return;
+    if (prio)
+        __builtin_amdgcn_s_setprio(2);  // the lookahead part of the update
+    // tiles of XCD x (blocks are dispatched round-robin over the 8 XCDs) are
+    // the contiguous range [x chunk, (x + 1) chunk); a grid smaller than the
+    // tile count loops (persistent), leaving compute-unit slots free
+    const int per = gridDim.x / 8, chunk = (ntiles + 7) / 8;
+    for (int it = blockIdx.x / 8; it < chunk; it += per) {
+    const int logical = (blockIdx.x % 8) * chunk + it;
+    if (logical >= ntiles)
+        break;
+    int ti, tj;
+    decode_tile(logical, t, tj_lo, tj_hi, ti, tj);
+    if (ti < 0)
+        break;
+    const int64_t crow = r0 + (int64_t)ti * SPD_TILE, ccol = r0 + (int64_t)tj * SPD_TILE;
+    const T *pa = H + ccol + k0 * ld;  // rows of tile tj (D rows = C columns)
+    const T *pb = H + crow + k0 * ld;  // rows of tile ti (D columns = C rows)
+    const int wm = wave >> 1, wn = wave & 1;
+
+    // The C tile is read once, up front, straight into the accumulators (so
+    // its latency overlaps the K loop); the MFMA operands are negated.
+    // Register j of tile (mi, ni) holds C[crow + 64 wn + 32 ni + col(j)][ccol + 64 wm + 32 mi + row(j)].
+    AccT acc[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int m = AccT::row(j, lane), nn = AccT::col(j, lane);
+                acc[mi][ni].set(j, H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld]);
+            }
+
+    // 128 rows x KC columns of each operand per chunk, 16-byte vector loads,
+    // staged through registers so the next chunk's loads overlap the MFMAs.
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int PER_COL = SPD_TILE / VEC;
+    constexpr int NV = PER_COL * KC / 256;  // vectors per thread per operand
+    static_assert(NV == 4, "staging layout");
+    // per-thread staging slots: vector v covers column col_v, rows r_v..r_v+VEC-1
+    int soff[NV];
+    size_t goff[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int idx = tid + 256 * v;
+        const int col = idx / PER_COL, r = (idx % PER_COL) * VEC;
+        soff[v] = col * LDT + r;
+        goff[v] = (size_t)col * ld + r;
+    }
+    V ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+#define SPD_GLOAD(kb)                                                       \
+    do {                                                                    \
+        const size_t o_ = (size_t)(kb) * ld;                                \
+        ra0 = *(const V *)&pa[o_ + goff[0]]; rb0 = *(const V *)&pb[o_ + goff[0]]; \
+        ra1 = *(const V *)&pa[o_ + goff[1]]; rb1 = *(const V *)&pb[o_ + goff[1]]; \
+        ra2 = *(const V *)&pa[o_ + goff[2]]; rb2 = *(const V *)&pb[o_ + goff[2]]; \
+        ra3 = *(const V *)&pa[o_ + goff[3]]; rb3 = *(const V *)&pb[o_ + goff[3]]; \
+    } while (0)
+#define SPD_SSTORE(buf)                                                     \
+    do {                                                                    \
+        *(V *)&As[buf][soff[0]] = ra0; *(V *)&Bs[buf][soff[0]] = rb0;       \
+        *(V *)&As[buf][soff[1]] = ra1; *(V *)&Bs[buf][soff[1]] = rb1;       \
+        *(V *)&As[buf][soff[2]] = ra2; *(V *)&Bs[buf][soff[2]] = rb2;       \
+        *(V *)&As[buf][soff[3]] = ra3; *(V *)&Bs[buf][soff[3]] = rb3;       \
+    } while (0)
+
+    SPD_GLOAD(0);
+    SPD_SSTORE(0);
+    __syncthreads();
+    int buf = 0;
+    for (int kb = 0; kb < nbk; kb += KC) {
+        // prefetch the next chunk (the last iteration re-reads its own chunk)
+        const int kn = (kb + KC < nbk) ? kb + KC : kb;
+        SPD_GLOAD(kn);
+        // keep the next chunk's loads here, ahead of the MFMAs (the scheduler
+        // would otherwise sink them to their LDS stores and expose their latency)
+        __builtin_amdgcn_sched_barrier(0);
+        const T *a0 = &As[buf][64 * wm];
+        const T *b0 = &Bs[buf][64 * wn];
+#pragma unroll
+        for (int k = 0; k < KC; k += FragT::K) {
+            FragT fa[2], fb[2];
+            fa[0].load(a0 + k * LDT, LDT, lane);
+            fa[1].load(a0 + 32 + k * LDT, LDT, lane);
+            fb[0].load(b0 + k * LDT, LDT, lane);
+            fb[1].load(b0 + 32 + k * LDT, LDT, lane);
+            fa[0].negate();
+            fa[1].negate();
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    mma(acc[mi][ni], fa[mi], fb[ni]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        SPD_SSTORE(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+#undef SPD_GLOAD
+#undef SPD_SSTORE
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int m = AccT::row(j, lane), nn = AccT::col(j, lane);
+                H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld] = acc[mi][ni].get(j);
+            }
+    __syncthreads();  // shared memory is reused by the next tile
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K4, binary32: the same update written for v_mfma_f32_16x16x4f32, on TS x TS
+// tiles (TS = 128, or 64 when a launch has too few 128-tiles to fill the
+// chip).  Each wave owns a TS/2 x TS/2 block of D = C^T as NB x NB 16 x 16
+// accumulators holding -C (the sign is applied once on load and once on
+// store, so the K loop only multiplies and adds).  Shared memory holds 32
+// columns of each operand as [k][row] with TS floats per k and the row index
+// XOR-ed with 16 (k % 4): a fragment read (lane l: row 16 b + l%16, k = 4 s +
+// l/16) then touches 64 distinct banks, and the 16-byte staging stores stay
+// contiguous.  Tiles are counted in TS units over the lower triangle of the
+// trailing region (t tiles per side), tile columns [tj_lo, tj_hi).
+template <int TS>
+__global__ __launch_bounds__(256, 2) void k_syrk_update_f32(float *__restrict__ H, int64_t ld, int64_t k0, int nbk,
+                                                           int64_t r0, int t, int tj_lo, int tj_hi, int ntiles,
+                                                           const unsigned long long *info, int prio)
+{
+    constexpr int KC = 32, NB = TS / 32, NV = TS / 32;  // 16-blocks per wave side; staged float4 per thread
+    __shared__ __align__(16) float As[2][KC * TS];
+    __shared__ __align__(16) float Bs[2][KC * TS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (*(volatile const unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
+        return;
+    if (prio)
+        __builtin_amdgcn_s_setprio(2);  // the lookahead part of the update
+    const int wm = wave >> 1, wn = wave & 1, r = lane & 15, u = lane >> 4;
+    const int ldi = (int)ld;  // offsets within a tile row block of <= 512 columns fit in 32 bits
+    // staging: thread covers rows 4 (tid % (TS/4)) .. +3 of columns tid / (TS/4) + (1024/TS) v
+    constexpr int TPC = TS / 4, CSTEP = 256 / TPC;
+    const int scol = tid / TPC, srow = (tid % TPC) * 4;
+    const int goff = scol * ldi + srow;
+    const int soff = scol * TS + (srow ^ (16 * (scol & 3)));  // CSTEP is a multiple of 4: col % 4 fixed
+    // fragment offsets: row 16 b + r of the wave's TS/2 rows, k-slot u (+ 4 s TS for k-step s)
+    int fa[NB], fb[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        fa[b] = u * TS + (((TS / 2) * wm + 16 * b) ^ (16 * u)) + r;
+        fb[b] = u * TS + (((TS / 2) * wn + 16 * b) ^ (16 * u)) + r;
+    }
+    const int coff = r + 4 * u * ldi;
+    const int per = gridDim.x / 8, chunk = (ntiles + 7) / 8;
+    for (int it = blockIdx.x / 8; it < chunk; it += per) {
+        const int logical = (blockIdx.x % 8) * chunk + it;
+        if (logical >= ntiles)
+            break;
+        int ti, tj;
+        decode_tile(logical, t, tj_lo, tj_hi, ti, tj);
+        if (ti < 0)
+            break;
+        const int64_t crow = r0 + (int64_t)ti * TS, ccol = r0 + (int64_t)tj * TS;
+        const float *pa = H + ccol + k0 * ld;  // rows of tile tj (D rows = C columns)
+        const float *pb = H + crow + k0 * ld;  // rows of tile ti (D columns = C rows)
+        // register q of block (mi, ni): -C[crow + TS/2 wn + 16 ni + r][ccol + TS/2 wm + 16 mi + 4 u + q]
+        float *cu = H + (crow + (TS / 2) * wn) + (ccol + (TS / 2) * wm) * ld;
+        floatx4 c[NB][NB];
+#pragma unroll
+        for (int mi = 0; mi < NB; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < NB; ++ni)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    c[mi][ni][q] = -cu[coff + 16 * ni + (16 * mi + q) * ldi];
+        // staging registers (named, not an array, so that they stay registers)
+        float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+#define SPD_GL(o)                                                                         \
+    do {                                                                                  \
+        ra0 = *(const float4 *)&pa[(o) + goff];                                           \
+        rb0 = *(const float4 *)&pb[(o) + goff];                                           \
+        ra1 = *(const float4 *)&pa[(o) + goff + CSTEP * ldi];                             \
+        rb1 = *(const float4 *)&pb[(o) + goff + CSTEP * ldi];                             \
+        if constexpr (NV > 2) {                                                           \
+            ra2 = *(const float4 *)&pa[(o) + goff + 2 * CSTEP * ldi];                     \
+            rb2 = *(const float4 *)&pb[(o) + goff + 2 * CSTEP * ldi];                     \
+            ra3 = *(const float4 *)&pa[(o) + goff + 3 * CSTEP * ldi];                     \
+            rb3 = *(const float4 *)&pb[(o) + goff + 3 * CSTEP * ldi];                     \
+        }                                                                                 \
+    } while (0)
+#define SPD_SS(bf)                                                                        \
+    do {                                                                                  \
+        *(float4 *)&As[bf][soff] = ra0;                                                   \
+        *(float4 *)&Bs[bf][soff] = rb0;                                                   \
+        *(float4 *)&As[bf][soff + CSTEP * TS] = ra1;                                      \
+        *(float4 *)&Bs[bf][soff + CSTEP * TS] = rb1;                                      \
+        if constexpr (NV > 2) {                                                           \
+            *(float4 *)&As[bf][soff + 2 * CSTEP * TS] = ra2;                              \
+            *(float4 *)&Bs[bf][soff + 2 * CSTEP * TS] = rb2;                              \
+            *(float4 *)&As[bf][soff + 3 * CSTEP * TS] = ra3;                              \
+            *(float4 *)&Bs[bf][soff + 3 * CSTEP * TS] = rb3;                              \
+        }                                                                                 \
+    } while (0)
+        static_assert(NV == 2 || NV == 4, "staging layout");
+        SPD_GL(0);
+        SPD_SS(0);
+        lds_barrier();
+        int buf = 0;
+        for (int kb = 0; kb < nbk; kb += KC) {
+            // prefetch the next chunk (the last iteration re-reads its own chunk)
+            const int o = ((kb + KC < nbk) ? kb + KC : kb) * ldi;
+            SPD_GL(o);
+            __builtin_amdgcn_sched_barrier(0);
+            const float *A0 = As[buf], *B0 = Bs[buf];
+#pragma unroll
+            for (int ks = 0; ks < KC / 4; ++ks) {
+                float a[NB], b[NB];
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    a[i] = A0[4 * ks * TS + fa[i]];
+                    b[i] = B0[4 * ks * TS + fb[i]];
+                }
+#pragma unroll
+                for (int mi = 0; mi < NB; ++mi)
+#pragma unroll
+                    for (int ni = 0; ni < NB; ++ni)
+                        c[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], c[mi][ni], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            SPD_SS(buf ^ 1);
+            lds_barrier();
+            buf ^= 1;
+        }
+#undef SPD_GL
+#undef SPD_SS
+#pragma unroll
+        for (int mi = 0; mi < NB; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < NB; ++ni)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    cu[coff + 16 * ni + (16 * mi + q) * ldi] = -c[mi][ni][q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K4, half-precision operands: H_ij -= round(L_ik) round(L_jk)^T with
+// binary16 or bfloat16 operands and binary32 accumulation
+// (v_mfma_f32_32x32x16_{f16,bf16}), one or two panels of K = 128.  The operand panel is the
+// fragment-layout copy written by the panel solve: row r (relative to the
+// first trailing row), column k lives at
+//   ((r/32) (NB/16) + k/16) * 512 + (32 ((k%16)/8) + r%32) * 8 + k%8,
+// so every fragment load is one contiguous 1 KiB per wave.  The C tile is the
+// only HBM traffic that scales with the tile count: 64 KiB in, 64 KiB out.
+template <int HK>
+__global__ __launch_bounds__(256) void k_syrk_update_h(float *__restrict__ H, int64_t ld,
+                                                       const void *__restrict__ Lh0, int skip0,
+                                                       const void *__restrict__ Lh1, int skip1, int64_t r0, int t,
+                                                       int tj_lo, int tj_hi, int ntiles,
+                                                       const unsigned long long *info, int prio)
+{
+    using V8 = typename HalfT<HK>::V8;
+    constexpr int KS = 128 / 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (*(volatile const unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
+        return;
+    if (prio)
+        __builtin_amdgcn_s_setprio(2);
+    // tiles of XCD x (blocks are dispatched round-robin over the 8 XCDs) are
+    // the contiguous range [x chunk, (x + 1) chunk); a grid smaller than the
+    // tile count loops (persistent), leaving compute-unit slots free
+    const int per = gridDim.x / 8, chunk = (ntiles + 7) / 8;
+    for (int it = blockIdx.x / 8; it < chunk; it += per) {
+    const int logical = (blockIdx.x % 8) * chunk + it;
+    if (logical >= ntiles)
+        break;
+    int ti, tj;
+    decode_tile(logical, t, tj_lo, tj_hi, ti, tj);
+    if (ti < 0)
+        break;
+    const int64_t crow = r0 + (int64_t)ti * SPD_TILE, ccol = r0 + (int64_t)tj * SPD_TILE;
+    const int wm = wave >> 1, wn = wave & 1;
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int m = Acc32<float>::row(j, lane), nn = Acc32<float>::col(j, lane);
+                acc[mi][ni][j] = H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld];
+            }
+    // one or two panels (K = 128 each); `skip` 32-row blocks precede row r0
+    // in a panel's copy
+    for (int pnl = 0; pnl < 2; ++pnl) {
+        const V8 *lh = (const V8 *)(pnl == 0 ? Lh0 : Lh1);
+        if (!lh)
+            break;
+        const int skip = pnl == 0 ? skip0 : skip1;
+        // A operand: rows of tile tj (C columns); B operand: rows of tile ti (C rows)
+        const V8 *pa0 = lh + (size_t)(skip + 4 * tj + 2 * wm) * KS * 64 + lane;
+        const V8 *pb0 = lh + (size_t)(skip + 4 * ti + 2 * wn) * KS * 64 + lane;
+        V8 fa[KS][2], fb[KS][2];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                fa[ks][q] = pa0[(q * KS + ks) * 64];
+                fb[ks][q] = pb0[(q * KS + ks) * 64];
+            }
+        // all operand loads in flight before the first MFMA
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi) {
+                const V8 na = HalfT<HK>::neg(fa[ks][mi]);
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = HalfT<HK>::mma(na, fb[ks][ni], acc[mi][ni]);
+            }
+        }
+    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int m = Acc32<float>::row(j, lane), nn = Acc32<float>::col(j, lane);
+                H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld] = acc[mi][ni][j];
+            }
+    }
+}
+
+namespace spd {
+
+void launch_syrk_update_half(float *H, int64_t ld, const void *Lh0, int skip0, const void *Lh1, int skip1, int half,
+                             int64_t r0, int t, int tj_lo, int tj_hi, const unsigned long long *info, hipStream_t st,
+                             int prio, int max_grid)
+{
+    if (t <= 0 || tj_lo >= tj_hi) return;
+    int64_t ntiles = 0;
+    for (int c = tj_lo; c < tj_hi; ++c) ntiles += t - c;
+    int64_t grid = ((ntiles + 7) / 8) * 8;
+    if (max_grid > 0 && grid > max_grid) grid = (max_grid / 8) * 8;
+    if (half == HALF_F16)
+        hipLaunchKernelGGL(k_syrk_update_h<HALF_F16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh0, skip0,
+                           Lh1, skip1, r0, t, tj_lo, tj_hi, (int)ntiles, info, prio);
+    else
+        hipLaunchKernelGGL(k_syrk_update_h<HALF_BF16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh0, skip0,
+                           Lh1, skip1, r0, t, tj_lo, tj_hi, (int)ntiles, info, prio);
+}
+
+// Below this many 128-tiles a binary32 update runs on 64-tiles (SPD_SMALL_TILES overrides).
+static int small_update_tiles()
+{
+    static const int v = [] {
+        const char *e = std::getenv("SPD_SMALL_TILES");
+        return e ? std::atoi(e) : 512;
+    }();
+    return v;
+}
+#define kSmallUpdateTiles small_update_tiles()
+
+template <typename T>
+void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,
+                        const unsigned long long *info, hipStream_t st, int prio, int max_grid)
+{
+    if (t <= 0 || tj_lo >= tj_hi) return;
+    int64_t ntiles = 0;
+    for (int c = tj_lo; c < tj_hi; ++c) ntiles += t - c;
+    int64_t grid = ((ntiles + 7) / 8) * 8;
+    if (max_grid > 0 && grid > max_grid) grid = (max_grid / 8) * 8;
+    if constexpr (sizeof(T) == 4) {
+        if (ntiles < kSmallUpdateTiles && max_grid == 0) {
+            // too few 128-tiles for the chip: 64-tiles, four times as many workgroups
+            const int t2 = 2 * t, lo2 = 2 * tj_lo, hi2 = 2 * tj_hi;
+            int64_t n2 = 0;
+            for (int c = lo2; c < hi2; ++c) n2 += t2 - c;
+            const int64_t g2 = ((n2 + 7) / 8) * 8;
+            hipLaunchKernelGGL(k_syrk_update_f32<64>, dim3((unsigned)g2), dim3(256), 0, st, H, ld, k0, nbk, r0, t2,
+                               lo2, hi2, (int)n2, info, prio);
+        } else {
+            hipLaunchKernelGGL(k_syrk_update_f32<128>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, k0, nbk, r0,
+                               t, tj_lo, tj_hi, (int)ntiles, info, prio);
+        }
+    } else
+        hipLaunchKernelGGL(k_syrk_update<T>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, k0, nbk, r0, t, tj_lo,
+                           tj_hi, (int)ntiles, info, prio);
+}
+template void launch_syrk_update<float>(float *, int64_t, int64_t, int, int64_t, int, int, int,
+                                        const unsigned long long *, hipStream_t, int, int);
+template void launch_syrk_update<double>(double *, int64_t, int64_t, int, int64_t, int, int, int,
+                                         const unsigned long long *, hipStream_t, int, int);
+
+}  // namespace spd

@@ -30,28 +30,34 @@ __global__ void k_equil(const double *__restrict__ A, int64_t lda, int64_t n, do
 }
 
 // K1b: H = round(mu * D A D) on the lower triangle; identity padding.
-// Grid: x = row tiles of 256 rows, y = groups of 8 columns.
+// Grid: x = row tiles of 256 rows, y = groups of 64 columns (eight at a
+// time: eight loads in flight per thread before the stores).
 template <typename T>
 __global__ __launch_bounds__(256) void k_convert(const double *__restrict__ A, int64_t lda, int64_t n, int64_t npad,
                                                  const double *__restrict__ d, double mu, T *__restrict__ H,
                                                  int64_t ldh)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t j0 = (int64_t)blockIdx.y * 8;
-    if ((int64_t)blockIdx.x * 256 + 255 < j0 || i >= npad)
+    const int64_t jb = (int64_t)blockIdx.y * 64;
+    if ((int64_t)blockIdx.x * 256 + 255 < jb || i >= npad)
         return;
     const double mdi = (i < n) ? mu * d[i] : 0.0;
+    for (int64_t j0 = jb; j0 < jb + 64 && j0 <= i && j0 < npad; j0 += 8) {
+        double a[8], dj[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int64_t j = j0 + c;
-        if (j > i || j >= npad)
-            continue;
-        T v;
-        if (i < n && j < n)
-            v = (T)((mdi * A[i + j * lda]) * d[j]);
-        else
-            v = (i == j) ? (T)1 : (T)0;
-        H[i + j * ldh] = v;
+        for (int c = 0; c < 8; ++c) {
+            const int64_t j = j0 + c;
+            const bool in = (j <= i && i < n && j < n);
+            a[c] = in ? A[i + j * lda] : 0.0;
+            dj[c] = in ? d[j] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int64_t j = j0 + c;
+            if (j > i || j >= npad)
+                continue;
+            H[i + j * ldh] = (i < n && j < n) ? (T)((mdi * a[c]) * dj[c]) : ((i == j) ? (T)1 : (T)0);
+        }
     }
 }
 
@@ -732,7 +738,7 @@ template <typename T>
 void launch_convert(const double *A, int64_t lda, int64_t n, int64_t npad, const double *d, double mu, T *H,
                     int64_t ldh, hipStream_t st)
 {
-    dim3 grid((unsigned)(npad / 256 + (npad % 256 != 0)), (unsigned)((npad + 7) / 8));
+    dim3 grid((unsigned)(npad / 256 + (npad % 256 != 0)), (unsigned)((npad + 63) / 64));
     hipLaunchKernelGGL(k_convert<T>, grid, dim3(256), 0, st, A, lda, n, npad, d, mu, H, ldh);
 }
 template void launch_convert<float>(const double *, int64_t, int64_t, int64_t, const double *, double, float *,

@@ -24,15 +24,27 @@
 //
 // Waits are bounded: after ~1 s without progress a workgroup raises the
 // error flag and leaves; every other waiter sees the flag and leaves too.
+//
+// Publishing a task's results: each XCD has its own L2, and a release fence
+// at agent scope writes that whole cache back to memory; once per task it
+// cuts the kernel's streaming rate about threefold.  Results that other
+// workgroups read are therefore written with agent-scope stores (coherent
+// across the L2s by themselves), and publishing waits only for those stores
+// to complete before the counter is raised.  The waiting side reads them
+// with agent-scope loads in turn, so it needs no acquire fence (an L2
+// invalidate) either.
 #include "common.h"
 #include "internal.h"
 
 #define TRSV_TIMEOUT_TICKS 100000000ULL  // wall_clock64 runs at 100 MHz on gfx9
 #define TRSV_NBS 1024                    // big diagonal block
+#define TRSV_NCRIT 64                    // workgroups on the chain's tasks
+#define TRSV_NBULK 192                   // workgroups streaming the other blocks
+#define TRSV_CDEPTH 1                    // U(p, p+d) tasks taken by the chain: d <= this
 
 // thread 0 only: wait until *addr >= want, or give up.  The polling loads are
 // relaxed agent-scope atomics (coherent loads that do not invalidate the
-// caches); one acquire fence follows a successful wait.
+// caches).
 SPD_DEV bool wait_ge(int *addr, int want, int *err)
 {
     const unsigned long long t0 = wall_clock64();
@@ -45,8 +57,19 @@ SPD_DEV bool wait_ge(int *addr, int want, int *err)
         }
         __builtin_amdgcn_s_sleep(2);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
+}
+
+// a result that other workgroups read (agent-coherent store), and its read
+template <typename T>
+SPD_DEV void store_shared(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+SPD_DEV T load_shared(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -303,16 +326,19 @@ template <typename T, int MC, bool FWD>
 __global__ __launch_bounds__(256) void k_trsv_blk(const T *__restrict__ L, int64_t ld, const T *__restrict__ WB,
                                                   int64_t npad, int nbs, int K, const T *__restrict__ Yin,
                                                   T *__restrict__ Zout, int64_t ldy, int c0, int m,
-                                                  T *__restrict__ P, int *ctl, int *err)
+                                                  T *__restrict__ P, int *ctl, int *err, int ncrit, int cdepth)
 {
     constexpr int NBS = TRSV_NBS;
     using BV = BlockVec<T, MC, FWD, NBS>;
     constexpr int R = BV::R;
+    // vector entries per thread, and partials summed per batch of loads
+    constexpr int PER = MC * NBS / 256, QB = PER >= 32 ? 1 : 32 / PER;
     __shared__ T vs[MC][NBS];
     __shared__ T red[4][R][MC];
-    __shared__ int s_task, s_ok;
+    __shared__ int s_task, s_ok, s_crit;
     const int tid = threadIdx.x;
-    int *qhead = ctl, *cntA = ctl + 1, *cntB = ctl + 1 + K, *cntZ = ctl + 1 + 2 * K;
+    int *qcrit = ctl, *qbulk = ctl + 1, *ticket = ctl + 2;
+    int *cntA = ctl + 3, *cntB = ctl + 3 + K, *cntZ = ctl + 3 + 2 * K;
     const int mc = min(MC, m - c0);
     BV bv;
     // Blocks in processing order p (FWD: block p; BWD: block K-1-p); only
@@ -335,32 +361,50 @@ __global__ __launch_bounds__(256) void k_trsv_blk(const T *__restrict__ L, int64
         }
     };
 
+    // The first ncrit workgroups to start take the chain's tasks in step
+    // order: every Z(p), the U(p, p+1) that feeds the next Z, and the U(p,
+    // p+d) for d <= cdepth; the others take the remaining U tasks column by
+    // column.  A workgroup that has started is resident, so the chain never
+    // waits for a workgroup that cannot run.
+    if (tid == 0)
+        s_crit = atomicAdd(ticket, 1) < ncrit;
+    __syncthreads();
+    const bool crit = s_crit != 0;
     for (;;) {
         if (tid == 0)
-            s_task = atomicAdd(qhead, 1);
+            s_task = atomicAdd(crit ? qcrit : qbulk, 1);
         __syncthreads();
-        // decode, column by column in processing order: column pj holds
-        // Z(pj, 0..) followed by U(pj, pi, 0..) for the blocks pi after it
-        int rem = s_task, pj = 0;
-        for (; pj < K; ++pj) {
-            const int cnt = (int)((npad - rows_before(pj)) / R);
-            if (rem < cnt)
-                break;
-            rem -= cnt;
-        }
-        if (pj >= K)
-            return;
-        int pi, c;
-        const int ncj = proc_size(pj) / R;
-        if (rem < ncj) {
-            pi = pj;
-            c = rem;
+        int rem = s_task, pi = -1, pj = -1, c = 0;
+        if (crit) {
+            // step p: Z(p, 0..), then U(p, p+d, 0..) for d = 1 .. cdepth
+            for (int p = 0; p < K && pi < 0; ++p) {
+                for (int d = 0; d <= cdepth && p + d < K; ++d) {
+                    const int nt = proc_size(p + d) / R;
+                    if (rem < nt) {
+                        pj = p;
+                        pi = p + d;
+                        c = rem;
+                        break;
+                    }
+                    rem -= nt;
+                }
+            }
         } else {
-            const int64_t pos = rows_before(pj) + proc_size(pj) + (int64_t)(rem - ncj) * R;
-            int off;
-            proc_locate(pos, pi, off);
-            c = off / R;
+            // column q: U(q, pi, 0..) for the blocks pi from q+1+cdepth on
+            for (int q = 0; q + 1 + cdepth < K; ++q) {
+                const int cnt = (int)((npad - rows_before(q + 1 + cdepth)) / R);
+                if (rem < cnt) {
+                    int off;
+                    proc_locate(rows_before(q + 1 + cdepth) + (int64_t)rem * R, pi, off);
+                    pj = q;
+                    c = off / R;
+                    break;
+                }
+                rem -= cnt;
+            }
         }
+        if (pi < 0)
+            return;
         const int nc = proc_size(pi) / R;
         const bool ztask = (pj == pi);
         const int ki = FWD ? pi : K - 1 - pi, kj = FWD ? pj : K - 1 - pj;
@@ -397,10 +441,18 @@ __global__ __launch_bounds__(256) void k_trsv_blk(const T *__restrict__ L, int64
             __syncthreads();
             if (!s_ok)
                 return;
-            for (int idx = tid; idx < MC * NBS; idx += 256) {
-                const int t = idx % NBS, cc = idx / NBS;
+            // all of this thread's loads issued before the first use
+            T zv[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int t = (tid + 256 * k) % NBS, cc = (tid + 256 * k) / NBS;
+                zv[k] = (t < sj && cc < mc) ? load_shared(&Zout[(oj + t) + (int64_t)(c0 + cc) * ldy]) : (T)0;
+            }
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int t = (tid + 256 * k) % NBS, cc = (tid + 256 * k) / NBS;
                 if (t < sj)
-                    vs[cc][t] = (cc < mc) ? Zout[(oj + t) + (int64_t)(c0 + cc) * ldy] : (T)0;
+                    vs[cc][t] = zv[k];
             }
         } else {
             if (pi >= 2) {
@@ -410,14 +462,34 @@ __global__ __launch_bounds__(256) void k_trsv_blk(const T *__restrict__ L, int64
                 if (!s_ok)
                     return;
             }
-            // v = y - (sum of the partials of blocks finished a step ago), fixed order
-            for (int idx = tid; idx < MC * NBS; idx += 256) {
-                const int t = idx % NBS, cc = idx / NBS;
-                if (t >= lo && t < hi) {
-                    T sA = (T)0;
-                    for (int q = 0; q + 1 < pi; ++q) sA += Pbase[(int64_t)q * NBS * MC + cc * NBS + t];
-                    vs[cc][t] = (cc < mc) ? Yin[(oi + t) + (int64_t)(c0 + cc) * ldy] - sA : (T)0;
-                }
+            // v = y - (sum of the partials of blocks finished a step ago), in
+            // order of q; the loads go out QB partials at a time
+            T sA[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) sA[k] = (T)0;
+            for (int q0 = 0; q0 + 1 < pi; q0 += QB) {
+                T pv[QB][PER];
+#pragma unroll
+                for (int u = 0; u < QB; ++u)
+#pragma unroll
+                    for (int k = 0; k < PER; ++k) {
+                        const int t = (tid + 256 * k) % NBS, cc = (tid + 256 * k) / NBS;
+                        pv[u][k] = (q0 + u + 1 < pi && t >= lo && t < hi)
+                                       ? load_shared(&Pbase[(int64_t)(q0 + u) * NBS * MC + cc * NBS + t])
+                                       : (T)0;
+                    }
+#pragma unroll
+                for (int u = 0; u < QB; ++u)
+#pragma unroll
+                    for (int k = 0; k < PER; ++k)
+                        if (q0 + u + 1 < pi)
+                            sA[k] += pv[u][k];
+            }
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int t = (tid + 256 * k) % NBS, cc = (tid + 256 * k) / NBS;
+                if (t >= lo && t < hi)
+                    vs[cc][t] = (cc < mc) ? Yin[(oi + t) + (int64_t)(c0 + cc) * ldy] - sA[k] : (T)0;
             }
             if (pi >= 1) {
                 if (tid == 0)
@@ -426,10 +498,17 @@ __global__ __launch_bounds__(256) void k_trsv_blk(const T *__restrict__ L, int64
                 if (!s_ok)
                     return;
                 const T *pB = Pbase + (int64_t)(pi - 1) * NBS * MC;
-                for (int idx = tid; idx < MC * NBS; idx += 256) {
-                    const int t = idx % NBS, cc = idx / NBS;
+                T bv_[PER];
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int t = (tid + 256 * k) % NBS, cc = (tid + 256 * k) / NBS;
+                    bv_[k] = (t >= lo && t < hi) ? load_shared(&pB[cc * NBS + t]) : (T)0;
+                }
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int t = (tid + 256 * k) % NBS, cc = (tid + 256 * k) / NBS;
                     if (t >= lo && t < hi)
-                        vs[cc][t] -= pB[cc * NBS + t];
+                        vs[cc][t] -= bv_[k];
                 }
             }
         }
@@ -452,18 +531,20 @@ __global__ __launch_bounds__(256) void k_trsv_blk(const T *__restrict__ L, int64
         }
         if (FWD) {
             if (tid < R * MC && tid / R < nvalid)
-                dst[tid % R + (tid / R) * dcol] = out[0];
+                store_shared(&dst[tid % R + (tid / R) * dcol], out[0]);
         } else if (tid % BV::TPC == 0) {
 #pragma unroll
             for (int cc = 0; cc < MC; ++cc)
                 if (cc < nvalid)
-                    dst[tid / BV::TPC + cc * dcol] = out[cc];
+                    store_shared(&dst[tid / BV::TPC + cc * dcol], out[cc]);
         }
+        // every thread's result stores complete, then one relaxed increment
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tid == 0) {
             int *ctr = ztask ? &cntZ[pi] : (pj == pi - 1 ? &cntB[pi] : &cntA[pi]);
-            __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -503,7 +584,7 @@ int64_t trsv_scratch_elems(int64_t npad)
     return std::max<int64_t>(K * (K - 1) / 2, 1) * TRSV_NBS * TRSV_MC;
 }
 
-int trsv_ctl_ints(int64_t npad) { return 1 + 3 * solve_nblocks(npad); }
+int trsv_ctl_ints(int64_t npad) { return 3 + 3 * solve_nblocks(npad); }
 
 template <typename T>
 void launch_build_winv(const T *L, int64_t ld, int64_t npad, const T *W128, T *WB, T *Tb, hipStream_t st)
@@ -531,28 +612,33 @@ static void launch_dir(const T *L, int64_t ld, const T *WB, int64_t npad, int m,
 {
     const int nbs = solve_nbs(npad), K = solve_nblocks(npad);
     constexpr int R = 8 * VecOf<T>::N;
-    int64_t total = 0;
+    // chain tasks: every Z and U(p, p+d), d <= TRSV_CDEPTH; the other U
+    // tasks stream
+    const int cdepth = TRSV_CDEPTH;
+    int64_t ncrit_tasks = 0, nbulk_tasks = 0;
     for (int p = 0; p < K; ++p) {
         const int64_t o = (int64_t)p * nbs, sz = std::min<int64_t>(nbs, npad - o);
-        total += (p + 1) * (sz / R);
+        ncrit_tasks += (1 + std::min(p, cdepth)) * (sz / R);
+        nbulk_tasks += std::max(p - cdepth, 0) * (sz / R);
     }
-    const int grid = (int)std::min<int64_t>(total, 512);
+    const int ncrit = (int)std::min<int64_t>(ncrit_tasks, TRSV_NCRIT);
+    const int grid = ncrit + (int)std::min<int64_t>(nbulk_tasks, TRSV_NBULK);
     const int nctl = trsv_ctl_ints(npad);
     for (int c0 = 0; c0 < m; c0 += TRSV_MC) {
         hipLaunchKernelGGL(k_zero_int, dim3((nctl + 255) / 256), dim3(256), 0, st, ctl, nctl);
         const int mc = m - c0;
         if (mc == 1)
             hipLaunchKernelGGL((k_trsv_blk<T, 1, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K, Yin,
-                               Zout, ldy, c0, m, P, ctl, err);
+                               Zout, ldy, c0, m, P, ctl, err, ncrit, cdepth);
         else if (mc == 2)
             hipLaunchKernelGGL((k_trsv_blk<T, 2, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K, Yin,
-                               Zout, ldy, c0, m, P, ctl, err);
+                               Zout, ldy, c0, m, P, ctl, err, ncrit, cdepth);
         else if (mc <= 4)
             hipLaunchKernelGGL((k_trsv_blk<T, 4, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K, Yin,
-                               Zout, ldy, c0, m, P, ctl, err);
+                               Zout, ldy, c0, m, P, ctl, err, ncrit, cdepth);
         else
             hipLaunchKernelGGL((k_trsv_blk<T, TRSV_MC, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K,
-                               Yin, Zout, ldy, c0, m, P, ctl, err);
+                               Yin, Zout, ldy, c0, m, P, ctl, err, ncrit, cdepth);
     }
 }
 

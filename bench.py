@@ -8,6 +8,7 @@ equilibrate/convert, low-precision factorisation, first solve, and the
 binary64 refinement loop until the backward error reaches binary64 level.
 
     python bench.py [--steps K] [--warmup W] [--n 16384] [--cond 1e4] [--nrhs 1]
+    python bench.py --workload covariance [--decay 1|2|4]   # Section 4 matrix, n=70000, 32 RHS
 
 Prints ONE JSON line on stdout (progress goes to stderr).  `value` is the
 effective rate F(n, m) / t_step with F = n^3/3 + n^2/2 + n/6 + 2 n^2 m (the
@@ -43,10 +44,11 @@ def algo_flops(n: int, m: int) -> float:
     return n ** 3 / 3.0 + n ** 2 / 2.0 + n / 6.0 + 2.0 * n ** 2 * m
 
 
-def cpu_baseline_leg(args, A_dev, X_dev, B_dev):
+def cpu_baseline_leg(args, A_dev, X_dev, B_dev, rows_check=True):
     """The only part of the benchmark that runs the CPU oracle: (1) the oracle's
     binary64 solve timed on a bounded sample system of the same recipe, and
-    (2) the oracle's residual on sampled rows of the GPU solution."""
+    (2) the oracle's residual on sampled rows of the GPU solution (it reads
+    the whole matrix on the host: skipped above n = 32768)."""
     import numpy as np
 
     import oracle
@@ -62,6 +64,12 @@ def cpu_baseline_leg(args, A_dev, X_dev, B_dev):
     t = time.perf_counter() - t0
     rate = algo_flops(ns, args.nrhs) / t / 1e12
     log(f"cpu oracle: n={ns} solve {t:.2f} s -> {rate * 1e3:.3f} GFLOP/s on {oracle.threads()} threads")
+    cpu = {"value": rate, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"oracle binary64 Cholesky + substitution (potrf+potrs) of the leading {ns} x {ns} "
+                     f"principal block of the benchmark matrix, {args.nrhs} RHS, {t:.1f} s; "
+                     f"rate = F(n,m)/t at that n"}
+    if not rows_check:
+        return cpu, None
     # oracle check of the GPU result on sampled rows
     n = A_dev.shape[0]
     rng = np.random.Generator(np.random.PCG64(7))
@@ -72,12 +80,8 @@ def cpu_baseline_leg(args, A_dev, X_dev, B_dev):
     R = oracle.residual_rows(A, Xh, Bh, rows)
     anorm_rows = np.abs(A[rows, :]).sum(axis=1).max()
     eta_rows = float(np.max(np.abs(R)) / (anorm_rows * np.max(np.abs(Xh)) + np.max(np.abs(Bh))))
-    return ({"value": rate, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
-             "sample": f"oracle binary64 Cholesky + substitution (potrf+potrs) of the leading {ns} x {ns} "
-                       f"principal block of the benchmark matrix, {args.nrhs} RHS, {t:.1f} s; "
-                       f"rate = F(n,m)/t at that n"},
-            {"rows": int(rows.size), "max_abs_residual": float(np.max(np.abs(R))),
-             "eta_lower_bound_rows": eta_rows})
+    return cpu, {"rows": int(rows.size), "max_abs_residual": float(np.max(np.abs(R))),
+                 "eta_lower_bound_rows": eta_rows}
 
 
 def measured_traffic(prec):
@@ -168,9 +172,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--n", type=int, default=None, help="16384 (70000 for --workload covariance)")
     ap.add_argument("--cond", type=float, default=1e4)
-    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=None, help="1 (32 for --workload covariance)")
+    ap.add_argument("--workload", choices=["logspaced", "covariance"], default="logspaced",
+                    help="logspaced: the headline matrix; covariance: the paper's Section 4 model "
+                         "covariance matrix 1/|i-j|^d, 1+sqrt(i) on the diagonal")
+    ap.add_argument("--decay", type=int, choices=[1, 2, 4], default=1, help="d of --workload covariance")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the binary64 baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -184,6 +192,11 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 3 times (calibrates HBM counters) and exit")
     args = ap.parse_args()
+    cov = args.workload == "covariance"
+    if args.n is None:
+        args.n = 70000 if cov else 16384
+    if args.nrhs is None:
+        args.nrhs = 32 if cov else 1
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -210,7 +223,11 @@ def main():
     n, m, cond = args.n, args.nrhs, args.cond
     t0 = time.perf_counter()
     sg, sx = spdgen.seeds(1, 0)
-    if args.input == "dominant":
+    if cov:
+        A = spdgen.covariance(n, args.decay, backend="torch", device="cuda")
+        _, sx = spdgen.seeds(5, args.decay)
+        cond = spdgen.covariance_cond_bound(n, args.decay)  # a bound: the forward-error bar uses it
+    elif args.input == "dominant":
         gen = torch.Generator(device="cuda")
         gen.manual_seed(sg)
         A = torch.rand(n, n, dtype=torch.float64, device="cuda", generator=gen) * 2.0 - 1.0
@@ -220,7 +237,8 @@ def main():
     Xt = spdgen.rhs(n, m, sx, backend="torch", device="cuda")
     B = spdgen.accurate_product(A, Xt)
     torch.cuda.synchronize()
-    log(f"generated n={n} cond={cond:g} m={m} in {time.perf_counter() - t0:.1f} s")
+    log(f"generated {args.workload} n={n} cond{'<=' if cov else '='}{cond:g} m={m} "
+        f"in {time.perf_counter() - t0:.1f} s")
 
     def run(prec, steps, warmup, profile):
         F = spd.Factor()
@@ -269,14 +287,16 @@ def main():
     cpu = None
     ocheck = None
     if not args.no_cpu_baseline:
-        cpu, ocheck = cpu_baseline_leg(args, A, X, B)
+        cpu, ocheck = cpu_baseline_leg(args, A, X, B, rows_check=n <= 32768)
 
     launches, ms, fl, by = upd
-    traffic = measured_traffic(args.prec)
+    traffic = None if cov or n != 16384 else measured_traffic(args.prec)
     achieved = fl / ms / 1e9 if ms > 0 else 0.0  # TFLOP/s
     peak = PEAK_TFLOPS[args.prec]
     out = {
-        "metric": "time to FP64-accurate solve & eff. TFLOP/s: mixed vs FP64 Cholesky, n=16384",
+        "metric": ("time to FP64-accurate solve & eff. TFLOP/s: mixed vs FP64 Cholesky, n=16384" if not cov else
+                   f"time to FP64-accurate solve & eff. TFLOP/s: mixed vs FP64 Cholesky, covariance d={args.decay}, "
+                   f"n={n}, m={m}"),
         "value": algo_flops(n, m) / dt / 1e12,
         "unit": "TFLOP/s",
         "n_gpus": 1,
@@ -288,9 +308,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if args.prec == "fp32" else f"{args.prec}+f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"dense SPD A X = B, n={n}, cond={cond:g} (log-spaced eigenvalues, random "
-                               f"orthogonal Q), {m} RHS, {args.prec} factor + binary64 refinement",
-                   "n": n, "nrhs": m, "cond": cond, "prec": args.prec},
+        "config": ({"workload": f"dense SPD A X = B, n={n}, cond={cond:g} (log-spaced eigenvalues, random "
+                                f"orthogonal Q), {m} RHS, {args.prec} factor + binary64 refinement",
+                    "n": n, "nrhs": m, "cond": cond, "prec": args.prec} if not cov else
+                   {"workload": f"model covariance matrix (Section 4), d={args.decay}, n={n}, {m} RHS, "
+                                f"{args.prec} factor + binary64 refinement",
+                    "n": n, "nrhs": m, "decay": args.decay, "cond_bound": cond, "prec": args.prec}),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": "k_syrk_update_f32 (128- and 64-row tiles)" if args.prec == "fp32" else (

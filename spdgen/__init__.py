@@ -203,14 +203,49 @@ def hilbert(n: int) -> np.ndarray:
     return np.asfortranarray(1.0 / (i[:, None] + i[None, :] - 1.0))
 
 
-def covariance(n: int, d: float) -> np.ndarray:
-    """Model covariance matrix of Section 4: 1/|i-j|^d off the diagonal, 1+sqrt(i) on it (1-based i)."""
-    i = np.arange(1, n + 1, dtype=np.float64)
-    dist = np.abs(i[:, None] - i[None, :])
-    with np.errstate(divide="ignore"):
-        A = 1.0 / dist ** d
-    A[np.arange(n), np.arange(n)] = 1.0 + np.sqrt(i)
-    return np.asfortranarray(A)
+def covariance(n: int, d: float, backend: str = "numpy", device=None, chunk: int = 2048):
+    """Model covariance matrix of Section 4: 1/|i-j|^d off the diagonal, 1+sqrt(i) on it (1-based i).
+
+    The torch backend builds it on the device a block of columns at a time
+    (n = 70000 in binary64 is 39 GB; the temporaries stay at n x chunk)."""
+    if backend == "numpy":
+        i = np.arange(1, n + 1, dtype=np.float64)
+        dist = np.abs(i[:, None] - i[None, :])
+        with np.errstate(divide="ignore"):
+            A = 1.0 / dist ** d
+        A[np.arange(n), np.arange(n)] = 1.0 + np.sqrt(i)
+        return np.asfortranarray(A)
+    if backend == "torch":
+        import torch
+        A = torch.empty(n, n, dtype=torch.float64, device=device)
+        i = torch.arange(1, n + 1, dtype=torch.float64, device=device)
+        # the diagonal from numpy, so that both backends give the same bits
+        diag = torch.from_numpy(1.0 + np.sqrt(np.arange(1, n + 1, dtype=np.float64))).to(device)
+        for c0 in range(0, n, chunk):
+            c1 = min(n, c0 + chunk)
+            j = i[c0:c1]
+            blk = (i[:, None] - j[None, :]).abs_().pow_(d).reciprocal_()
+            k = torch.arange(c0, c1, device=device)
+            blk[k, k - c0] = diag[c0:c1]
+            A[:, c0:c1] = blk  # symmetric: row-major storage is the column-major matrix
+            del blk
+        return A
+    raise ValueError(f"unknown backend {backend!r}")
+
+
+def covariance_cond_bound(n: int, d: int) -> float:
+    """Closed-form bound on cond(covariance(n, d)) for d in {1, 2, 4}.
+
+    The off-diagonal part is the symmetric Toeplitz matrix with symbol
+    f_d(t) = 2 sum_k cos(k t) / k^d; the eigenvalues of its finite sections lie
+    in [min f_d, max f_d], min f_d = f_d(pi) = -2 eta(d) (the alternating zeta:
+    ln 2, pi^2/12, 7 pi^4/720) and max f_d <= 2 sum_{k<n} k^-d.  With the
+    diagonal in [2, 1 + sqrt(n)]: lambda_min >= 2 - 2 eta(d) and
+    lambda_max <= 1 + sqrt(n) + 2 sum_{k<n} k^-d."""
+    import math
+    eta = {1: math.log(2.0), 2: math.pi ** 2 / 12.0, 4: 7.0 * math.pi ** 4 / 720.0}[int(d)]
+    zeta_n = sum(k ** -float(d) for k in range(1, n))
+    return (1.0 + math.sqrt(n) + 2.0 * zeta_n) / (2.0 - 2.0 * eta)
 
 
 def indefinite(n: int, j0: int, seed: int = 7) -> np.ndarray:

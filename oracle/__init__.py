@@ -84,6 +84,9 @@ def lib():
         L.oracle_rne_bf16.restype = C.c_float
         L.oracle_ir.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, i32, i32, f64, f64, i32,
                                 i32, C.POINTER(_Report)]
+        L.oracle_ir_factor.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, f64, i32,
+                                       C.POINTER(_Report)]
+        L.oracle_ir_factor.restype = i32
         L.oracle_ir.restype = i32
         L.oracle_threads.restype = i32
         _lib = L
@@ -209,6 +212,24 @@ def ir(A, Bt, prec="fp32", equilibrate=True, theta=0.1, tol=1e-14, max_iter=10, 
     p = PREC[prec] if isinstance(prec, str) else int(prec)
     lib().oracle_ir(n, m, _ptr(A), n, _ptr(B), n, _ptr(X), n, p, int(bool(equilibrate)),
                     float(theta), float(tol), int(max_iter), int(bool(fallback)), C.byref(rep))
+    return X, IRReport(rep.status, rep.prec_used, rep.iters_low, rep.iters_high, rep.fallbacks,
+                       rep.info, rep.eta)
+
+
+def ir_factor(A, L, Bt, prec="fp64", tol=1e-14, max_iter=10):
+    """Lines 2-7 of Algorithm 1 with a given lower-triangular factor L in place
+    of line 1 (the perturbed-factor experiment, Section 3.1, Fig. 3(b)):
+    binary64 substitutions (prec "fp64") or L rounded to binary32 ("fp32"),
+    no equilibration.  Returns (X as (m, n), IRReport)."""
+    A = _colmajor(A)
+    L = _colmajor(L)
+    B = _rhs(Bt)
+    m, n = B.shape
+    X = np.zeros_like(B)
+    rep = _Report()
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    lib().oracle_ir_factor(n, m, _ptr(A), n, _ptr(L), n, _ptr(B), n, _ptr(X), n, p, float(tol), int(max_iter),
+                           C.byref(rep))
     return X, IRReport(rep.status, rep.prec_used, rep.iters_low, rep.iters_high, rep.fallbacks,
                        rep.info, rep.eta)
 

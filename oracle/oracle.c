@@ -22,6 +22,8 @@
  *   oracle_ir        Algorithm 1 emulated step by step with a low-precision
  *                    factor (binary32, or binary16/bfloat16 operands with
  *                    binary32 accumulation) and binary64 residual/update.
+ *   oracle_ir_factor lines 2-7 of Algorithm 1 with a given factor (the
+ *                    perturbed-factor experiment, Fig. 3(b)).
  */
 #include <math.h>
 #include <stdint.h>
@@ -331,6 +333,10 @@ static double pow2_ceil(double v)
     return (f == 0.5) ? ldexp(1.0, e - 1) : ldexp(1.0, e);
 }
 
+static int ir_loop(int64_t n, int64_t m, const double *A, int64_t lda, const double *B, int64_t ldb,
+                   double *X, int64_t ldx, int prec, const double *d, double mu, const double *L64,
+                   const float *L32, double tol, int max_iter, oracle_report *rep);
+
 /* One attempt of Algorithm 1 at precision `prec`.  Returns status. */
 static int ir_attempt(int64_t n, int64_t m, const double *A, int64_t lda,
                       const double *B, int64_t ldb, double *X, int64_t ldx, int prec,
@@ -339,10 +345,6 @@ static int ir_attempt(int64_t n, int64_t m, const double *A, int64_t lda,
 {
     size_t nn = (size_t)n * (size_t)n;
     double *d = (double *)malloc((size_t)n * sizeof(double));
-    double *R = (double *)malloc((size_t)n * (size_t)m * sizeof(double));
-    double *eta = (double *)malloc((size_t)m * sizeof(double));
-    double *prev = (double *)malloc((size_t)m * sizeof(double));
-    float *y = (float *)malloc((size_t)n * sizeof(float));
     double *L64 = NULL;
     float *L32 = NULL;
     double mu = 1.0;
@@ -379,8 +381,27 @@ static int ir_attempt(int64_t n, int64_t m, const double *A, int64_t lda,
         goto done;
     }
 
-    /* line 2 (first solve, from r = b) and lines 5-6 (corrections) share one
-     * routine: z = s mu D L^{-T} L^{-1} round(D r / s) */
+    status = ir_loop(n, m, A, lda, B, ldb, X, ldx, prec, d, mu, L64, L32, tol, max_iter, rep);
+done:
+    free(d); free(L64); free(L32);
+    return status;
+}
+
+/* Lines 2-7 of Algorithm 1 with a given factor: L64 (binary64 solves) or
+ * L32 (binary32 solves of the scaled right-hand side), D = diag(d), mu.
+ * Line 2 (first solve, from r = b) and lines 5-6 (corrections) share one
+ * routine: z = s mu D L^{-T} L^{-1} round(D r / s).  Returns the status. */
+static int ir_loop(int64_t n, int64_t m, const double *A, int64_t lda, const double *B, int64_t ldb,
+                   double *X, int64_t ldx, int prec, const double *d, double mu, const double *L64,
+                   const float *L32, double tol, int max_iter, oracle_report *rep)
+{
+    double *R = (double *)malloc((size_t)n * (size_t)m * sizeof(double));
+    double *eta = (double *)malloc((size_t)m * sizeof(double));
+    double *prev = (double *)malloc((size_t)m * sizeof(double));
+    float *y = (float *)malloc((size_t)n * sizeof(float));
+    int status = 0;
+    rep->iters_low = rep->iters_high = 0;
+    rep->eta = NAN;
     for (int64_t c = 0; c < m; ++c)
         for (int64_t i = 0; i < n; ++i)
             X[IDX(i, c, ldx)] = 0.0;
@@ -444,8 +465,7 @@ static int ir_attempt(int64_t n, int64_t m, const double *A, int64_t lda,
         prev_worst = worst;
         memcpy(prev, eta, (size_t)m * sizeof(double));
     }
-done:
-    free(d); free(R); free(eta); free(prev); free(y); free(L64); free(L32);
+    free(R); free(eta); free(prev); free(y);
     return status;
 }
 
@@ -464,6 +484,58 @@ int32_t oracle_ir(int64_t n, int64_t m, const double *A, int64_t lda,
         prec = (prec < 2) ? 2 : 3;
         rep->fallbacks++;
     }
+}
+
+/* Lines 2-7 of Algorithm 1 with the factor line 1 would have produced
+ * replaced by a given lower-triangular L (n x n, leading dimension ldl): the
+ * perturbed-factor experiment of Section 3.1 (Fig. 3(b)), where R = L^T
+ * comes from a binary64 factorisation and is perturbed before use.  prec 3:
+ * binary64 substitutions with L; prec 2: L rounded once to binary32 and the
+ * binary32 solve of the scaled right-hand side.  No equilibration (D = I),
+ * mu = 1.  rep->info = first diagonal entry of L that is not positive and
+ * finite (1-based; status 2), else the refinement's status (0 converged,
+ * 3 no convergence). */
+int32_t oracle_ir_factor(int64_t n, int64_t m, const double *A, int64_t lda, const double *L, int64_t ldl,
+                         const double *B, int64_t ldb, double *X, int64_t ldx, int32_t prec, double tol,
+                         int32_t max_iter, oracle_report *rep)
+{
+    size_t nn = (size_t)n * (size_t)n;
+    double *d = (double *)malloc((size_t)n * sizeof(double));
+    double *L64 = NULL;
+    float *L32 = NULL;
+    int status;
+    rep->fallbacks = 0;
+    rep->prec_used = prec;
+    rep->info = 0;
+    rep->iters_low = rep->iters_high = 0;
+    rep->eta = NAN;
+    for (int64_t i = 0; i < n; ++i) {
+        d[i] = 1.0;
+        double a = L[IDX(i, i, ldl)];
+        if (!(a > 0.0) || !isfinite(a)) {
+            if (!rep->info) rep->info = i + 1;
+        }
+    }
+    if (rep->info) {
+        free(d);
+        rep->status = 2;
+        return 2;
+    }
+    if (prec == 3) {
+        L64 = (double *)malloc(nn * sizeof(double));
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < n; ++i)
+                L64[IDX(i, j, n)] = (i >= j) ? L[IDX(i, j, ldl)] : 0.0;
+    } else {
+        L32 = (float *)malloc(nn * sizeof(float));
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < n; ++i)
+                L32[IDX(i, j, n)] = (i >= j) ? (float)L[IDX(i, j, ldl)] : 0.0f;
+    }
+    status = ir_loop(n, m, A, lda, B, ldb, X, ldx, prec, d, 1.0, L64, L32, tol, max_iter, rep);
+    free(d); free(L64); free(L32);
+    rep->status = status;
+    return status;
 }
 
 /* Threads the OpenMP runtime would use (reported beside CPU timings). */

@@ -111,3 +111,73 @@ def test_convergence_condition_eq4(orc):
         assert (q < 1) == should, q
         _, rep = orc.ir(A, A @ np.ones(A.shape[0]), prec="fp32", fallback=False)
         assert (rep.status == 0) == should, rep
+
+
+# --- refinement with a given factor (the perturbed-factor experiment, Fig. 3(b)) ---
+
+def _ir_factor_case(n=200, cond=1e2, seed=31):
+    A = spdgen.logspaced(n, cond, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    Xt = rng.standard_normal((1, n))
+    B = (A @ Xt[0])[None, :]
+    return A, Xt, B
+
+
+def test_ir_factor_exact_factor_one_step(orc):
+    # the binary64 factor itself: one solve already reaches the binary64 floor
+    A, Xt, B = _ir_factor_case()
+    L, info = orc.potrf(A)
+    assert info == 0
+    X, rep = orc.ir_factor(A, L, B, prec="fp64")
+    assert rep.status == 0 and (rep.iters_low, rep.iters_high) == (1, 1)
+    assert rep.eta <= 2.0 ** -51
+
+
+@pytest.mark.parametrize("alpha", [0.9, 1.1, 1.25])
+def test_ir_factor_scaled_factor_closed_form(orc, alpha):
+    # L~ = alpha L gives L~ L~^T = alpha^2 A, so with c = 1 - 1/alpha^2 the
+    # error after j solves is exactly -c^j x: x_j = (1 - c^j) x and the j-th
+    # residual is r_j = c^j b, so
+    #   eta_j = |c|^j ||b|| / (||A|| ||x|| |1 - c^j| + ||b||),
+    # and the loop stops at the first eta_j <= 2^-51 (Eq. (4):
+    # ||A^{-1} dA|| = |1 - alpha^2| < 1 here).
+    A, Xt, B = _ir_factor_case()
+    L, _ = orc.potrf(A)
+    X, rep = orc.ir_factor(A, alpha * L, B, prec="fp64", max_iter=200)
+    c = 1.0 - 1.0 / alpha ** 2
+    an = np.abs(A).sum(axis=1).max()
+    nb, nx = np.abs(B).max(), np.abs(Xt).max()
+    j = 1
+    while abs(c) ** j * nb / (an * nx * abs(1.0 - c ** j) + nb) > 2.0 ** -51:
+        j += 1
+    assert rep.status == 0
+    assert abs(rep.iters_high - j) <= 1, (rep.iters_high, j)
+    assert np.abs(X - Xt).max() / np.abs(Xt).max() <= 1e-13
+
+
+def test_ir_factor_rising_eta_is_taken_for_divergence(orc):
+    # alpha = 0.8 (c = -0.5625): the iterate's norm drops from 1.56 ||x|| to
+    # 0.68 ||x|| after the first correction, so eta rises once even though
+    # the error contracts -- the divergence reading (eta above the first eta)
+    # stops it, as it does in the library
+    A, Xt, B = _ir_factor_case()
+    L, _ = orc.potrf(A)
+    X, rep = orc.ir_factor(A, 0.8 * L, B, prec="fp64", max_iter=200)
+    assert rep.status == 3 and rep.iters_high == 2
+
+
+def test_ir_factor_too_large_a_perturbation_diverges(orc):
+    # alpha = 0.6: c = 1 - 1/0.36 = -1.78, the error grows every step
+    A, Xt, B = _ir_factor_case()
+    L, _ = orc.potrf(A)
+    X, rep = orc.ir_factor(A, 0.6 * L, B, prec="fp64", max_iter=50)
+    assert rep.status == 3
+
+
+def test_ir_factor_rejects_a_bad_diagonal(orc):
+    A, Xt, B = _ir_factor_case(n=50)
+    L, _ = orc.potrf(A)
+    L = L.copy()
+    L[17, 17] = -1.0
+    X, rep = orc.ir_factor(A, L, B)
+    assert rep.status == 2 and rep.info == 18

@@ -96,6 +96,23 @@ void spd_opts_default(spd_opts *o);
 spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec,
                       const spd_opts *o, void *hip_stream, spd_factor_t *F, int64_t *info);
 
+/* A factor supplied by the caller in place of line 1 (the perturbed-factor
+ * experiment of Section 3.1, Fig. 3(b): a binary64 factor R = L^T perturbed
+ * by E, then refined with Eq. (4) deciding convergence).  L: n x n,
+ * column-major, leading dimension ldl >= max(1, n), device memory owned by
+ * the caller; only its lower triangle is read, and only during the call.
+ * prec is SPD_FP32 (L rounded once to binary32) or SPD_FP64 (used as is);
+ * no equilibration or scaling (D = I, mu = 1), so spd_solve applies
+ * (L L^T)^{-1} and spd_refine refines against any A given to it (with
+ * fallback enabled, a binary32 import that does not converge re-factors
+ * that A in binary64).  *F as in spd_factor.  On return *info is 0 or the
+ * 1-based index of the first diagonal entry of L that is not positive and
+ * finite, with status SPD_ERR_NOT_SPD (the handle stays valid).  Other
+ * precisions, n < 0, ldl < n or a NULL L (n > 0) give SPD_ERR_INVALID_ARG
+ * before any device work.  Synchronises `hip_stream` once. */
+spd_status spd_factor_import(const double *L, int64_t n, int64_t ldl, spd_prec prec, void *hip_stream,
+                             spd_factor_t *F, int64_t *info);
+
 /* Algorithm 1, line 2: X = L^{-T} L^{-1} B with the handle's low-precision
  * factor (binary32 substitution), including the equilibration scaling:
  * X = s mu D L^{-T} L^{-1} round32(D B / s), s a power of two per column.

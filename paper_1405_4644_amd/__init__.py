@@ -69,6 +69,7 @@ _SIGS = [
     ("spd_mlp_forward", C.c_int, [_vp, _vp, _i64, _vp, _vp]),
     ("spd_mlp_grad", C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     ("spd_mlp_adam", C.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
+    ("spd_factor_import", C.c_int, [_vp, _i64, _i64, C.c_int, _vp, C.POINTER(_vp), C.POINTER(_i64)]),
     ("spd_factor_destroy", None, [_vp]),
     ("spd_factor_query", C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32)]),
     ("spd_factor_export", C.c_int, [_vp, _vp, _i64, _vp, C.POINTER(_f64), _vp]),
@@ -189,6 +190,28 @@ def factor(A, prec="fp32", opts: Opts | None = None, F: Factor | None = None, ch
                         C.byref(F.h), C.byref(info))
     if check and st not in (OK, ERR_NOT_SPD):
         raise SPDError(st, "spd_factor")
+    return F, int(info.value), st
+
+
+def factor_import(L, prec="fp64", F: Factor | None = None, check=True):
+    """spd_factor_import: the caller's lower-triangular factor L (an n x n
+    float64 device tensor read as the matrix L[i][j], i >= j) becomes the
+    handle's factor at `prec` ("fp64" or "fp32"), with no equilibration or
+    scaling.  Returns (Factor, info, status)."""
+    _check_dev(L, "L")
+    if L.dim() != 2 or L.shape[0] != L.shape[1]:
+        raise ValueError("L must be square")
+    n = L.shape[0]
+    if not (L.stride(0) == 1 and (n <= 1 or L.stride(1) >= n)):
+        L = L.t().contiguous().t()  # column-major copy (the C ABI reads column-major)
+    ld = max(L.stride(1), n, 1)
+    lib = load()
+    F = F or Factor()
+    info = C.c_int64()
+    st = lib.spd_factor_import(C.c_void_p(L.data_ptr()), n, ld, _prec(prec), _stream(), C.byref(F.h),
+                               C.byref(info))
+    if check and st not in (OK, ERR_NOT_SPD):
+        raise SPDError(st, "spd_factor_import")
     return F, int(info.value), st
 
 

@@ -290,8 +290,10 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
     return SPD_OK;
 }
 
-spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, int prec, const spd_opts &o,
-                     hipStream_t st, int64_t *info)
+// sizes and buffers of a factor of order n at precision prec (L, W, Winv
+// zeroed when (re)allocated), the solve structures, d; mu and the operand
+// rounding from prec
+spd_status prepare_factor(spd_factor_t F, int64_t n, int prec, double theta, hipStream_t st)
 {
     F->n = n;
     F->prec = prec;
@@ -322,13 +324,21 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
     SPD_TRY(grow((void **)&F->d, &capd, (size_t)std::max<int64_t>(n, 1) * sizeof(double), false, st));
     F->cap_d = (int64_t)(capd / sizeof(double));
 
-    F->mu = (prec == SPD_FP16) ? fp16_scale(o.theta) : 1.0;
+    F->mu = (prec == SPD_FP16) ? fp16_scale(theta) : 1.0;
     F->half = (prec == SPD_FP16) ? HALF_F16 : (prec == SPD_BF16) ? HALF_BF16 : HALF_NONE;
     if (F->half) {
         size_t caph = F->cap_Lh;
         SPD_TRY(grow(&F->Lh, &caph, (size_t)4 * npad * F->nb * 2, false, st));
         F->cap_Lh = caph;
     }
+    return SPD_OK;
+}
+
+spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, int prec, const spd_opts &o,
+                     hipStream_t st, int64_t *info)
+{
+    SPD_TRY(prepare_factor(F, n, prec, o.theta, st));
+    const int64_t npad = F->npad;
     const int equil = (prec != SPD_FP64 && o.equilibrate) ? 1 : 0;
     *F->info_host = SPD_INFO_NONE_H;
     HIP_TRY(hipMemcpyAsync(F->info_dev, F->info_host, sizeof(unsigned long long), hipMemcpyHostToDevice, st));
@@ -340,6 +350,41 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
         spd::launch_convert<float>(A, lda, n, npad, F->d, F->mu, (float *)F->L, npad, st);
         SPD_TRY(factor_blocked<float>(F, st));
     }
+    HIP_TRY(hipMemcpyAsync(F->info_host, F->info_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const unsigned long long v = *F->info_host;
+    *info = (v == SPD_INFO_NONE_H) ? 0 : (int64_t)v;
+    return *info ? SPD_ERR_NOT_SPD : SPD_OK;
+}
+
+// A factor L of A supplied by the caller (binary64, lower triangle of an
+// n x n column-major array) taken as the handle's factor at precision prec
+// (binary32: rounded once; binary64: as is), with D = I and mu = 1; the
+// block inverses the solves use are formed from it.
+template <typename T>
+void import_factor(spd_factor_t F, const double *L, int64_t ldl, hipStream_t st)
+{
+    const int64_t n = F->n, npad = F->npad, nt = npad / spd::Panel<T>::NB;
+    spd::launch_equil(L, ldl, n, F->d, 0, st);  // d = 1
+    spd::launch_convert<T>(L, ldl, n, npad, F->d, 1.0, (T *)F->L, npad, st);
+    spd::launch_inv32_blocks<T>((const T *)F->L, npad, npad, (T *)F->Winv, F->info_dev, st);
+    spd::launch_trtri_blocks<T>((const T *)F->L, npad, nt, (const T *)F->Winv, (T *)F->W, st);
+    spd::launch_build_winv<T>((const T *)F->L, npad, npad, (const T *)F->W, (T *)F->WB, (T *)F->Tb, st);
+}
+
+spd_status do_import(spd_factor_t F, const double *L, int64_t n, int64_t ldl, int prec, hipStream_t st,
+                     int64_t *info)
+{
+    SPD_TRY(prepare_factor(F, n, prec, 0.1, st));
+    *F->info_host = SPD_INFO_NONE_H;
+    HIP_TRY(hipMemcpyAsync(F->info_dev, F->info_host, sizeof(unsigned long long), hipMemcpyHostToDevice, st));
+    if (n > 0) {
+        if (prec == SPD_FP64)
+            import_factor<double>(F, L, ldl, st);
+        else
+            import_factor<float>(F, L, ldl, st);
+    }
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(F->info_host, F->info_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const unsigned long long v = *F->info_host;
@@ -645,6 +690,32 @@ spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec, co
         }
     }
     spd_status s = do_factor(*F, A, n, lda, prec, op, (hipStream_t)hip_stream, info);
+    if (s != SPD_OK && s != SPD_ERR_NOT_SPD && created) {
+        spd_factor_destroy(*F);
+        *F = nullptr;
+    }
+    return s;
+}
+
+spd_status spd_factor_import(const double *L, int64_t n, int64_t ldl, spd_prec prec, void *hip_stream,
+                             spd_factor_t *F, int64_t *info)
+{
+    if (!F || !info || n < 0 || ldl < std::max<int64_t>(1, n) || (n > 0 && !L) ||
+        (prec != SPD_FP32 && prec != SPD_FP64))
+        return SPD_ERR_INVALID_ARG;
+    *info = 0;
+    bool created = false;
+    if (!*F) {
+        *F = new (std::nothrow) spd_factor_s();
+        if (!*F) return SPD_ERR_OUT_OF_MEMORY;
+        created = true;
+        if (hipGetDevice(&(*F)->device) != hipSuccess) {
+            delete *F;
+            *F = nullptr;
+            return SPD_ERR_DEVICE;
+        }
+    }
+    spd_status s = do_import(*F, L, n, ldl, prec, (hipStream_t)hip_stream, info);
     if (s != SPD_OK && s != SPD_ERR_NOT_SPD && created) {
         spd_factor_destroy(*F);
         *F = nullptr;

@@ -46,6 +46,10 @@ void launch_syrk_update_half(float *H, int64_t ld, const void *Lh0, int skip0, c
 // max_grid > 0 caps the workgroups (multiple of 8); they then loop over tiles
 template <typename T>
 void launch_trtri_blocks(const T *H, int64_t ld, int64_t nt, const T *Winv, T *W, hipStream_t st);
+// Inverses of the 32 x 32 diagonal sub-blocks of a given factor (Winv layout
+// as left by the factorisation); a non-positive diagonal entry raises info.
+template <typename T>
+void launch_inv32_blocks(const T *H, int64_t ld, int64_t npad, T *Winv, unsigned long long *info, hipStream_t st);
 
 // --- triangular solves and scaling (k_solve.hip) ---
 // smax[c] = max_i |d_i r_ic| over the n rows (zeroed by the caller first)

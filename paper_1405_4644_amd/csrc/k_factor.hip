@@ -796,3 +796,50 @@ template void launch_trtri_blocks<float>(const float *, int64_t, int64_t, const 
 template void launch_trtri_blocks<double>(const double *, int64_t, int64_t, const double *, double *, hipStream_t);
 
 }  // namespace spd
+
+// ---------------------------------------------------------------------------
+// For a factor supplied by the caller (no factorisation ran): the inverse of
+// every 32 x 32 diagonal sub-block, in the layout the factorisation leaves
+// (block g at Winv + 1024 g, column-major).  One workgroup of 32 threads per
+// block; thread c forms column c of W = L_gg^{-1} by forward substitution.
+// A diagonal entry that is not positive and finite raises info (1-based
+// column, smallest wins), as a breakdown of the factorisation would.
+template <typename T>
+__global__ __launch_bounds__(32) void k_inv32_blocks(const T *__restrict__ H, int64_t ld, T *__restrict__ Winv,
+                                                     unsigned long long *info)
+{
+    __shared__ T Ls[32][33];
+    const int c = threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * 32;
+    for (int j = 0; j < 32; ++j) Ls[c][j] = (c >= j) ? H[(g0 + c) + (g0 + j) * ld] : (T)0;
+    __syncthreads();
+    const T dc = Ls[c][c];
+    if (!(dc > (T)0) || !(dc < (T)INFINITY))
+        atomicMin(info, (unsigned long long)(g0 + c + 1));
+    T w[32];
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+        T s = (r == c) ? (T)1 : (T)0;
+#pragma unroll
+        for (int k = 0; k < r; ++k)
+            if (k >= c)
+                s -= Ls[r][k] * w[k];
+        w[r] = (r >= c) ? s / Ls[r][r] : (T)0;
+    }
+#pragma unroll
+    for (int r = 0; r < 32; ++r) Winv[blockIdx.x * 1024 + r + c * 32] = w[r];
+}
+
+namespace spd {
+
+template <typename T>
+void launch_inv32_blocks(const T *H, int64_t ld, int64_t npad, T *Winv, unsigned long long *info, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_inv32_blocks<T>, dim3((unsigned)(npad / 32)), dim3(32), 0, st, H, ld, Winv, info);
+}
+template void launch_inv32_blocks<float>(const float *, int64_t, int64_t, float *, unsigned long long *,
+                                         hipStream_t);
+template void launch_inv32_blocks<double>(const double *, int64_t, int64_t, double *, unsigned long long *,
+                                          hipStream_t);
+
+}  // namespace spd

@@ -28,7 +28,7 @@ def lib():
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for required in ("spd_factor", "spd_solve", "spd_refine", "spd_solve_batched", "spd_factor_destroy",
+    for required in ("spd_factor", "spd_factor_import", "spd_solve", "spd_refine", "spd_solve_batched", "spd_factor_destroy",
                      "spd_status_str"):
         assert required in names
 
@@ -83,6 +83,13 @@ def test_invalid_arguments_rejected_on_host(lib):
     # non-empty batch with a missing array: rejected before any device work
     assert lib.spd_solve_batched(3, fake, fake, fake, fake, None, fake, fake, fake, None, fake,
                                  None) == spd.ERR_INVALID_ARG
+    # factor import: binary32 / binary64 only, ldl >= n, L and F present
+    assert lib.spd_factor_import(fake, 10, 5, 3, None, C.byref(h), C.byref(info)) == spd.ERR_INVALID_ARG
+    assert lib.spd_factor_import(None, 10, 10, 3, None, C.byref(h), C.byref(info)) == spd.ERR_INVALID_ARG
+    assert lib.spd_factor_import(fake, 10, 10, 1, None, C.byref(h), C.byref(info)) == spd.ERR_INVALID_ARG
+    assert lib.spd_factor_import(fake, 10, 10, 0, None, C.byref(h), C.byref(info)) == spd.ERR_INVALID_ARG
+    assert lib.spd_factor_import(fake, -1, 10, 3, None, C.byref(h), C.byref(info)) == spd.ERR_INVALID_ARG
+    assert lib.spd_factor_import(fake, 10, 10, 3, None, None, C.byref(info)) == spd.ERR_INVALID_ARG
     assert lib.spd_factor_query(None, None, None, None) == spd.ERR_INVALID_ARG
     assert lib.spd_factor_export(None, None, 1, None, None, None) == spd.ERR_INVALID_ARG
     lib.spd_factor_destroy(None)  # no-op

@@ -1,0 +1,121 @@
+"""GPU parity of a caller-supplied factor (spd_factor_import) refined by
+Algorithm 1, lines 2-7: the perturbed-factor experiment of Section 3.1
+(Fig. 3(b)) against the oracle's refinement with the same factor
+(oracle.ir_factor, pinned on the CPU by closed forms).
+
+Bars: status and precision exactly; iteration counts within +-1 of the
+oracle's; the final backward error recomputed by the oracle <= 1e-14 and the
+forward error against X_true <= 10 cond 2^-53 when the refinement converges.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import spdgen
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _case(n, cond, seed):
+    s = spdgen.system(n, cond, 1, config=6, index=seed)
+    return s.A, s.Xt, s.Bt
+
+
+def _perturbation(L, gamma, seed):
+    """Lower-triangular E with ||E||_2 = 10^gamma ||L||_2 (E^T perturbs R = L^T)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    E = np.tril(rng.standard_normal(L.shape))
+    return E * (10.0 ** gamma * np.linalg.norm(L, 2) / np.linalg.norm(E, 2))
+
+
+def _run(spd, A, L, B, prec, max_iter=60):
+    import torch
+    F, info, st = spd.factor_import(dev(np.asfortranarray(L)), prec=prec)
+    assert info == 0 and st == spd.OK
+    Bd = dev(B)
+    X = spd.solve(F, Bd)
+    rep = spd.refine(F, dev(A), Bd, X, spd.default_opts(max_iter=max_iter, fallback=0))
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), rep
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_import_exact_factor(spd, orc, prec):
+    n, cond = 300, 1e3
+    _say(f"import exact factor {prec} n={n}")
+    A, Xt, B = _case(n, cond, 1)
+    L, info = orc.potrf(A)
+    assert info == 0
+    X, rep = _run(spd, A, L, B, prec)
+    Xo, ro = orc.ir_factor(A, L, B, prec=prec, max_iter=60)
+    _say(f"  library {rep.iters_low}/{rep.iters_high} eta {rep.eta:.2e}; oracle {ro.iters_low}/{ro.iters_high}")
+    assert rep.status == 0 and ro.status == 0
+    assert abs(rep.iters_high - ro.iters_high) <= 1
+    if prec == "fp64":
+        assert (rep.iters_low, rep.iters_high) == (1, 1)
+    assert orc.backward_error(A, X, B).max() <= 1e-14
+    assert np.abs(X - Xt).max() / np.abs(Xt).max() <= 10 * cond * U64
+
+
+@pytest.mark.parametrize("alpha", [0.9, 1.25])
+def test_import_scaled_factor(spd, orc, alpha):
+    n, cond = 256, 1e2
+    _say(f"import scaled factor alpha={alpha}")
+    A, Xt, B = _case(n, cond, 2)
+    L, _ = orc.potrf(A)
+    X, rep = _run(spd, A, alpha * L, B, "fp64", max_iter=200)
+    Xo, ro = orc.ir_factor(A, alpha * L, B, prec="fp64", max_iter=200)
+    _say(f"  library {rep.iters_low}/{rep.iters_high}; oracle {ro.iters_low}/{ro.iters_high}")
+    assert rep.status == ro.status == 0
+    assert abs(rep.iters_high - ro.iters_high) <= 1
+    assert orc.backward_error(A, X, B).max() <= 1e-14
+
+
+@pytest.mark.parametrize("gamma", [-3.25, -5.5, -7.75, -10.0])
+def test_import_perturbed_factor(spd, orc, gamma):
+    n, cond = 400, 1e3
+    _say(f"import perturbed factor gamma={gamma}")
+    A, Xt, B = _case(n, cond, 3)
+    L, _ = orc.potrf(A)
+    Lp = L + _perturbation(L, gamma, 40)
+    X, rep = _run(spd, A, Lp, B, "fp64")
+    Xo, ro = orc.ir_factor(A, Lp, B, prec="fp64", max_iter=60)
+    _say(f"  library {rep.status} {rep.iters_low}/{rep.iters_high}; oracle {ro.status} "
+         f"{ro.iters_low}/{ro.iters_high}")
+    assert rep.status == ro.status
+    assert abs(rep.iters_high - ro.iters_high) <= 1
+    if rep.status == 0:
+        assert orc.backward_error(A, X, B).max() <= 1e-14
+        assert np.abs(X - Xt).max() / np.abs(Xt).max() <= 10 * cond * U64
+
+
+def test_import_divergent_factor(spd, orc):
+    A, Xt, B = _case(200, 1e2, 4)
+    L, _ = orc.potrf(A)
+    X, rep = _run(spd, A, 0.6 * L, B, "fp64")
+    Xo, ro = orc.ir_factor(A, 0.6 * L, B, prec="fp64", max_iter=60)
+    assert rep.status == spd.ERR_NO_CONVERGENCE and ro.status == 3
+
+
+def test_import_bad_diagonal(spd, orc):
+    import torch
+    A, Xt, B = _case(100, 1e2, 5)
+    L, _ = orc.potrf(A)
+    L = L.copy()
+    L[40, 40] = 0.0
+    F, info, st = spd.factor_import(dev(np.asfortranarray(L)), prec="fp64")
+    torch.cuda.synchronize()
+    assert st == spd.ERR_NOT_SPD and info == 41

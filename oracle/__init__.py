@@ -87,6 +87,9 @@ def lib():
         L.oracle_ir_factor.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, f64, i32,
                                        C.POINTER(_Report)]
         L.oracle_ir_factor.restype = i32
+        L.oracle_cg_ir.argtypes = [i64, i64, vp, i64, i64, vp, i64, vp, i64, f64, f64, i32, i32,
+                                   C.POINTER(_Report)]
+        L.oracle_cg_ir.restype = i32
         L.oracle_ir.restype = i32
         L.oracle_threads.restype = i32
         _lib = L
@@ -230,6 +233,23 @@ def ir_factor(A, L, Bt, prec="fp64", tol=1e-14, max_iter=10):
     p = PREC[prec] if isinstance(prec, str) else int(prec)
     lib().oracle_ir_factor(n, m, _ptr(A), n, _ptr(L), n, _ptr(B), n, _ptr(X), n, p, float(tol), int(max_iter),
                            C.byref(rep))
+    return X, IRReport(rep.status, rep.prec_used, rep.iters_low, rep.iters_high, rep.fallbacks,
+                       rep.info, rep.eta)
+
+
+def cg_ir(A, Bt, X0t=None, half_band=-1, tol=1e-14, inner_tol=1e-6, max_outer=30, max_inner=2000):
+    """Algorithm 2 (CG with iterative refinement) emulated on the CPU: the
+    product with A~ (binary32, dense or the band |i-j| <= half_band) in
+    binary32, everything else in binary64, restarted from binary64 residuals.
+    Returns (X as (m, n), IRReport): iters_low = products, iters_high =
+    binary64 residuals."""
+    A = _colmajor(A)
+    B = _rhs(Bt)
+    m, n = B.shape
+    X = np.zeros_like(B) if X0t is None else np.array(_rhs(X0t), dtype=np.float64, order="C")
+    rep = _Report()
+    lib().oracle_cg_ir(n, m, _ptr(A), n, int(half_band), _ptr(B), n, _ptr(X), n, float(tol), float(inner_tol),
+                       int(max_outer), int(max_inner), C.byref(rep))
     return X, IRReport(rep.status, rep.prec_used, rep.iters_low, rep.iters_high, rep.fallbacks,
                        rep.info, rep.eta)
 

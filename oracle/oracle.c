@@ -24,6 +24,10 @@
  *                    binary32 accumulation) and binary64 residual/update.
  *   oracle_ir_factor lines 2-7 of Algorithm 1 with a given factor (the
  *                    perturbed-factor experiment, Fig. 3(b)).
+ *   oracle_cg_ir     Algorithm 2 (conjugate gradients with the matrix-vector
+ *                    product in binary32 on a dense or banded copy of A,
+ *                    everything else in binary64), restarted from a binary64
+ *                    residual until the backward error reaches the tolerance.
  */
 #include <math.h>
 #include <stdint.h>
@@ -534,6 +538,152 @@ int32_t oracle_ir_factor(int64_t n, int64_t m, const double *A, int64_t lda, con
     }
     status = ir_loop(n, m, A, lda, B, ldb, X, ldx, prec, d, 1.0, L64, L32, tol, max_iter, rep);
     free(d); free(L64); free(L32);
+    rep->status = status;
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 2 (Section 3.2): conjugate gradients with iterative refinement.
+ *
+ * The low-precision operator: A~ = fl32(A) on the band |i - j| <= k
+ * (k = half_band; k < 0 keeps every entry: the dense variant), zero outside
+ * it (Section 4's banded approximation).  One product z = A~ p rounds p to
+ * binary32 and forms each z_i as a binary32 dot product taken in the order
+ * j = 0, 1, ..., n-1 (binary32 products and sums), widened to binary64.
+ * Every other quantity (x, r, p, rho, alpha, beta) is binary64.
+ *
+ * One outer step (counted in iters_high): r = b - A x in binary64 and the
+ * backward error eta of each column.  A column with eta <= tol is done.
+ * Otherwise CG runs on the current residual -- Algorithm 2's loop body with
+ * x updated in place --
+ *     p = r, rho = r^T r, stop when r^T r <= inner_tol^2 rho_0 or after
+ *     max_inner products:
+ *       z = A~ p;  alpha = rho / (p^T z);  x += alpha p;  r -= alpha z;
+ *       rho' = r^T r;  beta = rho' / rho;  p = r + beta p;  rho = rho'
+ * (beta in the standard Fletcher-Reeves form: the printed beta = r^T z / rho
+ * is read as a misprint, since it does not give conjugate directions.)
+ * The columns run in lockstep: one inner phase lasts as long as its longest
+ * column, and iters_low counts the products of that schedule (the sum over
+ * outer steps of the longest inner run).  A column's own arithmetic does not
+ * depend on the others.
+ *
+ * After max_outer inner phases the residual is formed once more.  Status 0
+ * when every column has eta <= tol; 3 when eta is not finite, rises above
+ * its value at the first residual, or fails to fall below 0.9 of its
+ * previous value at two residuals in a row (no contraction: Eq. (4) does not
+ * hold for A~), or when max_outer phases end above tol.  X holds x0 on
+ * entry and the result on exit. */
+static void lowmv(int64_t n, const float *At, int64_t k, const double *p, float *pf, double *z)
+{
+    for (int64_t j = 0; j < n; ++j)
+        pf[j] = (float)p[j];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t j0 = 0, j1 = n;
+        if (k >= 0) {
+            j0 = i - k < 0 ? 0 : i - k;
+            j1 = i + k + 1 > n ? n : i + k + 1;
+        }
+        float s = 0.0f;
+        /* At holds column i of A~ (= row i, A~ being symmetric) */
+        for (int64_t j = j0; j < j1; ++j)
+            s += At[IDX(j, i, n)] * pf[j];
+        z[i] = (double)s;
+    }
+}
+
+static double dot64(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s += a[i] * b[i];
+    return s;
+}
+
+int32_t oracle_cg_ir(int64_t n, int64_t m, const double *A, int64_t lda, int64_t half_band,
+                     const double *B, int64_t ldb, double *X, int64_t ldx, double tol, double inner_tol,
+                     int32_t max_outer, int32_t max_inner, oracle_report *rep)
+{
+    size_t nn = (size_t)n * (size_t)n;
+    float *At = (float *)malloc(nn * sizeof(float));
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) {
+            int inb = half_band < 0 || (i - j <= half_band && j - i <= half_band);
+            At[IDX(i, j, n)] = inb ? (float)sym(A, lda, i, j) : 0.0f;
+        }
+    double *R = (double *)malloc((size_t)n * (size_t)m * sizeof(double));
+    double *P = (double *)malloc((size_t)n * sizeof(double));
+    double *Z = (double *)malloc((size_t)n * sizeof(double));
+    float *pf = (float *)malloc((size_t)n * sizeof(float));
+    double *eta = (double *)malloc((size_t)m * sizeof(double));
+    double *eta1 = (double *)malloc((size_t)m * sizeof(double));
+    double *prev = (double *)malloc((size_t)m * sizeof(double));
+    int *done = (int *)calloc((size_t)m, sizeof(int));
+    int *stalls = (int *)calloc((size_t)m, sizeof(int));
+    double an = oracle_norminf_sym(n, A, lda);
+    int status = 3;
+    rep->status = 0;
+    rep->prec_used = 2;
+    rep->fallbacks = 0;
+    rep->info = 0;
+    rep->iters_low = rep->iters_high = 0;
+    rep->eta = NAN;
+    for (int outer = 0;; ++outer) {
+        oracle_residual(n, m, A, lda, X, ldx, B, ldb, R, n);
+        rep->iters_high++;
+        double worst = 0.0;
+        int bad = 0, all_done = 1;
+        for (int64_t c = 0; c < m; ++c) {
+            double rn = vec_maxabs(n, R + (size_t)c * n);
+            double den = an * vec_maxabs(n, X + (size_t)c * ldx) + vec_maxabs(n, B + (size_t)c * ldb);
+            double e = (den > 0.0) ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+            if (rn != rn) e = NAN;
+            if (!done[c]) {
+                eta[c] = e;
+                if (!isfinite(e)) {
+                    bad = 1;
+                } else if (e <= tol) {
+                    done[c] = 1;
+                } else if (outer == 0) {
+                    eta1[c] = e;
+                } else {
+                    stalls[c] = (e > 0.9 * prev[c]) ? stalls[c] + 1 : 0;
+                    if (e > eta1[c] || stalls[c] >= 2) bad = 1;
+                }
+                prev[c] = e;
+            }
+            if (!done[c]) all_done = 0;
+            if (!(eta[c] <= worst)) worst = eta[c];
+        }
+        rep->eta = worst;
+        if (bad) { status = 3; break; }
+        if (all_done) { status = 0; break; }
+        if (outer >= max_outer) { status = 3; break; }
+        /* inner phase: CG on A~ for every column not done */
+        int longest = 0;
+        for (int64_t c = 0; c < m; ++c) {
+            if (done[c]) continue;
+            double *x = X + (size_t)c * ldx, *r = R + (size_t)c * n;
+            memcpy(P, r, (size_t)n * sizeof(double));
+            double rho = dot64(n, r, r);
+            double thr = inner_tol * inner_tol * rho;
+            int k = 0;
+            while (k < max_inner && rho > thr) {
+                lowmv(n, At, half_band, P, pf, Z);
+                ++k;
+                double alpha = rho / dot64(n, P, Z);
+                for (int64_t i = 0; i < n; ++i) x[i] += alpha * P[i];
+                for (int64_t i = 0; i < n; ++i) r[i] -= alpha * Z[i];
+                double rho1 = dot64(n, r, r);
+                double beta = rho1 / rho;
+                for (int64_t i = 0; i < n; ++i) P[i] = r[i] + beta * P[i];
+                rho = rho1;
+            }
+            if (k > longest) longest = k;
+        }
+        rep->iters_low += longest;
+    }
+    free(At); free(R); free(P); free(Z); free(pf); free(eta); free(eta1); free(prev); free(done); free(stalls);
     rep->status = status;
     return status;
 }

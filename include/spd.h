@@ -248,6 +248,57 @@ spd_status spd_factor_query(spd_factor_t F, int64_t *n, int32_t *prec, int32_t *
 spd_status spd_factor_export(spd_factor_t F, double *Lout, int64_t ldl, double *dout,
                              double *mu, void *hip_stream);
 
+/* ---- Algorithm 2 (Section 3.2): conjugate gradients with iterative
+ * refinement, on a dense or banded binary32 copy A~ of A (the banded
+ * approximation of Section 4: entries with |i - j| > half_band dropped).
+ *
+ * One outer step forms r = b - A x and each column's backward error eta in
+ * binary64 (as in Algorithm 1); a column with eta <= tol is finished.  The
+ * others run CG on A~ from the current x: z = A~ p in binary32 (p rounded to
+ * binary32, binary32 products and sums), and alpha = r^T r / p^T z,
+ * x += alpha p, r -= alpha z, beta = r'^T r' / r^T r, p = r + beta p all in
+ * binary64 (beta in the standard conjugate-direction form), until
+ * ||r||_2 <= inner_tol * ||r_0||_2 or max_inner products.  Columns advance in
+ * lockstep (a column that has stopped waits unchanged).  The outer steps
+ * repeat until every column is finished (SPD_OK) or eta is not finite, rises
+ * above its first value, or fails to fall below 0.9 of its previous value at
+ * two residuals in a row (Eq. (4) does not hold for A~), or after max_outer
+ * inner phases (SPD_ERR_NO_CONVERGENCE).  The report's iters_low counts
+ * products with A~ (the sum over phases of the longest column's count),
+ * iters_high the binary64 residuals, prec_used is SPD_FP32, eta the largest
+ * final backward error. */
+typedef struct {
+    double tol;        /* outer acceptance: eta <= tol (1e-14) */
+    double inner_tol;  /* inner stop: ||r||_2 <= inner_tol ||r_0||_2 (1e-6) */
+    int32_t max_outer; /* inner phases at most (30) */
+    int32_t max_inner; /* products per phase at most (2000) */
+} spd_cg_opts;
+
+typedef struct spd_cg_s *spd_cg_t;
+
+void spd_cg_opts_default(spd_cg_opts *o);
+
+/* Builds A~ from the lower triangle of A (n x n, leading dimension
+ * lda >= max(1, n), device memory; A is not kept).  half_band < 0 or
+ * >= n - 1: dense A~ (about 4 n^2 bytes of device memory); otherwise band
+ * storage of (2 half_band + 1) n binary32 values (half_band <= 4096, else
+ * SPD_ERR_UNSUPPORTED).  *H NULL creates a handle; a handle from an earlier
+ * call is rebuilt.  Asynchronous on hip_stream.  The handle owns its device
+ * memory; release it with spd_cg_destroy. */
+spd_status spd_cg_prepare(const double *A, int64_t n, int64_t lda, int64_t half_band, void *hip_stream,
+                          spd_cg_t *H);
+
+/* Refines X (n x nrhs, ldx; device memory; its entry value is x_0, e.g.
+ * zero) for A X = B with the handle's A~; A must be the matrix the handle
+ * was built from (binary64 residuals).  o NULL: defaults.  Synchronises
+ * hip_stream once per outer step and once per few inner iterations (the
+ * stopping tests).  Returns rep->status. */
+spd_status spd_cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrhs,
+                         double *X, int64_t ldx, const spd_cg_opts *o, spd_report *rep, void *hip_stream);
+
+/* Releases the handle (waits for the device first).  NULL is ignored. */
+void spd_cg_destroy(spd_cg_t H);
+
 /* Kernel timing for measurement tools.  While enabled, the library brackets
  * every launch of the kernel classes below with HIP events recorded on the
  * stream that launch uses, and tallies the algorithmic work of each launch:

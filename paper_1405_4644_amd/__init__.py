@@ -41,6 +41,10 @@ class Opts(C.Structure):
                 ("equilibrate", C.c_int32), ("theta", C.c_double)]
 
 
+class CGOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("max_inner", C.c_int32)]
+
+
 class Report(C.Structure):
     _fields_ = [("status", C.c_int32), ("prec_used", C.c_int32), ("iters_low", C.c_int32),
                 ("iters_high", C.c_int32), ("fallbacks", C.c_int32), ("info", C.c_int64),
@@ -73,6 +77,11 @@ _SIGS = [
     ("spd_factor_destroy", None, [_vp]),
     ("spd_factor_query", C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32)]),
     ("spd_factor_export", C.c_int, [_vp, _vp, _i64, _vp, C.POINTER(_f64), _vp]),
+    ("spd_cg_opts_default", None, [C.POINTER(CGOpts)]),
+    ("spd_cg_prepare", C.c_int, [_vp, _i64, _i64, _i64, _vp, C.POINTER(_vp)]),
+    ("spd_cg_refine", C.c_int, [_vp, _vp, _i64, _vp, _i64, _i64, _vp, _i64, C.POINTER(CGOpts), C.POINTER(Report),
+                                _vp]),
+    ("spd_cg_destroy", None, [_vp]),
     ("spd_profile_enable", None, [C.c_int]),
     ("spd_profile_reset", None, []),
     ("spd_profile_query", C.c_int, [C.c_int, C.POINTER(_i64), C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64)]),
@@ -174,6 +183,59 @@ class Factor:
         if st:
             raise SPDError(st, "spd_factor_query")
         return {"n": n.value, "prec": PREC_NAME[p.value], "nb": nb.value}
+
+
+class CG:
+    """Owns an spd_cg_t handle: the binary32 operator of Algorithm 2."""
+
+    def __init__(self):
+        self.h = C.c_void_p()
+        self.n = 0
+
+    def close(self):
+        if self.h:
+            load().spd_cg_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cg_default_opts(**kw) -> CGOpts:
+    o = CGOpts()
+    load().spd_cg_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def cg_prepare(A, half_band: int = -1, H: CG | None = None) -> CG:
+    """spd_cg_prepare: the binary32 operator A~ (dense, or the band
+    |i - j| <= half_band) for Algorithm 2."""
+    pa, n, lda = _mat(A)
+    H = H or CG()
+    st = load().spd_cg_prepare(pa, n, lda, int(half_band), _stream(), C.byref(H.h))
+    if st:
+        raise SPDError(st, "spd_cg_prepare")
+    H.n = n
+    return H
+
+
+def cg_refine(H: CG, A, B, X=None, opts: CGOpts | None = None):
+    """spd_cg_refine (Algorithm 2 with binary64 restarts).  X (zero if not
+    given) is the starting point and is updated in place.  Returns (X, Report)."""
+    torch = _torch()
+    pa, n, lda = _mat(A)
+    pb, ldb, m = _rhs(B, n)
+    if X is None:
+        X = torch.zeros_like(B)
+    px, ldx, _ = _rhs(X, n, "X")
+    rep = Report()
+    load().spd_cg_refine(H.h, pa, lda, pb, ldb, m, px, ldx, C.byref(opts) if opts else None, C.byref(rep), _stream())
+    return X, rep
 
 
 def _prec(p):

@@ -599,6 +599,149 @@ BatchCtx g_batch[kMaxDevices];
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Algorithm 2 (Section 3.2): conjugate gradients on the binary32 operator A~
+// with binary64 vectors and scalars, restarted from a binary64 residual.
+struct spd_cg_s {
+    int64_t n = 0, ldt = 0, k = -1;  // k >= 0: band |i - j| <= k; k < 0: dense
+    float *At = nullptr;             // dense ldt x ldt, or (2k + 1) rows of length ldt
+    int m = 0;                       // right-hand sides the workspace is sized for
+    double *R = nullptr, *P = nullptr, *Z = nullptr, *part = nullptr, *vpart = nullptr, *sc = nullptr;
+    double *norms = nullptr, *rscr = nullptr;
+    float *Pf = nullptr;
+    int *flags = nullptr;            // act[m], go[m], cnt[m]
+    double *norms_host = nullptr;
+    int *flags_host = nullptr;
+};
+
+namespace {
+
+void cg_free_ws(spd_cg_t H)
+{
+    hipFree(H->R); hipFree(H->P); hipFree(H->Z); hipFree(H->part); hipFree(H->vpart); hipFree(H->sc);
+    hipFree(H->norms); hipFree(H->rscr); hipFree(H->Pf); hipFree(H->flags);
+    if (H->norms_host) hipHostFree(H->norms_host);
+    if (H->flags_host) hipHostFree(H->flags_host);
+    H->R = H->P = H->Z = H->part = H->vpart = H->sc = H->norms = H->rscr = nullptr;
+    H->Pf = nullptr;
+    H->flags = nullptr;
+    H->norms_host = nullptr;
+    H->flags_host = nullptr;
+    H->m = 0;
+}
+
+spd_status cg_ensure_ws(spd_cg_t H, int m, hipStream_t st)
+{
+    if (H->m >= m) return SPD_OK;
+    HIP_TRY(hipStreamSynchronize(st));
+    cg_free_ws(H);
+    const int64_t n = H->n, ldt = H->ldt;
+    const size_t nm = (size_t)n * m * sizeof(double);
+    HIP_TRY(hipMalloc(&H->R, nm));
+    HIP_TRY(hipMalloc(&H->P, nm));
+    HIP_TRY(hipMalloc(&H->Z, nm));
+    HIP_TRY(hipMalloc(&H->part, (size_t)spd::cg_mv_parts(n, ldt, H->k, m) * m * sizeof(double)));
+    HIP_TRY(hipMalloc(&H->vpart, (size_t)spd::cg_vec_parts(n) * m * sizeof(double)));
+    HIP_TRY(hipMalloc(&H->sc, (size_t)4 * m * sizeof(double)));
+    HIP_TRY(hipMalloc(&H->norms, (size_t)(1 + 4 * m) * sizeof(double)));
+    HIP_TRY(hipMalloc(&H->rscr, (size_t)spd::resid_scratch(n, m) * sizeof(double)));
+    HIP_TRY(hipMalloc(&H->Pf, (size_t)ldt * m * sizeof(float)));
+    HIP_TRY(hipMalloc(&H->flags, (size_t)3 * m * sizeof(int)));
+    HIP_TRY(hipHostMalloc(&H->norms_host, (size_t)(1 + 4 * m) * sizeof(double), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&H->flags_host, (size_t)3 * m * sizeof(int), hipHostMallocDefault));
+    H->m = m;
+    return SPD_OK;
+}
+
+spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, int64_t ldb, int m, double *X,
+                     int64_t ldx, const spd_cg_opts &o, spd_report *rep, hipStream_t st)
+{
+    const int64_t n = H->n, ldt = H->ldt, k = H->k;
+    SPD_TRY(cg_ensure_ws(H, m, st));
+    // Pf's rows n..ldt-1 must read as zero in the dense product
+    spd::launch_zero((double *)H->Pf, ldt * m / 2, st);
+    const int64_t nmv = spd::cg_mv_parts(n, ldt, k, m), nv = spd::cg_vec_parts(n);
+    int *act = H->flags, *go = H->flags + m, *cnt = H->flags + 2 * m;
+    int *go_h = H->flags_host + m;
+    double *alpha = H->sc + 2 * m, *beta = H->sc + 3 * m;
+    const double it2 = o.inner_tol * o.inner_tol;
+    const int nn = 1 + 4 * m;
+    // iterations launched between host checks: a dense product is long
+    // enough that one check per iteration costs nothing
+    const int S = (k < 0) ? 2 : 16;
+    std::vector<double> eta1(m, 0.0), prev(m, 0.0);
+    std::vector<int> done(m, 0), stalls(m, 0);
+    std::vector<double> eta(m, 0.0);
+    double anorm = 0.0;
+    spd_status result = SPD_ERR_NO_CONVERGENCE;
+    rep->iters_low = rep->iters_high = 0;
+    for (int outer = 0;; ++outer) {
+        spd::launch_zero(outer == 0 ? H->norms : H->norms + 1, outer == 0 ? nn : nn - 1, st);
+        spd::launch_residual(A, lda, n, X, ldx, B, ldb, m, H->R, n, nullptr, H->norms, outer == 0, H->rscr, st);
+        HIP_TRY(hipMemcpyAsync(H->norms_host, H->norms, nn * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        rep->iters_high++;
+        if (outer == 0) anorm = H->norms_host[0];
+        bool bad = !(anorm == anorm), all_done = true;
+        double worst = 0.0;
+        for (int c = 0; c < m; ++c) {
+            const double rn = H->norms_host[1 + c], xn = H->norms_host[1 + m + c], bn = H->norms_host[1 + 2 * m + c];
+            const double den = anorm * xn + bn;
+            double e = (den > 0.0) ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+            if (!(rn == rn) || !(xn == xn)) e = NAN;
+            if (!done[c]) {
+                eta[c] = e;
+                if (!std::isfinite(e)) {
+                    bad = true;
+                } else if (e <= o.tol) {
+                    done[c] = 1;
+                } else if (outer == 0) {
+                    eta1[c] = e;
+                } else {
+                    stalls[c] = (e > 0.9 * prev[c]) ? stalls[c] + 1 : 0;
+                    if (e > eta1[c] || stalls[c] >= 2) bad = true;
+                }
+                prev[c] = e;
+            }
+            if (!done[c]) all_done = false;
+            if (!(eta[c] <= worst)) worst = eta[c];
+        }
+        rep->eta = worst;
+        if (bad) break;
+        if (all_done) { result = SPD_OK; break; }
+        if (outer >= o.max_outer) break;
+        // inner phase for the columns not done
+        for (int c = 0; c < m; ++c) go_h[c] = !done[c];
+        HIP_TRY(hipMemcpyAsync(go, go_h, m * sizeof(int), hipMemcpyHostToDevice, st));
+        spd::launch_cg_start(n, m, H->R, H->P, H->Pf, ldt, H->vpart, nv, go, st);
+        spd::launch_cg_scalars(spd::CG_START, H->vpart, nv, H->sc, act, go, cnt, it2, o.max_inner, m, st);
+        int launched = 0;
+        for (;;) {
+            for (int s = 0; s < S; ++s) {
+                spd::launch_cg_mv(H->At, ldt, n, k, m, H->Pf, H->P, H->Z, H->part, nmv, act, st);
+                spd::launch_cg_scalars(spd::CG_ALPHA, H->part, nmv, H->sc, act, go, cnt, it2, o.max_inner, m, st);
+                spd::launch_cg_xr(n, m, alpha, H->P, H->Z, X, ldx, H->R, H->vpart, nv, act, st);
+                spd::launch_cg_scalars(spd::CG_BETA, H->vpart, nv, H->sc, act, go, cnt, it2, o.max_inner, m, st);
+                spd::launch_cg_p(n, m, beta, H->R, H->P, H->Pf, ldt, act, st);
+            }
+            launched += S;
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipMemcpyAsync(H->flags_host, H->flags, 3 * m * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            bool any = false;
+            for (int c = 0; c < m; ++c) any |= H->flags_host[c] != 0;
+            if (!any || launched > o.max_inner + S) break;
+        }
+        int longest = 0;
+        for (int c = 0; c < m; ++c)
+            if (go_h[c]) longest = std::max(longest, H->flags_host[2 * m + c]);
+        rep->iters_low += longest;
+    }
+    return result;
+}
+
+}  // namespace
+
 extern "C" {
 
 void spd_opts_default(spd_opts *o)
@@ -1117,6 +1260,75 @@ spd_status spd_factor_export(spd_factor_t F, double *Lout, int64_t ldl, double *
     if (mu) *mu = F->mu;
     HIP_TRY(hipGetLastError());
     return SPD_OK;
+}
+
+void spd_cg_opts_default(spd_cg_opts *o)
+{
+    if (!o) return;
+    o->tol = 1e-14;
+    o->inner_tol = 1e-6;
+    o->max_outer = 30;
+    o->max_inner = 2000;
+}
+
+spd_status spd_cg_prepare(const double *A, int64_t n, int64_t lda, int64_t half_band, void *hip_stream,
+                          spd_cg_t *H)
+{
+    if (!H || n < 0 || lda < std::max<int64_t>(1, n) || (n > 0 && !A)) return SPD_ERR_INVALID_ARG;
+    if (half_band >= 0 && !spd::cg_band_ok(half_band)) return SPD_ERR_UNSUPPORTED;
+    hipStream_t st = (hipStream_t)hip_stream;
+    spd_cg_t h = *H;
+    if (!h) {
+        h = new (std::nothrow) spd_cg_s;
+        if (!h) return SPD_ERR_OUT_OF_MEMORY;
+        *H = h;
+    } else {
+        HIP_TRY(hipStreamSynchronize(st));
+        cg_free_ws(h);
+        hipFree(h->At);
+        h->At = nullptr;
+    }
+    h->n = n;
+    h->ldt = spd::cg_ldt(n);
+    h->k = (half_band >= 0 && half_band < n - 1) ? half_band : -1;  // a band covering A is A
+    const size_t elems = (h->k >= 0) ? (size_t)(2 * h->k + 1) * h->ldt : (size_t)h->ldt * h->ldt;
+    HIP_TRY(hipMalloc(&h->At, elems * sizeof(float)));
+    if (h->k >= 0)
+        spd::launch_cg_band(A, lda, n, h->k, h->At, h->ldt, st);
+    else
+        spd::launch_cg_dense(A, lda, n, h->At, h->ldt, st);
+    HIP_TRY(hipGetLastError());
+    return SPD_OK;
+}
+
+spd_status spd_cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrhs,
+                         double *X, int64_t ldx, const spd_cg_opts *o, spd_report *rep, void *hip_stream)
+{
+    if (!H || !rep) return SPD_ERR_INVALID_ARG;
+    const int64_t n = H->n;
+    spd_cg_opts oo;
+    spd_cg_opts_default(&oo);
+    if (o) oo = *o;
+    if (nrhs < 0 || nrhs > (1 << 20) || lda < std::max<int64_t>(1, n) || ldb < std::max<int64_t>(1, n) ||
+        ldx < std::max<int64_t>(1, n) || !(oo.tol >= 0.0) || !(oo.inner_tol >= 0.0) || oo.max_outer < 0 ||
+        oo.max_inner < 0)
+        return SPD_ERR_INVALID_ARG;
+    if (n > 0 && nrhs > 0 && (!A || !B || !X)) return SPD_ERR_INVALID_ARG;
+    std::memset(rep, 0, sizeof(*rep));
+    rep->prec_used = SPD_FP32;
+    if (n == 0 || nrhs == 0) return SPD_OK;
+    const spd_status s = cg_refine(H, A, lda, B, ldb, (int)nrhs, X, ldx, oo, rep, (hipStream_t)hip_stream);
+    rep->status = s;
+    return s;
+}
+
+void spd_cg_destroy(spd_cg_t H)
+{
+    if (!H) return;
+    hipDeviceSynchronize();
+    cg_free_ws(H);
+    hipFree(H->At);
+    delete H;
 }
 
 }  // extern "C"

@@ -29,7 +29,7 @@ def lib():
 def test_header_declares_the_boundary():
     names = _declared()
     for required in ("spd_factor", "spd_factor_import", "spd_solve", "spd_refine", "spd_solve_batched", "spd_factor_destroy",
-                     "spd_status_str"):
+                     "spd_status_str", "spd_cg_prepare", "spd_cg_refine", "spd_cg_destroy", "spd_cg_opts_default"):
         assert required in names
 
 
@@ -93,6 +93,19 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.spd_factor_query(None, None, None, None) == spd.ERR_INVALID_ARG
     assert lib.spd_factor_export(None, None, 1, None, None, None) == spd.ERR_INVALID_ARG
     lib.spd_factor_destroy(None)  # no-op
+    # CG (Algorithm 2): handle, sizes, pointers; band limit; defaults
+    hc = C.c_void_p()
+    assert lib.spd_cg_prepare(fake, 10, 10, -1, None, None) == spd.ERR_INVALID_ARG
+    assert lib.spd_cg_prepare(fake, -1, 10, -1, None, C.byref(hc)) == spd.ERR_INVALID_ARG
+    assert lib.spd_cg_prepare(fake, 10, 5, -1, None, C.byref(hc)) == spd.ERR_INVALID_ARG
+    assert lib.spd_cg_prepare(None, 10, 10, -1, None, C.byref(hc)) == spd.ERR_INVALID_ARG
+    assert lib.spd_cg_prepare(fake, 10000, 10000, 5000, None, C.byref(hc)) == spd.ERR_UNSUPPORTED
+    assert not hc
+    rep = spd.Report()
+    assert lib.spd_cg_refine(None, fake, 10, fake, 10, 1, fake, 10, None, C.byref(rep), None) == spd.ERR_INVALID_ARG
+    lib.spd_cg_destroy(None)  # no-op
+    o = spd.cg_default_opts()
+    assert (o.tol, o.inner_tol, o.max_outer, o.max_inner) == (1e-14, 1e-6, 30, 2000)
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

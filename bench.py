@@ -9,6 +9,8 @@ binary64 refinement loop until the backward error reaches binary64 level.
 
     python bench.py [--steps K] [--warmup W] [--n 16384] [--cond 1e4] [--nrhs 1]
     python bench.py --workload covariance [--decay 1|2|4]   # Section 4 matrix, n=70000, 32 RHS
+    python bench.py --workload covariance --solver cg [--band 16] [--nrhs 1]
+                                     # Algorithm 2 (CG-IR), dense or banded binary32 operator
 
 Prints ONE JSON line on stdout (progress goes to stderr).  `value` is the
 effective rate F(n, m) / t_step with F = n^3/3 + n^2/2 + n/6 + 2 n^2 m (the
@@ -82,6 +84,84 @@ def cpu_baseline_leg(args, A_dev, X_dev, B_dev, rows_check=True):
     eta_rows = float(np.max(np.abs(R)) / (anorm_rows * np.max(np.abs(Xh)) + np.max(np.abs(Bh))))
     return cpu, {"rows": int(rows.size), "max_abs_residual": float(np.max(np.abs(R))),
                  "eta_lower_bound_rows": eta_rows}
+
+
+def cg_leg(args, spd, spdgen, torch, A, Xt, B):
+    """Algorithm 2 (CG with iterative refinement) on the same system: one step
+    = build the binary32 operator (dense, or the band |i - j| <= band) and
+    refine X from zero to eta <= 1e-14.  The roofline is the product kernel
+    (HBM-bound: A~ is read once per product), timed with HIP events around its
+    launches in a second pass of the same steps."""
+    n, m = A.shape[0], B.shape[0]
+    H = spd.CG()
+    X = torch.zeros_like(B)
+
+    def step():
+        X.zero_()
+        spd.cg_prepare(A, half_band=args.band, H=H)
+        return spd.cg_refine(H, A, B, X)[1]
+
+    for _ in range(args.warmup):
+        rep = step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        rep = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    spd.profile_reset()
+    spd.profile_enable(True)
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt_prof = (time.perf_counter() - t) / args.steps
+    spd.profile_enable(False)
+    launches, ms, fl, by = spd.profile_query(spd.K_CG_MV)
+    H.close()
+    fwd = float(((X - Xt).abs().amax(dim=1) / Xt.abs().amax(dim=1)).max())
+    log(f"cg band={args.band}: {dt * 1e3:.2f} ms/solve, iters {rep.iters_low}/{rep.iters_high}, eta {rep.eta:.2e}, "
+        f"status {rep.status}, product {launches} launches {ms / max(launches, 1) * 1e3:.1f} us each")
+    gbs = by / ms / 1e6 if ms > 0 else 0.0
+    kind = "dense" if args.band < 0 or args.band >= n - 1 else f"band |i-j| <= {args.band}"
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.lib()
+        ns, ms_ = min(args.cpu_sample_n, n), min(m, 4)
+        As = spdgen.covariance(ns, args.decay) if args.workload == "covariance" else \
+            np.ascontiguousarray(A[:ns, :ns].cpu().numpy())
+        Xs = spdgen.rhs(ns, ms_, 17)
+        Bs = spdgen.accurate_product(As, Xs)
+        t = time.perf_counter()
+        _, orep = oracle.cg_ir(As, Bs, half_band=args.band)
+        tc = time.perf_counter() - t
+        w = (n / ns) * (n if kind == "dense" else 2 * args.band + 1) / (ns if kind == "dense" else 2 * args.band + 1)
+        cpu = {"value": tc * 1e3 * w * (m / ms_), "unit": "ms per solve (scaled)", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"oracle.cg_ir on the n={ns} {args.workload} matrix with {ms_} RHS ({kind} operator): "
+                         f"{tc:.2f} s, {orep.iters_low}/{orep.iters_high} iterations; scaled by the product's "
+                         f"work ratio {w:.0f} and the RHS ratio {m / ms_:g}"}
+    return {
+        "metric": f"time to FP64-accurate solve, CG with iterative refinement (Algorithm 2, {kind} binary32 "
+                  f"operator), n={n}, m={m}",
+        "value": dt * 1e3, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload} matrix, d={args.decay}, n={n}, {m} RHS, CG-IR with {kind} "
+                               f"binary32 operator, binary64 vectors and residuals",
+                   "n": n, "nrhs": m, "band": args.band, "decay": args.decay},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": ("k_cg_mv_valu" if m <= 4 else "k_cg_mv_mfma") if kind == "dense" else "k_cg_mv_band",
+                     "launches": launches, "avg_launch_ms": ms / max(launches, 1),
+                     "timed_with_events_ms_per_step": dt_prof * 1e3,
+                     "algorithmic_bytes_per_launch": by / max(launches, 1),
+                     "tflops": fl / ms / 1e9 if ms > 0 else 0.0},
+        "cpu_baseline": cpu,
+        "accuracy": {"status": rep.status, "iters": [rep.iters_low, rep.iters_high], "eta": rep.eta,
+                     "fwd_err_vs_xtrue": fwd},
+    }
 
 
 def measured_traffic(prec):
@@ -180,6 +260,9 @@ def main():
                          "covariance matrix 1/|i-j|^d, 1+sqrt(i) on the diagonal")
     ap.add_argument("--decay", type=int, choices=[1, 2, 4], default=1, help="d of --workload covariance")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--solver", choices=["cholesky", "cg"], default="cholesky",
+                    help="cholesky: Algorithm 1 (the default); cg: Algorithm 2 on the same system")
+    ap.add_argument("--band", type=int, default=-1, help="--solver cg: half-bandwidth of the operator (-1 dense)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the binary64 baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=8192)
@@ -239,6 +322,10 @@ def main():
     torch.cuda.synchronize()
     log(f"generated {args.workload} n={n} cond{'<=' if cov else '='}{cond:g} m={m} "
         f"in {time.perf_counter() - t0:.1f} s")
+
+    if args.solver == "cg":
+        print(json.dumps(cg_leg(args, spd, spdgen, torch, A, Xt, B)), flush=True)
+        return
 
     def run(prec, steps, warmup, profile):
         F = spd.Factor()

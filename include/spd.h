@@ -307,10 +307,14 @@ void spd_cg_destroy(spd_cg_t H);
  *                  their two panel operands)
  *   SPD_K_RESIDUAL binary64 residual (2 n^2 m flops; bytes = the lower
  *                  triangle of A plus X, B and R)
+ *   SPD_K_CG_MV    CG product z = A~ p (2 n^2 m flops dense, 2 (2k + 1) n m
+ *                  banded; bytes = A~ once (4 n^2, or 4 (2k + 1) n) plus
+ *                  the binary32 and binary64 directions read and z written,
+ *                  20 n m)
  * spd_profile_query synchronises on the recorded events, folds them into the
  * totals and returns launches, summed milliseconds, flops and bytes.  Not
  * thread-safe against concurrent factorisations; meant for benchmarks. */
-enum { SPD_K_UPDATE = 0, SPD_K_RESIDUAL = 1, SPD_K_COUNT = 2 };
+enum { SPD_K_UPDATE = 0, SPD_K_RESIDUAL = 1, SPD_K_CG_MV = 2, SPD_K_COUNT = 3 };
 void spd_profile_enable(int on);
 void spd_profile_reset(void);
 spd_status spd_profile_query(int kernel, int64_t *launches, double *total_ms, double *total_flops,

@@ -351,7 +351,7 @@ def export(F: Factor):
     return Lt.T, d, mu.value
 
 
-K_UPDATE, K_RESIDUAL = 0, 1
+K_UPDATE, K_RESIDUAL, K_CG_MV = 0, 1, 2
 
 
 def profile_enable(on: bool = True):

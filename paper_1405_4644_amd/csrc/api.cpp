@@ -669,6 +669,8 @@ spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, 
     // iterations launched between host checks: a dense product is long
     // enough that one check per iteration costs nothing
     const int S = (k < 0) ? 2 : 16;
+    const double band_w = (k < 0) ? (double)n : (double)(2 * k + 1);
+    const double mv_flops = 2.0 * band_w * n * m, mv_bytes = 4.0 * band_w * n + 20.0 * n * m;
     std::vector<double> eta1(m, 0.0), prev(m, 0.0);
     std::vector<int> done(m, 0), stalls(m, 0);
     std::vector<double> eta(m, 0.0);
@@ -718,7 +720,9 @@ spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, 
         int launched = 0;
         for (;;) {
             for (int s = 0; s < S; ++s) {
+                hipEvent_t pe = prof_begin(st);
                 spd::launch_cg_mv(H->At, ldt, n, k, m, H->Pf, H->P, H->Z, H->part, nmv, act, st);
+                if (pe) prof_end(pe, st, SPD_K_CG_MV, mv_flops, mv_bytes);
                 spd::launch_cg_scalars(spd::CG_ALPHA, H->part, nmv, H->sc, act, go, cnt, it2, o.max_inner, m, st);
                 spd::launch_cg_xr(n, m, alpha, H->P, H->Z, X, ldx, H->R, H->vpart, nv, act, st);
                 spd::launch_cg_scalars(spd::CG_BETA, H->vpart, nv, H->sc, act, go, cnt, it2, o.max_inner, m, st);

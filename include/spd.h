@@ -288,8 +288,8 @@ void spd_cg_opts_default(spd_cg_opts *o);
 spd_status spd_cg_prepare(const double *A, int64_t n, int64_t lda, int64_t half_band, void *hip_stream,
                           spd_cg_t *H);
 
-/* Refines X (n x nrhs, ldx; device memory; its entry value is x_0, e.g.
- * zero) for A X = B with the handle's A~; A must be the matrix the handle
+/* Refines X (n x nrhs, ldx, nrhs <= 65535; device memory; its entry value
+ * is x_0, e.g. zero) for A X = B with the handle's A~; A must be the matrix the handle
  * was built from (binary64 residuals).  o NULL: defaults.  Synchronises
  * hip_stream once per outer step and once per few inner iterations (the
  * stopping tests).  Returns rep->status. */

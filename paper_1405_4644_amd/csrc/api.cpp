@@ -609,7 +609,7 @@ struct spd_cg_s {
     double *R = nullptr, *P = nullptr, *Z = nullptr, *part = nullptr, *vpart = nullptr, *sc = nullptr;
     double *norms = nullptr, *rscr = nullptr;
     float *Pf = nullptr;
-    int *flags = nullptr;            // act[m], go[m], cnt[m]
+    int *flags = nullptr;            // act[2][m] (parity slots), go[m], cnt[m]
     double *norms_host = nullptr;
     int *flags_host = nullptr;
 };
@@ -645,10 +645,10 @@ spd_status cg_ensure_ws(spd_cg_t H, int m, hipStream_t st)
     HIP_TRY(hipMalloc(&H->sc, (size_t)4 * m * sizeof(double)));
     HIP_TRY(hipMalloc(&H->norms, (size_t)(1 + 4 * m) * sizeof(double)));
     HIP_TRY(hipMalloc(&H->rscr, (size_t)spd::resid_scratch(n, m) * sizeof(double)));
-    HIP_TRY(hipMalloc(&H->Pf, (size_t)ldt * m * sizeof(float)));
-    HIP_TRY(hipMalloc(&H->flags, (size_t)3 * m * sizeof(int)));
+    HIP_TRY(hipMalloc(&H->Pf, (size_t)spd::cg_pf_elems(ldt, m) * sizeof(float)));
+    HIP_TRY(hipMalloc(&H->flags, (size_t)4 * m * sizeof(int)));
     HIP_TRY(hipHostMalloc(&H->norms_host, (size_t)(1 + 4 * m) * sizeof(double), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc(&H->flags_host, (size_t)3 * m * sizeof(int), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&H->flags_host, (size_t)4 * m * sizeof(int), hipHostMallocDefault));
     H->m = m;
     return SPD_OK;
 }
@@ -658,12 +658,11 @@ spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, 
 {
     const int64_t n = H->n, ldt = H->ldt, k = H->k;
     SPD_TRY(cg_ensure_ws(H, m, st));
-    // Pf's rows n..ldt-1 must read as zero in the dense product
-    spd::launch_zero((double *)H->Pf, ldt * m / 2, st);
+    // Pf's padding (rows n..ldt-1, columns m.. of the last block) must read as zero
+    spd::launch_zero((double *)H->Pf, spd::cg_pf_elems(ldt, m) / 2, st);
     const int64_t nmv = spd::cg_mv_parts(n, ldt, k, m), nv = spd::cg_vec_parts(n);
-    int *act = H->flags, *go = H->flags + m, *cnt = H->flags + 2 * m;
-    int *go_h = H->flags_host + m;
-    double *alpha = H->sc + 2 * m, *beta = H->sc + 3 * m;
+    int *act = H->flags, *go = H->flags + 2 * m, *cnt = H->flags + 3 * m;  // act: two parity slots
+    int *go_h = H->flags_host + 2 * m;
     const double it2 = o.inner_tol * o.inner_tol;
     const int nn = 1 + 4 * m;
     // iterations launched between host checks: a dense product is long
@@ -716,29 +715,28 @@ spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, 
         for (int c = 0; c < m; ++c) go_h[c] = !done[c];
         HIP_TRY(hipMemcpyAsync(go, go_h, m * sizeof(int), hipMemcpyHostToDevice, st));
         spd::launch_cg_start(n, m, H->R, H->P, H->Pf, ldt, H->vpart, nv, go, st);
-        spd::launch_cg_scalars(spd::CG_START, H->vpart, nv, H->sc, act, go, cnt, it2, o.max_inner, m, st);
+        spd::launch_cg_begin(H->vpart, nv, H->sc, act, go, cnt, it2, o.max_inner, m, st);
         int launched = 0;
         for (;;) {
-            for (int s = 0; s < S; ++s) {
+            for (int s = 0; s < S; ++s) {  // S is even: iteration parity = s & 1
+                const int par = s & 1;
                 hipEvent_t pe = prof_begin(st);
-                spd::launch_cg_mv(H->At, ldt, n, k, m, H->Pf, H->P, H->Z, H->part, nmv, act, st);
+                spd::launch_cg_mv(H->At, ldt, n, k, m, H->Pf, H->P, H->Z, H->part, nmv, act + par * m, st);
                 if (pe) prof_end(pe, st, SPD_K_CG_MV, mv_flops, mv_bytes);
-                spd::launch_cg_scalars(spd::CG_ALPHA, H->part, nmv, H->sc, act, go, cnt, it2, o.max_inner, m, st);
-                spd::launch_cg_xr(n, m, alpha, H->P, H->Z, X, ldx, H->R, H->vpart, nv, act, st);
-                spd::launch_cg_scalars(spd::CG_BETA, H->vpart, nv, H->sc, act, go, cnt, it2, o.max_inner, m, st);
-                spd::launch_cg_p(n, m, beta, H->R, H->P, H->Pf, ldt, act, st);
+                spd::launch_cg_xr(n, m, H->part, nmv, H->sc, par, H->P, H->Z, X, ldx, H->R, H->vpart, nv, act, st);
+                spd::launch_cg_p(n, m, H->vpart, nv, H->sc, par, H->R, H->P, H->Pf, ldt, act, cnt, o.max_inner, st);
             }
             launched += S;
             HIP_TRY(hipGetLastError());
-            HIP_TRY(hipMemcpyAsync(H->flags_host, H->flags, 3 * m * sizeof(int), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(H->flags_host, H->flags, 4 * m * sizeof(int), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             bool any = false;
-            for (int c = 0; c < m; ++c) any |= H->flags_host[c] != 0;
+            for (int c = 0; c < m; ++c) any |= H->flags_host[c] != 0;  // slot 0 after an even count
             if (!any || launched > o.max_inner + S) break;
         }
         int longest = 0;
         for (int c = 0; c < m; ++c)
-            if (go_h[c]) longest = std::max(longest, H->flags_host[2 * m + c]);
+            if (go_h[c]) longest = std::max(longest, H->flags_host[3 * m + c]);
         rep->iters_low += longest;
     }
     return result;
@@ -1313,7 +1311,7 @@ spd_status spd_cg_refine(spd_cg_t H, const double *A, int64_t lda, const double 
     spd_cg_opts oo;
     spd_cg_opts_default(&oo);
     if (o) oo = *o;
-    if (nrhs < 0 || nrhs > (1 << 20) || lda < std::max<int64_t>(1, n) || ldb < std::max<int64_t>(1, n) ||
+    if (nrhs < 0 || nrhs > 65535 || lda < std::max<int64_t>(1, n) || ldb < std::max<int64_t>(1, n) ||
         ldx < std::max<int64_t>(1, n) || !(oo.tol >= 0.0) || !(oo.inner_tol >= 0.0) || oo.max_outer < 0 ||
         oo.max_inner < 0)
         return SPD_ERR_INVALID_ARG;

@@ -133,24 +133,27 @@ void launch_adam(float *P, const float *g, float *m, float *v, int64_t count, in
 
 // --- conjugate gradients with refinement (k_cg.hip) ---
 // Binary32 operator A~ (dense ldt x ldt, or band rows d = -k..k of length
-// ldt) and the steps of one CG iteration; partial sums per workgroup are
-// reduced per column by launch_cg_scalars (sc = rho, thr, alpha, beta: 4m).
-enum { CG_START = 0, CG_ALPHA = 1, CG_BETA = 2 };
+// ldt) and the steps of one CG iteration (product, x/r, p); partial sums per
+// workgroup are reduced per column by their consumers.  sc = rho[2][m],
+// thr[m]; act = act[2][m] (slots by iteration parity).
 int64_t cg_ldt(int64_t n);
 int cg_band_ok(int64_t k);
 void launch_cg_dense(const double *A, int64_t lda, int64_t n, float *At, int64_t ldt, hipStream_t st);
 void launch_cg_band(const double *A, int64_t lda, int64_t n, int64_t k, float *Bd, int64_t ldt, hipStream_t st);
+int cg_pf_width(int m);
+int64_t cg_pf_elems(int64_t ldt, int m);  // binary32 direction storage (elements)
 int64_t cg_mv_parts(int64_t n, int64_t ldt, int64_t k, int m);
 int64_t cg_vec_parts(int64_t n);
 void launch_cg_mv(const float *At, int64_t ldt, int64_t n, int64_t k, int m, const float *Pf, const double *P,
                   double *Z, double *part, int64_t npart, const int *act, hipStream_t st);
 void launch_cg_start(int64_t n, int m, const double *R, double *P, float *Pf, int64_t ldt, double *part,
                      int64_t npart, const int *go, hipStream_t st);
-void launch_cg_xr(int64_t n, int m, const double *alpha, const double *P, const double *Z, double *X, int64_t ldx,
-                  double *R, double *part, int64_t npart, const int *act, hipStream_t st);
-void launch_cg_p(int64_t n, int m, const double *beta, const double *R, double *P, float *Pf, int64_t ldt,
-                 const int *act, hipStream_t st);
-void launch_cg_scalars(int mode, const double *part, int64_t npart, double *sc, int *act, const int *go, int *cnt,
-                       double inner_tol2, int max_inner, int m, hipStream_t st);
+void launch_cg_xr(int64_t n, int m, const double *pzp, int64_t npz, const double *sc, int par, const double *P,
+                  const double *Z, double *X, int64_t ldx, double *R, double *part, int64_t npart, const int *act,
+                  hipStream_t st);
+void launch_cg_p(int64_t n, int m, const double *rrp, int64_t nrr, double *sc, int par, const double *R, double *P,
+                 float *Pf, int64_t ldt, int *act, int *cnt, int max_inner, hipStream_t st);
+void launch_cg_begin(const double *part, int64_t npart, double *sc, int *act, const int *go, int *cnt,
+                     double inner_tol2, int max_inner, int m, hipStream_t st);
 
 }  // namespace spd

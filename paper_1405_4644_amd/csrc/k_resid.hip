@@ -445,7 +445,7 @@ void launch_residual(const double *A, int64_t lda, int64_t n, const double *X, i
         else if (mc <= 16)
             launch_partial<16, 2, 2, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
         else if (mc <= 32)
-            launch_partial<32, 2, 4, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
+            launch_partial<32, 4, 4, 2>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
         else
             launch_partial<64, 4, 4, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
     }

@@ -605,6 +605,7 @@ BatchCtx g_batch[kMaxDevices];
 struct spd_cg_s {
     int64_t n = 0, ldt = 0, k = -1;  // k >= 0: band |i - j| <= k; k < 0: dense
     float *At = nullptr;             // dense ldt x ldt, or (2k + 1) rows of length ldt
+    size_t cap_At = 0;               // bytes allocated for At
     int m = 0;                       // right-hand sides the workspace is sized for
     double *R = nullptr, *P = nullptr, *Z = nullptr, *part = nullptr, *vpart = nullptr, *sc = nullptr;
     double *norms = nullptr, *rscr = nullptr;
@@ -1284,17 +1285,25 @@ spd_status spd_cg_prepare(const double *A, int64_t n, int64_t lda, int64_t half_
         h = new (std::nothrow) spd_cg_s;
         if (!h) return SPD_ERR_OUT_OF_MEMORY;
         *H = h;
-    } else {
+    }
+    const int64_t ldt = spd::cg_ldt(n);
+    const int64_t k = (half_band >= 0 && half_band < n - 1) ? half_band : -1;  // a band covering A is A
+    const size_t bytes = ((k >= 0) ? (size_t)(2 * k + 1) * ldt : (size_t)ldt * ldt) * sizeof(float);
+    if (h->n != n || h->ldt != ldt || h->k != k) {  // the workspace is laid out for n and k
         HIP_TRY(hipStreamSynchronize(st));
         cg_free_ws(h);
+    }
+    if (h->cap_At < bytes) {  // the operator's buffer is kept when large enough
+        HIP_TRY(hipStreamSynchronize(st));
         hipFree(h->At);
         h->At = nullptr;
+        h->cap_At = 0;
+        HIP_TRY(hipMalloc(&h->At, bytes));
+        h->cap_At = bytes;
     }
     h->n = n;
-    h->ldt = spd::cg_ldt(n);
-    h->k = (half_band >= 0 && half_band < n - 1) ? half_band : -1;  // a band covering A is A
-    const size_t elems = (h->k >= 0) ? (size_t)(2 * h->k + 1) * h->ldt : (size_t)h->ldt * h->ldt;
-    HIP_TRY(hipMalloc(&h->At, elems * sizeof(float)));
+    h->ldt = ldt;
+    h->k = k;
     if (h->k >= 0)
         spd::launch_cg_band(A, lda, n, h->k, h->At, h->ldt, st);
     else

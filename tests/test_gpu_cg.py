@@ -141,3 +141,26 @@ def test_cg_covariance_n70000(spd, d, band, m):
     assert bool((err <= bound).all())
     del A, B, X, Xt, R
     torch.cuda.empty_cache()
+
+
+def test_cg_handle_reuse_is_bitwise_equal(spd):
+    """One handle re-prepared dense -> band -> dense (the operator buffer and
+    workspace are reused or rebuilt) gives exactly the results of fresh
+    handles: every reduction is in a fixed order."""
+    import torch
+    n, m = 900, 3
+    A = dev(spdgen.covariance(n, 2))
+    Bt = dev(spdgen.rhs(n, m, 31))
+    fresh = {}
+    for band in (-1, 8):
+        H = spd.cg_prepare(A, half_band=band)
+        fresh[band] = spd.cg_refine(H, A, Bt)[0].clone()
+        H.close()
+    H = spd.CG()
+    for band in (-1, 8, -1):
+        spd.cg_prepare(A, half_band=band, H=H)
+        X, rep = spd.cg_refine(H, A, Bt)
+        torch.cuda.synchronize()
+        assert rep.status == 0
+        assert torch.equal(X, fresh[band])
+    H.close()

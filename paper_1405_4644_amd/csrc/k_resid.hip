@@ -130,6 +130,88 @@ __global__ __launch_bounds__(256) void k_resid_partial(const double *__restrict_
     }
 }
 
+// The same partial sums for 9..32 right-hand sides per chunk on binary64
+// MFMA (v_mfma_f64_16x16x4f64): wave w owns rows 16 w .. 16 w + 15 of the
+// tile and NT column tiles of 16; per k-step of 4 a lane feeds A(i, k) with
+// i = lane % 16, k = lane / 16 from the LDS tile and X(k, c) with
+// c = lane % 16 from the LDS copy of X (pitch 65: conflict-free columns).
+// The accumulator holds row lane / 16 + 4 r, column lane % 16 in register r
+// (the binary64 layout, unlike the binary32 16 x 16 one).
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+template <int NT>
+__global__ __launch_bounds__(256) void k_resid_mfma(const double *__restrict__ A, int64_t lda, int64_t n,
+                                                    const double *__restrict__ X, int64_t ldx, int m, int c0, int S,
+                                                    double *__restrict__ P, double *__restrict__ Pabs, int want_abs)
+{
+    constexpr int MC = 16 * NT, TS = 65;
+    __shared__ double Ts[64 * TS];
+    __shared__ double Xs[MC * TS];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int I = blockIdx.x, s = blockIdx.y;
+    const int64_t i0 = (int64_t)I * 64;
+    const int nrb = (int)((n + 63) / 64);
+    doublex4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+    double aabs = 0.0;
+    for (int J = s; J < nrb; J += S) {
+        const int64_t j0 = (int64_t)J * 64;
+        __syncthreads();
+        if (J < I) {
+            for (int idx = tid; idx < 4096; idx += 256) {
+                const int i = idx & 63, j = idx >> 6;
+                const int64_t gi = i0 + i, gj = j0 + j;
+                Ts[j * TS + i] = (gi < n && gj < n) ? A[gi + gj * lda] : 0.0;
+            }
+        } else if (J > I) {
+            for (int idx = tid; idx < 4096; idx += 256) {
+                const int j = idx & 63, i = idx >> 6;
+                const int64_t gi = i0 + i, gj = j0 + j;
+                Ts[j * TS + i] = (gi < n && gj < n) ? A[gj + gi * lda] : 0.0;
+            }
+        } else {
+            for (int idx = tid; idx < 4096; idx += 256) {
+                const int i = idx & 63, j = idx >> 6;
+                const int64_t gi = i0 + i, gj = j0 + j;
+                Ts[j * TS + i] = (i >= j && gi < n && gj < n) ? A[gi + gj * lda] : 0.0;
+            }
+            __syncthreads();
+            for (int idx = tid; idx < 4096; idx += 256) {
+                const int i = idx & 63, j = idx >> 6;
+                if (i < j)
+                    Ts[j * TS + i] = Ts[i * TS + j];
+            }
+        }
+        for (int idx = tid; idx < MC * 64; idx += 256) {
+            const int j = idx & 63, c = idx >> 6;
+            const int64_t gj = j0 + j;
+            Xs[c * TS + j] = (gj < n && c0 + c < m) ? X[gj + (int64_t)(c0 + c) * ldx] : 0.0;
+        }
+        __syncthreads();
+        if (want_abs && tid < 64)
+            for (int j = 0; j < 64; ++j) aabs += fabs(Ts[j * TS + tid]);
+#pragma unroll 4
+        for (int k0 = 0; k0 < 64; k0 += 4) {
+            const double a = Ts[(k0 + kq) * TS + 16 * w + r16];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const double b = Xs[(16 * t + r16) * TS + k0 + kq];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t gi = i0 + 16 * w + kq + 4 * r;
+            const int c = 16 * t + r16;
+            if (gi < n && c0 + c < m) P[((int64_t)s * m + c0 + c) * n + gi] = acc[t][r];
+        }
+    if (want_abs && tid < 64 && i0 + tid < n) Pabs[(int64_t)s * n + i0 + tid] = aabs;
+}
+
 // Single pass over the lower triangle for a few right-hand sides.  Workgroup
 // (J, q) walks tiles I = J + q CH .. of the 64-column strip J (contiguous in
 // memory); wave w holds columns 16 w .. 16 w + 15 of the tile, lane l its row
@@ -431,23 +513,26 @@ void launch_residual(const double *A, int64_t lda, int64_t n, const double *X, i
     }
     const int S = resid_splits(n);
     double *Pabs = P + (int64_t)S * n * m;
-    for (int c0 = 0; c0 < m; c0 += 64) {
-        const int mc = (m - c0 < 64) ? (m - c0) : 64;
+    const unsigned nrb = (unsigned)((n + 63) / 64);
+    const int step = (m > 8) ? 32 : 64;  // MFMA chunks of up to 32 columns
+    for (int c0 = 0; c0 < m; c0 += step) {
+        const int mc = (m - c0 < step) ? (m - c0) : step;
         const int wa = (want_anorm && c0 == 0) ? 1 : 0;
-        if (mc <= 1)
+        if (mc > 8) {
+            if (mc <= 16)
+                hipLaunchKernelGGL(k_resid_mfma<1>, dim3(nrb, (unsigned)S), dim3(256), 0, st, A, lda, n, X, ldx, m, c0,
+                                   S, P, Pabs, wa);
+            else
+                hipLaunchKernelGGL(k_resid_mfma<2>, dim3(nrb, (unsigned)S), dim3(256), 0, st, A, lda, n, X, ldx, m, c0,
+                                   S, P, Pabs, wa);
+        } else if (mc <= 1)
             launch_partial<1, 1, 1, 4>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
         else if (mc <= 2)
             launch_partial<2, 1, 1, 2>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
         else if (mc <= 4)
             launch_partial<4, 1, 1, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
-        else if (mc <= 8)
-            launch_partial<8, 1, 2, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
-        else if (mc <= 16)
-            launch_partial<16, 2, 2, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
-        else if (mc <= 32)
-            launch_partial<32, 4, 4, 2>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
         else
-            launch_partial<64, 4, 4, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
+            launch_partial<8, 1, 2, 1>(A, lda, n, X, ldx, m, c0, S, P, Pabs, wa, st);
     }
     hipLaunchKernelGGL(k_resid_reduce, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0, st, B, ldb, X,
                        ldx, n, m, S, P, Pabs, want_anorm, d, R, ldr, norms);

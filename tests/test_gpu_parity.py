@@ -138,7 +138,7 @@ def test_breakdown_column_matches_oracle(spd, orc, prec, n, j0):
 
 
 @pytest.mark.parametrize("n,m", [(1000, 1), (777, 5), (300, 64), (130, 70), (2049, 1), (513, 2), (65, 1), (1, 1),
-                                 (1100, 3)])
+                                 (1100, 3), (1000, 12), (700, 32), (129, 17)])
 def test_residual_kernel_elementwise(spd, orc, n, m):
     _say(f"residual n={n} m={m}")
     s = spdgen.system(n, 1e3, m, config=1, index=n)

@@ -641,7 +641,10 @@ spd_status cg_ensure_ws(spd_cg_t H, int m, hipStream_t st)
     HIP_TRY(hipMalloc(&H->R, nm));
     HIP_TRY(hipMalloc(&H->P, nm));
     HIP_TRY(hipMalloc(&H->Z, nm));
-    HIP_TRY(hipMalloc(&H->part, (size_t)spd::cg_mv_parts(n, ldt, H->k, m) * m * sizeof(double)));
+    // product partials: sized for the most per column any m' <= m uses (the
+    // workspace is reused for fewer right-hand sides)
+    const int64_t mvp = std::max(spd::cg_mv_parts(n, ldt, H->k, m), spd::cg_mv_parts(n, ldt, H->k, 1));
+    HIP_TRY(hipMalloc(&H->part, (size_t)mvp * m * sizeof(double)));
     HIP_TRY(hipMalloc(&H->vpart, (size_t)spd::cg_vec_parts(n) * m * sizeof(double)));
     HIP_TRY(hipMalloc(&H->sc, (size_t)4 * m * sizeof(double)));
     HIP_TRY(hipMalloc(&H->norms, (size_t)(1 + 4 * m) * sizeof(double)));

@@ -201,48 +201,59 @@ __global__ __launch_bounds__(256) void k_cg_mv_valu(const float *__restrict__ Af
 }
 
 // z = A~ p for 5..32 right-hand sides per launch row (blockIdx.y picks the
-// block of 32) on v_mfma_f32_32x32x2f32.  A workgroup owns the 32 rows of z
-// of one column block; its four waves split the row blocks.  Per row block
-// a lane loads two float4s of A~ (its MFMA A-operand values for k-slot h)
-// and the matching two float4s of the directions (B operand: column c =
-// lane % 32, the same eight rows), both fully coalesced.
+// block of 32) on v_mfma_f32_32x32x2f32.  A workgroup owns the 32 NB rows of
+// z of NB consecutive column blocks; its four waves split the row blocks.
+// Per row block a lane loads two float4s of A~ per column block (its MFMA
+// A-operand values for k-slot h) and the matching two float4s of the
+// directions once for all NB blocks (B operand: column c = lane % 32, the
+// same eight rows), all fully coalesced.  The directions of 32 columns
+// (4 ldt 32 bytes) exceed one XCD's L2, so sharing them across NB blocks
+// divides their re-reads by NB.
+template <int NB>
 __global__ __launch_bounds__(256) void k_cg_mv_mfma(const float *__restrict__ Af, int64_t ldt, int64_t n, int m,
                                                     const float *__restrict__ Pf, const double *__restrict__ P,
                                                     double *__restrict__ Z, double *__restrict__ part, int64_t npart,
                                                     const int *__restrict__ act)
 {
-    __shared__ float red[3][16][64];
+    __shared__ float red[3][NB][16][64];
     const int c0 = blockIdx.y * 32;
     const int mc = min(32, m - c0);
     if (!any_active(act, c0, mc)) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int h = lane >> 5, l32 = lane & 31;
     const int64_t nJ = ldt / 16, jq = nJ / 4;
-    const int64_t I = blockIdx.x;
-    const float *ab = Af + (I * nJ + w * jq) * 512 + lane * 4;
+    const int64_t I0 = (int64_t)blockIdx.x * NB;
+    const float *ab = Af + (I0 * nJ + w * jq) * 512 + lane * 4;
     // float4 number (4 J + 2 h) 32 + c of this block of 32 columns, and the next group
     const float4 *pb = reinterpret_cast<const float4 *>(Pf + (int64_t)blockIdx.y * ldt * 32) +
                        (w * jq * 4 + 2 * h) * 32 + l32;
-    floatx16 acc;
+    floatx16 acc[NB];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
 #pragma unroll 2
     for (int64_t J = 0; J < jq; ++J) {
-        const float4 a0 = *reinterpret_cast<const float4 *>(ab + J * 512);
-        const float4 a1 = *reinterpret_cast<const float4 *>(ab + J * 512 + 256);
         const float4 b0 = pb[J * 128], b1 = pb[J * 128 + 32];
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, b0.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, b0.y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, b0.z, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, b0.w, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, b1.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, b1.y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, b1.z, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, b1.w, acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const float4 a0 = *reinterpret_cast<const float4 *>(ab + (q * nJ + J) * 512);
+            const float4 a1 = *reinterpret_cast<const float4 *>(ab + (q * nJ + J) * 512 + 256);
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, b0.x, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, b0.y, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, b0.z, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, b0.w, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, b1.x, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, b1.y, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, b1.z, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, b1.w, acc[q], 0, 0, 0);
+        }
     }
     if (w > 0)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) red[w - 1][r][lane] = acc[r];
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) red[w - 1][q][r][lane] = acc[q][r];
     __syncthreads();
     if (w != 0) return;
     // register r of lane l: row 8(r/4) + 4(l/32) + r%4 of the block, column l%32
@@ -250,15 +261,17 @@ __global__ __launch_bounds__(256) void k_cg_mv_mfma(const float *__restrict__ Af
     const int c = c0 + l32;
     double pz = 0.0;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const float s = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
-        const int64_t i = I * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        if (cvalid && i < n) {
-            const double z = (double)s;
-            Z[i + (int64_t)c * n] = z;
-            pz += P[i + (int64_t)c * n] * z;
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float s = ((acc[q][r] + red[0][q][r][lane]) + red[1][q][r][lane]) + red[2][q][r][lane];
+            const int64_t i = (I0 + q) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+            if (cvalid && i < n) {
+                const double z = (double)s;
+                Z[i + (int64_t)c * n] = z;
+                pz += P[i + (int64_t)c * n] * z;
+            }
         }
-    }
     pz += __shfl_xor(pz, 32, 64);
     if (h == 0 && cvalid) part[blockIdx.x + (int64_t)c * npart] = pz;
 }
@@ -500,10 +513,17 @@ int64_t cg_pf_elems(int64_t ldt, int m)
     return (int64_t)((m + W - 1) / W) * W * ldt;
 }
 
+// column blocks per workgroup of the 5..32-column dense product (2 and 4
+// measured no faster at n = 70000, 32 right-hand sides: 4.46 and 5.41 ms
+// against 4.37 ms per product)
+#ifndef CG_MFMA_NB
+#define CG_MFMA_NB 1
+#endif
+
 int64_t cg_mv_parts(int64_t n, int64_t ldt, int64_t k, int m)
 {
-    (void)m;
-    return (k >= 0) ? (n + 255) / 256 : ldt / 32;
+    if (k >= 0) return (n + 255) / 256;
+    return (m <= 4) ? ldt / 32 : ldt / (32 * CG_MFMA_NB);
 }
 
 void launch_cg_mv(const float *At, int64_t ldt, int64_t n, int64_t k, int m, const float *Pf, const double *P,
@@ -528,8 +548,8 @@ void launch_cg_mv(const float *At, int64_t ldt, int64_t n, int64_t k, int m, con
     case 3: hipLaunchKernelGGL(k_cg_mv_valu<3>, g, blk, 0, st, At, ldt, n, Pf, P, Z, part, npart, act); break;
     case 4: hipLaunchKernelGGL(k_cg_mv_valu<4>, g, blk, 0, st, At, ldt, n, Pf, P, Z, part, npart, act); break;
     default:
-        hipLaunchKernelGGL(k_cg_mv_mfma, dim3((unsigned)(ldt / 32), (unsigned)((m + 31) / 32)), blk, 0, st, At, ldt,
-                           n, m, Pf, P, Z, part, npart, act);
+        hipLaunchKernelGGL(k_cg_mv_mfma<CG_MFMA_NB>, dim3((unsigned)(ldt / (32 * CG_MFMA_NB)), (unsigned)((m + 31) / 32)),
+                           blk, 0, st, At, ldt, n, m, Pf, P, Z, part, npart, act);
     }
 }
 

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_resid_mfma(const double *__restrict__ A
                                                     const double *__restrict__ X, int64_t ldx, int m, int c0, int S,
                                                     double *__restrict__ P, double *__restrict__ Pabs, int want_abs)
 {
-    constexpr int MC = 16 * NT, TS = 65;
+    constexpr int MC = 16 * NT, TS = 65, XU = MC * 64 / 256;
     __shared__ double Ts[64 * TS];
     __shared__ double Xs[MC * TS];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -155,27 +155,54 @@ __global__ __launch_bounds__(256) void k_resid_mfma(const double *__restrict__ A
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
     double aabs = 0.0;
-    for (int J = s; J < nrb; J += S) {
+    // The next tile's values are loaded into registers while the current
+    // tile is multiplied.  Element u of a thread: idx = tid + 256 u; for a
+    // tile left of the diagonal (and the diagonal tile, lower part only)
+    // i = idx % 64, j = idx / 64 read along A's column j; right of it
+    // j = idx % 64, i = idx / 64 read along A's column i (the transpose).
+    double av[16], xv[XU];
+    auto fetch = [&](int J) {
         const int64_t j0 = (int64_t)J * 64;
-        __syncthreads();
-        if (J < I) {
-            for (int idx = tid; idx < 4096; idx += 256) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u;
+            double v = 0.0;
+            if (J <= I) {
                 const int i = idx & 63, j = idx >> 6;
                 const int64_t gi = i0 + i, gj = j0 + j;
-                Ts[j * TS + i] = (gi < n && gj < n) ? A[gi + gj * lda] : 0.0;
-            }
-        } else if (J > I) {
-            for (int idx = tid; idx < 4096; idx += 256) {
+                if (gi < n && gj < n && (J < I || i >= j)) v = A[gi + gj * lda];
+            } else {
                 const int j = idx & 63, i = idx >> 6;
                 const int64_t gi = i0 + i, gj = j0 + j;
-                Ts[j * TS + i] = (gi < n && gj < n) ? A[gj + gi * lda] : 0.0;
+                if (gi < n && gj < n) v = A[gj + gi * lda];
             }
-        } else {
-            for (int idx = tid; idx < 4096; idx += 256) {
-                const int i = idx & 63, j = idx >> 6;
-                const int64_t gi = i0 + i, gj = j0 + j;
-                Ts[j * TS + i] = (i >= j && gi < n && gj < n) ? A[gi + gj * lda] : 0.0;
-            }
+            av[u] = v;
+        }
+#pragma unroll
+        for (int u = 0; u < XU; ++u) {
+            const int idx = tid + 256 * u;
+            const int j = idx & 63, c = idx >> 6;
+            const int64_t gj = j0 + j;
+            xv[u] = (gj < n && c0 + c < m) ? X[gj + (int64_t)(c0 + c) * ldx] : 0.0;
+        }
+    };
+    if (s < nrb) fetch(s);
+    for (int J = s; J < nrb; J += S) {
+        __syncthreads();  // the previous tile has been consumed
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int idx = tid + 256 * u;
+            if (J <= I)
+                Ts[(idx >> 6) * TS + (idx & 63)] = av[u];
+            else
+                Ts[(idx & 63) * TS + (idx >> 6)] = av[u];
+        }
+#pragma unroll
+        for (int u = 0; u < XU; ++u) {
+            const int idx = tid + 256 * u;
+            Xs[(idx >> 6) * TS + (idx & 63)] = xv[u];
+        }
+        if (J == I) {  // mirror the lower triangle of the diagonal tile
             __syncthreads();
             for (int idx = tid; idx < 4096; idx += 256) {
                 const int i = idx & 63, j = idx >> 6;
@@ -183,12 +210,8 @@ __global__ __launch_bounds__(256) void k_resid_mfma(const double *__restrict__ A
                     Ts[j * TS + i] = Ts[i * TS + j];
             }
         }
-        for (int idx = tid; idx < MC * 64; idx += 256) {
-            const int j = idx & 63, c = idx >> 6;
-            const int64_t gj = j0 + j;
-            Xs[c * TS + j] = (gj < n && c0 + c < m) ? X[gj + (int64_t)(c0 + c) * ldx] : 0.0;
-        }
         __syncthreads();
+        if (J + S < nrb) fetch(J + S);  // in flight during the products below
         if (want_abs && tid < 64)
             for (int j = 0; j < 64; ++j) aabs += fabs(Ts[j * TS + tid]);
 #pragma unroll 4

@@ -89,6 +89,12 @@ bool g_prof_on = false;
 std::vector<ProfRec> g_prof_pending;
 ProfTotals g_prof_tot[SPD_K_COUNT];
 
+bool prof_enabled()
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    return g_prof_on;
+}
+
 // Returns an event recorded before the launch (or nullptr when disabled).
 hipEvent_t prof_begin(hipStream_t st)
 {
@@ -613,6 +619,7 @@ struct spd_cg_s {
     int *flags = nullptr;            // act[2][m] (parity slots), go[m], cnt[m]
     double *norms_host = nullptr;
     int *flags_host = nullptr;
+    hipStream_t gstream = nullptr;   // capture stream for the banded iteration graph
 };
 
 namespace {
@@ -674,6 +681,38 @@ spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, 
     const int S = (k < 0) ? 2 : 16;
     const double band_w = (k < 0) ? (double)n : (double)(2 * k + 1);
     const double mv_flops = 2.0 * band_w * n * m, mv_bytes = 4.0 * band_w * n + 20.0 * n * m;
+    // one CG iteration: product, x/r update, p update (parity slot par); with
+    // profiling on, the product alone is bracketed by the caller
+    auto launch_iteration = [&](int par, hipStream_t q) {
+        spd::launch_cg_mv(H->At, ldt, n, k, m, H->Pf, H->P, H->Z, H->part, nmv, act + par * m, q);
+        spd::launch_cg_xr(n, m, H->part, nmv, H->sc, par, H->P, H->Z, X, ldx, H->R, H->vpart, nv, act, q);
+        spd::launch_cg_p(n, m, H->vpart, nv, H->sc, par, H->R, H->P, H->Pf, ldt, act, cnt, o.max_inner, q);
+    };
+    // Banded iterations are launch-bound: the S iterations between host
+    // checks are captured once per call into a graph (all arguments are fixed
+    // for the call) and replayed.  Not while kernel profiling is on (its
+    // events bracket single launches), and any capture failure falls back to
+    // direct launches.
+    hipGraphExec_t gexec = nullptr;
+    if (k >= 0 && !prof_enabled()) {
+        bool ok = H->gstream || hipStreamCreateWithFlags(&H->gstream, hipStreamNonBlocking) == hipSuccess;
+        hipGraph_t g = nullptr;
+        if (ok) ok = hipStreamBeginCapture(H->gstream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            for (int s = 0; s < S; ++s) launch_iteration(s & 1, H->gstream);
+            ok = hipStreamEndCapture(H->gstream, &g) == hipSuccess && g;
+        }
+        if (ok) ok = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) hipGraphDestroy(g);
+        if (!ok) {
+            gexec = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    struct GraphGuard {
+        hipGraphExec_t &e;
+        ~GraphGuard() { if (e) hipGraphExecDestroy(e); }
+    } gguard{gexec};
     std::vector<double> eta1(m, 0.0), prev(m, 0.0);
     std::vector<int> done(m, 0), stalls(m, 0);
     std::vector<double> eta(m, 0.0);
@@ -722,13 +761,14 @@ spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, 
         spd::launch_cg_begin(H->vpart, nv, H->sc, act, go, cnt, it2, o.max_inner, m, st);
         int launched = 0;
         for (;;) {
-            for (int s = 0; s < S; ++s) {  // S is even: iteration parity = s & 1
-                const int par = s & 1;
-                hipEvent_t pe = prof_begin(st);
-                spd::launch_cg_mv(H->At, ldt, n, k, m, H->Pf, H->P, H->Z, H->part, nmv, act + par * m, st);
-                if (pe) prof_end(pe, st, SPD_K_CG_MV, mv_flops, mv_bytes);
-                spd::launch_cg_xr(n, m, H->part, nmv, H->sc, par, H->P, H->Z, X, ldx, H->R, H->vpart, nv, act, st);
-                spd::launch_cg_p(n, m, H->vpart, nv, H->sc, par, H->R, H->P, H->Pf, ldt, act, cnt, o.max_inner, st);
+            if (gexec) {
+                HIP_TRY(hipGraphLaunch(gexec, st));
+            } else {
+                for (int s = 0; s < S; ++s) {  // S is even: iteration parity = s & 1
+                    hipEvent_t pe = prof_begin(st);
+                    launch_iteration(s & 1, st);
+                    if (pe) prof_end(pe, st, SPD_K_CG_MV, mv_flops, mv_bytes);
+                }
             }
             launched += S;
             HIP_TRY(hipGetLastError());
@@ -1342,6 +1382,7 @@ void spd_cg_destroy(spd_cg_t H)
     hipDeviceSynchronize();
     cg_free_ws(H);
     hipFree(H->At);
+    if (H->gstream) hipStreamDestroy(H->gstream);
     delete H;
 }
 

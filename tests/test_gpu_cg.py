@@ -164,3 +164,27 @@ def test_cg_handle_reuse_is_bitwise_equal(spd):
         assert rep.status == 0
         assert torch.equal(X, fresh[band])
     H.close()
+
+
+@pytest.mark.parametrize("m", [1, 3])
+def test_cg_band_graph_matches_direct_launches(spd, m):
+    """Banded iterations are replayed from a captured graph (about a hundred
+    replays per solve, with host checks between them); with kernel profiling
+    on, the same iterations are launched one by one.  Both give the same bits."""
+    import torch
+    n = 3000
+    A = dev(spdgen.covariance(n, 1))
+    Bt = dev(spdgen.rhs(n, m, 41))
+    H = spd.cg_prepare(A, half_band=16)
+    X1, r1 = spd.cg_refine(H, A, Bt)
+    torch.cuda.synchronize()
+    spd.profile_enable(True)
+    try:
+        X2, r2 = spd.cg_refine(H, A, Bt)
+        torch.cuda.synchronize()
+    finally:
+        spd.profile_enable(False)
+    H.close()
+    assert r1.status == r2.status == 0
+    assert (r1.iters_low, r1.iters_high) == (r2.iters_low, r2.iters_high) and r1.iters_low > 100
+    assert torch.equal(X1, X2)

@@ -284,7 +284,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py: this solver runs on one GPU (requested --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "multi-GPU runs are not part of this build.", file=sys.stderr, flush=True)
+              "runs over several GPUs are not supported.", file=sys.stderr, flush=True)
         sys.exit(2)
 
     import torch

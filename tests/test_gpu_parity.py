@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Tolerances (derived in DESIGN.md, "Parity bars"):
+Tolerances (each derived from the arithmetic it bounds):
   * refined solutions: backward error eta <= 1e-14 recomputed by the oracle,
     and normwise forward error <= 10 cond(A) 2^-53 against the oracle's binary64
     solution and against X_true (B formed in double-double);

@@ -153,7 +153,7 @@ def cg_leg(args, spd, spdgen, torch, A, Xt, B):
                    "n": n, "nrhs": m, "band": args.band, "decay": args.decay},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ("k_cg_mv_valu" if m <= 4 else "k_cg_mv_mfma") if kind == "dense" else "k_cg_mv_band",
+                     "kernel": ("k_cg_mv_valu" if m <= 4 else "k_cg_mv_mfma_ks + k_cg_mv_ksum") if kind == "dense" else "k_cg_mv_band",
                      "launches": launches, "avg_launch_ms": ms / max(launches, 1),
                      "timed_with_events_ms_per_step": dt_prof * 1e3,
                      "algorithmic_bytes_per_launch": by / max(launches, 1),

@@ -616,6 +616,7 @@ struct spd_cg_s {
     double *R = nullptr, *P = nullptr, *Z = nullptr, *part = nullptr, *vpart = nullptr, *sc = nullptr;
     double *norms = nullptr, *rscr = nullptr;
     float *Pf = nullptr;
+    float *Zp = nullptr;             // k-slice partials of the dense multi-column product
     int *flags = nullptr;            // act[2][m] (parity slots), go[m], cnt[m]
     double *norms_host = nullptr;
     int *flags_host = nullptr;
@@ -627,11 +628,12 @@ namespace {
 void cg_free_ws(spd_cg_t H)
 {
     hipFree(H->R); hipFree(H->P); hipFree(H->Z); hipFree(H->part); hipFree(H->vpart); hipFree(H->sc);
-    hipFree(H->norms); hipFree(H->rscr); hipFree(H->Pf); hipFree(H->flags);
+    hipFree(H->norms); hipFree(H->rscr); hipFree(H->Pf); hipFree(H->Zp); hipFree(H->flags);
     if (H->norms_host) hipHostFree(H->norms_host);
     if (H->flags_host) hipHostFree(H->flags_host);
     H->R = H->P = H->Z = H->part = H->vpart = H->sc = H->norms = H->rscr = nullptr;
     H->Pf = nullptr;
+    H->Zp = nullptr;
     H->flags = nullptr;
     H->norms_host = nullptr;
     H->flags_host = nullptr;
@@ -657,6 +659,8 @@ spd_status cg_ensure_ws(spd_cg_t H, int m, hipStream_t st)
     HIP_TRY(hipMalloc(&H->norms, (size_t)(1 + 4 * m) * sizeof(double)));
     HIP_TRY(hipMalloc(&H->rscr, (size_t)spd::resid_scratch(n, m) * sizeof(double)));
     HIP_TRY(hipMalloc(&H->Pf, (size_t)spd::cg_pf_elems(ldt, m) * sizeof(float)));
+    if (H->k < 0 && spd::cg_zp_elems(n, m) > 0)
+        HIP_TRY(hipMalloc(&H->Zp, (size_t)spd::cg_zp_elems(n, m) * sizeof(float)));
     HIP_TRY(hipMalloc(&H->flags, (size_t)4 * m * sizeof(int)));
     HIP_TRY(hipHostMalloc(&H->norms_host, (size_t)(1 + 4 * m) * sizeof(double), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(&H->flags_host, (size_t)4 * m * sizeof(int), hipHostMallocDefault));
@@ -684,7 +688,7 @@ spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, 
     // one CG iteration: product, x/r update, p update (parity slot par); with
     // profiling on, the product alone is bracketed by the caller
     auto launch_iteration = [&](int par, hipStream_t q) {
-        spd::launch_cg_mv(H->At, ldt, n, k, m, H->Pf, H->P, H->Z, H->part, nmv, act + par * m, q);
+        spd::launch_cg_mv(H->At, ldt, n, k, m, H->Pf, H->P, H->Z, H->part, nmv, act + par * m, H->Zp, q);
         spd::launch_cg_xr(n, m, H->part, nmv, H->sc, par, H->P, H->Z, X, ldx, H->R, H->vpart, nv, act, q);
         spd::launch_cg_p(n, m, H->vpart, nv, H->sc, par, H->R, H->P, H->Pf, ldt, act, cnt, o.max_inner, q);
     };

@@ -144,8 +144,10 @@ int cg_pf_width(int m);
 int64_t cg_pf_elems(int64_t ldt, int m);  // binary32 direction storage (elements)
 int64_t cg_mv_parts(int64_t n, int64_t ldt, int64_t k, int m);
 int64_t cg_vec_parts(int64_t n);
+// Zp: binary32 k-slice partials of the 5..32-column dense product, cg_zp_elems(n, m) elements
+int64_t cg_zp_elems(int64_t n, int m);
 void launch_cg_mv(const float *At, int64_t ldt, int64_t n, int64_t k, int m, const float *Pf, const double *P,
-                  double *Z, double *part, int64_t npart, const int *act, hipStream_t st);
+                  double *Z, double *part, int64_t npart, const int *act, float *Zp, hipStream_t st);
 void launch_cg_start(int64_t n, int m, const double *R, double *P, float *Pf, int64_t ldt, double *part,
                      int64_t npart, const int *go, hipStream_t st);
 void launch_cg_xr(int64_t n, int m, const double *pzp, int64_t npz, const double *sc, int par, const double *P,

@@ -201,79 +201,87 @@ __global__ __launch_bounds__(256) void k_cg_mv_valu(const float *__restrict__ Af
 }
 
 // z = A~ p for 5..32 right-hand sides per launch row (blockIdx.y picks the
-// block of 32) on v_mfma_f32_32x32x2f32.  A workgroup owns the 32 NB rows of
-// z of NB consecutive column blocks; its four waves split the row blocks.
-// Per row block a lane loads two float4s of A~ per column block (its MFMA
-// A-operand values for k-slot h) and the matching two float4s of the
-// directions once for all NB blocks (B operand: column c = lane % 32, the
-// same eight rows), all fully coalesced.  The directions of 32 columns
-// (4 ldt 32 bytes) exceed one XCD's L2, so sharing them across NB blocks
-// divides their re-reads by NB.
-template <int NB>
-__global__ __launch_bounds__(256) void k_cg_mv_mfma(const float *__restrict__ Af, int64_t ldt, int64_t n, int m,
-                                                    const float *__restrict__ Pf, const double *__restrict__ P,
-                                                    double *__restrict__ Z, double *__restrict__ part, int64_t npart,
-                                                    const int *__restrict__ act)
+// block of 32) on v_mfma_f32_32x32x2f32, split along k over CG_KS slices.
+// Workgroup b owns the 32 rows of z of column block b / CG_KS and the
+// row-block slice b % CG_KS; its four waves split the slice.  Per row block a
+// lane loads two float4s of A~ (its MFMA A-operand values for k-slot h) and
+// the matching two float4s of the directions (B operand: column c =
+// lane % 32, the same eight rows), both fully coalesced.  Workgroups are
+// dealt to the eight XCDs round-robin, so with CG_KS = 8 every XCD streams
+// one eighth of the binary32 directions, which fits its L2, instead of all
+// of them (9 MB at n = 70000, 32 columns).  Each slice writes its binary32
+// partial z to Zp[slice][c][i]; k_cg_mv_ksum adds the slices in order.
+constexpr int CG_KS = 8;
+__global__ __launch_bounds__(256) void k_cg_mv_mfma_ks(const float *__restrict__ Af, int64_t ldt, int64_t n, int m,
+                                                       const float *__restrict__ Pf, float *__restrict__ Zp,
+                                                       const int *__restrict__ act)
 {
-    __shared__ float red[3][NB][16][64];
+    __shared__ float red[3][16][64];
     const int c0 = blockIdx.y * 32;
     const int mc = min(32, m - c0);
     if (!any_active(act, c0, mc)) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int h = lane >> 5, l32 = lane & 31;
-    const int64_t nJ = ldt / 16, jq = nJ / 4;
-    const int64_t I0 = (int64_t)blockIdx.x * NB;
-    const float *ab = Af + (I0 * nJ + w * jq) * 512 + lane * 4;
-    // float4 number (4 J + 2 h) 32 + c of this block of 32 columns, and the next group
-    const float4 *pb = reinterpret_cast<const float4 *>(Pf + (int64_t)blockIdx.y * ldt * 32) +
-                       (w * jq * 4 + 2 * h) * 32 + l32;
-    floatx16 acc[NB];
+    const int64_t nJ = ldt / 16;
+    const int64_t I = blockIdx.x / CG_KS, sl = blockIdx.x % CG_KS;
+    const int64_t js = nJ * sl / CG_KS, je = nJ * (sl + 1) / CG_KS;
+    const int64_t jb = js + (je - js) * w / 4, jend = js + (je - js) * (w + 1) / 4;
+    const float *ab = Af + (I * nJ) * 512 + lane * 4;
+    const float4 *pb = reinterpret_cast<const float4 *>(Pf + (int64_t)blockIdx.y * ldt * 32) + (2 * h) * 32 + l32;
+    floatx16 acc;
 #pragma unroll
-    for (int q = 0; q < NB; ++q)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 #pragma unroll 2
-    for (int64_t J = 0; J < jq; ++J) {
+    for (int64_t J = jb; J < jend; ++J) {
+        const float4 a0 = *reinterpret_cast<const float4 *>(ab + J * 512);
+        const float4 a1 = *reinterpret_cast<const float4 *>(ab + J * 512 + 256);
         const float4 b0 = pb[J * 128], b1 = pb[J * 128 + 32];
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const float4 a0 = *reinterpret_cast<const float4 *>(ab + (q * nJ + J) * 512);
-            const float4 a1 = *reinterpret_cast<const float4 *>(ab + (q * nJ + J) * 512 + 256);
-            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, b0.x, acc[q], 0, 0, 0);
-            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, b0.y, acc[q], 0, 0, 0);
-            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, b0.z, acc[q], 0, 0, 0);
-            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, b0.w, acc[q], 0, 0, 0);
-            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, b1.x, acc[q], 0, 0, 0);
-            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, b1.y, acc[q], 0, 0, 0);
-            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, b1.z, acc[q], 0, 0, 0);
-            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, b1.w, acc[q], 0, 0, 0);
-        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, b0.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, b0.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, b0.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, b0.w, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, b1.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, b1.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, b1.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, b1.w, acc, 0, 0, 0);
     }
     if (w > 0)
 #pragma unroll
-        for (int q = 0; q < NB; ++q)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) red[w - 1][q][r][lane] = acc[q][r];
+        for (int r = 0; r < 16; ++r) red[w - 1][r][lane] = acc[r];
     __syncthreads();
     if (w != 0) return;
-    // register r of lane l: row 8(r/4) + 4(l/32) + r%4 of the block, column l%32
-    const bool cvalid = l32 < mc;
     const int c = c0 + l32;
+    if (l32 >= mc) return;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const float s = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+        const int64_t i = I * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (i < n) Zp[(sl * m + c) * n + i] = s;
+    }
+}
+
+// z = sum of the CG_KS slices (binary32, slice order), widened; one partial
+// of p^T z per workgroup and column (blockIdx.y = column)
+__global__ __launch_bounds__(256) void k_cg_mv_ksum(int64_t n, int m, const float *__restrict__ Zp,
+                                                    const double *__restrict__ P, double *__restrict__ Z,
+                                                    double *__restrict__ part, int64_t npart,
+                                                    const int *__restrict__ act)
+{
+    __shared__ double red[4];
+    const int c = blockIdx.y;
+    if (!act[c]) return;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double pz = 0.0;
+    if (i < n) {
+        float s = Zp[(int64_t)c * n + i];
 #pragma unroll
-    for (int q = 0; q < NB; ++q)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float s = ((acc[q][r] + red[0][q][r][lane]) + red[1][q][r][lane]) + red[2][q][r][lane];
-            const int64_t i = (I0 + q) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-            if (cvalid && i < n) {
-                const double z = (double)s;
-                Z[i + (int64_t)c * n] = z;
-                pz += P[i + (int64_t)c * n] * z;
-            }
-        }
-    pz += __shfl_xor(pz, 32, 64);
-    if (h == 0 && cvalid) part[blockIdx.x + (int64_t)c * npart] = pz;
+        for (int q = 1; q < CG_KS; ++q) s += Zp[((int64_t)q * m + c) * n + i];
+        const double z = (double)s;
+        Z[i + (int64_t)c * n] = z;
+        pz = P[i + (int64_t)c * n] * z;
+    }
+    pz = block_sum256(pz, red);
+    if (threadIdx.x == 0) part[blockIdx.x + (int64_t)c * npart] = pz;
 }
 
 // z = A~ p on the band: a thread per row; the directions of up to CB
@@ -513,21 +521,16 @@ int64_t cg_pf_elems(int64_t ldt, int m)
     return (int64_t)((m + W - 1) / W) * W * ldt;
 }
 
-// column blocks per workgroup of the 5..32-column dense product (2 and 4
-// measured no faster at n = 70000, 32 right-hand sides: 4.46 and 5.41 ms
-// against 4.37 ms per product)
-#ifndef CG_MFMA_NB
-#define CG_MFMA_NB 1
-#endif
-
 int64_t cg_mv_parts(int64_t n, int64_t ldt, int64_t k, int m)
 {
     if (k >= 0) return (n + 255) / 256;
-    return (m <= 4) ? ldt / 32 : ldt / (32 * CG_MFMA_NB);
+    return (m <= 4) ? ldt / 32 : (n + 255) / 256;
 }
 
+int64_t cg_zp_elems(int64_t n, int m) { return (m > 4) ? (int64_t)CG_KS * m * n : 0; }
+
 void launch_cg_mv(const float *At, int64_t ldt, int64_t n, int64_t k, int m, const float *Pf, const double *P,
-                  double *Z, double *part, int64_t npart, const int *act, hipStream_t st)
+                  double *Z, double *part, int64_t npart, const int *act, float *Zp, hipStream_t st)
 {
     const int W = cg_pf_width(m);
     if (k >= 0) {
@@ -548,8 +551,10 @@ void launch_cg_mv(const float *At, int64_t ldt, int64_t n, int64_t k, int m, con
     case 3: hipLaunchKernelGGL(k_cg_mv_valu<3>, g, blk, 0, st, At, ldt, n, Pf, P, Z, part, npart, act); break;
     case 4: hipLaunchKernelGGL(k_cg_mv_valu<4>, g, blk, 0, st, At, ldt, n, Pf, P, Z, part, npart, act); break;
     default:
-        hipLaunchKernelGGL(k_cg_mv_mfma<CG_MFMA_NB>, dim3((unsigned)(ldt / (32 * CG_MFMA_NB)), (unsigned)((m + 31) / 32)),
-                           blk, 0, st, At, ldt, n, m, Pf, P, Z, part, npart, act);
+        hipLaunchKernelGGL(k_cg_mv_mfma_ks, dim3((unsigned)(ldt / 32 * CG_KS), (unsigned)((m + 31) / 32)), blk, 0, st,
+                           At, ldt, n, m, Pf, Zp, act);
+        hipLaunchKernelGGL(k_cg_mv_ksum, dim3((unsigned)((n + 255) / 256), (unsigned)m), blk, 0, st, n, m, Zp, P, Z,
+                           part, npart, act);
     }
 }
 

@@ -125,3 +125,31 @@ def test_zero_rhs(orc):
     X, rep = orc.cg_ir(A, np.zeros(20))
     assert rep.status == 0 and rep.iters_low == 0 and rep.iters_high == 1 and rep.eta == 0.0
     assert not X.any()
+
+
+@pytest.mark.parametrize("n,d,k", [(200, 1, 0), (200, 1, 1), (200, 1, 3), (200, 1, 8), (120, 1, 2),
+                                   (200, 2, 1), (200, 2, 2), (200, 2, 8)])
+def test_outer_contraction_follows_the_spectral_radius(orc, n, d, k):
+    """With the inner solve run to the end, each outer step multiplies the
+    error by I - A~^{-1} A.  Refinement therefore diverges when that matrix's
+    spectral radius rho exceeds 1, and otherwise needs about
+    1 + ln(1/tol) / ln(1/rho) residuals from x0 = 0 (eta_1 = 1).  Where
+    Eq. (4)'s sufficient condition ||A^{-1} (A - A~)||_inf < 1 holds, it
+    converges.  rho and the norm come from numpy, not from the oracle."""
+    A = spdgen.covariance(n, d)
+    i, j = np.indices((n, n))
+    At = A.astype(np.float32).astype(np.float64)
+    At[np.abs(i - j) > k] = 0.0
+    rho = max(abs(np.linalg.eigvals(np.eye(n) - np.linalg.solve(At, A))))
+    eq4 = np.abs(np.linalg.solve(A, A - At)).sum(axis=1).max()
+    b = spdgen.rhs(n, 1, 5)[0]
+    _, rep = orc.cg_ir(A, b, half_band=k, inner_tol=1e-12, max_inner=5000, max_outer=400)
+    if rho > 1.05:
+        assert rep.status == 3
+        return
+    assert rho <= 0.8, "case outside the pinned range"
+    assert rep.status == 0
+    if eq4 < 1.0:
+        assert rep.status == 0
+    predicted = 1.0 + np.log(1e14) / np.log(1.0 / rho)
+    assert 0.75 * predicted <= rep.iters_high <= 1.25 * predicted, (rep.iters_high, predicted)

@@ -13,7 +13,8 @@
 // Reductions are deterministic: every kernel that needs a dot product
 // writes one partial per workgroup, and its consumers sum them for each
 // column in a fixed order (every workgroup of a consumer the same way).
-// One CG iteration is three launches: product, x/r update, p update.
+// One CG iteration is three launches (four for the dense 5..32-column
+// product, which adds its slice sum): product, x/r update, p update.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

@@ -188,3 +188,20 @@ def test_cg_band_graph_matches_direct_launches(spd, m):
     assert r1.status == r2.status == 0
     assert (r1.iters_low, r1.iters_high) == (r2.iters_low, r2.iters_high) and r1.iters_low > 100
     assert torch.equal(X1, X2)
+
+
+@pytest.mark.parametrize("n", [1, 2, 33])
+@pytest.mark.parametrize("band", [-1, 0, 1])
+@pytest.mark.parametrize("m", [1, 5])
+def test_cg_tiny_systems_match_oracle(spd, orc, n, band, m):
+    """Sizes below one 256-row tile (padding everywhere; empty k-slices for
+    some waves of the split product): status and counts as the oracle's."""
+    A = spdgen.covariance(n, 1)
+    Bt = spdgen.rhs(n, m, 50 + n)
+    X, rep = _gpu_cg(spd, A, Bt, band)
+    Xo, ro = orc.cg_ir(A, Bt, half_band=band)
+    assert rep.status == ro.status
+    assert abs(rep.iters_high - ro.iters_high) <= 1
+    assert abs(rep.iters_low - ro.iters_low) <= max(3, 0.1 * ro.iters_low)
+    if ro.status == 0:
+        assert orc.backward_error(A, X, Bt).max() <= 1e-14

@@ -181,3 +181,21 @@ def test_ir_factor_rejects_a_bad_diagonal(orc):
     L[17, 17] = -1.0
     X, rep = orc.ir_factor(A, L, B)
     assert rep.status == 2 and rep.info == 18
+
+
+def test_ir_factor_fp32_matches_own_factor_when_exact(orc):
+    """min(i, j) has the all-ones lower triangle as its Cholesky factor, exact
+    in binary32, and the binary32 factorisation reproduces it exactly (every
+    pivot is 1, every subtraction exact).  Importing that factor rounded to
+    binary32 (Section 3.1, Fig. 3(b) path) must then give bit for bit the
+    refinement of line 1's own binary32 factor without equilibration."""
+    n = 40
+    A = spdgen.minij(n)
+    L = np.tril(np.ones((n, n)))
+    assert np.array_equal(L @ L.T, A)
+    b = A @ np.arange(1.0, n + 1.0)
+    X1, r1 = orc.ir_factor(A, L, b, prec="fp32", max_iter=30)
+    X2, r2 = orc.ir(A, b, prec="fp32", equilibrate=False, fallback=False, max_iter=30)
+    assert r1.status == r2.status == 0
+    assert (r1.iters_low, r1.iters_high) == (r2.iters_low, r2.iters_high)
+    assert np.array_equal(X1, X2)

@@ -537,7 +537,9 @@ void launch_cg_mv(const float *At, int64_t ldt, int64_t n, int64_t k, int m, con
     if (k >= 0) {
         const int64_t pitch = 256 + 2 * k + 1;
         const dim3 g((unsigned)((n + 255) / 256));
-        if (m > 1 && pitch * 32 * (int64_t)sizeof(float) <= 65536)
+        // dynamic LDS for 32 columns, plus the kernel's static reduction
+        // space (1 KB), within the 64 KB a workgroup may use
+        if (m > 1 && pitch * 32 * (int64_t)sizeof(float) + 1024 <= 65536)
             hipLaunchKernelGGL(k_cg_mv_band<32>, g, dim3(256), (size_t)pitch * 32 * sizeof(float), st, At, ldt, n, k,
                                m, W, Pf, P, Z, part, npart, act);
         else

@@ -82,6 +82,8 @@ def lib():
         L.oracle_rne_f16.restype = C.c_float
         L.oracle_rne_bf16.argtypes = [C.c_float]
         L.oracle_rne_bf16.restype = C.c_float
+        L.oracle_lowprec_factor.argtypes = [i64, vp, i64, i32, i32, f64, vp, i64, vp, C.POINTER(f64)]
+        L.oracle_lowprec_factor.restype = i64
         L.oracle_ir.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, i32, i32, f64, f64, i32,
                                 i32, C.POINTER(_Report)]
         L.oracle_ir_factor.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, i32, f64, i32,
@@ -203,6 +205,22 @@ def rne_f16(x: float) -> float:
 
 def rne_bf16(x: float) -> float:
     return float(lib().oracle_rne_bf16(float(np.float32(x))))
+
+
+def lowprec_factor(A, prec="fp32", equilibrate=True, theta=0.1):
+    """Line 1 of Algorithm 1 with its scaling, as ``ir`` forms it.  Returns
+    (L widened to binary64, d, mu, info): L is the factor of
+    H = round32(mu D A D) (binary32 arithmetic; binary16/bfloat16 update
+    operands), or of A itself for "fp64" (d = 1, mu = 1)."""
+    A = _colmajor(A)
+    n = A.shape[0]
+    L = np.zeros((n, n), dtype=np.float64, order="F")
+    d = np.empty(n, dtype=np.float64)
+    mu = C.c_double(0.0)
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    info = lib().oracle_lowprec_factor(n, _ptr(A), n, p, int(bool(equilibrate)), float(theta), _ptr(L), n,
+                                       _ptr(d), C.byref(mu))
+    return L, d, float(mu.value), int(info)
 
 
 def ir(A, Bt, prec="fp32", equilibrate=True, theta=0.1, tol=1e-14, max_iter=10, fallback=True):

@@ -19,6 +19,8 @@
  *   oracle_norm1_sym / oracle_backward_error  norms and eta
  *   oracle_rne_f16 / oracle_rne_bf16  binary32 -> binary16 / bfloat16 rounding
  *                    to nearest even, from the formats' definitions
+ *   oracle_lowprec_factor  line 1 of Algorithm 1 with its scaling (d, mu) on
+ *                    its own, for pins
  *   oracle_ir        Algorithm 1 emulated step by step with a low-precision
  *                    factor (binary32, or binary16/bfloat16 operands with
  *                    binary32 accumulation) and binary64 residual/update.
@@ -341,22 +343,18 @@ static int ir_loop(int64_t n, int64_t m, const double *A, int64_t lda, const dou
                    double *X, int64_t ldx, int prec, const double *d, double mu, const double *L64,
                    const float *L32, double tol, int max_iter, oracle_report *rep);
 
-/* One attempt of Algorithm 1 at precision `prec`.  Returns status. */
-static int ir_attempt(int64_t n, int64_t m, const double *A, int64_t lda,
-                      const double *B, int64_t ldb, double *X, int64_t ldx, int prec,
-                      int equil, double theta, double tol, int max_iter,
-                      oracle_report *rep)
+/* Line 1 with its scaling: d (equilibration, 1 for binary64 or when `equil`
+ * is off), mu, and the low-precision factor -- L64 (binary64, from A itself)
+ * or L32 (binary32 factor of H = round32(mu D A D), update operands rounded
+ * to binary16/bfloat16 for prec 1/0).  The caller frees *L64 / *L32.
+ * Returns the 1-based breakdown column, or 0. */
+static int64_t lowprec_factor(int64_t n, const double *A, int64_t lda, int prec, int equil, double theta,
+                              double *d, double *mu, double **L64, float **L32)
 {
     size_t nn = (size_t)n * (size_t)n;
-    double *d = (double *)malloc((size_t)n * sizeof(double));
-    double *L64 = NULL;
-    float *L32 = NULL;
-    double mu = 1.0;
-    int status = 0;
-    rep->info = 0;
-    rep->iters_low = rep->iters_high = 0;
-    rep->eta = NAN;
-
+    *mu = 1.0;
+    *L64 = NULL;
+    *L32 = NULL;
     /* scaling (not in the paper; needed so binary16 neither overflows nor underflows) */
     for (int64_t i = 0; i < n; ++i) {
         double a = A[IDX(i, i, lda)];
@@ -366,20 +364,55 @@ static int ir_attempt(int64_t n, int64_t m, const double *A, int64_t lda,
         /* largest power of two <= theta * 65504 */
         int e;
         frexp(theta * 65504.0, &e);
-        mu = ldexp(1.0, e - 1);
+        *mu = ldexp(1.0, e - 1);
     }
+    if (prec == 3) {
+        *L64 = (double *)malloc(nn * sizeof(double));
+        return oracle_potrf(n, A, lda, *L64, n);
+    }
+    float *H = (float *)malloc(nn * sizeof(float));
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i)
+            H[IDX(i, j, n)] = (i >= j) ? (float)(*mu * d[i] * A[IDX(i, j, lda)] * d[j]) : 0.0f;
+    *L32 = H;
+    return potrf_lowprec(n, H, prec);
+}
+
+/* Line 1 on its own, for pins: the scaling and the low-precision factor as
+ * ir_attempt forms them.  L (n x n, leading dimension ldl) receives the
+ * factor widened to binary64 (lower triangle; zeros above), d the
+ * equilibration, *mu the scale.  Returns the 1-based breakdown column, or 0
+ * (L then holds the partial factor). */
+int64_t oracle_lowprec_factor(int64_t n, const double *A, int64_t lda, int32_t prec, int32_t equil,
+                              double theta, double *L, int64_t ldl, double *d, double *mu)
+{
+    double *L64;
+    float *L32;
+    int64_t info = lowprec_factor(n, A, lda, prec, equil, theta, d, mu, &L64, &L32);
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i)
+            L[IDX(i, j, ldl)] = (i < j) ? 0.0 : (L64 ? L64[IDX(i, j, n)] : (double)L32[IDX(i, j, n)]);
+    free(L64);
+    free(L32);
+    return info;
+}
+
+/* One attempt of Algorithm 1 at precision `prec`.  Returns status. */
+static int ir_attempt(int64_t n, int64_t m, const double *A, int64_t lda,
+                      const double *B, int64_t ldb, double *X, int64_t ldx, int prec,
+                      int equil, double theta, double tol, int max_iter,
+                      oracle_report *rep)
+{
+    double *d = (double *)malloc((size_t)n * sizeof(double));
+    double *L64 = NULL;
+    float *L32 = NULL;
+    double mu = 1.0;
+    int status = 0;
+    rep->iters_low = rep->iters_high = 0;
+    rep->eta = NAN;
 
     /* line 1: low-precision factorisation */
-    if (prec == 3) {
-        L64 = (double *)malloc(nn * sizeof(double));
-        rep->info = oracle_potrf(n, A, lda, L64, n);
-    } else {
-        L32 = (float *)malloc(nn * sizeof(float));
-        for (int64_t j = 0; j < n; ++j)
-            for (int64_t i = 0; i < n; ++i)
-                L32[IDX(i, j, n)] = (i >= j) ? (float)(mu * d[i] * A[IDX(i, j, lda)] * d[j]) : 0.0f;
-        rep->info = potrf_lowprec(n, L32, prec);
-    }
+    rep->info = lowprec_factor(n, A, lda, prec, equil, theta, d, &mu, &L64, &L32);
     if (rep->info) {
         status = 2;
         goto done;

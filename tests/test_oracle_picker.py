@@ -118,3 +118,44 @@ def test_label_rule():
     assert pk.label([False, True, True, True], [9.0, 2.0, 2.03, 4.0]) == 2  # tie within 2 % -> higher
     assert pk.label([False, False, False, True], [0, 0, 0, 7.0]) == 3
     assert pk.label([False, False, False, False], [0, 0, 0, 0]) == 3
+
+
+def test_features_arrow_matrix_max_and_mean_radius():
+    # arrow matrix with unit diagonal: h_1j = h_j1 = c (j > 1), zero elsewhere;
+    # SPD for c sqrt(n - 1) < 1.  Radii: r_1 = (n - 1) c, r_j = c, so the
+    # largest radius (f5) and the mean radius (f6) differ in closed form
+    n, c = 5, 0.25
+    A = np.eye(n)
+    A[0, 1:] = A[1:, 0] = c
+    f = pk.features(A, 1)
+    rmax, rmean = (n - 1) * c, 2 * (n - 1) * c / n
+    assert f[5] == pytest.approx(math.log10(1 + rmax) / 3, abs=1e-15)
+    assert f[6] == pytest.approx(math.log10(1 + rmean) / 3, abs=1e-15)
+    assert f[7] == pytest.approx((n - 1) / n)          # r_1 = 1 is not < 1
+    assert f[8] == pytest.approx(np.clip(1 - rmax, -10, 1) / 10)
+    assert f[12] == pytest.approx(c)
+
+
+def test_feature_f14_full_lanczos_against_krylov_basis():
+    # K = 4 steps with no early stop: 2 [-1, 2, -1] of order 10 has five
+    # eigenvectors that are symmetric under reversal, so ones/sqrt(n) spans
+    # a Krylov space of dimension 5 > 4.  Independently of the three-term
+    # recurrence, T_4 = Q^T H Q with Q an orthonormal basis of
+    # span{v, Hv, H^2 v, H^3 v} (numpy QR), and beta_4 = ||(I - Q Q^T) H q_4||.
+    n = 10
+    A = 2.0 * spdgen.tridiag(n)
+    f = pk.features(A, 1)
+    d = 1 / np.sqrt(np.diag(A))
+    H = (d[:, None] * A) * d[None, :]
+    v = np.ones(n) / np.sqrt(n)
+    K = np.stack([np.linalg.matrix_power(H, j) @ v for j in range(4)], axis=1)
+    Q, R = np.linalg.qr(K)
+    Q = Q * np.sign(np.diag(R))[None, :]
+    T = Q.T @ H @ Q
+    th = np.linalg.eigvalsh(T)
+    w = H @ Q[:, 3]
+    beta4 = np.linalg.norm(w - Q @ (Q.T @ w))
+    assert beta4 > 1e-3  # no early stop
+    assert f[14] == pytest.approx(beta4 / th[-1], rel=1e-9)
+    assert f[9] == pytest.approx(math.log10(th[-1]) / 3, rel=1e-9)
+    assert f[15] == pytest.approx((th[1] - th[0]) / (th[-1] - th[0]), rel=1e-9)

@@ -260,11 +260,12 @@ float oracle_rne_bf16(float x)
  *   line 2   x = s mu D L^{-T} L^{-1} round32(D b / s), s a power of two
  *            normalising max |D b| (per column); binary32 substitution.
  *   line 3   r = b - A x in binary64; eta per column as above.
- *   line 4   the loop ends when max_c eta_c <= 2^-51 (binary64 floor), or
- *            when eta <= tol and the last step shrank eta by less than half.
- *            Divergence (only while eta > tol): eta not finite, eta above the
- *            first eta, or two consecutive steps with eta_k > 0.9 eta_{k-1}.
- *            At most `max_iter` corrections; then success iff eta <= tol.
+ *   line 4   the loop ends when every column is done: eta <= tol and the
+ *            corrections show x accurate to binary64 level (the rule is
+ *            stated above ir_loop).  Divergence (only while eta > tol): eta
+ *            not finite, eta above the first eta, or two consecutive steps
+ *            with eta_k > 0.9 eta_{k-1}.  At most `max_iter` corrections;
+ *            without success by then, no convergence.
  *   line 5-7 z from the same low-precision solve of r; x += z (binary64);
  *            new residual.
  *   fallback on breakdown or divergence: binary16/bfloat16 -> binary32 ->
@@ -323,10 +324,31 @@ static void solve_f32(int64_t n, const float *L, float *y)
     }
 }
 
-/* Refinement keeps going past the requested tolerance while it still
- * contracts, down to a few units of binary64 roundoff: eta <= tol alone leaves
- * a forward error of about cond * tol, not cond * u; the relative forward
- * error is at most about 2 cond eta, so 4u keeps it below 10 cond u. */
+/* When the refinement is done (Algorithm 1's while-test read as "until x is
+ * accurate to binary64 level"; Eq. (4) decides whether it converges at all).
+ * The backward error alone does not tell: eta <= tol, even eta at the
+ * binary64 floor, is reached while x still carries error along the
+ * eigenvectors of the smallest eigenvalues, which the residual hardly sees.
+ * The corrections do see it.  Per column, after correction k (z_k solved
+ * from the residual of x_k, whose backward error is eta_k; x_{k+1} = x_k + z_k):
+ *   zeta_k = ||z_k||_inf / ||x_{k+1}||_inf   (about the relative error of x_k)
+ *   rho_k  = zeta_k / zeta_{k-1}              (the observed contraction)
+ * With geometric contraction the error left in x_{k+1} is about
+ * rho_k/(1 - rho_k) zeta_k; the solve turned a backward error eta_k into
+ * zeta_k, so residuals rounded at binary64 level (eta ~ u) limit x to about
+ * (zeta_k/eta_k) u.  A column is done once eta_{k+1} <= tol and
+ *   (a) eta_{k+1} = 0 or zeta_k <= u (x no longer moves), or
+ *   (b) rho_k < 1/2 and rho_k/(1 - rho_k) eta_k <= u (the error left is below
+ *       what binary64 residuals resolve), or
+ *   (c) rho_k >= 1/2 and eta_k <= 4u (the correction came from a residual
+ *       at rounding level and no longer contracts: x is as accurate as the
+ *       binary64 residual allows).
+ * A binary64 factor of A itself is backward stable, so its first solve is
+ * accepted at eta <= tol.  The refinement succeeds when every column is done;
+ * divergence (eta not finite, above its first value, or two consecutive steps
+ * with eta_k > 0.9 eta_{k-1} in every column) is judged only while eta > tol;
+ * after max_iter corrections without success it has not converged. */
+#define U64 (0x1p-53)
 #define ETA_FLOOR (0x1p-51)
 
 /* power of two s with s/2 < v <= s (1 for v == 0 or non-finite) */
@@ -341,7 +363,7 @@ static double pow2_ceil(double v)
 
 static int ir_loop(int64_t n, int64_t m, const double *A, int64_t lda, const double *B, int64_t ldb,
                    double *X, int64_t ldx, int prec, const double *d, double mu, const double *L64,
-                   const float *L32, double tol, int max_iter, oracle_report *rep);
+                   const float *L32, int stable, double tol, int max_iter, oracle_report *rep);
 
 /* Line 1 with its scaling: d (equilibration, 1 for binary64 or when `equil`
  * is off), mu, and the low-precision factor -- L64 (binary64, from A itself)
@@ -418,7 +440,7 @@ static int ir_attempt(int64_t n, int64_t m, const double *A, int64_t lda,
         goto done;
     }
 
-    status = ir_loop(n, m, A, lda, B, ldb, X, ldx, prec, d, mu, L64, L32, tol, max_iter, rep);
+    status = ir_loop(n, m, A, lda, B, ldb, X, ldx, prec, d, mu, L64, L32, prec == 3, tol, max_iter, rep);
 done:
     free(d); free(L64); free(L32);
     return status;
@@ -427,15 +449,19 @@ done:
 /* Lines 2-7 of Algorithm 1 with a given factor: L64 (binary64 solves) or
  * L32 (binary32 solves of the scaled right-hand side), D = diag(d), mu.
  * Line 2 (first solve, from r = b) and lines 5-6 (corrections) share one
- * routine: z = s mu D L^{-T} L^{-1} round(D r / s).  Returns the status. */
+ * routine: z = s mu D L^{-T} L^{-1} round(D r / s).  `stable`: the factor is
+ * line 1's own binary64 factor (first solve accepted at eta <= tol).
+ * Returns the status. */
 static int ir_loop(int64_t n, int64_t m, const double *A, int64_t lda, const double *B, int64_t ldb,
                    double *X, int64_t ldx, int prec, const double *d, double mu, const double *L64,
-                   const float *L32, double tol, int max_iter, oracle_report *rep)
+                   const float *L32, int stable, double tol, int max_iter, oracle_report *rep)
 {
     double *R = (double *)malloc((size_t)n * (size_t)m * sizeof(double));
-    double *eta = (double *)malloc((size_t)m * sizeof(double));
-    double *prev = (double *)malloc((size_t)m * sizeof(double));
+    double *eta = (double *)malloc((size_t)m * 4 * sizeof(double));
+    double *eprev = eta + m, *zeta = eta + 2 * m, *zprev = eta + 3 * m;
+    int *done = (int *)calloc((size_t)m, sizeof(int));
     float *y = (float *)malloc((size_t)n * sizeof(float));
+    double *z = (double *)malloc((size_t)n * sizeof(double));
     int status = 0;
     rep->iters_low = rep->iters_high = 0;
     rep->eta = NAN;
@@ -446,7 +472,7 @@ static int ir_loop(int64_t n, int64_t m, const double *A, int64_t lda, const dou
         for (int64_t i = 0; i < n; ++i)
             R[IDX(i, c, n)] = B[IDX(i, c, ldb)];
     int stalls = 0;
-    double eta0 = 0.0, prev_worst = 0.0;
+    double eta0 = 0.0;
     for (;;) {
         /* low-precision solve of the current residual, then x += z */
         for (int64_t c = 0; c < m; ++c) {
@@ -455,7 +481,7 @@ static int ir_loop(int64_t n, int64_t m, const double *A, int64_t lda, const dou
                 oracle_fsub(n, 1, L64, n, r, n);
                 oracle_bsub(n, 1, L64, n, r, n);
                 for (int64_t i = 0; i < n; ++i)
-                    X[IDX(i, c, ldx)] += r[i];
+                    z[i] = r[i];
             } else {
                 double mx = 0.0;
                 for (int64_t i = 0; i < n; ++i)
@@ -465,8 +491,12 @@ static int ir_loop(int64_t n, int64_t m, const double *A, int64_t lda, const dou
                     y[i] = (float)(d[i] * r[i] / s);
                 solve_f32(n, L32, y);
                 for (int64_t i = 0; i < n; ++i)
-                    X[IDX(i, c, ldx)] += s * mu * d[i] * (double)y[i];
+                    z[i] = s * mu * d[i] * (double)y[i];
             }
+            for (int64_t i = 0; i < n; ++i)
+                X[IDX(i, c, ldx)] += z[i];
+            double zn = vec_maxabs(n, z), xn = vec_maxabs(n, X + (size_t)c * ldx);
+            zeta[c] = (zn == 0.0) ? 0.0 : zn / xn; /* xn = 0 < zn: +inf */
         }
         rep->iters_low++;
         /* binary64 residual and backward error */
@@ -485,24 +515,37 @@ static int ir_loop(int64_t n, int64_t m, const double *A, int64_t lda, const dou
         }
         rep->eta = finite ? worst : NAN;
         if (!finite) { status = 3; break; }
-        /* binary64 floor reached: nothing more to gain */
-        if (worst <= ETA_FLOOR) { status = 0; break; }
-        if (rep->iters_high == 1) {
+        /* which columns are done (k = corrections so far) */
+        const int k = rep->iters_high - 1;
+        int all = 1;
+        for (int64_t c = 0; c < m; ++c) {
+            if (!done[c] && eta[c] <= tol) {
+                if (eta[c] == 0.0 || zeta[c] <= U64)
+                    done[c] = 1;
+                else if (k == 0)
+                    done[c] = stable;
+                else {
+                    double rho = zeta[c] / zprev[c];
+                    done[c] = (rho < 0.5) ? (rho / (1.0 - rho)) * eprev[c] <= U64 : eprev[c] <= ETA_FLOOR;
+                }
+            }
+            all = all && done[c];
+        }
+        if (all && worst <= tol) { status = 0; break; }
+        if (k == 0) {
             eta0 = worst;
         } else {
-            /* inside the tolerance and no longer contracting: accept */
-            if (worst <= tol && worst > 0.5 * prev_worst) { status = 0; break; }
             int stall = 1;
             for (int64_t c = 0; c < m; ++c)
-                if (!(eta[c] > 0.9 * prev[c])) stall = 0;
+                if (!(eta[c] > 0.9 * eprev[c])) stall = 0;
             stalls = stall ? stalls + 1 : 0;
             if (worst > tol && (worst > eta0 || stalls >= 2)) { status = 3; break; }
         }
-        if (rep->iters_low > max_iter) { status = (worst <= tol) ? 0 : 3; break; }
-        prev_worst = worst;
-        memcpy(prev, eta, (size_t)m * sizeof(double));
+        if (rep->iters_low > max_iter) { status = 3; break; }
+        memcpy(eprev, eta, (size_t)m * sizeof(double));
+        memcpy(zprev, zeta, (size_t)m * sizeof(double));
     }
-    free(R); free(eta); free(prev); free(y);
+    free(R); free(eta); free(done); free(y); free(z);
     return status;
 }
 
@@ -569,7 +612,7 @@ int32_t oracle_ir_factor(int64_t n, int64_t m, const double *A, int64_t lda, con
             for (int64_t i = 0; i < n; ++i)
                 L32[IDX(i, j, n)] = (i >= j) ? (float)L[IDX(i, j, ldl)] : 0.0f;
     }
-    status = ir_loop(n, m, A, lda, B, ldb, X, ldx, prec, d, 1.0, L64, L32, tol, max_iter, rep);
+    status = ir_loop(n, m, A, lda, B, ldb, X, ldx, prec, d, 1.0, L64, L32, 0, tol, max_iter, rep);
     free(d); free(L64); free(L32);
     rep->status = status;
     return status;
@@ -586,7 +629,10 @@ int32_t oracle_ir_factor(int64_t n, int64_t m, const double *A, int64_t lda, con
  * Every other quantity (x, r, p, rho, alpha, beta) is binary64.
  *
  * One outer step (counted in iters_high): r = b - A x in binary64 and the
- * backward error eta of each column.  A column with eta <= tol is done.
+ * backward error eta of each column.  A column is done by Algorithm 1's
+ * stopping rule (above ir_loop): eta <= tol and the change of x over its
+ * last inner phase (the correction) shows x accurate to binary64 level;
+ * a start x0 counts as a first solve.
  * Otherwise CG runs on the current residual -- Algorithm 2's loop body with
  * x updated in place --
  *     p = r, rho = r^T r, stop when r^T r <= inner_tol^2 rho_0 or after
@@ -601,7 +647,7 @@ int32_t oracle_ir_factor(int64_t n, int64_t m, const double *A, int64_t lda, con
  * depend on the others.
  *
  * After max_outer inner phases the residual is formed once more.  Status 0
- * when every column has eta <= tol; 3 when eta is not finite, rises above
+ * when every column is done; 3 when eta is not finite, rises above
  * its value at the first residual, or fails to fall below 0.9 of its
  * previous value at two residuals in a row (no contraction: Eq. (4) does not
  * hold for A~), or when max_outer phases end above tol.  X holds x0 on
@@ -647,10 +693,10 @@ int32_t oracle_cg_ir(int64_t n, int64_t m, const double *A, int64_t lda, int64_t
     double *R = (double *)malloc((size_t)n * (size_t)m * sizeof(double));
     double *P = (double *)malloc((size_t)n * sizeof(double));
     double *Z = (double *)malloc((size_t)n * sizeof(double));
+    double *X0 = (double *)malloc((size_t)n * sizeof(double));
     float *pf = (float *)malloc((size_t)n * sizeof(float));
-    double *eta = (double *)malloc((size_t)m * sizeof(double));
-    double *eta1 = (double *)malloc((size_t)m * sizeof(double));
-    double *prev = (double *)malloc((size_t)m * sizeof(double));
+    double *eta = (double *)malloc((size_t)m * 5 * sizeof(double));
+    double *eta1 = eta + m, *prev = eta + 2 * m, *zeta = eta + 3 * m, *zprev = eta + 4 * m;
     int *done = (int *)calloc((size_t)m, sizeof(int));
     int *stalls = (int *)calloc((size_t)m, sizeof(int));
     double an = oracle_norminf_sym(n, A, lda);
@@ -661,6 +707,8 @@ int32_t oracle_cg_ir(int64_t n, int64_t m, const double *A, int64_t lda, int64_t
     rep->info = 0;
     rep->iters_low = rep->iters_high = 0;
     rep->eta = NAN;
+    for (int64_t c = 0; c < m; ++c)
+        zeta[c] = 1.0; /* no phase before the first: x0 counts as a first solve */
     for (int outer = 0;; ++outer) {
         oracle_residual(n, m, A, lda, X, ldx, B, ldb, R, n);
         rep->iters_high++;
@@ -676,13 +724,19 @@ int32_t oracle_cg_ir(int64_t n, int64_t m, const double *A, int64_t lda, int64_t
                 if (!isfinite(e)) {
                     bad = 1;
                 } else if (e <= tol) {
-                    done[c] = 1;
-                } else if (outer == 0) {
-                    eta1[c] = e;
-                } else {
+                    /* the stopping rule of Algorithm 1 (see ir_loop), with the
+                     * correction = the change of x over the last inner phase */
+                    if (e == 0.0 || zeta[c] <= U64) {
+                        done[c] = 1;
+                    } else if (outer > 0) {
+                        double rho = zeta[c] / zprev[c];
+                        done[c] = (rho < 0.5) ? (rho / (1.0 - rho)) * prev[c] <= U64 : prev[c] <= ETA_FLOOR;
+                    }
+                } else if (outer > 0) {
                     stalls[c] = (e > 0.9 * prev[c]) ? stalls[c] + 1 : 0;
                     if (e > eta1[c] || stalls[c] >= 2) bad = 1;
                 }
+                if (outer == 0) eta1[c] = e;
                 prev[c] = e;
             }
             if (!done[c]) all_done = 0;
@@ -697,6 +751,7 @@ int32_t oracle_cg_ir(int64_t n, int64_t m, const double *A, int64_t lda, int64_t
         for (int64_t c = 0; c < m; ++c) {
             if (done[c]) continue;
             double *x = X + (size_t)c * ldx, *r = R + (size_t)c * n;
+            memcpy(X0, x, (size_t)n * sizeof(double));
             memcpy(P, r, (size_t)n * sizeof(double));
             double rho = dot64(n, r, r);
             double thr = inner_tol * inner_tol * rho;
@@ -713,10 +768,16 @@ int32_t oracle_cg_ir(int64_t n, int64_t m, const double *A, int64_t lda, int64_t
                 rho = rho1;
             }
             if (k > longest) longest = k;
+            /* the phase's correction, relative to the new iterate */
+            double dn = 0.0;
+            for (int64_t i = 0; i < n; ++i)
+                if (fabs(x[i] - X0[i]) > dn) dn = fabs(x[i] - X0[i]);
+            zprev[c] = zeta[c];
+            zeta[c] = (dn == 0.0) ? 0.0 : dn / vec_maxabs(n, x);
         }
         rep->iters_low += longest;
     }
-    free(At); free(R); free(P); free(Z); free(pf); free(eta); free(eta1); free(prev); free(done); free(stalls);
+    free(At); free(R); free(P); free(Z); free(X0); free(pf); free(eta); free(done); free(stalls);
     rep->status = status;
     return status;
 }

@@ -153,3 +153,36 @@ def test_outer_contraction_follows_the_spectral_radius(orc, n, d, k):
         assert rep.status == 0
     predicted = 1.0 + np.log(1e14) / np.log(1.0 / rho)
     assert 0.75 * predicted <= rep.iters_high <= 1.25 * predicted, (rep.iters_high, predicted)
+
+
+def test_converged_start_takes_one_confirming_phase(orc):
+    # x0 = the binary64 solution: its backward error is already at rounding
+    # level, but only a correction shows that x is accurate -- one inner
+    # phase from a rounding-level residual moves x by about u cond, and the
+    # stopping rule accepts after that residual
+    A = spdgen.covariance(300, 2)
+    rng = np.random.Generator(np.random.PCG64(5))
+    Xt = rng.standard_normal((1, 300))
+    B = spdgen.accurate_product(A, Xt)
+    X0, _ = orc.solve(A, B)
+    X, rep = orc.cg_ir(A, B, X0t=X0, half_band=-1)
+    assert rep.status == 0 and rep.iters_high == 2 and rep.iters_low >= 1
+    assert np.abs(X - Xt).max() / np.abs(Xt).max() <= 1e-13
+
+
+def test_cg_success_implies_forward_error_bar(orc):
+    # Algorithm 2 with a banded operator contracts by a fixed factor per
+    # outer step; eta <= tol alone stops it while x still carries about
+    # cond * tol of error.  With the stopping rule, success means the
+    # forward error meets 10 cond u against x_true
+    n, d, k = 600, 1, 16
+    A = spdgen.covariance(n, d)
+    lam = np.linalg.eigvalsh(A)
+    cond = lam[-1] / lam[0]
+    rng = np.random.Generator(np.random.PCG64(6))
+    Xt = rng.standard_normal((2, n))
+    B = spdgen.accurate_product(A, Xt)
+    X, rep = orc.cg_ir(A, B, half_band=k)
+    assert rep.status == 0
+    for c in range(2):
+        assert np.abs(X[c] - Xt[c]).max() / np.abs(Xt[c]).max() <= 10 * cond * U64

@@ -123,33 +123,59 @@ def _ir_factor_case(n=200, cond=1e2, seed=31):
     return A, Xt, B
 
 
-def test_ir_factor_exact_factor_one_step(orc):
-    # the binary64 factor itself: one solve already reaches the binary64 floor
+def test_ir_factor_exact_factor_one_correction(orc):
+    # the binary64 factor itself, handed in as a given factor: nothing says
+    # it is backward stable, so one correction confirms it -- a correction
+    # computed from a rounding-level residual, far below the first solve
     A, Xt, B = _ir_factor_case()
     L, info = orc.potrf(A)
     assert info == 0
     X, rep = orc.ir_factor(A, L, B, prec="fp64")
-    assert rep.status == 0 and (rep.iters_low, rep.iters_high) == (1, 1)
+    assert rep.status == 0 and (rep.iters_low, rep.iters_high) == (2, 2)
     assert rep.eta <= 2.0 ** -51
+    assert np.abs(X - Xt).max() / np.abs(Xt).max() <= 10 * 1e2 * U64
+
+
+def _scaled_factor_stop(c, alpha, an, nx, nb, tol=1e-14):
+    """The stopping rule applied to the closed-form sequences of the scaled
+    factor alpha L (c = 1 - 1/alpha^2): x_j = (1 - c^j) x, r_j = c^j b,
+    z_j = c^j x / alpha^2, so with max norms
+      eta_j  = |c|^j ||b|| / (||A|| ||x|| |1 - c^j| + ||b||),
+      zeta_0 = 1,  zeta_j = |c|^j / (alpha^2 |1 - c^(j+1)|)  (j >= 1).
+    Returns the number of residuals at the first k >= 1 where the rule
+    accepts x_{k+1}."""
+    def eta(j):
+        return abs(c) ** j * nb / (an * nx * abs(1.0 - c ** j) + nb)
+
+    def zeta(j):
+        return 1.0 if j == 0 else abs(c) ** j / (alpha ** 2 * abs(1.0 - c ** (j + 1)))
+
+    k = 1
+    while True:
+        if eta(k + 1) <= tol:
+            rho = zeta(k) / zeta(k - 1)
+            if zeta(k) <= U64:
+                return k + 1
+            if rho < 0.5 and rho / (1 - rho) * eta(k) <= U64:
+                return k + 1
+            if rho >= 0.5 and eta(k) <= 2.0 ** -51:
+                return k + 1
+        k += 1
 
 
 @pytest.mark.parametrize("alpha", [0.9, 1.1, 1.25])
 def test_ir_factor_scaled_factor_closed_form(orc, alpha):
-    # L~ = alpha L gives L~ L~^T = alpha^2 A, so with c = 1 - 1/alpha^2 the
-    # error after j solves is exactly -c^j x: x_j = (1 - c^j) x and the j-th
-    # residual is r_j = c^j b, so
-    #   eta_j = |c|^j ||b|| / (||A|| ||x|| |1 - c^j| + ||b||),
-    # and the loop stops at the first eta_j <= 2^-51 (Eq. (4):
-    # ||A^{-1} dA|| = |1 - alpha^2| < 1 here).
+    # L~ = alpha L gives L~ L~^T = alpha^2 A, so the error after j solves is
+    # exactly -c^j x with c = 1 - 1/alpha^2 (Eq. (4): ||A^{-1} dA|| =
+    # |1 - alpha^2| < 1 here), and both the backward errors and the
+    # corrections the stopping rule reads follow in closed form
     A, Xt, B = _ir_factor_case()
     L, _ = orc.potrf(A)
     X, rep = orc.ir_factor(A, alpha * L, B, prec="fp64", max_iter=200)
     c = 1.0 - 1.0 / alpha ** 2
     an = np.abs(A).sum(axis=1).max()
     nb, nx = np.abs(B).max(), np.abs(Xt).max()
-    j = 1
-    while abs(c) ** j * nb / (an * nx * abs(1.0 - c ** j) + nb) > 2.0 ** -51:
-        j += 1
+    j = _scaled_factor_stop(c, alpha, an, nx, nb)
     assert rep.status == 0
     assert abs(rep.iters_high - j) <= 1, (rep.iters_high, j)
     assert np.abs(X - Xt).max() / np.abs(Xt).max() <= 1e-13
@@ -199,3 +225,51 @@ def test_ir_factor_fp32_matches_own_factor_when_exact(orc):
     assert r1.status == r2.status == 0
     assert (r1.iters_low, r1.iters_high) == (r2.iters_low, r2.iters_high)
     assert np.array_equal(X1, X2)
+
+
+# --- the stopping rule: success means binary64 accuracy, not only eta <= tol ---
+
+@pytest.mark.parametrize("prec,cond,n", [("fp32", 1e4, 512), ("fp32", 1e6, 512), ("fp16", 1e2, 512),
+                                         ("fp16", 1e3, 512), ("fp16", 1e4, 512), ("bf16", 1e1, 512),
+                                         ("bf16", 1e1, 1024), ("bf16", 1e2, 512)])
+def test_success_implies_forward_error_bar(orc, prec, cond, n):
+    # slowly contracting refinements reach eta <= tol (even eta at the
+    # binary64 floor) while x still misses the forward-error bar
+    # 10 cond u; reported success must mean the bar is met, against both
+    # x_true and the binary64 solution.  (Stopping at the first eta <= 2^-51
+    # reported success 1.1-4x above the bar for binary16 at cond 1e4 and
+    # 1.02x for bfloat16 at cond 10, n = 1024, on these systems.)
+    s = spdgen.system(n, cond, 2, config=2, index=11)
+    X, rep = orc.ir(s.A, s.Bt, prec=prec, fallback=False)
+    if rep.status != 0:
+        assert rep.status == orc.STATUS_NO_CONVERGENCE
+        return
+    bar = 10 * cond * U64
+    Xd, _ = orc.solve(s.A, s.Bt)
+    for c in range(2):
+        scale = np.abs(s.Xt[c]).max()
+        assert np.abs(X[c] - s.Xt[c]).max() / scale <= bar, (c, rep)
+        assert np.abs(X[c] - Xd[c]).max() / scale <= bar, (c, rep)
+    assert np.all(orc.backward_error(s.A, X, s.Bt) <= 1e-14)
+
+
+def test_success_needs_a_contracting_correction(orc):
+    # a low-precision factor is never accepted on its first solve, even
+    # when that solve happens to be backward stable to 1e-14: without a
+    # correction there is no evidence of the error left (binary32 at cond 10,
+    # n = 8: eta after line 2 is about 1e-8 anyway; with tol = 1 the first
+    # eta passes the tolerance and one correction is still taken)
+    s = spdgen.system(8, 10.0, 1, config=2, index=12)
+    X, rep = orc.ir(s.A, s.Bt, prec="fp32", tol=1.0, fallback=False)
+    assert rep.status == 0 and rep.iters_high >= 2
+    X, rep = orc.ir(s.A, s.Bt, prec="fp64", tol=1.0, fallback=False)
+    assert rep.status == 0 and (rep.iters_low, rep.iters_high) == (1, 1)
+
+
+def test_max_iter_ends_without_success_inside_tol(orc):
+    # bfloat16 at cond 1e3 contracts slowly (cond * u_bf16 ~ 4, saved by the
+    # scaling): after 3 corrections eta may be small, but the rule has no
+    # evidence of binary64 accuracy yet -- no convergence, not success
+    s = spdgen.system(256, 1e3, 1, config=2, index=5)
+    X, rep = orc.ir(s.A, s.Bt, prec="bf16", max_iter=3, fallback=False)
+    assert rep.status == orc.STATUS_NO_CONVERGENCE and rep.iters_low == 4

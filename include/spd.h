@@ -60,8 +60,8 @@ typedef enum { SPD_BF16 = 0, SPD_FP16 = 1, SPD_FP32 = 2, SPD_FP64 = 3, SPD_AUTO 
 
 /* Options; passing NULL means the defaults shown. */
 typedef struct {
-    double tol;          /* accept when the backward error eta <= tol (1e-14) */
-    int32_t max_iter;    /* maximum number of corrections (10) */
+    double tol;          /* required backward error: eta <= tol (1e-14) */
+    int32_t max_iter;    /* maximum number of corrections (10); none left: no convergence */
     int32_t fallback;    /* on breakdown/divergence retry BF16/FP16 -> FP32 -> FP64 (1) */
     int32_t equilibrate; /* scale by D = diag(a_ii)^{-1/2} before rounding (1) */
     double theta;        /* FP16 headroom: mu = largest 2^k <= theta * 65504 (0.1) */
@@ -117,23 +117,47 @@ spd_status spd_factor_import(const double *L, int64_t n, int64_t ldl, spd_prec p
  * factor (binary32 substitution), including the equilibration scaling:
  * X = s mu D L^{-T} L^{-1} round32(D B / s), s a power of two per column.
  * B (n x nrhs, ldb >= n) is read; X (n x nrhs, ldx >= n) is written; X may
- * equal B.  Asynchronous on `hip_stream`. */
+ * equal B.  Asynchronous on `hip_stream`: a wait of the solve that gave up
+ * cannot be reported here; the next spd_refine on the handle reports it. */
 spd_status spd_solve(spd_factor_t F, const double *B, int64_t ldb, int64_t nrhs,
                      double *X, int64_t ldx, void *hip_stream);
 
-/* Algorithm 1, lines 3-7: starting from the iterate in X, repeat
+/* Algorithm 1, lines 3-7: starting from the iterate in X (counted as one
+ * low-precision solve), repeat
  * { R = B - A X (binary64); eta; Z = low-precision solve of R; X += Z }
- * until eta reaches the binary64 floor (2^-51), or eta <= o->tol and the
- * last step no longer halves it; divergence (eta not finite, above the first
- * eta, or stagnating while above tol) or max_iter corrections end it.  With
- * o->fallback set, breakdown or divergence re-factors A at the next
- * precision (BF16/FP16 -> FP32 -> FP64; F then holds that precision) and
- * restarts from X = solve(B).  A must be the matrix F was built from.
- * Synchronises `hip_stream` once per iteration (to read eta); *rep (host) is
- * filled and rep->status equals the returned status. */
+ * until every column is accurate to binary64 level (the while-test of line 4
+ * read so).  Per column, with zeta_k = ||z_k||_inf / ||x_{k+1}||_inf the size
+ * of correction k, rho_k = zeta_k / zeta_{k-1} its observed contraction and
+ * eta_k the backward error of the residual it was solved from, a column is
+ * done when eta <= o->tol and one of: eta = 0 or zeta_k <= 2^-53;
+ * rho_k < 1/2 and rho_k/(1 - rho_k) eta_k <= 2^-53 (the error left is below
+ * what binary64 residuals resolve); rho_k >= 1/2 and eta_k <= 2^-51 (no
+ * contraction left from a rounding-level residual).  A binary64 factor made
+ * by spd_factor is backward stable: its first solve is accepted at
+ * eta <= tol.  So SPD_OK means eta <= tol and x at the accuracy binary64
+ * residuals allow, not eta <= tol alone.  Divergence (eta not finite, above
+ * the first eta, or two steps in a row above 0.9 of the previous eta in every
+ * column, while above tol) or max_iter corrections without success end it
+ * with SPD_ERR_NO_CONVERGENCE.  With o->fallback set, breakdown or
+ * non-convergence re-factors A at the next precision (BF16/FP16 -> FP32 ->
+ * FP64; F then holds that precision) and restarts from X = solve(B).  A must
+ * be the matrix F was built from.  Synchronises `hip_stream` once per
+ * iteration (to read the norms); *rep (host) is filled and rep->status
+ * equals the returned status.  A triangular-solve wait of this handle that
+ * gave up (see spd_factor_set_wait_limit), here or in an earlier spd_solve,
+ * is reported as SPD_ERR_DEVICE; the flag is cleared by the next
+ * spd_factor / spd_factor_import on the handle. */
 spd_status spd_refine(spd_factor_t F, const double *A, int64_t lda, const double *B, int64_t ldb,
                       int64_t nrhs, double *X, int64_t ldx, const spd_opts *o,
                       spd_report *rep, void *hip_stream);
+
+/* The substitutions' work items wait for one another through counters in
+ * device memory, each wait bounded: a wait that is not satisfied within
+ * `seconds` (default 1) gives up, makes every other wait of the solve give
+ * up too, and marks the handle (spd_refine then returns SPD_ERR_DEVICE; the
+ * solution is not usable).  0 gives up at the first unsatisfied poll -- for
+ * tests of that error path.  seconds < 0 or F NULL: SPD_ERR_INVALID_ARG. */
+spd_status spd_factor_set_wait_limit(spd_factor_t F, double seconds);
 
 /* The whole of Algorithm 1 in one call: spd_factor + spd_solve + spd_refine,
  * with the fallback chain applied from the factorisation on.  *F as in
@@ -172,7 +196,13 @@ spd_status spd_residual(const double *A, int64_t n, int64_t lda, const double *X
  * allocate nothing and never synchronise the host, so they can be captured in
  * a graph; under capture without such a first call the status is
  * SPD_ERR_UNSUPPORTED.  Per-system outcomes are only in reps (the returned
- * status covers the arguments and the launch). */
+ * status covers the arguments and the launch).  Each system's refinement
+ * stops by the rule of spd_refine.  Every call on a device shares one
+ * workspace: a call on a stream other than the previous call's first makes
+ * its stream wait for that call's launch, so direct calls on different
+ * streams are ordered by the library.  Graph replays are not: a captured
+ * call must not run concurrently with any other batched call on the device
+ * (the caller orders them). */
 spd_status spd_solve_batched(int64_t batch, const int32_t *n, const int32_t *nrhs,
                              const int64_t *a_off, const double *A, const int64_t *b_off,
                              const double *B, double *X, spd_prec *prec, const spd_opts *o,
@@ -253,8 +283,10 @@ spd_status spd_factor_export(spd_factor_t F, double *Lout, int64_t ldl, double *
  * approximation of Section 4: entries with |i - j| > half_band dropped).
  *
  * One outer step forms r = b - A x and each column's backward error eta in
- * binary64 (as in Algorithm 1); a column with eta <= tol is finished.  The
- * others run CG on A~ from the current x: z = A~ p in binary32 (p rounded to
+ * binary64 (as in Algorithm 1); a column is finished by spd_refine's
+ * stopping rule, with the change of x over its last inner phase as the
+ * correction (the entry x_0 counts as a first solve, so even an accurate
+ * x_0 takes one confirming phase).  The others run CG on A~ from the current x: z = A~ p in binary32 (p rounded to
  * binary32, binary32 products and sums), and alpha = r^T r / p^T z,
  * x += alpha p, r -= alpha z, beta = r'^T r' / r^T r, p = r + beta p all in
  * binary64 (beta in the standard conjugate-direction form), until
@@ -268,7 +300,7 @@ spd_status spd_factor_export(spd_factor_t F, double *Lout, int64_t ldl, double *
  * iters_high the binary64 residuals, prec_used is SPD_FP32, eta the largest
  * final backward error. */
 typedef struct {
-    double tol;        /* outer acceptance: eta <= tol (1e-14) */
+    double tol;        /* required backward error: eta <= tol (1e-14) */
     double inner_tol;  /* inner stop: ||r||_2 <= inner_tol ||r_0||_2 (1e-6) */
     int32_t max_outer; /* inner phases at most (30) */
     int32_t max_inner; /* products per phase at most (2000) */

@@ -75,6 +75,7 @@ def lib():
         L.oracle_potrs.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64]
         L.oracle_residual.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, vp, i64]
         L.oracle_residual_rows.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, i64, vp, vp]
+        L.oracle_residual_given_rows.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, i64, vp, vp]
         L.oracle_norminf_sym.argtypes = [i64, vp, i64]
         L.oracle_norminf_sym.restype = f64
         L.oracle_backward_error.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64, vp]
@@ -181,6 +182,20 @@ def residual_rows(A, Xt, Bt, rows):
     R = np.empty((m, rows.size), dtype=np.float64)
     lib().oracle_residual_rows(n, m, _ptr(A), n, _ptr(X), n, _ptr(B), n, rows.size,
                                _ptr(rows), _ptr(R))
+    return R
+
+
+def residual_given_rows(Arows, Xt, Bt, rows):
+    """Residual entries b_i - sum_j a_ij x_j of the listed rows, from those
+    rows of the symmetric A only (Arows: len(rows) x n).  Returns (m, len(rows))."""
+    X, B = _rhs(Xt), _rhs(Bt)
+    m, n = X.shape
+    rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+    Ar = np.asfortranarray(np.asarray(Arows, dtype=np.float64))
+    assert Ar.shape == (rows.size, n)
+    R = np.empty((m, rows.size), dtype=np.float64)
+    lib().oracle_residual_given_rows(n, m, _ptr(Ar), rows.size, _ptr(X), n, _ptr(B), n, rows.size,
+                                     _ptr(rows), _ptr(R))
     return R
 
 

@@ -15,7 +15,8 @@
  *   oracle_potrf     Cholesky A = L L^T (Section 3.1: A = R^T R with R = L^T)
  *   oracle_fsub      forward substitution  L Y = B   (first half of Eq. (3))
  *   oracle_bsub      back substitution   L^T X = Y   (second half of Eq. (3))
- *   oracle_residual  R = B - A X in binary64 (Algorithm 1, residual step)
+ *   oracle_residual  R = B - A X in binary64 (Algorithm 1, residual step);
+ *                    _rows / _given_rows: of listed rows only
  *   oracle_norm1_sym / oracle_backward_error  norms and eta
  *   oracle_rne_f16 / oracle_rne_bf16  binary32 -> binary16 / bfloat16 rounding
  *                    to nearest even, from the formats' definitions
@@ -149,6 +150,25 @@ void oracle_residual_rows(int64_t n, int64_t m, const double *A, int64_t lda,
             double s = B[IDX(i, c, ldb)];
             for (int64_t j = 0; j < n; ++j)
                 s -= sym(A, lda, i, j) * x[j];
+            R[IDX(k, c, nrows)] = s;
+        }
+}
+
+/* The same residual of listed rows when only those rows of the symmetric A
+ * are at hand (systems too large to copy whole to the host): Arows is
+ * nrows x n, row k holding a_{rows[k], j} for j = 0..n-1, leading dimension
+ * ldr (column-major: element (k, j) at Arows[k + j*ldr]). */
+void oracle_residual_given_rows(int64_t n, int64_t m, const double *Arows, int64_t ldr,
+                                const double *X, int64_t ldx, const double *B, int64_t ldb,
+                                int64_t nrows, const int64_t *rows, double *R /* nrows x m */)
+{
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t c = 0; c < m; ++c)
+        for (int64_t k = 0; k < nrows; ++k) {
+            const double *x = X + (size_t)c * ldx;
+            double s = B[IDX(rows[k], c, ldb)];
+            for (int64_t j = 0; j < n; ++j)
+                s -= Arows[IDX(k, j, ldr)] * x[j];
             R[IDX(k, c, nrows)] = s;
         }
 }

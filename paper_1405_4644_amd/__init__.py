@@ -74,6 +74,7 @@ _SIGS = [
     ("spd_mlp_grad", C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     ("spd_mlp_adam", C.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
     ("spd_factor_import", C.c_int, [_vp, _i64, _i64, C.c_int, _vp, C.POINTER(_vp), C.POINTER(_i64)]),
+    ("spd_factor_set_wait_limit", C.c_int, [_vp, _f64]),
     ("spd_factor_destroy", None, [_vp]),
     ("spd_factor_query", C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32)]),
     ("spd_factor_export", C.c_int, [_vp, _vp, _i64, _vp, C.POINTER(_f64), _vp]),
@@ -176,6 +177,12 @@ class Factor:
             self.close()
         except Exception:
             pass
+
+    def set_wait_limit(self, seconds: float):
+        """spd_factor_set_wait_limit: bound of the substitutions' waits."""
+        st = load().spd_factor_set_wait_limit(self.h, float(seconds))
+        if st:
+            raise SPDError(st, "spd_factor_set_wait_limit")
 
     def query(self):
         n, p, nb = C.c_int64(), C.c_int32(), C.c_int32()

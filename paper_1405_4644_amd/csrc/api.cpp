@@ -41,6 +41,7 @@ struct spd_factor_s {
     int half = HALF_NONE;    // operand rounding of the trailing update (BF16 / FP16 factors)
     int group = 4;           // panels per trailing-update group (SPD_GROUP overrides)
     int upd_slots = 0;       // cap on the main-stream update's workgroups (SPD_UPD_SLOTS; 0: one per tile)
+    bool imported = false;   // the factor came from spd_factor_import (not line 1's own)
     void *Lh = nullptr;      // two panel copies in that precision (npad x NB halves each)
     size_t cap_Lh = 0;
     unsigned long long *info_dev = nullptr;
@@ -60,6 +61,7 @@ struct spd_factor_s {
     int *tctl = nullptr;         // work-queue head + per-row counters
     int cap_tctl = 0;
     int *terr = nullptr;         // sticky error flag (device)
+    unsigned long long wait_ticks = 100000000ULL;  // bounded waits of the solves: 1 s of the 100 MHz clock
     int *terr_host = nullptr;    // pinned mirror
     // refinement workspace
     double *R = nullptr;
@@ -344,6 +346,8 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
                      hipStream_t st, int64_t *info)
 {
     SPD_TRY(prepare_factor(F, n, prec, o.theta, st));
+    F->imported = false;
+    if (F->terr) HIP_TRY(hipMemsetAsync(F->terr, 0, sizeof(int), st));  // a new factor starts with no timeout
     const int64_t npad = F->npad;
     const int equil = (prec != SPD_FP64 && o.equilibrate) ? 1 : 0;
     *F->info_host = SPD_INFO_NONE_H;
@@ -382,6 +386,8 @@ spd_status do_import(spd_factor_t F, const double *L, int64_t n, int64_t ldl, in
                      int64_t *info)
 {
     SPD_TRY(prepare_factor(F, n, prec, 0.1, st));
+    F->imported = true;
+    if (F->terr) HIP_TRY(hipMemsetAsync(F->terr, 0, sizeof(int), st));
     *F->info_host = SPD_INFO_NONE_H;
     HIP_TRY(hipMemcpyAsync(F->info_dev, F->info_host, sizeof(unsigned long long), hipMemcpyHostToDevice, st));
     if (n > 0) {
@@ -440,15 +446,15 @@ spd_status ensure_solve_ws(spd_factor_t F, int64_t m, hipStream_t st)
 // Low-precision solve of (D R / s) and X (+)= s mu D Y  (Algorithm 1, lines 2, 5, 6)
 template <typename T>
 void solve_apply(spd_factor_t F, const double *R, int64_t ldr, int64_t m, const double *smax, double *X, int64_t ldx,
-                 int accumulate, hipStream_t st)
+                 int accumulate, double *zmax, hipStream_t st)
 {
     const int64_t npad = F->npad;
     T *Y = (T *)F->Y;
     T *Z = (T *)((char *)F->Y + npad * m * sizeof(T));
     spd::launch_rhs_scale<T>(R, ldr, F->n, npad, (int)m, F->d, smax, Y, npad, st);
     spd::launch_trsv<T>((const T *)F->L, npad, (const T *)F->WB, npad, (int)m, Y, Z, npad, (T *)F->tP, F->tctl,
-                        F->terr, st);
-    spd::launch_update_x<T>(X, ldx, F->n, (int)m, Y, npad, F->d, F->mu, smax, accumulate, st);
+                        F->terr, F->wait_ticks, st);
+    spd::launch_update_x<T>(X, ldx, F->n, (int)m, Y, npad, F->d, F->mu, smax, accumulate, zmax, st);
 }
 
 spd_status do_solve(spd_factor_t F, const double *B, int64_t ldb, int64_t m, double *X, int64_t ldx,
@@ -459,9 +465,9 @@ spd_status do_solve(spd_factor_t F, const double *B, int64_t ldb, int64_t m, dou
     spd::launch_zero(F->smax, m, st);
     spd::launch_rhs_max(B, ldb, F->n, (int)m, F->d, F->smax, st);
     if (F->elem == 8)
-        solve_apply<double>(F, B, ldb, m, F->smax, X, ldx, 0, st);
+        solve_apply<double>(F, B, ldb, m, F->smax, X, ldx, 0, nullptr, st);
     else
-        solve_apply<float>(F, B, ldb, m, F->smax, X, ldx, 0, st);
+        solve_apply<float>(F, B, ldb, m, F->smax, X, ldx, 0, nullptr, st);
     HIP_TRY(hipGetLastError());
     return SPD_OK;
 }
@@ -474,7 +480,7 @@ spd_status ensure_refine_ws(spd_factor_t F, int64_t m, hipStream_t st)
     cap = F->cap_P;
     SPD_TRY(grow((void **)&F->P, &cap, (size_t)spd::resid_scratch(F->n, (int)m) * sizeof(double), false, st));
     F->cap_P = cap;
-    const int64_t nn = 1 + 4 * m;
+    const int64_t nn = 1 + 5 * m;
     if (F->cap_norms < nn) {
         if (F->norms) {
             HIP_TRY(hipStreamSynchronize(st));
@@ -491,29 +497,58 @@ spd_status ensure_refine_ws(spd_factor_t F, int64_t m, hipStream_t st)
 
 int next_prec(int p) { return (p == SPD_BF16 || p == SPD_FP16) ? SPD_FP32 : SPD_FP64; }
 
-constexpr double ETA_FLOOR = 0x1p-51;  // 4u: relative forward error <= ~2 cond eta stays under 10 cond u
+// The stopping rule (Algorithm 1's while-test read as "until x is accurate to
+// binary64 level"; the divergence test guards Eq. (4)).  Per column, after
+// correction k (z_k solved from the residual of x_k, backward error eta_k,
+// x_{k+1} = x_k + z_k): zeta_k = ||z_k|| / ||x_{k+1}|| and the observed
+// contraction rho_k = zeta_k / zeta_{k-1}.  z_k tracks the error of x_k; with
+// geometric contraction x_{k+1} keeps about rho_k/(1-rho_k) zeta_k of it,
+// while residuals rounded at binary64 level resolve x only to about
+// (zeta_k/eta_k) u.  A column is done once eta_{k+1} <= tol and
+//   eta_{k+1} = 0 or zeta_k <= u; or rho_k < 1/2 and rho_k/(1-rho_k) eta_k <= u;
+//   or rho_k >= 1/2 and eta_k <= 4u (no contraction left from a rounding-level
+//   residual).
+// The backward error alone does not decide: it reaches 1e-14, even 4u, while x
+// still misses 10 cond u along the eigenvectors of the smallest eigenvalues.
+// Line 1's own binary64 factor is backward stable: its first solve is
+// accepted at eta <= tol.  The iterate handed to the loop counts as a first
+// solve (zeta_0 = 1).
+constexpr double U64 = 0x1p-53;
+constexpr double ETA_FLOOR = 0x1p-51;
 
-// One refinement run at the handle's current precision, from the iterate in X.
-// Returns SPD_OK (converged) or SPD_ERR_NO_CONVERGENCE (diverged / out of
-// iterations); device errors propagate.
+bool column_done(double eta_new, double zeta, double zeta_prev, double eta_in, int k, bool stable, double tol)
+{
+    if (!(eta_new <= tol)) return false;
+    if (eta_new == 0.0 || zeta <= U64) return true;
+    if (k == 0) return stable;
+    const double rho = zeta / zeta_prev;
+    return (rho < 0.5) ? (rho / (1.0 - rho)) * eta_in <= U64 : eta_in <= ETA_FLOOR;
+}
+
+// One refinement run at the handle's current precision, from the iterate in
+// X (taken as the result of one low-precision solve).  Returns SPD_OK (every
+// column done), SPD_ERR_NO_CONVERGENCE (diverged, or max_iter corrections
+// without success); device errors propagate.
 spd_status refine_once(spd_factor_t F, const double *A, int64_t lda, const double *B, int64_t ldb, int64_t m,
                        double *X, int64_t ldx, const spd_opts &o, spd_report *rep, hipStream_t st)
 {
     const int64_t n = F->n;
     SPD_TRY(ensure_solve_ws(F, m, st));
     SPD_TRY(ensure_refine_ws(F, m, st));
-    const int64_t nn = 1 + 4 * m;
-    double *eta = new (std::nothrow) double[2 * m];
-    if (!eta) return SPD_ERR_OUT_OF_MEMORY;
-    double *prev = eta + m;
+    const int64_t nn = 1 + 5 * m;  // ||A||, then per column max|r|, max|x|, max|b|, max|D r|, max|z|
+    std::vector<double> eta(m), eprev(m), zeta(m, 1.0), zprev(m, 1.0);
+    std::vector<char> done(m, 0);
+    const bool stable = (F->prec == SPD_FP64 && !F->imported);
     rep->iters_low = 1;  // the iterate came from one low-precision solve
     rep->iters_high = 0;
-    double eta0 = 0.0, prev_worst = 0.0, anorm = 0.0;
+    double eta0 = 0.0, anorm = 0.0;
     int stalls = 0;
     spd_status result = SPD_ERR_NO_CONVERGENCE;
     for (;;) {
         const int first = (rep->iters_high == 0);
-        spd::launch_zero(first ? F->norms : F->norms + 1, first ? nn : nn - 1, st);
+        // the residual's norms; the correction norms (last m) were written
+        // by the correction before this residual
+        spd::launch_zero(first ? F->norms : F->norms + 1, first ? nn - m : nn - m - 1, st);
         hipEvent_t pr = prof_begin(st);
         spd::launch_residual(A, lda, n, X, ldx, B, ldb, (int)m, F->R, n, F->d, F->norms, first, F->P, st);
         if (pr)
@@ -523,17 +558,12 @@ spd_status refine_once(spd_factor_t F, const double *A, int64_t lda, const doubl
         if (e == hipSuccess)
             e = hipMemcpyAsync(F->terr_host, F->terr, sizeof(int), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) {
-            delete[] eta;
-            return map_err(e);
-        }
-        if (*F->terr_host) {  // a triangular-solve wait timed out
-            delete[] eta;
-            return SPD_ERR_DEVICE;
-        }
+        if (e != hipSuccess) return map_err(e);
+        if (*F->terr_host) return SPD_ERR_DEVICE;  // a triangular-solve wait timed out
+        const int k = rep->iters_high;  // corrections applied so far
         rep->iters_high++;
         if (first) anorm = F->norms_host[0];
-        bool finite = std::isfinite(anorm);
+        bool finite = std::isfinite(anorm), all = true;
         double worst = 0.0;
         for (int64_t c = 0; c < m; ++c) {
             const double rn = F->norms_host[1 + c], xn = F->norms_host[1 + m + c], bn = F->norms_host[1 + 2 * m + c];
@@ -543,40 +573,40 @@ spd_status refine_once(spd_factor_t F, const double *A, int64_t lda, const doubl
             eta[c] = v;
             if (!std::isfinite(v)) finite = false;
             if (v > worst) worst = v;
+            if (k > 0) {
+                const double zn = F->norms_host[1 + 4 * m + c];
+                zeta[c] = (zn == 0.0) ? 0.0 : zn / xn;
+            }
+            if (!done[c]) done[c] = column_done(v, zeta[c], zprev[c], eprev[c], k, stable, o.tol);
+            all = all && done[c];
         }
         rep->eta = finite ? worst : NAN;
-        if (!finite) break;                                   // diverged
-        if (worst <= ETA_FLOOR) { result = SPD_OK; break; }  // binary64 floor
-        if (rep->iters_high == 1) {
+        if (!finite) break;                                  // diverged
+        if (all && worst <= o.tol) { result = SPD_OK; break; }
+        if (k == 0) {
             eta0 = worst;
         } else {
-            if (worst <= o.tol && worst > 0.5 * prev_worst) { result = SPD_OK; break; }  // stalled inside tol
             bool all_slow = true;
             for (int64_t c = 0; c < m; ++c)
-                if (!(eta[c] > 0.9 * prev[c])) all_slow = false;
+                if (!(eta[c] > 0.9 * eprev[c])) all_slow = false;
             stalls = all_slow ? stalls + 1 : 0;
             if (worst > o.tol && (worst > eta0 || stalls >= 2)) break;  // diverged / stagnated
         }
-        if (rep->iters_low > o.max_iter) {
-            if (worst <= o.tol) result = SPD_OK;
-            break;
-        }
-        prev_worst = worst;
-        std::memcpy(prev, eta, m * sizeof(double));
+        if (rep->iters_low > o.max_iter) break;  // out of corrections: no convergence
+        eprev = eta;
+        zprev = zeta;
         // correction: Z = low-precision solve of D R / s, X += s mu D Z
         const double *dmax = F->norms + 1 + 3 * m;
+        double *zmax = F->norms + 1 + 4 * m;
+        spd::launch_zero(zmax, m, st);
         if (F->elem == 8)
-            solve_apply<double>(F, F->R, n, m, dmax, X, ldx, 1, st);
+            solve_apply<double>(F, F->R, n, m, dmax, X, ldx, 1, zmax, st);
         else
-            solve_apply<float>(F, F->R, n, m, dmax, X, ldx, 1, st);
+            solve_apply<float>(F, F->R, n, m, dmax, X, ldx, 1, zmax, st);
         e = hipGetLastError();
-        if (e != hipSuccess) {
-            delete[] eta;
-            return map_err(e);
-        }
+        if (e != hipSuccess) return map_err(e);
         rep->iters_low++;
     }
-    delete[] eta;
     return result;
 }
 
@@ -594,6 +624,10 @@ struct BatchEntry {
 };
 struct BatchCtx {
     void *ws = nullptr;
+    // the workspace is shared by every call on the device: a call on another
+    // stream first waits for the previous call's launch (not under capture)
+    hipEvent_t last = nullptr;
+    hipStream_t last_stream = nullptr;
     std::map<int64_t, BatchEntry> per_batch;
     float *picker = nullptr;  // perceptron parameters (device), kept until the process ends
     bool picker_on = false;
@@ -615,6 +649,7 @@ struct spd_cg_s {
     int m = 0;                       // right-hand sides the workspace is sized for
     double *R = nullptr, *P = nullptr, *Z = nullptr, *part = nullptr, *vpart = nullptr, *sc = nullptr;
     double *norms = nullptr, *rscr = nullptr;
+    double *Xs = nullptr;            // x at the start of the inner phase (its change is the correction)
     float *Pf = nullptr;
     float *Zp = nullptr;             // k-slice partials of the dense multi-column product
     int *flags = nullptr;            // act[2][m] (parity slots), go[m], cnt[m]
@@ -627,11 +662,11 @@ namespace {
 
 void cg_free_ws(spd_cg_t H)
 {
-    hipFree(H->R); hipFree(H->P); hipFree(H->Z); hipFree(H->part); hipFree(H->vpart); hipFree(H->sc);
+    hipFree(H->R); hipFree(H->P); hipFree(H->Z); hipFree(H->part); hipFree(H->vpart); hipFree(H->sc); hipFree(H->Xs);
     hipFree(H->norms); hipFree(H->rscr); hipFree(H->Pf); hipFree(H->Zp); hipFree(H->flags);
     if (H->norms_host) hipHostFree(H->norms_host);
     if (H->flags_host) hipHostFree(H->flags_host);
-    H->R = H->P = H->Z = H->part = H->vpart = H->sc = H->norms = H->rscr = nullptr;
+    H->R = H->P = H->Z = H->part = H->vpart = H->sc = H->norms = H->rscr = H->Xs = nullptr;
     H->Pf = nullptr;
     H->Zp = nullptr;
     H->flags = nullptr;
@@ -650,19 +685,20 @@ spd_status cg_ensure_ws(spd_cg_t H, int m, hipStream_t st)
     HIP_TRY(hipMalloc(&H->R, nm));
     HIP_TRY(hipMalloc(&H->P, nm));
     HIP_TRY(hipMalloc(&H->Z, nm));
+    HIP_TRY(hipMalloc(&H->Xs, nm));
     // product partials: sized for the most per column any m' <= m uses (the
     // workspace is reused for fewer right-hand sides)
     const int64_t mvp = std::max(spd::cg_mv_parts(n, ldt, H->k, m), spd::cg_mv_parts(n, ldt, H->k, 1));
     HIP_TRY(hipMalloc(&H->part, (size_t)mvp * m * sizeof(double)));
     HIP_TRY(hipMalloc(&H->vpart, (size_t)spd::cg_vec_parts(n) * m * sizeof(double)));
     HIP_TRY(hipMalloc(&H->sc, (size_t)4 * m * sizeof(double)));
-    HIP_TRY(hipMalloc(&H->norms, (size_t)(1 + 4 * m) * sizeof(double)));
+    HIP_TRY(hipMalloc(&H->norms, (size_t)(1 + 5 * m) * sizeof(double)));
     HIP_TRY(hipMalloc(&H->rscr, (size_t)spd::resid_scratch(n, m) * sizeof(double)));
     HIP_TRY(hipMalloc(&H->Pf, (size_t)spd::cg_pf_elems(ldt, m) * sizeof(float)));
     if (H->k < 0 && spd::cg_zp_elems(n, m) > 0)
         HIP_TRY(hipMalloc(&H->Zp, (size_t)spd::cg_zp_elems(n, m) * sizeof(float)));
     HIP_TRY(hipMalloc(&H->flags, (size_t)4 * m * sizeof(int)));
-    HIP_TRY(hipHostMalloc(&H->norms_host, (size_t)(1 + 4 * m) * sizeof(double), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&H->norms_host, (size_t)(1 + 5 * m) * sizeof(double), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(&H->flags_host, (size_t)4 * m * sizeof(int), hipHostMallocDefault));
     H->m = m;
     return SPD_OK;
@@ -679,7 +715,7 @@ spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, 
     int *act = H->flags, *go = H->flags + 2 * m, *cnt = H->flags + 3 * m;  // act: two parity slots
     int *go_h = H->flags_host + 2 * m;
     const double it2 = o.inner_tol * o.inner_tol;
-    const int nn = 1 + 4 * m;
+    const int nn = 1 + 5 * m;  // as refine_once: the last m hold each column's change over its phase
     // iterations launched between host checks: a dense product is long
     // enough that one check per iteration costs nothing
     const int S = (k < 0) ? 2 : 16;
@@ -717,14 +753,14 @@ spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, 
         hipGraphExec_t &e;
         ~GraphGuard() { if (e) hipGraphExecDestroy(e); }
     } gguard{gexec};
-    std::vector<double> eta1(m, 0.0), prev(m, 0.0);
+    std::vector<double> eta1(m, 0.0), prev(m, 0.0), zeta(m, 1.0), zprev(m, 1.0);
     std::vector<int> done(m, 0), stalls(m, 0);
     std::vector<double> eta(m, 0.0);
     double anorm = 0.0;
     spd_status result = SPD_ERR_NO_CONVERGENCE;
     rep->iters_low = rep->iters_high = 0;
     for (int outer = 0;; ++outer) {
-        spd::launch_zero(outer == 0 ? H->norms : H->norms + 1, outer == 0 ? nn : nn - 1, st);
+        spd::launch_zero(outer == 0 ? H->norms : H->norms + 1, outer == 0 ? nn - m : nn - m - 1, st);
         spd::launch_residual(A, lda, n, X, ldx, B, ldb, m, H->R, n, nullptr, H->norms, outer == 0, H->rscr, st);
         HIP_TRY(hipMemcpyAsync(H->norms_host, H->norms, nn * sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -739,16 +775,20 @@ spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, 
             if (!(rn == rn) || !(xn == xn)) e = NAN;
             if (!done[c]) {
                 eta[c] = e;
+                if (outer > 0) {  // the column ran the last inner phase
+                    const double dn = H->norms_host[1 + 4 * m + c];
+                    zprev[c] = zeta[c];
+                    zeta[c] = (dn == 0.0) ? 0.0 : dn / xn;
+                }
                 if (!std::isfinite(e)) {
                     bad = true;
                 } else if (e <= o.tol) {
-                    done[c] = 1;
-                } else if (outer == 0) {
-                    eta1[c] = e;
-                } else {
+                    done[c] = column_done(e, zeta[c], zprev[c], prev[c], outer, false, o.tol);
+                } else if (outer > 0) {
                     stalls[c] = (e > 0.9 * prev[c]) ? stalls[c] + 1 : 0;
                     if (e > eta1[c] || stalls[c] >= 2) bad = true;
                 }
+                if (outer == 0) eta1[c] = e;
                 prev[c] = e;
             }
             if (!done[c]) all_done = false;
@@ -758,9 +798,11 @@ spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, 
         if (bad) break;
         if (all_done) { result = SPD_OK; break; }
         if (outer >= o.max_outer) break;
-        // inner phase for the columns not done
+        // inner phase for the columns not done, from x saved in Xs
         for (int c = 0; c < m; ++c) go_h[c] = !done[c];
         HIP_TRY(hipMemcpyAsync(go, go_h, m * sizeof(int), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpy2DAsync(H->Xs, n * sizeof(double), X, ldx * sizeof(double), n * sizeof(double), m,
+                                 hipMemcpyDeviceToDevice, st));
         spd::launch_cg_start(n, m, H->R, H->P, H->Pf, ldt, H->vpart, nv, go, st);
         spd::launch_cg_begin(H->vpart, nv, H->sc, act, go, cnt, it2, o.max_inner, m, st);
         int launched = 0;
@@ -786,6 +828,9 @@ spd_status cg_refine(spd_cg_t H, const double *A, int64_t lda, const double *B, 
         for (int c = 0; c < m; ++c)
             if (go_h[c]) longest = std::max(longest, H->flags_host[3 * m + c]);
         rep->iters_low += longest;
+        // each column's change of x over the phase (columns that sat out: 0)
+        spd::launch_zero(H->norms + 1 + 4 * m, m, st);
+        spd::launch_col_maxdiff(X, ldx, H->Xs, n, n, m, H->norms + 1 + 4 * m, st);
     }
     return result;
 }
@@ -978,6 +1023,13 @@ spd_status spd_refine(spd_factor_t F, const double *A, int64_t lda, const double
     }
 }
 
+spd_status spd_factor_set_wait_limit(spd_factor_t F, double seconds)
+{
+    if (!F || !(seconds >= 0.0) || seconds > 1e6) return SPD_ERR_INVALID_ARG;
+    F->wait_ticks = (unsigned long long)(seconds * 1e8);  // wall_clock64: 100 MHz
+    return SPD_OK;
+}
+
 spd_status spd_posv(const double *A, int64_t n, int64_t lda, const double *B, int64_t ldb, int64_t nrhs, double *X,
                     int64_t ldx, spd_prec prec, const spd_opts *o, spd_report *rep, void *hip_stream,
                     spd_factor_t *F)
@@ -1092,6 +1144,10 @@ static spd_status solve_batched_impl(int64_t batch, const int32_t *n, const int3
         const size_t bytes = (size_t)kBatchMaxGrid * spd::batch_ws_stride();
         HIP_TRY(hipMalloc(&c.ws, bytes));
     }
+    if (!capturing) {
+        if (!c.last) HIP_TRY(hipEventCreateWithFlags(&c.last, hipEventDisableTiming));
+        else if (c.last_stream != st) HIP_TRY(hipStreamWaitEvent(st, c.last, 0));
+    }
     spd::BatchLaunch l;
     l.batch = batch;
     l.n = n;
@@ -1161,6 +1217,10 @@ static spd_status solve_batched_impl(int64_t batch, const int32_t *n, const int3
     l.order = it->second.order;
     l.queue = it->second.queue;
     HIP_TRY(spd::launch_batch(l, st));
+    if (!capturing) {
+        HIP_TRY(hipEventRecord(c.last, st));
+        c.last_stream = st;
+    }
     return SPD_OK;
 }
 

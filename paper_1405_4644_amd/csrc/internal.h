@@ -78,11 +78,15 @@ int64_t trsv_scratch_elems(int64_t npad);
 int trsv_ctl_ints(int64_t npad);
 template <typename T>
 void launch_trsv(const T *L, int64_t ld, const T *WB, int64_t npad, int m, T *Y, T *Z, int64_t ldy, T *P, int *ctl,
-                 int *err, hipStream_t st);
-// X[i][c] (+)= s_c mu d_i Y[i][c]
+                 int *err, unsigned long long wait_ticks, hipStream_t st);
+// X[i][c] (+)= s_c mu d_i Y[i][c]; zmax (optional, m entries, non-negative on
+// entry): raised to max_i |s_c mu d_i Y[i][c]| per column
 template <typename T>
 void launch_update_x(double *X, int64_t ldx, int64_t n, int m, const T *Y, int64_t ldy, const double *d,
-                     double mu, const double *smax, int accumulate, hipStream_t st);
+                     double mu, const double *smax, int accumulate, double *zmax, hipStream_t st);
+// out[c] = max(out[c], max_i |X[i][c] - S[i][c]|), then S = X (n x m)
+void launch_col_maxdiff(const double *X, int64_t ldx, double *S, int64_t lds, int64_t n, int m, double *out,
+                        hipStream_t st);
 // fill a double array with zeros (a kernel, not a memset node)
 void launch_zero(double *p, int64_t count, hipStream_t st);
 // Lout (binary64, n x n, column-major) <- lower triangle of the factor, zeros above

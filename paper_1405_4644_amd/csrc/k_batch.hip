@@ -74,6 +74,7 @@ struct BatchSmem {
     double red[16][4 * SPD_BATCH_MAXRHS + 1];
     double norms[1 + 4 * SPD_BATCH_MAXRHS];
     double smax[SPD_BATCH_MAXRHS];
+    unsigned long long zmax[SPD_BATCH_MAXRHS];  // max |z| per column of the last solve (binary64 bits)
     double arow[SPD_BATCH_NMAX];  // row sums of |A|
     double csum[SPD_BATCH_MAXRHS * SPD_BATCH_NMAX];  // residual: column-pass sums
     double cabs[SPD_BATCH_NMAX];
@@ -366,12 +367,16 @@ SPD_DEV void b_solve(const T *L, const T *Winv, int n, int np, int m, const doub
             ys[(tid / BNB) * NM + k0 + tid % BNB] = x;
         __syncthreads();
     }
+    if (tid < m)
+        sm.zmax[tid] = 0ull;
+    __syncthreads();
     for (int idx = tid; idx < m * n; idx += NT) {
         const int c = idx / n, i = idx % n;
         const double s = pow2_ceil(sm.smax[c]);
         const double z = ((s * mu) * d[i]) * (double)ys[c * NM + i];
         double *px = X + i + (int64_t)c * n;
         *px = accumulate ? *px + z : z;
+        atomicMax(&sm.zmax[c], (unsigned long long)__double_as_longlong(fabs(z)));
     }
     __syncthreads();
 }
@@ -838,26 +843,43 @@ SPD_DEV int b_pick(const float *P, BatchSmem &sm)
 SPD_DEV int b_next_prec(int p) { return (p == SPD_BF16 || p == SPD_FP16) ? SPD_FP32 : SPD_FP64; }
 
 // Refinement at the precision of the current factor (T), from the iterate in
-// X; same rules as the single-system path.  Returns SPD_OK or
-// SPD_ERR_NO_CONVERGENCE and fills the iteration counts and eta.
+// X (the first solve); the single-system path's stopping rule: a column is
+// done once eta <= tol and its last correction z_k (zeta_k = ||z_k|| /
+// ||x_{k+1}||, rho_k = zeta_k / zeta_{k-1}, eta_k the backward error it was
+// solved from) shows x accurate to binary64 level -- eta = 0 or
+// zeta_k <= 2^-53; rho_k < 1/2 and rho_k/(1-rho_k) eta_k <= 2^-53; or
+// rho_k >= 1/2 and eta_k <= 2^-51.  A binary64 factor's first solve is
+// accepted at eta <= tol.  Divergence as before; max_iter corrections
+// without success: no convergence.  Returns SPD_OK or SPD_ERR_NO_CONVERGENCE
+// and fills the iteration counts and eta.
 template <typename T, int WAVES>
 SPD_DEV int b_refine(const BatchArgs &a, const double *A, const double *B, double *X, int n, int np, int m,
                      const BatchWs &w, double mu, spd_report &rep, BatchSmem &sm)
 {
-    constexpr double FLOOR = 0x1p-51;
+    constexpr double U = 0x1p-53, FLOOR = 0x1p-51;
+    constexpr bool STABLE = sizeof(T) == 8;
     rep.iters_low = 1;
     rep.iters_high = 0;
     constexpr int MR = SPD_BATCH_MAXRHS;
-    double eta0 = 0.0, prev_worst = 0.0, anorm = 0.0;
-    double eta[MR], prev[MR];  // identical in every thread
+    double eta0 = 0.0, anorm = 0.0;
+    // identical in every thread
+    double eta[MR], eprev[MR], zeta[MR], zprev[MR];
+    bool done[MR];
+#pragma unroll
+    for (int c = 0; c < MR; ++c) {
+        zeta[c] = zprev[c] = 1.0;
+        eprev[c] = 0.0;
+        done[c] = false;
+    }
     int stalls = 0;
     for (;;) {
         const int first = (rep.iters_high == 0);
+        const int k = rep.iters_high;  // corrections applied so far
         b_residual<WAVES>(A, n, m, X, B, w.d, w.R, first, sm);
         rep.iters_high++;
         if (first)
             anorm = sm.norms[0];
-        bool finite = isfinite(anorm);
+        bool finite = isfinite(anorm), all = true;
         double worst = 0.0;
 #pragma unroll
         for (int c = 0; c < MR; ++c) {
@@ -873,31 +895,46 @@ SPD_DEV int b_refine(const BatchArgs &a, const double *A, const double *B, doubl
                 finite = false;
             if (v > worst)
                 worst = v;
+            if (k > 0) {
+                const double zn = __longlong_as_double((long long)sm.zmax[c]);
+                zeta[c] = (zn == 0.0) ? 0.0 : zn / xn;
+            }
+            if (!done[c] && v <= a.tol) {
+                if (v == 0.0 || zeta[c] <= U) {
+                    done[c] = true;
+                } else if (k == 0) {
+                    done[c] = STABLE;
+                } else {
+                    const double rho = zeta[c] / zprev[c];
+                    done[c] = (rho < 0.5) ? (rho / (1.0 - rho)) * eprev[c] <= U : eprev[c] <= FLOOR;
+                }
+            }
+            all = all && done[c];
         }
         rep.eta = finite ? worst : __builtin_nan("");
         if (!finite)
             return SPD_ERR_NO_CONVERGENCE;
-        if (worst <= FLOOR)
+        if (all && worst <= a.tol)
             return SPD_OK;
-        if (rep.iters_high == 1) {
+        if (k == 0) {
             eta0 = worst;
         } else {
-            if (worst <= a.tol && worst > 0.5 * prev_worst)
-                return SPD_OK;
             bool all_slow = true;
 #pragma unroll
             for (int c = 0; c < MR; ++c)
-                if (c < m && !(eta[c] > 0.9 * prev[c]))
+                if (c < m && !(eta[c] > 0.9 * eprev[c]))
                     all_slow = false;
             stalls = all_slow ? stalls + 1 : 0;
             if (worst > a.tol && (worst > eta0 || stalls >= 2))
                 return SPD_ERR_NO_CONVERGENCE;
         }
         if (rep.iters_low > a.max_iter)
-            return worst <= a.tol ? SPD_OK : SPD_ERR_NO_CONVERGENCE;
-        prev_worst = worst;
+            return SPD_ERR_NO_CONVERGENCE;
 #pragma unroll
-        for (int c = 0; c < MR; ++c) prev[c] = eta[c];
+        for (int c = 0; c < MR; ++c) {
+            eprev[c] = eta[c];
+            zprev[c] = zeta[c];
+        }
         __syncthreads();
         if (threadIdx.x < m)
             sm.smax[threadIdx.x] = sm.norms[1 + 3 * m + threadIdx.x];

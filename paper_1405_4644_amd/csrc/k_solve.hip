@@ -43,19 +43,46 @@ __global__ __launch_bounds__(256) void k_rhs_scale(const double *__restrict__ R,
     Y[i + c * ldy] = (i < n) ? (T)(d[i] * R[i + c * ldr] / s) : (T)0;
 }
 
+// x += z (or x = z) with z = s mu d_i Y_i; with zmax, also max_i |z_i| per
+// column (the correction's size, read by the stopping rule)
 template <typename T>
 __global__ __launch_bounds__(256) void k_update_x(double *__restrict__ X, int64_t ldx, int64_t n,
                                                   const T *__restrict__ Y, int64_t ldy, const double *__restrict__ d,
-                                                  double mu, const double *__restrict__ smax, int accumulate)
+                                                  double mu, const double *__restrict__ smax, int accumulate,
+                                                  double *zmax)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int c = blockIdx.y;
-    if (i >= n)
-        return;
-    const double s = pow2_ceil(smax[c]);
-    const double z = ((s * mu) * d[i]) * (double)Y[i + c * ldy];
-    double *px = X + i + c * ldx;
-    *px = accumulate ? *px + z : z;
+    double z = 0.0;
+    if (i < n) {
+        const double s = pow2_ceil(smax[c]);
+        z = ((s * mu) * d[i]) * (double)Y[i + c * ldy];
+        double *px = X + i + c * ldx;
+        *px = accumulate ? *px + z : z;
+    }
+    if (zmax) {
+        const double v = wave_max(fabs(z));
+        if ((threadIdx.x & 63) == 0)
+            atomic_max_nonneg(zmax + c, v);
+    }
+}
+
+// out[c] raised to max_i |X[i][c] - S[i][c]| (a correction taken as the
+// change of x); then S = X
+__global__ __launch_bounds__(256) void k_col_maxdiff(const double *__restrict__ X, int64_t ldx, double *__restrict__ S,
+                                                     int64_t lds, int64_t n, double *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    double v = 0.0;
+    if (i < n) {
+        const double x = X[i + c * ldx];
+        v = fabs(x - S[i + c * lds]);
+        S[i + c * lds] = x;
+    }
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0)
+        atomic_max_nonneg(out + c, v);
 }
 
 __global__ void k_zero(double *p, int64_t count)
@@ -89,16 +116,24 @@ template void launch_rhs_scale<double>(const double *, int64_t, int64_t, int64_t
 
 template <typename T>
 void launch_update_x(double *X, int64_t ldx, int64_t n, int m, const T *Y, int64_t ldy, const double *d, double mu,
-                     const double *smax, int accumulate, hipStream_t st)
+                     const double *smax, int accumulate, double *zmax, hipStream_t st)
 {
     if (n <= 0 || m <= 0) return;
     hipLaunchKernelGGL(k_update_x<T>, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0, st, X, ldx, n, Y,
-                       ldy, d, mu, smax, accumulate);
+                       ldy, d, mu, smax, accumulate, zmax);
 }
 template void launch_update_x<float>(double *, int64_t, int64_t, int, const float *, int64_t, const double *, double,
-                                     const double *, int, hipStream_t);
+                                     const double *, int, double *, hipStream_t);
 template void launch_update_x<double>(double *, int64_t, int64_t, int, const double *, int64_t, const double *,
-                                      double, const double *, int, hipStream_t);
+                                      double, const double *, int, double *, hipStream_t);
+
+void launch_col_maxdiff(const double *X, int64_t ldx, double *S, int64_t lds, int64_t n, int m, double *out,
+                        hipStream_t st)
+{
+    if (n <= 0 || m <= 0) return;
+    hipLaunchKernelGGL(k_col_maxdiff, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0, st, X, ldx, S,
+                       lds, n, out);
+}
 
 void launch_zero(double *p, int64_t count, hipStream_t st)
 {

@@ -36,22 +36,22 @@
 #include "common.h"
 #include "internal.h"
 
-#define TRSV_TIMEOUT_TICKS 100000000ULL  // wall_clock64 runs at 100 MHz on gfx9
 #define TRSV_NBS 1024                    // big diagonal block
 #define TRSV_NCRIT 64                    // workgroups on the chain's tasks
 #define TRSV_NBULK 192                   // workgroups streaming the other blocks
 #define TRSV_CDEPTH 1                    // U(p, p+d) tasks taken by the chain: d <= this
 
-// thread 0 only: wait until *addr >= want, or give up.  The polling loads are
-// relaxed agent-scope atomics (coherent loads that do not invalidate the
-// caches).
-SPD_DEV bool wait_ge(int *addr, int want, int *err)
+// thread 0 only: wait until *addr >= want, or give up after `tmo` ticks of
+// wall_clock64 (100 MHz on gfx9) or as soon as another wait has given up.
+// The polling loads are relaxed agent-scope atomics (coherent loads that do
+// not invalidate the caches).
+SPD_DEV bool wait_ge(int *addr, int want, int *err, unsigned long long tmo)
 {
     const unsigned long long t0 = wall_clock64();
     while (__hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return false;
-        if (wall_clock64() - t0 > TRSV_TIMEOUT_TICKS) {
+        if (wall_clock64() - t0 > tmo) {
             __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
@@ -326,7 +326,8 @@ template <typename T, int MC, bool FWD>
 __global__ __launch_bounds__(256) void k_trsv_blk(const T *__restrict__ L, int64_t ld, const T *__restrict__ WB,
                                                   int64_t npad, int nbs, int K, const T *__restrict__ Yin,
                                                   T *__restrict__ Zout, int64_t ldy, int c0, int m,
-                                                  T *__restrict__ P, int *ctl, int *err, int ncrit, int cdepth)
+                                                  T *__restrict__ P, int *ctl, int *err, int ncrit, int cdepth,
+                                                  unsigned long long tmo)
 {
     constexpr int NBS = TRSV_NBS;
     using BV = BlockVec<T, MC, FWD, NBS>;
@@ -437,7 +438,7 @@ __global__ __launch_bounds__(256) void k_trsv_blk(const T *__restrict__ L, int64
 
         if (!ztask) {
             if (tid == 0)
-                s_ok = wait_ge(&cntZ[pj], sj / R, err) ? 1 : 0;
+                s_ok = wait_ge(&cntZ[pj], sj / R, err, tmo) ? 1 : 0;
             __syncthreads();
             if (!s_ok)
                 return;
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(256) void k_trsv_blk(const T *__restrict__ L, int64
         } else {
             if (pi >= 2) {
                 if (tid == 0)
-                    s_ok = wait_ge(&cntA[pi], (pi - 1) * nc, err) ? 1 : 0;
+                    s_ok = wait_ge(&cntA[pi], (pi - 1) * nc, err, tmo) ? 1 : 0;
                 __syncthreads();
                 if (!s_ok)
                     return;
@@ -493,7 +494,7 @@ __global__ __launch_bounds__(256) void k_trsv_blk(const T *__restrict__ L, int64
             }
             if (pi >= 1) {
                 if (tid == 0)
-                    s_ok = wait_ge(&cntB[pi], nc, err) ? 1 : 0;
+                    s_ok = wait_ge(&cntB[pi], nc, err, tmo) ? 1 : 0;
                 __syncthreads();
                 if (!s_ok)
                     return;
@@ -608,7 +609,7 @@ template void launch_build_winv<double>(const double *, int64_t, int64_t, const 
 
 template <typename T, bool FWD>
 static void launch_dir(const T *L, int64_t ld, const T *WB, int64_t npad, int m, const T *Yin, T *Zout,
-                       int64_t ldy, T *P, int *ctl, int *err, hipStream_t st)
+                       int64_t ldy, T *P, int *ctl, int *err, unsigned long long tmo, hipStream_t st)
 {
     const int nbs = solve_nbs(npad), K = solve_nblocks(npad);
     constexpr int R = 8 * VecOf<T>::N;
@@ -629,29 +630,29 @@ static void launch_dir(const T *L, int64_t ld, const T *WB, int64_t npad, int m,
         const int mc = m - c0;
         if (mc == 1)
             hipLaunchKernelGGL((k_trsv_blk<T, 1, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K, Yin,
-                               Zout, ldy, c0, m, P, ctl, err, ncrit, cdepth);
+                               Zout, ldy, c0, m, P, ctl, err, ncrit, cdepth, tmo);
         else if (mc == 2)
             hipLaunchKernelGGL((k_trsv_blk<T, 2, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K, Yin,
-                               Zout, ldy, c0, m, P, ctl, err, ncrit, cdepth);
+                               Zout, ldy, c0, m, P, ctl, err, ncrit, cdepth, tmo);
         else if (mc <= 4)
             hipLaunchKernelGGL((k_trsv_blk<T, 4, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K, Yin,
-                               Zout, ldy, c0, m, P, ctl, err, ncrit, cdepth);
+                               Zout, ldy, c0, m, P, ctl, err, ncrit, cdepth, tmo);
         else
             hipLaunchKernelGGL((k_trsv_blk<T, TRSV_MC, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K,
-                               Yin, Zout, ldy, c0, m, P, ctl, err, ncrit, cdepth);
+                               Yin, Zout, ldy, c0, m, P, ctl, err, ncrit, cdepth, tmo);
     }
 }
 
 template <typename T>
 void launch_trsv(const T *L, int64_t ld, const T *WB, int64_t npad, int m, T *Y, T *Z, int64_t ldy, T *P, int *ctl,
-                 int *err, hipStream_t st)
+                 int *err, unsigned long long wait_ticks, hipStream_t st)
 {
-    launch_dir<T, true>(L, ld, WB, npad, m, Y, Z, ldy, P, ctl, err, st);
-    launch_dir<T, false>(L, ld, WB, npad, m, Z, Y, ldy, P, ctl, err, st);
+    launch_dir<T, true>(L, ld, WB, npad, m, Y, Z, ldy, P, ctl, err, wait_ticks, st);
+    launch_dir<T, false>(L, ld, WB, npad, m, Z, Y, ldy, P, ctl, err, wait_ticks, st);
 }
 template void launch_trsv<float>(const float *, int64_t, const float *, int64_t, int, float *, float *, int64_t,
-                                 float *, int *, int *, hipStream_t);
+                                 float *, int *, int *, unsigned long long, hipStream_t);
 template void launch_trsv<double>(const double *, int64_t, const double *, int64_t, int, double *, double *, int64_t,
-                                  double *, int *, int *, hipStream_t);
+                                  double *, int *, int *, unsigned long long, hipStream_t);
 
 }  // namespace spd

@@ -35,7 +35,7 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = [
-    "seeds", "logspaced", "rhs", "accurate_product", "system",
+    "seeds", "logspaced", "logspaced_kron", "rhs", "accurate_product", "system",
     "tridiag", "minij", "hilbert", "covariance", "indefinite",
     "batch_shapes", "sha256", "SPDSystem",
 ]
@@ -66,6 +66,8 @@ def logspaced(n: int, cond: float, seed: int, backend: str = "numpy", device=Non
         return np.asfortranarray(A)
     if backend == "torch":
         import torch
+        if n * n >= 2 ** 31:
+            return logspaced_kron(n, cond, seed, device=device)
         gen = torch.Generator(device=device)
         gen.manual_seed(seed)
         G = torch.randn(n, n, dtype=torch.float64, device=device, generator=gen)
@@ -81,6 +83,63 @@ def logspaced(n: int, cond: float, seed: int, backend: str = "numpy", device=Non
         # same values; callers read it with lda = n.
         return A.contiguous()
     raise ValueError(f"unknown backend {backend!r}")
+
+
+def _haar(k: int, gen, device):
+    """Orthogonal k x k from the QR of a seeded N(0,1) matrix, diag(R) > 0."""
+    import torch
+    G = torch.randn(k, k, dtype=torch.float64, device=device, generator=gen)
+    Q, R = torch.linalg.qr(G)
+    return Q * torch.sign(torch.diagonal(R))[None, :]
+
+
+def _kron_apply(Q1, Q2, M):
+    """(Q1 kron Q2) M for M of shape (a b, c): row i = i1 b + i2."""
+    a, b, c = Q1.shape[0], Q2.shape[0], M.shape[1]
+    T = (Q1 @ M.reshape(a, b * c)).reshape(a, b, c).transpose(0, 1).reshape(b, a * c)
+    return (Q2 @ T).reshape(b, a, c).transpose(0, 1).reshape(a * b, c)
+
+
+def _kron_split(n: int) -> tuple[int, int]:
+    a = int(math.isqrt(n))
+    while a > 1 and n % a:
+        a -= 1
+    if a < 2:
+        raise ValueError(f"n = {n} is prime: no factorisation a b with 2 <= a <= b")
+    return a, n // a
+
+
+def logspaced_kron(n: int, cond: float, seed: int, device=None, chunk: int = 2048):
+    """A = Q diag(lambda) Q^T with lambda log-spaced from 1 to ``cond`` as in
+    ``logspaced``, for orders whose n x n arrays exceed 2^31 elements (torch's
+    dense QR returned a rank-deficient Q beyond that on ROCm, so no order-n
+    QR is taken).  Q = (Q1 kron Q2) P (Q3 kron Q4): Q1, Q3 of order a and Q2,
+    Q4 of order b (n = a b, a the largest divisor <= sqrt(n)) from seeded
+    Gaussian QRs, P a seeded permutation -- dense and orthogonal up to
+    rounding, with the same eigenvalues.  A is built a block of ``chunk``
+    columns at a time (A E_J = Q Lambda Q^T E_J), every intermediate below 2^31
+    elements, then symmetrised exactly."""
+    import torch
+    a, b = _kron_split(n)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    Q1, Q2, Q3, Q4 = _haar(a, gen, device), _haar(b, gen, device), _haar(a, gen, device), _haar(b, gen, device)
+    perm = torch.randperm(n, generator=gen, device=device)
+    lam = _eigs(n, cond, torch, dtype=torch.float64, device=device)
+    A = torch.empty(n, n, dtype=torch.float64, device=device)
+    for j0 in range(0, n, chunk):
+        c = min(chunk, n - j0)
+        M = torch.zeros(n, c, dtype=torch.float64, device=device)
+        M[torch.arange(j0, j0 + c, device=device), torch.arange(c, device=device)] = 1.0
+        M = _kron_apply(Q1.T, Q2.T, M)          # K1^T E_J
+        Mp = torch.empty_like(M)
+        Mp[perm] = M                            # P^T
+        M = _kron_apply(Q3.T, Q4.T, Mp) * lam[:, None]
+        M = _kron_apply(Q3, Q4, M)[perm]        # K2, then P
+        A[:, j0:j0 + c] = _kron_apply(Q1, Q2, M)
+        del M, Mp
+    A = 0.5 * (A + A.T)
+    return A.contiguous()
 
 
 def rhs(n: int, m: int, seed: int, backend: str = "numpy", device=None):

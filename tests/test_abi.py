@@ -117,3 +117,8 @@ def test_binding_fails_loudly_without_library(tmp_path):
             spd.load(str(tmp_path / "missing.so"))
     finally:
         spd._lib = saved
+
+
+def test_wait_limit_argument_checks(lib):
+    import paper_1405_4644_amd as spd
+    assert lib.spd_factor_set_wait_limit(None, 1.0) == spd.ERR_INVALID_ARG

@@ -56,7 +56,39 @@ def test_covariance_n70000_m32(spd, d):
          f"eta {rep.eta:.2e} fwd {fe:.2e} (bar {10 * kappa * U64:.2e})")
     assert rep.status == 0
     assert spd.PREC_NAME[rep.prec_used] == "fp32" and rep.fallbacks == 0
-    assert rep.eta <= 2.0 ** -51
+    assert rep.eta <= 1e-14
     assert fe <= 10 * kappa * U64
     del A, B, X, Xt, F
     torch.cuda.empty_cache()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [2000, 4096])
+@pytest.mark.parametrize("d", [1, 2, 4])
+def test_covariance_against_oracle(spd, orc, n, d):
+    # the Section 4 matrix at sizes the oracle finishes in seconds: the GPU
+    # solution element by element against the oracle's binary64 solve, and
+    # the refinement's iteration count against the oracle's emulation of
+    # Algorithm 1 (same stopping rule)
+    import numpy as np
+    import torch
+    _say(f"covariance vs oracle n={n} d={d}")
+    A = spdgen.covariance(n, d)
+    _, sx = spdgen.seeds(5, d)
+    Xt = spdgen.rhs(n, 2, sx)
+    Bt = spdgen.accurate_product(A, Xt)
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(np.ascontiguousarray(Bt)).cuda()
+    X, rep, F = spd.posv(Ad, Bd, prec="fp32")
+    F.close()
+    Xh = X.cpu().numpy()
+    Xo, _ = orc.solve(A, Bt)
+    _, ro = orc.ir(A, Bt, prec="fp32")
+    kappa = cond_bound(n, d)
+    fe = float((np.abs(Xh - Xo).max(axis=1) / np.abs(Xo).max(axis=1)).max())
+    _say(f"  library {rep.status} {rep.iters_low}/{rep.iters_high}; oracle {ro.status} {ro.iters_low}/{ro.iters_high}; "
+         f"|x - x_oracle| {fe:.2e} (bar {10 * kappa * U64:.2e})")
+    assert rep.status == 0 and ro.status == 0
+    assert rep.prec_used == ro.prec_used == 2 and rep.fallbacks == ro.fallbacks == 0
+    assert abs(rep.iters_low - ro.iters_low) <= 1
+    assert fe <= 10 * kappa * U64
+    assert orc.backward_error(A, Xh, Bt).max() <= 1e-14

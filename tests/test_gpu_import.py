@@ -65,7 +65,9 @@ def test_import_exact_factor(spd, orc, prec):
     assert rep.status == 0 and ro.status == 0
     assert abs(rep.iters_high - ro.iters_high) <= 1
     if prec == "fp64":
-        assert (rep.iters_low, rep.iters_high) == (1, 1)
+        # an imported factor gets one confirming correction (it is not
+        # known to be backward stable)
+        assert (rep.iters_low, rep.iters_high) == (2, 2)
     assert orc.backward_error(A, X, B).max() <= 1e-14
     assert np.abs(X - Xt).max() / np.abs(Xt).max() <= 10 * cond * U64
 

@@ -136,3 +136,29 @@ def test_golden_exact_small(orc):
         xe = np.array([float(Fraction(v)) for v in c["x"]])
         cond = np.linalg.cond(A)
         assert np.max(np.abs(x[0] - xe)) <= 10 * cond * U64 * np.max(np.abs(xe)) * n
+
+
+def test_residual_given_rows_matches_full_residual(orc):
+    # the rows-only residual is the full residual restricted to those rows
+    s = spdgen.system(90, 1e3, 2, config=0, index=21)
+    X = s.Xt + 1e-6
+    rows = np.array([0, 7, 45, 89])
+    R = orc.residual(s.A, X, s.Bt)
+    Rg = orc.residual_given_rows(s.A[rows, :], X, s.Bt, rows)
+    assert np.array_equal(Rg, R[:, rows])
+
+
+def test_logspaced_kron_generator_spectrum():
+    # the large-order recipe (no order-n QR): exactly symmetric, dense, and
+    # its eigenvalues are the log-spaced lambda_i = cond^((i-1)/(n-1))
+    import torch
+    n, cond = 12 * 16, 1e5
+    A = spdgen.logspaced_kron(n, cond, 5, device="cpu", chunk=50).numpy()
+    assert np.array_equal(A, A.T)
+    assert np.count_nonzero(A) == n * n
+    lam = np.linalg.eigvalsh(A)
+    want = cond ** (np.arange(n) / (n - 1))
+    assert np.abs(lam - want).max() <= 1e-13 * cond
+    # seeded: the same call gives the same bytes
+    B = spdgen.logspaced_kron(n, cond, 5, device="cpu", chunk=64).numpy()
+    assert np.array_equal(A, B)

@@ -175,6 +175,24 @@ spd_status spd_posv(const double *A, int64_t n, int64_t lda, const double *B, in
 spd_status spd_residual(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx, const double *B,
                         int64_t ldb, int64_t nrhs, double *R, int64_t ldr, double *eta, void *hip_stream);
 
+/* spd_residual for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, results and rounding as spd_residual (R bit for bit, eta
+ * to the last bit), but it calls no allocator.  Its partial sums, norms, eta
+ * and (R NULL) the residual live in one static device array of
+ * SPD_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; a call
+ * whose parts need more is rejected with SPD_ERR_INVALID_ARG before any
+ * device work (n = 16384 fits with 1 or 2 right-hand sides; with 3 or more,
+ * any n up to about 60 of them).  With eta NULL the call is asynchronous on
+ * `hip_stream` (capturable); with eta (host) it synchronises to read it.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on one
+ * GPU (other streams, other threads, graph replays) race and give wrong
+ * results -- the caller orders them. */
+#define SPD_NOALLOC_SCRATCH_BYTES (128u << 20)
+spd_status spd_residual_noalloc(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx,
+                                const double *B, int64_t ldb, int64_t nrhs, double *R, int64_t ldr,
+                                double *eta, void *hip_stream);
+
 /* Limits of the batched entry point (per system). */
 #define SPD_BATCH_NMAX 512
 #define SPD_BATCH_MAXRHS 8

@@ -64,6 +64,7 @@ _SIGS = [
     ("spd_posv", C.c_int, [_vp, _i64, _i64, _vp, _i64, _i64, _vp, _i64, C.c_int, C.POINTER(Opts),
                            C.POINTER(Report), _vp, C.POINTER(_vp)]),
     ("spd_residual", C.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _vp]),
+    ("spd_residual_noalloc", C.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _vp]),
     ("spd_solve_batched", C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Opts), _vp, _vp]),
     ("spd_batched_config", C.c_int, [_i64, C.POINTER(_i32), C.POINTER(_i32)]),
     ("spd_solve_batched_timed", C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(Opts), _vp, _vp,

@@ -74,6 +74,12 @@ struct spd_factor_s {
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 };
 
+// Device memory of spd_residual_noalloc: partial sums, norms, eta and (when
+// the caller passes no R) the residual itself.  Each device holds its own copy
+// until the process ends; host code uses only the address
+// hipGetSymbolAddress returns for it (per device), never the name.
+static __device__ __align__(256) char scratch[SPD_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 // ---- optional kernel timing (spd_profile_*) ----
@@ -1066,6 +1072,73 @@ spd_status spd_posv(const double *A, int64_t n, int64_t lda, const double *B, in
     s = spd_refine(*F, A, lda, B, ldb, nrhs, X, ldx, &op, rep, hip_stream);
     rep->fallbacks += fallbacks;
     return s;
+}
+
+}  // extern "C"
+
+namespace {
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// this device's copy of `scratch` (looked up once per device, with it current)
+spd_status noalloc_scratch(char **ptr)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return SPD_ERR_DEVICE;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return SPD_ERR_DEVICE;
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return SPD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+spd_status spd_residual_noalloc(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx,
+                                const double *B, int64_t ldb, int64_t nrhs, double *R, int64_t ldr, double *eta,
+                                void *hip_stream)
+{
+    if (n < 0 || nrhs < 0 || lda < std::max<int64_t>(1, n) || ldx < std::max<int64_t>(1, n) ||
+        ldb < std::max<int64_t>(1, n) || (R && ldr < std::max<int64_t>(1, n)))
+        return SPD_ERR_INVALID_ARG;
+    if (n > 0 && nrhs > 0 && (!A || !X || !B)) return SPD_ERR_INVALID_ARG;
+    if (n > INT32_MAX || nrhs > INT32_MAX) return SPD_ERR_INVALID_ARG;
+    // layout in the scratch array, each part 256-byte aligned; sizes beyond
+    // the array are rejected before any device work
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const int64_t nn = 1 + 4 * nrhs;
+    const size_t bP = (n > 0 && nrhs > 0) ? up((size_t)spd::resid_scratch(n, (int)nrhs) * sizeof(double)) : 0;
+    const size_t bR = R ? 0 : up((size_t)n * nrhs * sizeof(double));
+    const size_t bN = up((size_t)nn * sizeof(double)), bE = up((size_t)nrhs * sizeof(double));
+    if (bP + bR + bN + bE > (size_t)SPD_NOALLOC_SCRATCH_BYTES) return SPD_ERR_INVALID_ARG;
+    if (n == 0 || nrhs == 0) {
+        for (int64_t c = 0; eta && c < nrhs; ++c) eta[c] = 0.0;
+        return SPD_OK;
+    }
+    char *base = nullptr;
+    SPD_TRY(noalloc_scratch(&base));
+    hipStream_t st = (hipStream_t)hip_stream;
+    double *P = (double *)base;
+    double *Rw = R ? R : (double *)(base + bP);
+    const int64_t ldrw = R ? ldr : n;
+    double *norms = (double *)(base + bP + bR);
+    double *etad = (double *)(base + bP + bR + bN);
+    spd::launch_zero(norms, nn, st);
+    spd::launch_residual(A, lda, n, X, ldx, B, ldb, (int)nrhs, Rw, ldrw, nullptr, norms, 1, P, st);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && eta) {
+        spd::launch_eta_from_norms(norms, (int)nrhs, etad, st);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(eta, etad, (size_t)nrhs * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    return map_err(e);
 }
 
 spd_status spd_residual(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx, const double *B,

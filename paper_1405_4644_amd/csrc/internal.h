@@ -99,6 +99,8 @@ void launch_export(const T *L, int64_t ld, int64_t n, double *Lout, int64_t ldo,
 // max; zero them first);
 // with want_anorm, norms[0] = ||A||_inf.  P is scratch of resid_scratch(n, m) doubles.
 int64_t resid_scratch(int64_t n, int m);
+// eta (device, m) from the norms launch_residual wrote (with want_anorm)
+void launch_eta_from_norms(const double *norms, int m, double *eta, hipStream_t st);
 void launch_residual(const double *A, int64_t lda, int64_t n, const double *X, int64_t ldx, const double *B,
                      int64_t ldb, int m, double *R, int64_t ldr, const double *d, double *norms, int want_anorm,
                      double *P, hipStream_t st);

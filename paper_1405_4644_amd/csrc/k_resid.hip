@@ -499,6 +499,23 @@ int64_t resid_scratch(int64_t n, int m)
     return need;
 }
 
+// eta[c] = ||r_c|| / (||A|| ||x_c|| + ||b_c||) from the residual's norms
+// (norms[0] = ||A||, then max|r|, max|x|, max|b| per column), rounded as the
+// host formula rounds it (no fused multiply-add)
+__global__ void k_eta_from_norms(const double *__restrict__ norms, int m, double *__restrict__ eta)
+{
+#pragma clang fp contract(off)
+    const int c = blockIdx.x * 64 + threadIdx.x;
+    if (c >= m)
+        return;
+    const double an = norms[0], rn = norms[1 + c], xn = norms[1 + m + c], bn = norms[1 + 2 * m + c];
+    const double den = an * xn + bn;
+    double v = (den > 0.0) ? rn / den : (rn > 0.0 ? __builtin_inf() : 0.0);
+    if (!(rn == rn) || !(xn == xn) || !(an == an))
+        v = __builtin_nan("");
+    eta[c] = v;
+}
+
 template <int MC, int RB, int CB, int JS>
 static void launch_partial(const double *A, int64_t lda, int64_t n, const double *X, int64_t ldx, int m, int c0,
                            int S, double *P, double *Pabs, int want_abs, hipStream_t st)
@@ -506,6 +523,12 @@ static void launch_partial(const double *A, int64_t lda, int64_t n, const double
     const unsigned nrb = (unsigned)((n + 63) / 64);
     hipLaunchKernelGGL((k_resid_partial<MC, RB, CB, JS>), dim3(nrb, (unsigned)S), dim3(256), 0, st, A, lda, n, X,
                        ldx, m, c0, S, P, Pabs, want_abs);
+}
+
+void launch_eta_from_norms(const double *norms, int m, double *eta, hipStream_t st)
+{
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_eta_from_norms, dim3((unsigned)((m + 63) / 64)), dim3(64), 0, st, norms, m, eta);
 }
 
 void launch_residual(const double *A, int64_t lda, int64_t n, const double *X, int64_t ldx, const double *B,

@@ -122,3 +122,13 @@ def test_binding_fails_loudly_without_library(tmp_path):
 def test_wait_limit_argument_checks(lib):
     import paper_1405_4644_amd as spd
     assert lib.spd_factor_set_wait_limit(None, 1.0) == spd.ERR_INVALID_ARG
+
+
+def test_noalloc_residual_rejects_sizes_beyond_its_array(lib):
+    # checked before any device work: n = 20000 with 2 right-hand sides needs
+    # more partial sums than the static array holds
+    import paper_1405_4644_amd as spd
+    fake = C.c_void_p(0x1000)
+    assert lib.spd_residual_noalloc(fake, 20000, 20000, fake, 20000, fake, 20000, 2, fake, 20000, None,
+                                    None) == spd.ERR_INVALID_ARG
+    assert lib.spd_residual_noalloc(fake, 10, 5, fake, 10, fake, 10, 1, fake, 10, None, None) == spd.ERR_INVALID_ARG

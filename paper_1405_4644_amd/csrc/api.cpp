@@ -39,7 +39,8 @@ struct spd_factor_s {
     int64_t cap_d = 0;
     double mu = 1.0;
     int half = HALF_NONE;    // operand rounding of the trailing update (BF16 / FP16 factors)
-    int group = 4;           // panels per trailing-update group (SPD_GROUP overrides)
+    int group = 4;           // panels per trailing-update group, binary32/64 (SPD_GROUP overrides)
+    int group_half = 8;      // the same for binary16/bfloat16 operands, even, <= 8 (SPD_GROUP_HALF overrides)
     int upd_slots = 0;       // cap on the main-stream update's workgroups (SPD_UPD_SLOTS; 0: one per tile)
     bool imported = false;   // the factor came from spd_factor_import (not line 1's own)
     void *Lh = nullptr;      // two panel copies in that precision (npad x NB halves each)
@@ -226,16 +227,21 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
     const int64_t wi_blk = (NB / SPD_IB_H) * SPD_IB_H * SPD_IB_H;
     hipEvent_t evU = F->ev[0], evP = F->ev[1];
     // Panels are factored one by one (NB wide) but the trailing update is
-    // applied per group of G panels (K = G NB), which halves the C-tile
-    // traffic per flop at G = 2.  Lookahead is one group.
+    // applied per group of G panels (K = G NB), which cuts the C-tile
+    // traffic per flop G-fold.  Lookahead is one group.  With half-precision
+    // operands the update is bound by that traffic up to K ~ 1000 (the
+    // binary32 C tile against 2.5 PFLOP/s), so their groups are wider and
+    // their trailing update runs on 256 x 256 tiles (npad is then a multiple
+    // of 256 and G even, so every group's trailing region is whole tiles).
     const int half = (sizeof(T) == 4) ? F->half : HALF_NONE;
-    const int64_t G = half ? std::min<int64_t>(F->group, 2) : F->group;
+    const int64_t G = half ? F->group_half : F->group;
     const int64_t ng = (nt + G - 1) / G;
     const int op_elem = half ? 2 : (int)sizeof(T);
-    // half-precision operand copies of panels k mod 4 (two groups), written by
-    // the panel solve and read by the updates
+    // half-precision operand copies of panels k mod 16 (two groups), written
+    // by the panel solve and read by the updates
+    const int64_t lh_slot = npad * NB;  // halves per copy
     auto lh = [&](int64_t k) -> void * {
-        return half ? (void *)((char *)F->Lh + (size_t)(k & 3) * npad * NB * 2) : nullptr;
+        return half ? (void *)((char *)F->Lh + (size_t)(k & 15) * lh_slot * 2) : nullptr;
     };
     // H -= L_{.,[p0,p1)} L_{.,[p0,p1)}^T on tile columns [lo, hi) of the
     // region starting at row/column r0
@@ -246,7 +252,13 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
         const int t = (int)((npad - r0) / SPD_TILE_H);
         if (t <= 0 || lo >= hi) return;
         hipEvent_t pe = prof_begin(s);
-        if (half) {
+        const int64_t rem = npad - r0;
+        if (half && p1 - p0 > 1 && rem % 256 == 0 && lo % 2 == 0) {
+            // a group's trailing update: 256 x 256 tiles, all its panels in one pass
+            const int sk0 = (int)((r0 - (p0 + 1) * NB) / SPD_IB_H);
+            spd::launch_syrk_update_h256((float *)H, npad, F->Lh, (int)(p0 & 15), lh_slot / 8, sk0, (int)(p1 - p0),
+                                         half, r0, (int)(rem / 256), lo / 2, (hi + 1) / 2, F->info_dev, s, prio, cap);
+        } else if (half) {
             // copy of panel p starts at row (p + 1) NB
             const int sk0 = (int)((r0 - (p0 + 1) * NB) / SPD_IB_H);
             const void *l1 = (p1 - p0 > 1) ? lh(p0 + 1) : nullptr;
@@ -285,8 +297,9 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
         HIP_TRY(hipEventRecord(evP, st));
         for (int64_t g = 0; g + 1 < ng; ++g) {
             const int64_t p0 = g * G, p1 = std::min<int64_t>(p0 + G, nt), r0 = p1 * NB;
-            const int next = (int)((std::min<int64_t>(p1 + G, nt) - p1) * (NB / SPD_TILE_H));
             const int t = (int)((npad - r0) / SPD_TILE_H);
+            int next = (int)((std::min<int64_t>(p1 + G, nt) - p1) * (NB / SPD_TILE_H));
+            if (half) next = std::min(t, (next + 1) & ~1);  // whole 256-tile columns on both sides of the split
             HIP_TRY(hipStreamWaitEvent(st, evP, 0));
             update(p0, p1, r0, 0, next, st, 1);
             HIP_TRY(hipEventRecord(evU, st));
@@ -309,12 +322,16 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
 // rounding from prec
 spd_status prepare_factor(spd_factor_t F, int64_t n, int prec, double theta, hipStream_t st)
 {
+    const int64_t old_npad = F->npad;
+    const int old_elem = F->elem;
     F->n = n;
     F->prec = prec;
     F->elem = (prec == SPD_FP64) ? 8 : 4;
     F->nb = (prec == SPD_FP64) ? spd::Panel<double>::NB : spd::Panel<float>::NB;
-    F->npad = ((n + F->nb - 1) / F->nb) * F->nb;
-    if (F->npad == 0) F->npad = F->nb;
+    // half-precision operands: whole 256 x 256 tiles in every group's trailing region
+    const int64_t pad = (prec == SPD_FP16 || prec == SPD_BF16) ? 256 : F->nb;
+    F->npad = ((n + pad - 1) / pad) * pad;
+    if (F->npad == 0) F->npad = pad;
     const int64_t npad = F->npad;
     SPD_TRY(ensure_stream_objs(F));
     // one allocation for L, W and Winv (all zeroed when (re)allocated)
@@ -329,8 +346,17 @@ spd_status prepare_factor(spd_factor_t F, int64_t n, int prec, double theta, hip
     F->W = (char *)base + bL;
     F->Winv = (char *)base + bL + bW;
     size_t capw = F->cap_WB;
-    SPD_TRY(grow(&F->WB, &capw, (size_t)spd::solve_winv_elems(npad) * F->elem, true, st));
+    const size_t bWB = (size_t)spd::solve_winv_elems(npad) * F->elem;
+    SPD_TRY(grow(&F->WB, &capw, bWB, true, st));
     F->cap_WB = capw;
+    // The factorisation writes only the lower parts of W, Winv and WB; the
+    // zeros above rely on these buffers being zero there.  Buffers kept from
+    // a factor of another layout (npad or element size: a precision switch
+    // on the handle) hold that factor's values at those places: clear them.
+    if (old_npad != npad || old_elem != F->elem) {
+        spd::launch_zero((double *)F->W, (int64_t)((bW + bWi) / sizeof(double)), st);
+        spd::launch_zero((double *)F->WB, (int64_t)(bWB / sizeof(double)), st);
+    }
     size_t capt = F->cap_Tb;
     SPD_TRY(grow(&F->Tb, &capt, (size_t)spd::solve_tmp_elems(npad) * F->elem, false, st));
     F->cap_Tb = capt;
@@ -342,7 +368,7 @@ spd_status prepare_factor(spd_factor_t F, int64_t n, int prec, double theta, hip
     F->half = (prec == SPD_FP16) ? HALF_F16 : (prec == SPD_BF16) ? HALF_BF16 : HALF_NONE;
     if (F->half) {
         size_t caph = F->cap_Lh;
-        SPD_TRY(grow(&F->Lh, &caph, (size_t)4 * npad * F->nb * 2, false, st));
+        SPD_TRY(grow(&F->Lh, &caph, (size_t)16 * npad * F->nb * 2, false, st));
         F->cap_Lh = caph;
     }
     return SPD_OK;
@@ -926,6 +952,8 @@ spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec, co
         if (!*F) return SPD_ERR_OUT_OF_MEMORY;
         created = true;
         if (const char *e = std::getenv("SPD_GROUP")) (*F)->group = std::max(1, std::min(8, std::atoi(e)));
+        if (const char *e = std::getenv("SPD_GROUP_HALF"))
+            (*F)->group_half = std::max(2, std::min(8, std::atoi(e) & ~1));
         if (const char *e = std::getenv("SPD_UPD_SLOTS")) (*F)->upd_slots = std::max(0, std::atoi(e));
         if (hipGetDevice(&(*F)->device) != hipSuccess) {
             delete *F;

@@ -134,6 +134,10 @@ SPD_DEV void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Word 3 of a raw buffer resource on gfx950 (32-bit data format, no
+// swizzle): used with __builtin_amdgcn_make_buffer_rsrc.
+#define SPD_BUFFER_RSRC_WORD3 0x00020000
+
 // Monotone atomic max of a non-negative double via its bit pattern (NaN,
 // whose bits exceed +inf's, wins -- so a NaN anywhere propagates).
 SPD_DEV void atomic_max_nonneg(double *addr, double v)

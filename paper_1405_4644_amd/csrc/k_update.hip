@@ -400,7 +400,153 @@ __global__ __launch_bounds__(256) void k_syrk_update_h(float *__restrict__ H, in
     }
 }
 
+// ---------------------------------------------------------------------------
+// K4, half-precision operands, 256 x 256 tiles: a whole group of np panels
+// (K = 128 np, np <= 16) in one pass over each C tile, so the binary32 C tile
+// crosses HBM once per group instead of once per one or two panels.  Each
+// wave owns a 128 x 128 block of the tile as 4 x 4 accumulators of
+// v_mfma_f32_32x32x16_{f16,bf16} (256 registers: one wave per SIMD), and
+// streams its operand fragments straight from the panel copies -- one
+// contiguous 1 KiB per fragment per wave -- with the next k-step's eight
+// fragments in flight while the current step's sixteen MFMAs run.
+// Panel p of the group is the copy in ring slot (slot0 + p) % 16 (slot
+// stride `sstride` fragments); the copy of panel p starts 4 32-row blocks
+// later than that of panel p - 1, so skip_p = skip0 - 4 p.
+template <int HK>
+__global__ __launch_bounds__(256, 1) void k_syrk_update_h256(float *__restrict__ H, int64_t ld,
+                                                             const void *__restrict__ Lh, int slot0, int64_t sstride,
+                                                             int skip0, int np, int64_t r0, int t, int tj_lo,
+                                                             int tj_hi, int ntiles, const unsigned long long *info,
+                                                             int prio)
+{
+    using V8 = typename HalfT<HK>::V8;
+    constexpr int KS = 128 / 16;  // k-steps per panel
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (*(volatile const unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
+        return;
+    if (prio)
+        __builtin_amdgcn_s_setprio(2);
+    const int wm = wave >> 1, wn = wave & 1;
+    const V8 *base = (const V8 *)Lh;
+    const int per = gridDim.x / 8, chunk = (ntiles + 7) / 8;
+    for (int it = blockIdx.x / 8; it < chunk; it += per) {
+        const int logical = (blockIdx.x % 8) * chunk + it;
+        if (logical >= ntiles)
+            break;
+        int ti, tj;
+        decode_tile(logical, t, tj_lo, tj_hi, ti, tj);
+        if (ti < 0)
+            break;
+        const int64_t crow = r0 + (int64_t)ti * 256, ccol = r0 + (int64_t)tj * 256;
+        // register j of acc[a][b] accumulates -sum L L^T for
+        // C[crow + 128 wn + 32 b + col(j)][ccol + 128 wm + 32 a + row(j)];
+        // C itself is added at the end (holding it through the K loop would
+        // need a second register file)
+        float *cb = H + (crow + 128 * wn) + (ccol + 128 * wm) * ld;
+        const int ldi = (int)ld;  // byte offsets inside the wave's 128 x 128 block fit in 31 bits (ld < 2^22)
+        floatx16 acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    acc[a][b][j] = 0.0f;
+        // operand 32-row blocks: A (C columns) 8 tj + 4 wm + a, B (C rows) 8 ti + 4 wn + b
+        const int ba = 8 * tj + 4 * wm, bb = 8 * ti + 4 * wn;
+        const int S = np * KS;
+        V8 fa0[4], fb0[4], fa1[4], fb1[4];
+        auto load = [&](int s, V8 *fa, V8 *fb) {
+            const int p = s / KS, ks = s % KS;
+            const V8 *lh = base + (int64_t)((slot0 + p) & 15) * sstride + lane;
+            const int sk = skip0 - 4 * p;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                fa[a] = lh[((int64_t)(sk + ba + a) * KS + ks) * 64];
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                fb[b] = lh[((int64_t)(sk + bb + b) * KS + ks) * 64];
+        };
+        auto step = [&](const V8 *fa, const V8 *fb) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const V8 na = HalfT<HK>::neg(fa[a]);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = HalfT<HK>::mma(na, fb[b], acc[a][b]);
+            }
+        };
+        load(0, fa0, fb0);
+        for (int s = 0; s < S; s += 2) {
+            // S is even (KS = 8): steps s and s + 1 both exist
+            load(s + 1, fa1, fb1);
+            __builtin_amdgcn_sched_barrier(0);
+            step(fa0, fb0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (s + 2 < S)
+                load(s + 2, fa0, fb0);
+            __builtin_amdgcn_sched_barrier(0);
+            step(fa1, fb1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // C += acc, one 32 x 32 block at a time, the next block's C values
+        // in flight while the current one is added and stored.  Buffer
+        // loads/stores: the lane's part of the offset is one register, the
+        // block's part a scalar (global addressing would keep a 64-bit
+        // address per element alive through the K loop).
+        // Offsets: register j of block (a, b) is at lane part + row part
+        // (8 (j/4) + j%4) ldi (one register per j) + block part 32 a ldi
+        // (scalar) + 32 b (immediate).  The asm statement keeps the compiler
+        // from computing them before the K loop, where they would stay live.
+        int rowb = ldi * 4;
+        asm volatile("" : "+s"(rowb));
+        const __amdgpu_buffer_rsrc_t rc =
+            __builtin_amdgcn_make_buffer_rsrc(cb, (short)0, 0x7fffffff, SPD_BUFFER_RSRC_WORD3);
+        const int voff = Acc32<float>::col(0, lane) * 4 + 4 * (lane >> 5) * rowb;
+        int vj[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            vj[j] = voff + (8 * (j / 4) + j % 4) * rowb;
+        float cv[2][16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            cv[0][j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, vj[j], 0, 0));
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int a = q / 4, b = q % 4;
+            if (q + 1 < 16) {
+                const int a1 = (q + 1) / 4, b1 = (q + 1) % 4;
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    cv[(q + 1) & 1][j] = __builtin_bit_cast(
+                        float, __builtin_amdgcn_raw_buffer_load_b32(rc, vj[j] + 128 * b1, 32 * a1 * rowb, 0));
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, cv[q & 1][j] + acc[a][b][j]), rc,
+                                                      vj[j] + 128 * b, 32 * a * rowb, 0);
+        }
+    }
+}
+
 namespace spd {
+
+void launch_syrk_update_h256(float *H, int64_t ld, const void *Lh, int slot0, int64_t sstride, int skip0, int np,
+                             int half, int64_t r0, int t, int tj_lo, int tj_hi, const unsigned long long *info,
+                             hipStream_t st, int prio, int max_grid)
+{
+    if (t <= 0 || tj_lo >= tj_hi || np <= 0) return;
+    int64_t ntiles = 0;
+    for (int c = tj_lo; c < tj_hi; ++c) ntiles += t - c;
+    int64_t grid = ((ntiles + 7) / 8) * 8;
+    if (max_grid > 0 && grid > max_grid) grid = (max_grid / 8) * 8;
+    if (half == HALF_F16)
+        hipLaunchKernelGGL(k_syrk_update_h256<HALF_F16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh, slot0,
+                           sstride, skip0, np, r0, t, tj_lo, tj_hi, (int)ntiles, info, prio);
+    else
+        hipLaunchKernelGGL(k_syrk_update_h256<HALF_BF16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh, slot0,
+                           sstride, skip0, np, r0, t, tj_lo, tj_hi, (int)ntiles, info, prio);
+}
 
 void launch_syrk_update_half(float *H, int64_t ld, const void *Lh0, int skip0, const void *Lh1, int skip1, int half,
                              int64_t r0, int t, int tj_lo, int tj_hi, const unsigned long long *info, hipStream_t st,

@@ -59,9 +59,11 @@ def iters_close(gpu, orc):
 # (n, cond, m, prec): converging cases in both formats, the BF16 -> FP32
 # fallback at cond 1e3 and the FP16 -> FP32 fallback at cond 1e5 (the outcomes
 # the analysis of Eq. (4) predicts: cond * u_h well below / above 1).
+# Sizes past 2048 take the group trailing update on 256 x 256 tiles (three
+# groups of 1024 columns at n = 3000, ragged last group at 2300).
 CASES = [(1024, 1e1, 1, "bf16"), (1024, 1e1, 1, "fp16"), (700, 1e2, 2, "fp16"), (1024, 1e3, 1, "fp16"),
          (1024, 1e3, 1, "bf16"), (1300, 1e5, 1, "fp16"), (512, 1e5, 3, "bf16"), (257, 1e1, 1, "fp16"),
-         (129, 1e2, 4, "bf16")]
+         (129, 1e2, 4, "bf16"), (3000, 1e2, 2, "fp16"), (2300, 1e1, 1, "bf16"), (3000, 1e3, 1, "fp16")]
 
 
 @pytest.mark.parametrize("n,cond,m,prec", CASES)
@@ -87,7 +89,7 @@ def test_posv_half_matches_oracle(spd, orc, n, cond, m, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
-@pytest.mark.parametrize("n,cond", [(640, 1e1), (1100, 1e2)])
+@pytest.mark.parametrize("n,cond", [(640, 1e1), (1100, 1e2), (3000, 1e2), (4400, 1e1)])
 def test_factor_half_backward_bound(spd, orc, prec, n, cond):
     _say(f"factor {prec} n={n} cond={cond}")
     A = spdgen.logspaced(n, cond, 300 + n)

@@ -253,18 +253,16 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
         if (t <= 0 || lo >= hi) return;
         hipEvent_t pe = prof_begin(s);
         const int64_t rem = npad - r0;
-        if (half && p1 - p0 > 1 && rem % 256 == 0 && lo % 2 == 0) {
+        if (half && p1 - p0 > 1 && rem % 256 == 0 && lo % 2 == 0 && hi % 2 == 0) {
             // a group's trailing update: 256 x 256 tiles, all its panels in one pass
             const int sk0 = (int)((r0 - (p0 + 1) * NB) / SPD_IB_H);
             spd::launch_syrk_update_h256((float *)H, npad, F->Lh, (int)(p0 & 15), lh_slot / 8, sk0, (int)(p1 - p0),
-                                         half, r0, (int)(rem / 256), lo / 2, (hi + 1) / 2, F->info_dev, s, prio, cap);
+                                         half, r0, (int)(rem / 256), lo / 2, hi / 2, F->info_dev, s, prio, cap);
         } else if (half) {
             // copy of panel p starts at row (p + 1) NB
             const int sk0 = (int)((r0 - (p0 + 1) * NB) / SPD_IB_H);
-            const void *l1 = (p1 - p0 > 1) ? lh(p0 + 1) : nullptr;
-            const int sk1 = (p1 - p0 > 1) ? (int)((r0 - (p0 + 2) * NB) / SPD_IB_H) : 0;
-            spd::launch_syrk_update_half((float *)H, npad, lh(p0), sk0, l1, sk1, half, r0, t, lo, hi, F->info_dev, s,
-                                         prio, cap);
+            spd::launch_syrk_update_half((float *)H, npad, F->Lh, (int)(p0 & 15), lh_slot / 8, sk0, (int)(p1 - p0),
+                                         half, r0, t, lo, hi, F->info_dev, s, prio, cap);
         } else {
             spd::launch_syrk_update<T>(H, npad, p0 * NB, (int)((p1 - p0) * NB), r0, t, lo, hi, F->info_dev, s, prio,
                                        cap);
@@ -275,16 +273,18 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
             prof_end(pe, s, SPD_K_UPDATE, fl, by);
         }
     };
-    // the panel chain of group g: factor each panel, solve the rows below it,
-    // and update the group's remaining panels with it
+    // the panel chain of group g, left-looking inside the group: panel k's
+    // columns take the updates of the group's earlier panels in one launch
+    // (K up to (G - 1) NB, one tile column), then its diagonal block is
+    // factored and the rows below it solved
     auto chain = [&](int64_t g, hipStream_t s) {
-        const int64_t p1 = std::min<int64_t>((g + 1) * G, nt);
-        for (int64_t k = g * G; k < p1; ++k) {
+        const int64_t p0 = g * G, p1 = std::min<int64_t>((g + 1) * G, nt);
+        for (int64_t k = p0; k < p1; ++k) {
             const int64_t r = k * NB;
+            if (k > p0) update(p0, k, r, 0, (int)(NB / SPD_TILE_H), s, 1);
             spd::launch_potrf_diag<T>(H + r + r * npad, npad, r, Wi + k * wi_blk, F->info_dev, s);
             spd::launch_trsm_panel<T>(H, npad, r, r + NB, npad - r - NB, Wi + k * wi_blk, F->info_dev, s, lh(k),
                                       half);
-            if (k + 1 < p1) update(k, k + 1, r + NB, 0, (int)((p1 - k - 1) * (NB / SPD_TILE_H)), s, 1);
         }
     };
 

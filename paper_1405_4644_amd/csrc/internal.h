@@ -37,12 +37,13 @@ void launch_trsm_panel(T *H, int64_t ld, int64_t k0, int64_t row0, int64_t nrows
 template <typename T>
 void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,
                         const unsigned long long *info, hipStream_t st, int prio = 0, int max_grid = 0);
-// Trailing update with binary16 / bfloat16 operands from the panel copies
-// Lh0 and (if not NULL) Lh1, K = 128 each, binary32 accumulation into H; in
-// copy p, skip_p 32-row blocks precede row r0.
-void launch_syrk_update_half(float *H, int64_t ld, const void *Lh0, int skip0, const void *Lh1, int skip1, int half,
-                             int64_t r0, int t, int tj_lo, int tj_hi, const unsigned long long *info, hipStream_t st,
-                             int prio = 0, int max_grid = 0);
+// Trailing update with binary16 / bfloat16 operands from np panel copies
+// (K = 128 each) on 128 x 128 tiles, binary32 accumulation into H: panel p's
+// copy in ring slot (slot0 + p) % 16 of Lh (slot stride sstride fragments of
+// 8 halves), with skip0 - 4 p 32-row blocks before row r0.
+void launch_syrk_update_half(float *H, int64_t ld, const void *Lh, int slot0, int64_t sstride, int skip0, int np,
+                             int half, int64_t r0, int t, int tj_lo, int tj_hi, const unsigned long long *info,
+                             hipStream_t st, int prio = 0, int max_grid = 0);
 // The same for a whole group of np <= 16 panels on 256 x 256 tiles (t per
 // side of the region at r0, tile columns [tj_lo, tj_hi)): panel p's copy in
 // ring slot (slot0 + p) % 16 of Lh (slot stride sstride fragments of 8

@@ -313,17 +313,17 @@ __global__ __launch_bounds__(256, 2) void k_syrk_update_f32(float *__restrict__ 
 // ---------------------------------------------------------------------------
 // K4, half-precision operands: H_ij -= round(L_ik) round(L_jk)^T with
 // binary16 or bfloat16 operands and binary32 accumulation
-// (v_mfma_f32_32x32x16_{f16,bf16}), one or two panels of K = 128.  The operand panel is the
-// fragment-layout copy written by the panel solve: row r (relative to the
-// first trailing row), column k lives at
+// (v_mfma_f32_32x32x16_{f16,bf16}) on 128 x 128 tiles, np panels of K = 128
+// each.  The operand panels are the fragment-layout copies written by the
+// panel solve: row r (relative to the first row of the copy), column k at
 //   ((r/32) (NB/16) + k/16) * 512 + (32 ((k%16)/8) + r%32) * 8 + k%8,
-// so every fragment load is one contiguous 1 KiB per wave.  The C tile is the
-// only HBM traffic that scales with the tile count: 64 KiB in, 64 KiB out.
+// so every fragment load is one contiguous 1 KiB per wave.  Panel p of the
+// launch is the copy in ring slot (slot0 + p) % 16 (stride `sstride`
+// fragments), with skip0 - 4 p 32-row blocks before row r0.
 template <int HK>
-__global__ __launch_bounds__(256) void k_syrk_update_h(float *__restrict__ H, int64_t ld,
-                                                       const void *__restrict__ Lh0, int skip0,
-                                                       const void *__restrict__ Lh1, int skip1, int64_t r0, int t,
-                                                       int tj_lo, int tj_hi, int ntiles,
+__global__ __launch_bounds__(256) void k_syrk_update_h(float *__restrict__ H, int64_t ld, const void *__restrict__ Lh,
+                                                       int slot0, int64_t sstride, int skip0, int np, int64_t r0,
+                                                       int t, int tj_lo, int tj_hi, int ntiles,
                                                        const unsigned long long *info, int prio)
 {
     using V8 = typename HalfT<HK>::V8;
@@ -336,6 +336,7 @@ __global__ __launch_bounds__(256) void k_syrk_update_h(float *__restrict__ H, in
     // tiles of XCD x (blocks are dispatched round-robin over the 8 XCDs) are
     // the contiguous range [x chunk, (x + 1) chunk); a grid smaller than the
     // tile count loops (persistent), leaving compute-unit slots free
+    const V8 *base = (const V8 *)Lh;
     const int per = gridDim.x / 8, chunk = (ntiles + 7) / 8;
     for (int it = blockIdx.x / 8; it < chunk; it += per) {
     const int logical = (blockIdx.x % 8) * chunk + it;
@@ -357,13 +358,9 @@ __global__ __launch_bounds__(256) void k_syrk_update_h(float *__restrict__ H, in
                 const int m = Acc32<float>::row(j, lane), nn = Acc32<float>::col(j, lane);
                 acc[mi][ni][j] = H[(crow + 64 * wn + 32 * ni + nn) + (ccol + 64 * wm + 32 * mi + m) * ld];
             }
-    // one or two panels (K = 128 each); `skip` 32-row blocks precede row r0
-    // in a panel's copy
-    for (int pnl = 0; pnl < 2; ++pnl) {
-        const V8 *lh = (const V8 *)(pnl == 0 ? Lh0 : Lh1);
-        if (!lh)
-            break;
-        const int skip = pnl == 0 ? skip0 : skip1;
+    for (int pnl = 0; pnl < np; ++pnl) {
+        const V8 *lh = base + (int64_t)((slot0 + pnl) & 15) * sstride;
+        const int skip = skip0 - 4 * pnl;
         // A operand: rows of tile tj (C columns); B operand: rows of tile ti (C rows)
         const V8 *pa0 = lh + (size_t)(skip + 4 * tj + 2 * wm) * KS * 64 + lane;
         const V8 *pb0 = lh + (size_t)(skip + 4 * ti + 2 * wn) * KS * 64 + lane;
@@ -548,21 +545,21 @@ void launch_syrk_update_h256(float *H, int64_t ld, const void *Lh, int slot0, in
                            sstride, skip0, np, r0, t, tj_lo, tj_hi, (int)ntiles, info, prio);
 }
 
-void launch_syrk_update_half(float *H, int64_t ld, const void *Lh0, int skip0, const void *Lh1, int skip1, int half,
-                             int64_t r0, int t, int tj_lo, int tj_hi, const unsigned long long *info, hipStream_t st,
-                             int prio, int max_grid)
+void launch_syrk_update_half(float *H, int64_t ld, const void *Lh, int slot0, int64_t sstride, int skip0, int np,
+                             int half, int64_t r0, int t, int tj_lo, int tj_hi, const unsigned long long *info,
+                             hipStream_t st, int prio, int max_grid)
 {
-    if (t <= 0 || tj_lo >= tj_hi) return;
+    if (t <= 0 || tj_lo >= tj_hi || np <= 0) return;
     int64_t ntiles = 0;
     for (int c = tj_lo; c < tj_hi; ++c) ntiles += t - c;
     int64_t grid = ((ntiles + 7) / 8) * 8;
     if (max_grid > 0 && grid > max_grid) grid = (max_grid / 8) * 8;
     if (half == HALF_F16)
-        hipLaunchKernelGGL(k_syrk_update_h<HALF_F16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh0, skip0,
-                           Lh1, skip1, r0, t, tj_lo, tj_hi, (int)ntiles, info, prio);
+        hipLaunchKernelGGL(k_syrk_update_h<HALF_F16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh, slot0,
+                           sstride, skip0, np, r0, t, tj_lo, tj_hi, (int)ntiles, info, prio);
     else
-        hipLaunchKernelGGL(k_syrk_update_h<HALF_BF16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh0, skip0,
-                           Lh1, skip1, r0, t, tj_lo, tj_hi, (int)ntiles, info, prio);
+        hipLaunchKernelGGL(k_syrk_update_h<HALF_BF16>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, Lh, slot0,
+                           sstride, skip0, np, r0, t, tj_lo, tj_hi, (int)ntiles, info, prio);
 }
 
 // Below this many 128-tiles a binary32 update runs on 64-tiles (SPD_SMALL_TILES overrides).

@@ -65,11 +65,25 @@ def cpu_baseline_leg(args, A_dev, X_dev, B_dev, rows_check=True):
     X, info = oracle.solve(As, Bs)
     t = time.perf_counter() - t0
     rate = algo_flops(ns, args.nrhs) / t / 1e12
-    log(f"cpu oracle: n={ns} solve {t:.2f} s -> {rate * 1e3:.3f} GFLOP/s on {oracle.threads()} threads")
-    cpu = {"value": rate, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
+    cores = oracle.threads()
+    log(f"cpu oracle: n={ns} solve {t:.2f} s -> {rate * 1e3:.3f} GFLOP/s on {cores} threads")
+    cpu = {"value": rate, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
            "sample": f"oracle binary64 Cholesky + substitution (potrf+potrs) of the leading {ns} x {ns} "
                      f"principal block of the benchmark matrix, {args.nrhs} RHS, {t:.1f} s; "
                      f"rate = F(n,m)/t at that n"}
+    # the same oracle on one core, on a smaller leading block (about 5 s)
+    n1 = min(args.cpu_sample_n_1core, ns)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.solve(np.ascontiguousarray(As[:n1, :n1]), Bs[:, :n1])
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    rate1 = algo_flops(n1, args.nrhs) / t1 / 1e12
+    log(f"cpu oracle, 1 core: n={n1} solve {t1:.2f} s -> {rate1 * 1e3:.3f} GFLOP/s")
+    cpu["one_core"] = {"value": rate1, "unit": "TFLOP/s", "cores": 1,
+                       "sample": f"the leading {n1} x {n1} block, {t1:.1f} s"}
     if not rows_check:
         return cpu, None
     # oracle check of the GPU result on sampled rows
@@ -179,7 +193,84 @@ def measured_traffic(prec):
         sha = hashlib.sha256(f.read()).hexdigest()
     if rec.get("source_sha256") != sha:
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return rec.get("traffic_bytes_per_launch"), rec.get("input")
+
+
+def kernel_summary(spd, prec):
+    """Live per-class kernel figures from the library's HIP events (stream of
+    each launch) over the evented steps: launches, average duration, and the
+    fraction of the MFMA peak (contractions) or of HBM (the rest) that their
+    algorithmic flops / bytes reach."""
+    peak = PEAK_TFLOPS[prec]
+    out = {}
+    for name, k, bound in (("trailing_update", spd.K_UPDATE, "mfma"), ("chain_update", spd.K_CHAIN_UPDATE, "mfma"),
+                           ("residual", spd.K_RESIDUAL, "hbm"), ("triangular_solves", spd.K_TRSV, "hbm"),
+                           ("convert", spd.K_CONVERT, "hbm")):
+        launches, ms, fl, by = spd.profile_query(k)
+        if not launches or ms <= 0:
+            continue
+        d = {"launches": launches, "avg_ms": ms / launches, "total_ms": ms}
+        if bound == "mfma":
+            d.update(bound="mfma", tflops=fl / ms / 1e9, peak_tflops=peak, frac=fl / ms / 1e9 / peak)
+        else:
+            d.update(bound="hbm", gbs=by / ms / 1e6, peak_gbs=HBM_PEAK_GBS, frac=by / ms / 1e6 / HBM_PEAK_GBS)
+        out[name] = d
+    return out
+
+
+def external_fp64_leg(args, torch, A, B, Xt):
+    """A library binary64 Cholesky for context (torch.linalg.cholesky +
+    cholesky_solve, i.e. the ROCm solver library): not this project's code."""
+    ts = []
+    X = None
+    for i in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        L = torch.linalg.cholesky(A)
+        X = torch.cholesky_solve(B.T, L).T
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            ts.append(time.perf_counter() - t)
+        del L
+    dt = float(np.median(ts))
+    fwd = float((X - Xt).abs().max() / Xt.abs().max())
+    log(f"external fp64 (torch.linalg.cholesky + cholesky_solve): {dt * 1e3:.2f} ms/solve")
+    return {"ms_per_step": dt * 1e3, "value": algo_flops(A.shape[0], B.shape[0]) / dt / 1e12,
+            "fwd_err": fwd, "kind": "library binary64 Cholesky (torch.linalg.cholesky + torch.cholesky_solve "
+                                    "on ROCm), context only"}
+
+
+def energy_leg(args, spd, torch, systems, window):
+    """Energy to solution per solve from the GPU's energy accumulator (the
+    power-trace method: each configuration repeated for `window` seconds,
+    steady-state power from the accumulator's publications), with the idle
+    draw measured the same way.  systems: [(label, prec, A, B, flops)]."""
+    from paper_1405_4644_amd.power_trace import PowerMonitor
+    mon = PowerMonitor(0.002)
+    mon.start()
+    try:
+        mon.phase("idle", lambda: time.sleep(0.05), window)
+        for label, prec, A, B, fl in systems:
+            F = spd.Factor()
+            X = torch.empty_like(B)
+            spd.posv(A, B, prec=prec, F=F, X=X)
+            mon.phase(label, lambda: spd.posv(A, B, prec=prec, F=F, X=X), window)
+            F.close()
+    finally:
+        mon.stop()
+    rep = {p["phase"]: p for p in mon.report()}
+    idle = rep["idle"]["avg_watts"]
+    out = {"idle_watts": idle, "window_s": window, "method": "GPU socket energy accumulator (amdsmi), "
+           "steady state over repeated solves; GPU board only, host not included"}
+    for label, prec, A, B, fl in systems:
+        p = rep[label]
+        j = p["joules"]
+        out[label] = {"prec": prec, "ms_per_solve": p["seconds"] * 1e3, "avg_watts": p["avg_watts"],
+                      "joules_per_solve": j,
+                      "joules_above_idle": (j - idle * p["seconds"]) if (j is not None and idle) else None,
+                      "tflops_per_watt": (fl / p["seconds"] / 1e12 / p["avg_watts"]) if p["avg_watts"] else None}
+        log(f"energy {label}: {p['avg_watts']:.0f} W, {j:.2f} J/solve" if j else f"energy {label}: n/a")
+    return out
 
 
 def batched_leg(args, spd, spdgen, torch):
@@ -266,6 +357,12 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the binary64 baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=8192)
+    ap.add_argument("--cpu-sample-n-1core", type=int, default=3072)
+    ap.add_argument("--no-half", action="store_true", help="skip the binary16 leg (cond 1e2 system)")
+    ap.add_argument("--half-cond", type=float, default=1e2)
+    ap.add_argument("--no-energy", action="store_true", help="skip energy per solve")
+    ap.add_argument("--energy-window", type=float, default=2.5)
+    ap.add_argument("--no-external", action="store_true", help="skip the library binary64 Cholesky")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-small-systems leg")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--loop-sample", type=int, default=512)
@@ -354,6 +451,7 @@ def main():
     dt_prof, _, _ = run(args.prec, args.steps, 1, True)
     upd = spd.profile_query(spd.K_UPDATE)
     res = spd.profile_query(spd.K_RESIDUAL)
+    kernels = kernel_summary(spd, args.prec)
     log(f"{args.prec}: {dt * 1e3:.2f} ms/solve ({dt_prof * 1e3:.2f} with kernel events), iters "
         f"{rep.iters_low}/{rep.iters_high}, eta {rep.eta:.2e}, status {rep.status}, update kernel {upd[0]} "
         f"launches {upd[1]:.2f} ms")
@@ -369,6 +467,48 @@ def main():
                 "status": rep64.status}
         log(f"fp64: {dt64 * 1e3:.2f} ms/solve, eta {rep64.eta:.2e}")
 
+    external = None if (args.no_external or cov) else external_fp64_leg(args, torch, A, B, Xt)
+
+    # the binary16 factor on a system of the same recipe at cond 1e2, where
+    # cond u16 << 1 (configuration: the half-precision path at this size)
+    half = None
+    A16 = B16 = None
+    if not args.no_half and not cov and args.prec == "fp32":
+        A16 = spdgen.logspaced(n, args.half_cond, sg + 2, backend="torch", device="cuda")
+        X16t = spdgen.rhs(n, m, sx + 2, backend="torch", device="cuda")
+        B16 = spdgen.accurate_product(A16, X16t)
+        Asave, Bsave = A, B
+        A, B = A16, B16
+        dt16, rep16, X16 = run("fp16", args.steps, args.warmup, False)
+        dt16p, _, _ = run("fp16", args.steps, 1, True)
+        k16 = kernel_summary(spd, "fp16")
+        dt16_64, rep16_64, _ = run("fp64", args.steps, max(1, args.warmup), False) if not args.no_fp64 else (None, None, None)
+        A, B = Asave, Bsave
+        fwd16 = float((X16 - X16t).abs().max() / X16t.abs().max())
+        half = {"workload": f"dense SPD, n={n}, cond={args.half_cond:g} (same recipe), {m} RHS, fp16 factor "
+                            f"(equilibrated, mu = 4096) + binary64 refinement",
+                "ms_per_step": dt16 * 1e3, "value": algo_flops(n, m) / dt16 / 1e12,
+                "timed_with_events_ms_per_step": dt16p * 1e3,
+                "accuracy": {"status": rep16.status, "prec_used": spd.PREC_NAME[rep16.prec_used],
+                             "iters": [rep16.iters_low, rep16.iters_high], "eta": rep16.eta, "fwd_err_vs_xtrue": fwd16,
+                             "fwd_bound_10cond_u": 10 * args.half_cond * 2.0 ** -53},
+                "fp64_same_system_ms": dt16_64 * 1e3 if dt16_64 else None,
+                "speedup_vs_fp64": (dt16_64 / dt16) if dt16_64 else None,
+                "kernels": k16}
+        log(f"fp16 (cond {args.half_cond:g}): {dt16 * 1e3:.2f} ms/solve, iters {rep16.iters_low}/{rep16.iters_high}, "
+            f"fp64 {dt16_64 * 1e3 if dt16_64 else float('nan'):.2f} ms")
+
+    energy = None
+    if not args.no_energy and not cov and args.prec == "fp32":
+        try:
+            systems = [("fp32+IR", "fp32", A, B, algo_flops(n, m)), ("fp64", "fp64", A, B, algo_flops(n, m))]
+            if A16 is not None:
+                systems.insert(1, (f"fp16+IR cond {args.half_cond:g}", "fp16", A16, B16, algo_flops(n, m)))
+            energy = energy_leg(args, spd, torch, systems, args.energy_window)
+        except Exception as e:  # no power telemetry on this host
+            energy = {"error": f"{type(e).__name__}: {e}"}
+    del A16, B16
+
     batched = None if args.no_batched else batched_leg(args, spd, spdgen, torch)
 
     cpu = None
@@ -378,6 +518,9 @@ def main():
 
     launches, ms, fl, by = upd
     traffic = None if cov or n != 16384 else measured_traffic(args.prec)
+    traffic_input = None
+    if traffic is not None:
+        traffic, traffic_input = traffic
     achieved = fl / ms / 1e9 if ms > 0 else 0.0  # TFLOP/s
     peak = PEAK_TFLOPS[args.prec]
     out = {
@@ -402,19 +545,25 @@ def main():
                                 f"{args.prec} factor + binary64 refinement",
                     "n": n, "nrhs": m, "decay": args.decay, "cond_bound": cond, "prec": args.prec}),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "k_syrk_update_f32 (128- and 64-row tiles)" if args.prec == "fp32" else (
-                         "k_syrk_update_h (binary16/bfloat16 operands)" if args.prec in ("fp16", "bf16")
-                         else "k_syrk_update<double>"),
+                     "frac": achieved / peak, "traffic": traffic, "traffic_input": traffic_input,
+                     "kernel": ("k_syrk_update_f32 (a group's trailing update, 128- or 64-row tiles)"
+                                if args.prec == "fp32" else (
+                                    "k_syrk_update_h256 / k_syrk_update_h (a group's trailing update, "
+                                    "binary16/bfloat16 operands)" if args.prec in ("fp16", "bf16")
+                                    else "k_syrk_update<double>")),
                      "launches": launches, "avg_launch_ms": ms / max(launches, 1),
                      "timed_with_events_ms_per_step": dt_prof * 1e3,
                      "flops_per_launch": fl / max(launches, 1),
                      "algorithmic_bytes_per_launch": by / max(launches, 1)},
+        "kernels": kernels,
         "cpu_baseline": cpu,
         "accuracy": {"status": rep.status, "iters": [rep.iters_low, rep.iters_high], "eta": rep.eta,
                      "fwd_err_vs_xtrue": fwd, "fwd_bound_10cond_u": fwd_bound, "oracle_rows": ocheck},
         "fp64_baseline": fp64,
         "speedup_vs_fp64": (fp64["ms_per_step"] / (dt * 1e3)) if fp64 else None,
+        "external_fp64_reference": external,
+        "fp16_leg": half,
+        "energy": energy,
         "batched": batched,
         "residual_kernel": {"launches": res[0], "avg_ms": res[1] / max(res[0], 1),
                             "achieved_GBs": (res[3] / res[1] / 1e6) if res[1] > 0 else None,

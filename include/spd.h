@@ -361,10 +361,19 @@ void spd_cg_destroy(spd_cg_t H);
  *                  banded; bytes = A~ once (4 n^2, or 4 (2k + 1) n) plus
  *                  the binary32 and binary64 directions read and z written,
  *                  20 n m)
+ *   SPD_K_UPDATE is a group's trailing update (the factorisation's bulk);
+ *   SPD_K_CHAIN_UPDATE the panel chain's update of one panel's columns by the
+ *                  group's earlier panels (same flop/byte accounting)
+ *   SPD_K_TRSV     one pair of triangular solves L L^T (both directions;
+ *                  flops 2 n^2 m, bytes = the factor's lower triangle read
+ *                  once per direction plus the vectors)
+ *   SPD_K_CONVERT  equilibrate/convert A -> H (bytes = A's lower triangle read
+ *                  in binary64 and H's written in the factor type)
  * spd_profile_query synchronises on the recorded events, folds them into the
  * totals and returns launches, summed milliseconds, flops and bytes.  Not
  * thread-safe against concurrent factorisations; meant for benchmarks. */
-enum { SPD_K_UPDATE = 0, SPD_K_RESIDUAL = 1, SPD_K_CG_MV = 2, SPD_K_COUNT = 3 };
+enum { SPD_K_UPDATE = 0, SPD_K_RESIDUAL = 1, SPD_K_CG_MV = 2, SPD_K_CHAIN_UPDATE = 3, SPD_K_TRSV = 4,
+       SPD_K_CONVERT = 5, SPD_K_COUNT = 6 };
 void spd_profile_enable(int on);
 void spd_profile_reset(void);
 spd_status spd_profile_query(int kernel, int64_t *launches, double *total_ms, double *total_flops,

@@ -95,6 +95,8 @@ def lib():
         L.oracle_cg_ir.restype = i32
         L.oracle_ir.restype = i32
         L.oracle_threads.restype = i32
+        L.oracle_set_threads.argtypes = [i32]
+        L.oracle_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -289,3 +291,8 @@ def cg_ir(A, Bt, X0t=None, half_band=-1, tol=1e-14, inner_tol=1e-6, max_outer=30
 
 def threads() -> int:
     return int(lib().oracle_threads())
+
+
+def set_threads(k: int) -> None:
+    """Threads of the oracle's parallel loops from now on (OpenMP)."""
+    lib().oracle_set_threads(int(k))

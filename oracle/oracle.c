@@ -806,6 +806,9 @@ int32_t oracle_cg_ir(int64_t n, int64_t m, const double *A, int64_t lda, int64_t
 #ifdef _OPENMP
 #include <omp.h>
 int32_t oracle_threads(void) { return omp_get_max_threads(); }
+/* threads of the parallel loops from now on (timing with one core) */
+void oracle_set_threads(int32_t k) { omp_set_num_threads(k > 0 ? k : 1); }
 #else
 int32_t oracle_threads(void) { return 1; }
+void oracle_set_threads(int32_t k) { (void)k; }
 #endif

@@ -359,7 +359,7 @@ def export(F: Factor):
     return Lt.T, d, mu.value
 
 
-K_UPDATE, K_RESIDUAL, K_CG_MV = 0, 1, 2
+K_UPDATE, K_RESIDUAL, K_CG_MV, K_CHAIN_UPDATE, K_TRSV, K_CONVERT = 0, 1, 2, 3, 4, 5
 
 
 def profile_enable(on: bool = True):

@@ -247,7 +247,7 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
     // region starting at row/column r0
     // the main stream's updates use at most F->upd_slots workgroups (looping
     // over tiles), so that the panel chain always finds free slots
-    auto update = [&](int64_t p0, int64_t p1, int64_t r0, int lo, int hi, hipStream_t s, int prio) {
+    auto update = [&](int64_t p0, int64_t p1, int64_t r0, int lo, int hi, hipStream_t s, int prio, int kind) {
         const int cap = (s == st) ? F->upd_slots : 0;
         const int t = (int)((npad - r0) / SPD_TILE_H);
         if (t <= 0 || lo >= hi) return;
@@ -270,7 +270,7 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
         if (pe) {
             double fl, by;
             update_work(t, lo, hi, (int)((p1 - p0) * NB), (int)sizeof(T), op_elem, &fl, &by);
-            prof_end(pe, s, SPD_K_UPDATE, fl, by);
+            prof_end(pe, s, kind, fl, by);
         }
     };
     // the panel chain of group g, left-looking inside the group: panel k's
@@ -281,7 +281,7 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
         const int64_t p0 = g * G, p1 = std::min<int64_t>((g + 1) * G, nt);
         for (int64_t k = p0; k < p1; ++k) {
             const int64_t r = k * NB;
-            if (k > p0) update(p0, k, r, 0, (int)(NB / SPD_TILE_H), s, 1);
+            if (k > p0) update(p0, k, r, 0, (int)(NB / SPD_TILE_H), s, 1, SPD_K_CHAIN_UPDATE);
             spd::launch_potrf_diag<T>(H + r + r * npad, npad, r, Wi + k * wi_blk, F->info_dev, s);
             spd::launch_trsm_panel<T>(H, npad, r, r + NB, npad - r - NB, Wi + k * wi_blk, F->info_dev, s, lh(k),
                                       half);
@@ -301,12 +301,12 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
             int next = (int)((std::min<int64_t>(p1 + G, nt) - p1) * (NB / SPD_TILE_H));
             if (half) next = std::min(t, (next + 1) & ~1);  // whole 256-tile columns on both sides of the split
             HIP_TRY(hipStreamWaitEvent(st, evP, 0));
-            update(p0, p1, r0, 0, next, st, 1);
+            update(p0, p1, r0, 0, next, st, 1, SPD_K_UPDATE);
             HIP_TRY(hipEventRecord(evU, st));
             HIP_TRY(hipStreamWaitEvent(F->side, evU, 0));
             chain(g + 1, F->side);
             HIP_TRY(hipEventRecord(evP, F->side));
-            update(p0, p1, r0, next, t, st, 0);
+            update(p0, p1, r0, next, t, st, 0, SPD_K_UPDATE);
         }
         HIP_TRY(hipStreamWaitEvent(st, evP, 0));
     }
@@ -385,13 +385,17 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
     *F->info_host = SPD_INFO_NONE_H;
     HIP_TRY(hipMemcpyAsync(F->info_dev, F->info_host, sizeof(unsigned long long), hipMemcpyHostToDevice, st));
     if (n > 0) spd::launch_equil(A, lda, n, F->d, equil, st);
-    if (prec == SPD_FP64) {
+    const double tri = (double)n * (n + 1) / 2;
+    hipEvent_t pe = prof_begin(st);
+    if (prec == SPD_FP64)
         spd::launch_convert<double>(A, lda, n, npad, F->d, 1.0, (double *)F->L, npad, st);
-        SPD_TRY(factor_blocked<double>(F, st));
-    } else {
+    else
         spd::launch_convert<float>(A, lda, n, npad, F->d, F->mu, (float *)F->L, npad, st);
+    if (pe) prof_end(pe, st, SPD_K_CONVERT, tri, tri * (8.0 + F->elem));
+    if (prec == SPD_FP64)
+        SPD_TRY(factor_blocked<double>(F, st));
+    else
         SPD_TRY(factor_blocked<float>(F, st));
-    }
     HIP_TRY(hipMemcpyAsync(F->info_host, F->info_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const unsigned long long v = *F->info_host;
@@ -484,8 +488,12 @@ void solve_apply(spd_factor_t F, const double *R, int64_t ldr, int64_t m, const 
     T *Y = (T *)F->Y;
     T *Z = (T *)((char *)F->Y + npad * m * sizeof(T));
     spd::launch_rhs_scale<T>(R, ldr, F->n, npad, (int)m, F->d, smax, Y, npad, st);
+    hipEvent_t pe = prof_begin(st);
     spd::launch_trsv<T>((const T *)F->L, npad, (const T *)F->WB, npad, (int)m, Y, Z, npad, (T *)F->tP, F->tctl,
                         F->terr, F->wait_ticks, st);
+    if (pe)
+        prof_end(pe, st, SPD_K_TRSV, 2.0 * (double)npad * npad * m,
+                 (double)sizeof(T) * ((double)npad * (npad + 1) + 4.0 * npad * m));
     spd::launch_update_x<T>(X, ldx, F->n, (int)m, Y, npad, F->d, F->mu, smax, accumulate, zmax, st);
 }
 

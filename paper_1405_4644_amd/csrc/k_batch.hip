@@ -14,6 +14,8 @@
 // host, so it can be captured in a graph.
 #include <spd.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "internal.h"
 
@@ -67,7 +69,7 @@ SPD_DEV BatchWs batch_ws(const BatchArgs &a)
 SPD_DEV double b_nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
 // shared state of the workgroup
-struct BatchSmem {
+struct SolveSmem {
     double ys[SPD_BATCH_MAXRHS * SPD_BATCH_NMAX];  // solve vectors (factor type)
     double Lk[BNB * (BNB + 1)];                    // inverse of the diagonal block
     double ts[SPD_BATCH_MAXRHS * BNB];
@@ -76,12 +78,15 @@ struct BatchSmem {
     double smax[SPD_BATCH_MAXRHS];
     unsigned long long zmax[SPD_BATCH_MAXRHS];  // max |z| per column of the last solve (binary64 bits)
     double arow[SPD_BATCH_NMAX];  // row sums of |A|
-    double csum[SPD_BATCH_MAXRHS * SPD_BATCH_NMAX];  // residual: column-pass sums
+    int info;
+};
+// the picker's features need more (the solving kernels do without it)
+struct BatchSmem : SolveSmem {
+    double csum[SPD_BATCH_MAXRHS * SPD_BATCH_NMAX];
     double cabs[SPD_BATCH_NMAX];
     float feat[PICK_NFEAT];
     float hid[2][PICK_NH];
     float logit[PICK_NCLS];
-    int info;
 };
 
 template <typename T>
@@ -192,7 +197,7 @@ __device__ __attribute__((noinline)) int b_diag(T *L, int np, int k0, T *Ws, T *
 // the 32 x 32 diagonal blocks.  With half != HALF_NONE the trailing-update
 // operands are rounded to that format (binary32 accumulation).
 template <typename T, int WAVES>
-SPD_DEV int b_factor(T *L, int np, T *Winv, int half, BatchSmem &sm)
+SPD_DEV int b_factor(T *L, int np, T *Winv, int half, SolveSmem &sm)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nb = np / BNB;
@@ -266,7 +271,7 @@ SPD_DEV int b_factor(T *L, int np, T *Winv, int half, BatchSmem &sm)
 // load-to-use dependency).
 template <typename T, int WAVES>
 SPD_DEV void b_solve(const T *L, const T *Winv, int n, int np, int m, const double *R, const double *d, double mu,
-                     double *X, int accumulate, BatchSmem &sm)
+                     double *X, int accumulate, SolveSmem &sm)
 {
     constexpr int NT = WAVES * 64, MR = SPD_BATCH_MAXRHS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -391,7 +396,7 @@ SPD_DEV void b_solve(const T *L, const T *Winv, int n, int np, int m, const doub
 // from the cache); r = b - (row + col).
 template <int WAVES>
 SPD_DEV void b_residual(const double *A, int n, int m, const double *X, const double *B, const double *d, double *R,
-                        int want_anorm, BatchSmem &sm)
+                        int want_anorm, SolveSmem &sm)
 {
     constexpr int NT = WAVES * 64, NM = SPD_BATCH_NMAX;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -481,24 +486,18 @@ SPD_DEV void b_residual(const double *A, int n, int m, const double *X, const do
 #pragma unroll
             for (int u = 0; u < CH; ++u) a[u] = an[u];
         }
+        // r_j = b_j - (row sum + column sum): row j's entry is this lane's alone
         if (j < n) {
 #pragma unroll
             for (int c = 0; c < MR; ++c)
-                if (c < m)
-                    sm.csum[c * NM + j] = acc[c];
+                if (c < m) {
+                    const double y = R[j + (int64_t)c * n] + acc[c];
+                    R[j + (int64_t)c * n] = B[j + (int64_t)c * n] - y;
+                }
             if (want_anorm)
-                sm.cabs[j] = aa;
+                abs_rows[j] += aa;
         }
     }
-    __syncthreads();
-    // r = b - (row + column sums)
-    for (int idx = tid; idx < m * n; idx += NT) {
-        const int c = idx / n, i = idx % n;
-        const double y = R[i + (int64_t)c * n] + sm.csum[c * NM + i];
-        R[i + (int64_t)c * n] = B[i + (int64_t)c * n] - y;
-    }
-    if (want_anorm)
-        for (int i = tid; i < n; i += NT) abs_rows[i] += sm.cabs[i];
     __syncthreads();
     // maxima (NaN propagates), per column, then ||A||_inf
     double v[4 * MR + 1];
@@ -840,7 +839,6 @@ SPD_DEV int b_pick(const float *P, BatchSmem &sm)
     return best;
 }
 
-SPD_DEV int b_next_prec(int p) { return (p == SPD_BF16 || p == SPD_FP16) ? SPD_FP32 : SPD_FP64; }
 
 // Refinement at the precision of the current factor (T), from the iterate in
 // X (the first solve); the single-system path's stopping rule: a column is
@@ -854,7 +852,7 @@ SPD_DEV int b_next_prec(int p) { return (p == SPD_BF16 || p == SPD_FP16) ? SPD_F
 // and fills the iteration counts and eta.
 template <typename T, int WAVES>
 SPD_DEV int b_refine(const BatchArgs &a, const double *A, const double *B, double *X, int n, int np, int m,
-                     const BatchWs &w, double mu, spd_report &rep, BatchSmem &sm)
+                     const BatchWs &w, double mu, spd_report &rep, SolveSmem &sm)
 {
     constexpr double U = 0x1p-53, FLOOR = 0x1p-51;
     constexpr bool STABLE = sizeof(T) == 8;
@@ -944,54 +942,87 @@ SPD_DEV int b_refine(const BatchArgs &a, const double *A, const double *B, doubl
     }
 }
 
-// Factor at precision p (with the fallback chain on breakdown when enabled);
-// returns the 1-based failing column of the last attempt (0 = success).
+// smax[c] = max_i |d_i B[i][c]| (the first solve's scaling)
 template <int WAVES>
-SPD_DEV int b_factor_at(const BatchArgs &a, const double *A, int n, int np, const BatchWs &w, int &p,
-                        int &fallbacks, double &mu, BatchSmem &sm)
+SPD_DEV void b_rhs_max(const double *B, const double *d, int n, int m, SolveSmem &sm)
 {
-    for (;;) {
-        int info;
-        if (p == SPD_FP64) {
-            mu = 1.0;
-            b_convert<double>(A, n, np, w.d, 1.0, 0, (double *)w.L, WAVES * 64);
-            info = b_factor<double, WAVES>((double *)w.L, np, (double *)w.Winv, HALF_NONE, sm);
-        } else {
-            mu = (p == SPD_FP16) ? a.mu16 : 1.0;
-            b_convert<float>(A, n, np, w.d, mu, a.equilibrate, (float *)w.L, WAVES * 64);
-            const int half = (p == SPD_FP16) ? HALF_F16 : (p == SPD_BF16) ? HALF_BF16 : HALF_NONE;
-            info = b_factor<float, WAVES>((float *)w.L, np, (float *)w.Winv, half, sm);
-        }
-        if (info && a.fallback && p != SPD_FP64) {
-            ++fallbacks;
-            p = b_next_prec(p);
-            continue;
-        }
-        return info;
+    double v[SPD_BATCH_MAXRHS];
+#pragma unroll
+    for (int c = 0; c < SPD_BATCH_MAXRHS; ++c) v[c] = 0.0;
+    for (int i = threadIdx.x; i < n; i += WAVES * 64)
+#pragma unroll
+        for (int c = 0; c < SPD_BATCH_MAXRHS; ++c)
+            if (c < m)
+                v[c] = b_nanmax(v[c], fabs(d[i] * B[i + (int64_t)c * n]));
+#pragma unroll
+    for (int c = 0; c < SPD_BATCH_MAXRHS; ++c) {
+        for (int off = 32; off > 0; off >>= 1) v[c] = b_nanmax(v[c], __shfl_xor(v[c], off));
+        if ((threadIdx.x & 63) == 0)
+            sm.red[threadIdx.x >> 6][c] = v[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < m) {
+        double x = 0.0;
+        for (int q = 0; q < WAVES; ++q) x = b_nanmax(x, sm.red[q][threadIdx.x]);
+        sm.smax[threadIdx.x] = x;
+    }
+    __syncthreads();
+}
+
+// Factor in the factor type T at precision p (binary32 factor for BF16, FP16,
+// FP32: equilibrated, mu for FP16, rounded update operands for the half
+// formats; binary64 factor of A itself for FP64).  Returns the 1-based
+// failing column (0 on success).
+template <typename T, int WAVES>
+SPD_DEV int b_factor_p(const BatchArgs &a, const double *A, int n, int np, const BatchWs &w, int p, double &mu,
+                       SolveSmem &sm)
+{
+    if constexpr (sizeof(T) == 8) {
+        mu = 1.0;
+        b_convert<double>(A, n, np, w.d, 1.0, 0, (double *)w.L, WAVES * 64);
+        return b_factor<double, WAVES>((double *)w.L, np, (double *)w.Winv, HALF_NONE, sm);
+    } else {
+        mu = (p == SPD_FP16) ? a.mu16 : 1.0;
+        b_convert<float>(A, n, np, w.d, mu, a.equilibrate, (float *)w.L, WAVES * 64);
+        const int half = (p == SPD_FP16) ? HALF_F16 : (p == SPD_BF16) ? HALF_BF16 : HALF_NONE;
+        return b_factor<float, WAVES>((float *)w.L, np, (float *)w.Winv, half, sm);
     }
 }
 
-template <int WAVES>
-SPD_DEV void b_system(const BatchArgs &a, int64_t s, BatchSmem &sm)
+// One system through Algorithm 1 by one workgroup, at the precisions of the
+// kernel's factor type: HI = false takes BF16, FP16 and FP32 requests (and
+// the half -> binary32 fallback), HI = true the FP64 requests and every
+// system the low-precision kernel handed over (a binary32 breakdown or
+// non-convergence with fallback on: prec[s] = FP64, reps[s].fallbacks the
+// count so far).  Systems of the other kernel are skipped; the
+// low-precision kernel also reports invalid sizes.  ticks[s] (zeroed by the
+// order kernel) accumulates every kernel's time on the system.
+template <int WAVES, bool HI>
+SPD_DEV void b_system(const BatchArgs &a, int64_t s, SolveSmem &sm)
 {
+    using T = typename std::conditional<HI, double, float>::type;
     const int n = a.n[s], m = a.nrhs[s];
+    int p = a.prec[s];
+    if (p == SPD_AUTO)
+        p = SPD_FP32;
+    const bool valid = n >= 0 && m >= 0 && n <= SPD_BATCH_NMAX && m <= SPD_BATCH_MAXRHS && p >= SPD_BF16 &&
+                       p <= SPD_FP64;
+    if (HI ? (!valid || p != SPD_FP64) : (valid && p == SPD_FP64)) {
+        // the other kernel's system; the low-precision kernel starts its count
+        if (!HI && threadIdx.x == 0)
+            a.reps[s].fallbacks = 0;
+        return;
+    }
+    const unsigned long long t0 = wall_clock64();
     spd_report rep;
     rep.status = SPD_OK;
-    rep.prec_used = a.prec[s];
-    rep.iters_low = rep.iters_high = rep.fallbacks = 0;
+    rep.prec_used = p;
+    rep.iters_low = rep.iters_high = 0;
+    rep.fallbacks = HI ? a.reps[s].fallbacks : 0;
     rep.info = 0;
     rep.eta = 0.0;
-    const unsigned long long t0 = wall_clock64();
-    int p = a.prec[s];
-    const bool sizes_ok = n >= 0 && m >= 0 && n <= SPD_BATCH_NMAX && m <= SPD_BATCH_MAXRHS;
-    if (p == SPD_AUTO) {
-        p = SPD_FP32;
-        if (a.picker && sizes_ok && n > 0 && m > 0) {
-            b_features<WAVES>(a.A + a.a_off[s], n, m, sm);
-            p = b_pick(a.picker, sm);
-        }
-    }
-    if (!sizes_ok || p < SPD_BF16 || p > SPD_FP64) {
+    bool handover = false;
+    if (!valid) {
         rep.status = SPD_ERR_INVALID_ARG;
     } else if (n > 0 && m > 0) {
         const double *A = a.A + a.a_off[s];
@@ -1000,83 +1031,92 @@ SPD_DEV void b_system(const BatchArgs &a, int64_t s, BatchSmem &sm)
         const int np = ((n + BNB - 1) / BNB) * BNB;
         const BatchWs w = batch_ws(a);
         double mu = 1.0;
-        int info = b_factor_at<WAVES>(a, A, n, np, w, p, rep.fallbacks, mu, sm);
-        rep.info = info;
-        rep.prec_used = p;
-        int status = info ? SPD_ERR_NOT_SPD : SPD_OK;
-        // first solve from B (smax = max |d b|), then refinement with fallback
-        bool need_solve = (status == SPD_OK);
-        while (status == SPD_OK && need_solve) {
-            // smax from B
-            double v[SPD_BATCH_MAXRHS];
-#pragma unroll
-            for (int c = 0; c < SPD_BATCH_MAXRHS; ++c) v[c] = 0.0;
-            for (int i = threadIdx.x; i < n; i += WAVES * 64)
-#pragma unroll
-                for (int c = 0; c < SPD_BATCH_MAXRHS; ++c)
-                    if (c < m)
-                        v[c] = b_nanmax(v[c], fabs(w.d[i] * B[i + (int64_t)c * n]));
-#pragma unroll
-            for (int c = 0; c < SPD_BATCH_MAXRHS; ++c) {
-                for (int off = 32; off > 0; off >>= 1) v[c] = b_nanmax(v[c], __shfl_xor(v[c], off));
-                if ((threadIdx.x & 63) == 0)
-                    sm.red[threadIdx.x >> 6][c] = v[c];
-            }
-            __syncthreads();
-            if (threadIdx.x < m) {
-                double x = 0.0;
-                for (int q = 0; q < WAVES; ++q) x = b_nanmax(x, sm.red[q][threadIdx.x]);
-                sm.smax[threadIdx.x] = x;
-            }
-            __syncthreads();
+        int status = SPD_OK;
+        for (;;) {
+            const int info = b_factor_p<T, WAVES>(a, A, n, np, w, p, mu, sm);
+            rep.info = info;
+            rep.prec_used = p;
             int r;
-            if (p == SPD_FP64) {
-                b_solve<double, WAVES>((const double *)w.L, (const double *)w.Winv, n, np, m, B, w.d, mu, X, 0,
-                                       sm);
-                r = b_refine<double, WAVES>(a, A, B, X, n, np, m, w, mu, rep, sm);
+            if (info) {
+                r = SPD_ERR_NOT_SPD;
             } else {
-                b_solve<float, WAVES>((const float *)w.L, (const float *)w.Winv, n, np, m, B, w.d, mu, X, 0, sm);
-                r = b_refine<float, WAVES>(a, A, B, X, n, np, m, w, mu, rep, sm);
+                // first solve from B, then refinement
+                b_rhs_max<WAVES>(B, w.d, n, m, sm);
+                b_solve<T, WAVES>((const T *)w.L, (const T *)w.Winv, n, np, m, B, w.d, mu, X, 0, sm);
+                r = b_refine<T, WAVES>(a, A, B, X, n, np, m, w, mu, rep, sm);
             }
-            need_solve = false;
-            if (r == SPD_ERR_NO_CONVERGENCE && a.fallback && p != SPD_FP64) {
-                rep.fallbacks++;
-                p = b_next_prec(p);
-                info = b_factor_at<WAVES>(a, A, n, np, w, p, rep.fallbacks, mu, sm);
-                rep.info = info;
-                rep.prec_used = p;
-                if (info)
-                    status = SPD_ERR_NOT_SPD;
-                else
-                    need_solve = true;
-            } else {
+            if (r == SPD_OK || !a.fallback || HI) {
                 status = r;
+                break;
             }
+            // fallback: a half format retries in binary32 here; binary32 goes
+            // to the binary64 kernel
+            rep.fallbacks++;
+            if (p == SPD_FP32) {
+                handover = true;
+                status = r;
+                break;
+            }
+            p = SPD_FP32;
         }
         rep.status = status;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        a.reps[s] = rep;
-        a.prec[s] = rep.prec_used;
+        if (handover) {
+            a.reps[s].fallbacks = rep.fallbacks;
+            a.prec[s] = SPD_FP64;
+        } else {
+            a.reps[s] = rep;
+            a.prec[s] = rep.prec_used;
+        }
         if (a.ticks)
-            a.ticks[s] = (int64_t)(wall_clock64() - t0);
+            a.ticks[s] += (int64_t)(wall_clock64() - t0);
     }
 }
 
-template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_batch(BatchArgs a)
+// The precision picker for SPD_AUTO systems: features and perceptron by one
+// workgroup per system; prec[s] becomes the chosen class.
+__global__ __launch_bounds__(256) void k_batch_pick(BatchArgs a)
 {
     __shared__ BatchSmem sm;
     __shared__ int s_q;
     for (;;) {
         if (threadIdx.x == 0)
-            s_q = atomicAdd(a.queue, 1);
+            s_q = atomicAdd(a.queue + 0, 1);
         __syncthreads();
         const int64_t q = s_q;
         if (q >= a.batch)
             return;
-        b_system<WAVES>(a, a.order[q], sm);
+        const int64_t s = a.order[q];
+        const int n = a.n[s], m = a.nrhs[s];
+        if (a.prec[s] == SPD_AUTO && n > 0 && m > 0 && n <= SPD_BATCH_NMAX && m <= SPD_BATCH_MAXRHS) {
+            const unsigned long long t0 = wall_clock64();
+            b_features<4>(a.A + a.a_off[s], n, m, sm);
+            const int p = b_pick(a.picker, sm);
+            if (threadIdx.x == 0) {
+                a.prec[s] = p;
+                if (a.ticks)
+                    a.ticks[s] += (int64_t)(wall_clock64() - t0);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int WAVES, bool HI>
+__global__ __launch_bounds__(WAVES * 64, 2) void k_batch(BatchArgs a)
+{
+    __shared__ SolveSmem sm;
+    __shared__ int s_q;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_q = atomicAdd(a.queue + (HI ? 2 : 1), 1);
+        __syncthreads();
+        const int64_t q = s_q;
+        if (q >= a.batch)
+            return;
+        b_system<WAVES, HI>(a, a.order[q], sm);
         __syncthreads();
     }
 }
@@ -1103,7 +1143,7 @@ __global__ __launch_bounds__(256) void k_features(int64_t batch, const int32_t *
 // Order of work: systems sorted by decreasing n (counting sort, one
 // workgroup); also clears the work-queue counter.
 __global__ __launch_bounds__(1024) void k_batch_order(int64_t batch, const int32_t *__restrict__ n,
-                                                      int32_t *__restrict__ order, int *queue)
+                                                      int32_t *__restrict__ order, int *queue, int64_t *ticks)
 {
     constexpr int NBIN = SPD_BATCH_NMAX + 1;
     __shared__ int hist[NBIN], start[NBIN];
@@ -1122,8 +1162,10 @@ __global__ __launch_bounds__(1024) void k_batch_order(int64_t batch, const int32
             start[b] = acc;
             acc += hist[b];
         }
-        *queue = 0;
+        queue[0] = queue[1] = queue[2] = 0;
     }
+    if (ticks)
+        for (int64_t s = tid; s < batch; s += 1024) ticks[s] = 0;
     __syncthreads();
     for (int64_t s = tid; s < batch; s += 1024) {
         int v = n[s];
@@ -1166,9 +1208,13 @@ hipError_t launch_batch(const BatchLaunch &l, hipStream_t st)
     a.ws_stride = batch_ws_stride();
     a.picker = l.picker;
     a.ticks = l.ticks;
-    hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, st, l.batch, l.n, l.order, l.queue);
-    (void)l.waves;  // four wavefronts per workgroup (larger workgroups spill)
-    hipLaunchKernelGGL(k_batch<4>, dim3((unsigned)l.grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, st, l.batch, l.n, l.order, l.queue, l.ticks);
+    // picker (AUTO systems), then the low-precision systems, then binary64
+    // (requests and hand-overs); four wavefronts per workgroup
+    if (l.picker)
+        hipLaunchKernelGGL(k_batch_pick, dim3((unsigned)l.grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_batch<4, false>), dim3((unsigned)l.grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_batch<4, true>), dim3((unsigned)l.grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

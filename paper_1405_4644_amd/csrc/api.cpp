@@ -41,6 +41,7 @@ struct spd_factor_s {
     int half = HALF_NONE;    // operand rounding of the trailing update (BF16 / FP16 factors)
     int group = 4;           // panels per trailing-update group, binary32/64 (SPD_GROUP overrides)
     int group_half = 8;      // the same for binary16/bfloat16 operands, even, <= 8 (SPD_GROUP_HALF overrides)
+    bool small_main = false; // a group's thin trailing updates on 64-tiles too (SPD_SMALL_MAIN=1)
     int upd_slots = 0;       // cap on the main-stream update's workgroups (SPD_UPD_SLOTS; 0: one per tile)
     bool imported = false;   // the factor came from spd_factor_import (not line 1's own)
     void *Lh = nullptr;      // two panel copies in that precision (npad x NB halves each)
@@ -264,8 +265,10 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
             spd::launch_syrk_update_half((float *)H, npad, F->Lh, (int)(p0 & 15), lh_slot / 8, sk0, (int)(p1 - p0),
                                          half, r0, t, lo, hi, F->info_dev, s, prio, cap);
         } else {
+            // a group's trailing update keeps 128-tiles (64-tiles for the
+            // chain's single tile columns): one kernel instance per role
             spd::launch_syrk_update<T>(H, npad, p0 * NB, (int)((p1 - p0) * NB), r0, t, lo, hi, F->info_dev, s, prio,
-                                       cap);
+                                       cap, kind == SPD_K_CHAIN_UPDATE || F->small_main);
         }
         if (pe) {
             double fl, by;
@@ -960,6 +963,7 @@ spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec, co
         if (!*F) return SPD_ERR_OUT_OF_MEMORY;
         created = true;
         if (const char *e = std::getenv("SPD_GROUP")) (*F)->group = std::max(1, std::min(8, std::atoi(e)));
+        if (const char *e = std::getenv("SPD_SMALL_MAIN")) (*F)->small_main = std::atoi(e) != 0;
         if (const char *e = std::getenv("SPD_GROUP_HALF"))
             (*F)->group_half = std::max(2, std::min(8, std::atoi(e) & ~1));
         if (const char *e = std::getenv("SPD_UPD_SLOTS")) (*F)->upd_slots = std::max(0, std::atoi(e));

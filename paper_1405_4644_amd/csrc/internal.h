@@ -34,9 +34,12 @@ void launch_potrf_diag(T *Hkk, int64_t ld, int64_t col0, T *Winv, unsigned long 
 template <typename T>
 void launch_trsm_panel(T *H, int64_t ld, int64_t k0, int64_t row0, int64_t nrows, const T *Winv,
                        const unsigned long long *info, hipStream_t st, void *Lh = nullptr, int half = HALF_NONE);
+// small_tiles: a binary32 launch with fewer than 512 128-tiles may run on
+// 64-tiles (more workgroups for a thin region)
 template <typename T>
 void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,
-                        const unsigned long long *info, hipStream_t st, int prio = 0, int max_grid = 0);
+                        const unsigned long long *info, hipStream_t st, int prio = 0, int max_grid = 0,
+                        bool small_tiles = true);
 // Trailing update with binary16 / bfloat16 operands from np panel copies
 // (K = 128 each) on 128 x 128 tiles, binary32 accumulation into H: panel p's
 // copy in ring slot (slot0 + p) % 16 of Lh (slot stride sstride fragments of

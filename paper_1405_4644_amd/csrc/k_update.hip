@@ -575,7 +575,7 @@ static int small_update_tiles()
 
 template <typename T>
 void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,
-                        const unsigned long long *info, hipStream_t st, int prio, int max_grid)
+                        const unsigned long long *info, hipStream_t st, int prio, int max_grid, bool small_tiles)
 {
     if (t <= 0 || tj_lo >= tj_hi) return;
     int64_t ntiles = 0;
@@ -583,7 +583,7 @@ void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t
     int64_t grid = ((ntiles + 7) / 8) * 8;
     if (max_grid > 0 && grid > max_grid) grid = (max_grid / 8) * 8;
     if constexpr (sizeof(T) == 4) {
-        if (ntiles < kSmallUpdateTiles && max_grid == 0) {
+        if (small_tiles && ntiles < kSmallUpdateTiles && max_grid == 0) {
             // too few 128-tiles for the chip: 64-tiles, four times as many workgroups
             const int t2 = 2 * t, lo2 = 2 * tj_lo, hi2 = 2 * tj_hi;
             int64_t n2 = 0;
@@ -600,8 +600,8 @@ void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t
                            tj_hi, (int)ntiles, info, prio);
 }
 template void launch_syrk_update<float>(float *, int64_t, int64_t, int, int64_t, int, int, int,
-                                        const unsigned long long *, hipStream_t, int, int);
+                                        const unsigned long long *, hipStream_t, int, int, bool);
 template void launch_syrk_update<double>(double *, int64_t, int64_t, int, int64_t, int, int, int,
-                                         const unsigned long long *, hipStream_t, int, int);
+                                         const unsigned long long *, hipStream_t, int, int, bool);
 
 }  // namespace spd

@@ -363,6 +363,7 @@ def main():
     ap.add_argument("--no-energy", action="store_true", help="skip energy per solve")
     ap.add_argument("--energy-window", type=float, default=2.5)
     ap.add_argument("--no-external", action="store_true", help="skip the library binary64 Cholesky")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default schedule)")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-small-systems leg")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--loop-sample", type=int, default=512)
@@ -443,6 +444,17 @@ def main():
             spd.profile_enable(False)
         F.close()
         return dt, rep, X
+
+    # the autotuner's schedule for this order (binary32 and, for its leg,
+    # binary16), chosen before any timed step
+    tuned = {}
+    if not args.no_tune:
+        for p in ([args.prec] + (["fp16"] if (args.prec == "fp32" and not args.no_half and not cov) else []) +
+                  ([] if args.no_fp64 else ["fp64"])):
+            t = time.perf_counter()
+            tuned[p] = spd.autotune(n, p)
+            tuned[p]["tuning_s"] = time.perf_counter() - t
+            log(f"autotune {p}: {tuned[p]}")
 
     # the headline steps run without per-kernel events; the same number of
     # steps then runs again with events around every trailing-update and
@@ -562,6 +574,7 @@ def main():
         "fp64_baseline": fp64,
         "speedup_vs_fp64": (fp64["ms_per_step"] / (dt * 1e3)) if fp64 else None,
         "external_fp64_reference": external,
+        "autotune": tuned or None,
         "fp16_leg": half,
         "energy": energy,
         "batched": batched,

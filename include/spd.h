@@ -159,6 +159,32 @@ spd_status spd_refine(spd_factor_t F, const double *A, int64_t lda, const double
  * tests of that error path.  seconds < 0 or F NULL: SPD_ERR_INVALID_ARG. */
 spd_status spd_factor_set_wait_limit(spd_factor_t F, double seconds);
 
+/* Autotuner of the factorisation's schedule (the order of the work, never
+ * its result): panels per trailing-update group and a cap on the group
+ * update's workgroups (leaving compute units to the panel chain), chosen by
+ * timing spd_factor on a diagonally dominant test matrix of order n rounded
+ * to a power of two (log scale), for precision `prec`.  The choice is kept
+ * per (device architecture, HIP runtime version, precision, rounded order)
+ * for the process, and in the JSON file named by the environment variable
+ * SPD_TUNE_CACHE when it is set (read on first use, rewritten on each new
+ * entry); every later spd_factor of that precision and size uses it unless
+ * SPD_GROUP / SPD_GROUP_HALF / SPD_UPD_SLOTS fix the schedule.  A choice
+ * already held is returned without timing (from_cache 1: this process, 2:
+ * read from the file).  The batched solver's grid choice per batch size is
+ * kept the same way.  Allocates an n x n binary64 test matrix and a factor
+ * while timing; synchronises `hip_stream`.  n outside 1..2^20, an invalid
+ * precision or out NULL: SPD_ERR_INVALID_ARG. */
+typedef struct {
+    int32_t group;       /* 128-wide panels per trailing-update group */
+    int32_t upd_slots;   /* cap on the group update's workgroups (0: one per tile) */
+    double ms;           /* factorisation time of the test matrix under that schedule */
+    int32_t from_cache;  /* 0 timed now, 1 held by this process, 2 read from SPD_TUNE_CACHE */
+    int64_t n;           /* the rounded order the choice is kept for */
+} spd_tune_result;
+spd_status spd_autotune(int64_t n, spd_prec prec, void *hip_stream, spd_tune_result *out);
+/* Forget the autotuner's in-memory choices (the next use reads SPD_TUNE_CACHE again). */
+void spd_autotune_clear(void);
+
 /* The whole of Algorithm 1 in one call: spd_factor + spd_solve + spd_refine,
  * with the fallback chain applied from the factorisation on.  *F as in
  * spd_factor (reused if non-NULL). */
@@ -279,8 +305,10 @@ spd_status spd_mlp_adam(float *params, const float *grad, float *m, float *v, in
                         int32_t step, float lr, float beta1, float beta2, float eps, void *hip_stream);
 
 /* Launch shape the batched solver chose for this batch size on the current
- * device (workgroups of the persistent grid, waves per workgroup);
- * SPD_ERR_INVALID_ARG if no call with that batch size has been made yet. */
+ * device (workgroups of the persistent grid, timed among 256, 512, 768 and
+ * 1024 on the first call; waves per workgroup, always 4: the kernels are
+ * built for that size); SPD_ERR_INVALID_ARG if no call with that batch size
+ * has been made yet. */
 spd_status spd_batched_config(int64_t batch, int32_t *grid, int32_t *waves);
 
 /* Release every device buffer the handle owns.  NULL is ignored. */

@@ -54,6 +54,14 @@ class Report(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("group", C.c_int32), ("upd_slots", C.c_int32), ("ms", C.c_double), ("from_cache", C.c_int32),
+                ("n", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # exported entry points: (name, restype, argtypes)
 _vp, _i64, _i32, _f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double
 _SIGS = [
@@ -76,6 +84,8 @@ _SIGS = [
     ("spd_mlp_adam", C.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
     ("spd_factor_import", C.c_int, [_vp, _i64, _i64, C.c_int, _vp, C.POINTER(_vp), C.POINTER(_i64)]),
     ("spd_factor_set_wait_limit", C.c_int, [_vp, _f64]),
+    ("spd_autotune", C.c_int, [_i64, C.c_int, _vp, C.POINTER(TuneResult)]),
+    ("spd_autotune_clear", None, []),
     ("spd_factor_destroy", None, [_vp]),
     ("spd_factor_query", C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32)]),
     ("spd_factor_export", C.c_int, [_vp, _vp, _i64, _vp, C.POINTER(_f64), _vp]),
@@ -527,6 +537,20 @@ def batched_config(batch: int):
     g, w = _i32(), _i32()
     st = load().spd_batched_config(int(batch), C.byref(g), C.byref(w))
     return (g.value, w.value) if st == OK else None
+
+
+def autotune(n: int, prec="fp32") -> dict:
+    """spd_autotune: the factorisation schedule for this order (rounded to a
+    power of two) and precision, timed now or taken from the cache."""
+    r = TuneResult()
+    st = load().spd_autotune(int(n), _prec(prec), _stream(), C.byref(r))
+    if st:
+        raise SPDError(st, "spd_autotune")
+    return r.as_dict()
+
+
+def autotune_clear():
+    load().spd_autotune_clear()
 
 
 def version() -> str:

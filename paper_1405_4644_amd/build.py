@@ -21,7 +21,7 @@ INC = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libspd.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["k_factor.hip", "k_update.hip", "k_solve.hip", "k_trsv.hip", "k_resid.hip", "k_batch.hip", "k_picker.hip", "k_cg.hip", "api.cpp"]
+SOURCES = ["k_factor.hip", "k_update.hip", "k_solve.hip", "k_trsv.hip", "k_resid.hip", "k_batch.hip", "k_picker.hip", "k_cg.hip", "api.cpp", "tune.cpp"]
 
 
 def _hipcc() -> str:

@@ -42,6 +42,7 @@ struct spd_factor_s {
     int group = 4;           // panels per trailing-update group, binary32/64 (SPD_GROUP overrides)
     int group_half = 8;      // the same for binary16/bfloat16 operands, even, <= 8 (SPD_GROUP_HALF overrides)
     bool small_main = false; // a group's thin trailing updates on 64-tiles too (SPD_SMALL_MAIN=1)
+    bool pinned = false;     // schedule fixed by the environment or the tuner: no cache lookup
     int upd_slots = 0;       // cap on the main-stream update's workgroups (SPD_UPD_SLOTS; 0: one per tile)
     bool imported = false;   // the factor came from spd_factor_import (not line 1's own)
     void *Lh = nullptr;      // two panel copies in that precision (npad x NB halves each)
@@ -205,6 +206,8 @@ spd_status ensure_stream_objs(spd_factor_t F)
     if (!F->info_host) HIP_TRY(hipHostMalloc(&F->info_host, sizeof(unsigned long long), hipHostMallocDefault));
     return SPD_OK;
 }
+
+const char *prec_tag(int p) { return p == SPD_BF16 ? "bf16" : p == SPD_FP16 ? "fp16" : p == SPD_FP32 ? "fp32" : "fp64"; }
 
 double fp16_scale(double theta)
 {
@@ -382,6 +385,17 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
 {
     SPD_TRY(prepare_factor(F, n, prec, o.theta, st));
     F->imported = false;
+    if (!F->pinned) {
+        // the autotuner's schedule for this precision and size, when there is one
+        spd::TuneVal tv;
+        if (spd::tune_lookup(spd::tune_key(prec_tag(prec), spd::tune_bucket(n)), &tv)) {
+            if (prec == SPD_FP16 || prec == SPD_BF16)
+                F->group_half = tv.a;
+            else
+                F->group = tv.a;
+            F->upd_slots = tv.b;
+        }
+    }
     if (F->terr) HIP_TRY(hipMemsetAsync(F->terr, 0, sizeof(int), st));  // a new factor starts with no timeout
     const int64_t npad = F->npad;
     const int equil = (prec != SPD_FP64 && o.equilibrate) ? 1 : 0;
@@ -658,8 +672,9 @@ bool valid_prec(int p) { return p >= SPD_BF16 && p <= SPD_FP64; }
 // ---- batched solver state (per device; kept until the process ends) ----
 constexpr int kMaxDevices = 64;
 constexpr int kBatchMaxGrid = 1024;
-// launch shapes tried by the autotuner: {workgroups, waves per workgroup}
-constexpr int kBatchCandidates[][2] = {{256, 4}, {512, 4}, {1024, 4}};
+// persistent grid sizes tried by the batched autotuner (four wavefronts per
+// workgroup: the kernels are built for that size)
+constexpr int kBatchGrids[] = {256, 512, 768, 1024};
 struct BatchEntry {
     int32_t *order = nullptr;  // work order (and, after it, the queue counter)
     int *queue = nullptr;
@@ -962,6 +977,7 @@ spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec, co
         *F = new (std::nothrow) spd_factor_s();
         if (!*F) return SPD_ERR_OUT_OF_MEMORY;
         created = true;
+        (*F)->pinned = std::getenv("SPD_GROUP") || std::getenv("SPD_GROUP_HALF") || std::getenv("SPD_UPD_SLOTS");
         if (const char *e = std::getenv("SPD_GROUP")) (*F)->group = std::max(1, std::min(8, std::atoi(e)));
         if (const char *e = std::getenv("SPD_SMALL_MAIN")) (*F)->small_main = std::atoi(e) != 0;
         if (const char *e = std::getenv("SPD_GROUP_HALF"))
@@ -1068,6 +1084,89 @@ spd_status spd_refine(spd_factor_t F, const double *A, int64_t lda, const double
         }
     }
 }
+
+spd_status spd_autotune(int64_t n, spd_prec prec, void *hip_stream, spd_tune_result *out)
+{
+    if (n < 1 || n > (int64_t)1 << 20 || !valid_prec(prec) || !out) return SPD_ERR_INVALID_ARG;
+    std::memset(out, 0, sizeof(*out));
+    const int64_t nb = spd::tune_bucket(n);
+    const std::string key = spd::tune_key(prec_tag(prec), nb);
+    spd::TuneVal tv;
+    if (int src = spd::tune_lookup(key, &tv)) {
+        out->group = tv.a;
+        out->upd_slots = tv.b;
+        out->ms = tv.ms;
+        out->from_cache = src;
+        out->n = nb;
+        return SPD_OK;
+    }
+    // time the factorisation of a test matrix of the bucket's order under
+    // every candidate schedule (the schedule changes no result)
+    const bool half = (prec == SPD_FP16 || prec == SPD_BF16);
+    std::vector<std::pair<int, int>> cand;
+    if (half) {
+        for (int g : {2, 4, 8})
+            for (int c : {0, 224}) cand.push_back({g, c});
+    } else if (prec == SPD_FP32) {
+        for (int g : {2, 4, 6, 8})
+            for (int c : {0, 448}) cand.push_back({g, c});
+    } else {
+        for (int g : {2, 4, 6, 8}) cand.push_back({g, 0});
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    double *A = nullptr;
+    HIP_TRY(hipMalloc(&A, (size_t)nb * nb * sizeof(double)));
+    spd::launch_tune_matrix(A, nb, st);
+    spd_factor_t F = new (std::nothrow) spd_factor_s();
+    if (!F) {
+        hipFree(A);
+        return SPD_ERR_OUT_OF_MEMORY;
+    }
+    F->pinned = true;
+    spd_status result = SPD_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) result = map_err(he);
+    if (result == SPD_OK && hipGetDevice(&F->device) != hipSuccess) result = SPD_ERR_DEVICE;
+    const spd_opts op = defaults();
+    double best = 1e30;
+    int64_t info = 0;
+    for (size_t i = 0; i < cand.size() && result == SPD_OK; ++i) {
+        (half ? F->group_half : F->group) = cand[i].first;
+        F->upd_slots = cand[i].second;
+        double t = 1e30;
+        for (int r = 0; r < 3 && result == SPD_OK; ++r) {  // first run warms up
+            hipEventRecord(e0, st);
+            result = do_factor(F, A, nb, nb, prec, op, st, &info);
+            hipEventRecord(e1, st);
+            float ms = 0.f;
+            if (result == SPD_OK && hipEventSynchronize(e1) == hipSuccess &&
+                hipEventElapsedTime(&ms, e0, e1) == hipSuccess && r > 0)
+                t = std::min(t, (double)ms);
+        }
+        if (result == SPD_OK && t < best) {
+            best = t;
+            tv.a = cand[i].first;
+            tv.b = cand[i].second;
+            tv.ms = t;
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    spd_factor_destroy(F);
+    hipFree(A);
+    if (result != SPD_OK) return result;
+    spd::tune_store(key, tv);
+    out->group = tv.a;
+    out->upd_slots = tv.b;
+    out->ms = tv.ms;
+    out->from_cache = 0;
+    out->n = nb;
+    return SPD_OK;
+}
+
+void spd_autotune_clear(void) { spd::tune_clear(); }
 
 spd_status spd_factor_set_wait_limit(spd_factor_t F, double seconds)
 {
@@ -1294,9 +1393,14 @@ static spd_status solve_batched_impl(int64_t batch, const int32_t *n, const int3
         HIP_TRY(hipEventCreate(&eb));
         float best = 1e30f;
         hipError_t err = hipSuccess;
-        for (const auto &cand : kBatchCandidates) {
-            l.grid = (int)std::min<int64_t>(cand[0], batch);
-            l.waves = cand[1];
+        // a grid chosen for this batch size earlier (the cache file) is reused
+        spd::TuneVal tv;
+        const std::string key = spd::tune_key("batched", batch);
+        const bool cached = spd::tune_lookup(key, &tv) != 0;
+        for (int cand : kBatchGrids) {
+            if (cached && cand != tv.a) continue;
+            l.grid = (int)std::min<int64_t>(cand, batch);
+            l.waves = 4;
             l.order = e.order;
             l.queue = e.queue;
             if (err == hipSuccess)
@@ -1311,8 +1415,11 @@ static spd_status solve_batched_impl(int64_t batch, const int32_t *n, const int3
                 best = ms;
                 e.grid = l.grid;
                 e.waves = l.waves;
+                tv.a = cand;
+                tv.ms = ms;
             }
         }
+        if (err == hipSuccess && !cached) spd::tune_store(key, tv);
         if (err == hipSuccess)
             err = hipMemcpyAsync(prec, saved, (size_t)batch * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
         if (err == hipSuccess) err = hipStreamSynchronize(st);

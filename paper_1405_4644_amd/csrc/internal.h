@@ -1,5 +1,6 @@
 // Host-side declarations shared by the libspd translation units.
 #pragma once
+#include <string>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -135,6 +136,19 @@ struct BatchLaunch {
     int64_t *ticks = nullptr;       // per-system wall-clock ticks, or NULL
 };
 int64_t batch_ws_stride();
+// autotuner cache (tune.cpp): values a, b, c of a setting and its time
+struct TuneVal {
+    int a = 0, b = 0, c = 0;
+    double ms = 0.0;
+};
+int64_t tune_bucket(int64_t n);                               // n rounded to a power of two (log scale)
+std::string tune_key(const char *kind, int64_t size);         // "<arch>|hip<ver>|<kind>|<size>"
+int tune_lookup(const std::string &key, TuneVal *v);          // 0 absent, 1 in memory, 2 read from the file
+void tune_store(const std::string &key, const TuneVal &v);    // memory, and the file when SPD_TUNE_CACHE is set
+void tune_clear();                                            // forget memory; the next lookup rereads the file
+// a diagonally dominant symmetric n x n test matrix (tuning input): a_ii = 2,
+// a_ij = hash(i, j) / n in (-1/n, 1/n) off the diagonal (both triangles)
+void launch_tune_matrix(double *A, int64_t n, hipStream_t st);
 hipError_t launch_batch(const BatchLaunch &l, hipStream_t st);
 // picker features of every system (16 floats each)
 void launch_features(int64_t batch, const int32_t *n, const int32_t *nrhs, const int64_t *a_off, const double *A,

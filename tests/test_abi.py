@@ -132,3 +132,11 @@ def test_noalloc_residual_rejects_sizes_beyond_its_array(lib):
     assert lib.spd_residual_noalloc(fake, 20000, 20000, fake, 20000, fake, 20000, 2, fake, 20000, None,
                                     None) == spd.ERR_INVALID_ARG
     assert lib.spd_residual_noalloc(fake, 10, 5, fake, 10, fake, 10, 1, fake, 10, None, None) == spd.ERR_INVALID_ARG
+
+
+def test_autotune_argument_checks(lib):
+    import paper_1405_4644_amd as spd
+    r = spd.TuneResult()
+    assert lib.spd_autotune(0, 2, None, C.byref(r)) == spd.ERR_INVALID_ARG
+    assert lib.spd_autotune(1024, 7, None, C.byref(r)) == spd.ERR_INVALID_ARG
+    assert lib.spd_autotune(1024, 2, None, None) == spd.ERR_INVALID_ARG

@@ -80,10 +80,18 @@ struct SolveSmem {
     double arow[SPD_BATCH_NMAX];  // row sums of |A|
     int info;
 };
-// the picker's features need more (the solving kernels do without it)
-struct BatchSmem : SolveSmem {
-    double csum[SPD_BATCH_MAXRHS * SPD_BATCH_NMAX];
-    double cabs[SPD_BATCH_NMAX];
+// the picker's features and perceptron (about 30 KB: several workgroups per CU)
+struct PickSmem {
+    double d[SPD_BATCH_NMAX];   // d_i = a_ii^{-1/2}
+    double v[SPD_BATCH_NMAX];   // Lanczos vectors v_j, v_{j-1}, w
+    double vp[SPD_BATCH_NMAX];
+    double w[SPD_BATCH_NMAX];
+    double rs[SPD_BATCH_NMAX];  // Gershgorin radii of H
+    double ycol[SPD_BATCH_NMAX];
+    double rcol[SPD_BATCH_NMAX];
+    double red[16][8];
+    double ab[2][PICK_LANCZOS];  // Lanczos alpha, beta
+    double th[PICK_LANCZOS];     // Ritz values
     float feat[PICK_NFEAT];
     float hid[2][PICK_NH];
     float logit[PICK_NCLS];
@@ -114,79 +122,108 @@ SPD_DEV double rl(double v, int src)
 // ---------------------------------------------------------------------------
 // H = round(mu D A D) (lower), identity padding up to np; d (binary64).
 template <typename T>
-SPD_DEV void b_convert(const double *A, int n, int np, double *d, double mu, int equil, T *L, int nthr)
+SPD_DEV void b_convert(const double *A, int n, int np, double *d, double mu, int equil, T *L, int nthr,
+                       double *dsh)
 {
     const int tid = threadIdx.x;
     for (int i = tid; i < n; i += nthr) {
         const double a = A[i + (int64_t)i * n];
-        d[i] = (equil && a > 0.0) ? 1.0 / sqrt(a) : 1.0;
+        const double di = (equil && a > 0.0) ? 1.0 / sqrt(a) : 1.0;
+        d[i] = di;
+        dsh[i] = di;
     }
     __syncthreads();
+    // column j by one wave, 8 rows per lane loaded before any is stored
     const int lane = tid & 63, wave = tid >> 6, nw = nthr / 64;
+    constexpr int U = 8;
     for (int j = wave; j < np; j += nw) {
-        const double dj = (j < n) ? d[j] : 0.0;
-        for (int i = j + lane; i < np; i += 64) {
-            T v;
-            if (i < n && j < n)
-                v = (T)(((mu * d[i]) * A[i + (int64_t)j * n]) * dj);
-            else
-                v = (i == j) ? (T)1 : (T)0;
-            L[i + (int64_t)j * np] = v;
+        const double dj = (j < n) ? dsh[j] : 0.0;
+        for (int i0 = j; i0 < np; i0 += 64 * U) {
+            double a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + 64 * u + lane;
+                a[u] = (i < n && j < n) ? A[i + (int64_t)j * n] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + 64 * u + lane;
+                if (i < np) {
+                    T v;
+                    if (i < n && j < n)
+                        v = (T)(((mu * dsh[i]) * a[u]) * dj);
+                    else
+                        v = (i == j) ? (T)1 : (T)0;
+                    L[i + (int64_t)j * np] = v;
+                }
+            }
         }
     }
     __syncthreads();
 }
 
-// Factor the 32 x 32 diagonal block at (k0, k0) in one wavefront (lane r
-// holds row r; right-looking, one column per step, broadcasts by readlane)
-// and form its inverse W (lane c builds column c:
-// W[r][c] = (delta_rc - sum_{q<r} L[r][q] W[q][c]) / L[r][r]) into Ws
-// (Ws[c * 33 + r]) and Wg (column-major).  Returns the 1-based failing column
-// of the block, 0 on success.  A function of its own so that its registers
-// are allocated apart from the rest of the factorisation.
+// Factor the 32 x 32 diagonal block at (k0, k0) in one wavefront and form
+// its inverse W, left-looking: lane r holds row r; at column j every lane
+// forms a_rj - sum_{q<j} L[r][q] L[j][q] with row j of L read from shared
+// memory (Lr, row-major, every lane the same address: a broadcast, four
+// values per read), lane j's value is the pivot (one readlane), and each lane
+// publishes its new L[r][j] to Lr.  W follows by forward substitution
+// L W = I, lane c building column c (W[r][c] = (delta_rc -
+// sum_{q<r} L[r][q] W[q][c]) / L[r][r]) from the same rows.  Lanes 32..63
+// mirror lanes 0..31 and store nothing.  Outputs: the block in L, W in Ws
+// (Ws[c * 33 + r]) and Wg (column-major).  Returns the 1-based failing
+// column of the block, 0 on success.
 template <typename T>
-__device__ __attribute__((noinline)) int b_diag(T *L, int np, int k0, T *Ws, T *Wg)
+__device__ __attribute__((noinline)) int b_diag(T *L, int np, int k0, T *Ws, T *Wg, T *Lr)
 {
-    const int lane = threadIdx.x & 63;
+    constexpr int S = 36;  // Lr row stride (16-byte aligned rows)
+    const int lane = threadIdx.x & 63, r = lane & 31;
+    const bool store = lane < BNB;
     T row[BNB];
 #pragma unroll
     for (int c = 0; c < BNB; ++c)
-        row[c] = (lane < BNB && c <= lane) ? L[(k0 + lane) + (int64_t)(k0 + c) * np] : (T)0;
+        row[c] = (c <= r) ? L[(k0 + r) + (int64_t)(k0 + c) * np] : (T)0;
+    int bad = 0;
 #pragma unroll
     for (int j = 0; j < BNB; ++j) {
-        const T p = rl(row[j], j);
-        if (!(p > (T)0))
-            return j + 1;
-        const T ljj = sqrt(p);
-        if (lane == j)
-            row[j] = ljj;
-        else if (lane > j)
-            row[j] = row[j] / ljj;
+        T p[4] = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
-        for (int c = j + 1; c < BNB; ++c) {
-            const T lcj = rl(row[j], c);
-            row[c] -= row[j] * lcj;
+        for (int q = 0; q < j; ++q) p[q & 3] = fma(row[q], Lr[j * S + q], p[q & 3]);
+        const T sv = row[j] - ((p[0] + p[1]) + (p[2] + p[3]));
+        const T piv = rl(sv, j);
+        if (!(piv > (T)0)) {
+            bad = j + 1;
+            break;
         }
+        const T ljj = sqrt(piv);
+        row[j] = (r == j) ? ljj : ((r > j) ? sv / ljj : (T)0);
+        if (store)
+            Lr[r * S + j] = row[j];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_sched_barrier(0);
     }
+    if (bad)
+        return bad;
+    // W: each new row of W goes to Ws as it is formed
     T w[BNB];
 #pragma unroll
-    for (int r = 0; r < BNB; ++r) {
-        T sacc = (lane == r) ? (T)1 : (T)0;
+    for (int i = 0; i < BNB; ++i) {
+        T p[4] = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
-        for (int q = 0; q < r; ++q) sacc -= rl(row[q], r) * w[q];
-        w[r] = sacc / rl(row[r], r);
+        for (int q = 0; q < i; ++q) p[q & 3] = fma(Lr[i * S + q], w[q], p[q & 3]);
+        const T rhs = ((r == i) ? (T)1 : (T)0) - ((p[0] + p[1]) + (p[2] + p[3]));
+        w[i] = (i < r) ? (T)0 : rhs / Lr[i * S + i];
+        if (store)
+            Ws[r * (BNB + 1) + i] = w[i];  // lane r = column r of W
+        __builtin_amdgcn_sched_barrier(0);
     }
-    if (lane < BNB) {
-#pragma unroll
-        for (int c = 0; c < BNB; ++c)
-            if (c <= lane)
-                L[(k0 + lane) + (int64_t)(k0 + c) * np] = row[c];
-#pragma unroll
-        for (int r = 0; r < BNB; ++r) {
-            const T v = (r < lane) ? (T)0 : w[r];
-            Ws[lane * (BNB + 1) + r] = v;
-            Wg[r + lane * BNB] = v;
-        }
+    __builtin_amdgcn_wave_barrier();
+    // the block of L and W (column-major) to global memory, column by column
+    for (int e = lane; e < BNB * BNB; e += 64) {
+        const int rr = e % BNB, cc = e / BNB;
+        if (cc <= rr)
+            L[(k0 + rr) + (int64_t)(k0 + cc) * np] = Lr[rr * S + cc];
+        Wg[e] = Ws[cc * (BNB + 1) + rr];
     }
     return 0;
 }
@@ -197,7 +234,7 @@ __device__ __attribute__((noinline)) int b_diag(T *L, int np, int k0, T *Ws, T *
 // the 32 x 32 diagonal blocks.  With half != HALF_NONE the trailing-update
 // operands are rounded to that format (binary32 accumulation).
 template <typename T, int WAVES>
-SPD_DEV int b_factor(T *L, int np, T *Winv, int half, SolveSmem &sm)
+__device__ __attribute__((noinline)) int b_factor(T *L, int np, T *Winv, int half, SolveSmem &sm)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nb = np / BNB;
@@ -205,7 +242,7 @@ SPD_DEV int b_factor(T *L, int np, T *Winv, int half, SolveSmem &sm)
     for (int kb = 0; kb < nb; ++kb) {
         const int k0 = kb * BNB;
         if (wave == 0) {
-            const int bad = b_diag<T>(L, np, k0, Ws, Winv + (int64_t)kb * BNB * BNB);
+            const int bad = b_diag<T>(L, np, k0, Ws, Winv + (int64_t)kb * BNB * BNB, (T *)sm.ys);
             if (lane == 0)
                 sm.info = bad ? k0 + bad : 0;
         }
@@ -225,35 +262,54 @@ SPD_DEV int b_factor(T *L, int np, T *Winv, int half, SolveSmem &sm)
             }
         }
         __syncthreads();
-        // trailing update of the lower tiles (I, J), kb < J <= I
+        // trailing update of the lower tiles (I, J), kb < J <= I; a wave's
+        // next tile's C values and this tile's operands are loaded before
+        // this tile's MFMAs
         const int t = nb - kb - 1, ntile = t * (t + 1) / 2;
-        for (int q = wave; q < ntile; q += WAVES) {
+        auto tile_of = [&](int q, int &gI, int &gJ) {
             int I = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
             while (I * (I + 1) / 2 > q) --I;
             while ((I + 1) * (I + 2) / 2 <= q) ++I;
-            const int J = q - I * (I + 1) / 2;
-            const int gI = kb + 1 + I, gJ = kb + 1 + J;
-            T *C = L + (int64_t)gI * BNB + (int64_t)gJ * BNB * np;
-            Acc32<T> acc;
+            gI = kb + 1 + I;
+            gJ = kb + 1 + q - I * (I + 1) / 2;
+        };
+        auto load_c = [&](Acc32<T> &acc, const T *C) {
             // register j: column Acc32::row(j) of the tile, row Acc32::col(j)
 #pragma unroll
             for (int j = 0; j < 16; ++j)
                 acc.set(j, C[Acc32<T>::col(j, lane) + (int64_t)Acc32<T>::row(j, lane) * np]);
+        };
+        int gI = 0, gJ = 0;
+        Acc32<T> nxt;
+        if (wave < ntile) {
+            tile_of(wave, gI, gJ);
+            load_c(nxt, L + (int64_t)gI * BNB + (int64_t)gJ * BNB * np);
+        }
+        for (int q = wave; q < ntile; q += WAVES) {
+            T *C = L + (int64_t)gI * BNB + (int64_t)gJ * BNB * np;
             const T *pJ = L + (int64_t)gJ * BNB + (int64_t)k0 * np;
             const T *pI = L + (int64_t)gI * BNB + (int64_t)k0 * np;
-#pragma unroll 4
-            for (int kk = 0; kk < BNB; kk += Frag<T>::K) {
-                Frag<T> fa, fb;
-                fa.load(pJ + (int64_t)kk * np, np, lane);
-                fb.load(pI + (int64_t)kk * np, np, lane);
+            Acc32<T> acc = nxt;
+            Frag<T> fa[BNB / Frag<T>::K], fb[BNB / Frag<T>::K];
+#pragma unroll
+            for (int s2 = 0; s2 < BNB / Frag<T>::K; ++s2) {
+                fa[s2].load(pJ + (int64_t)s2 * Frag<T>::K * np, np, lane);
+                fb[s2].load(pI + (int64_t)s2 * Frag<T>::K * np, np, lane);
+            }
+            if (q + WAVES < ntile) {
+                tile_of(q + WAVES, gI, gJ);
+                load_c(nxt, L + (int64_t)gI * BNB + (int64_t)gJ * BNB * np);
+            }
+#pragma unroll
+            for (int s2 = 0; s2 < BNB / Frag<T>::K; ++s2) {
                 if constexpr (sizeof(T) == 4) {
                     if (half) {
-                        fa.v = round_half(fa.v, half);
-                        fb.v = round_half(fb.v, half);
+                        fa[s2].v = round_half(fa[s2].v, half);
+                        fb[s2].v = round_half(fb[s2].v, half);
                     }
                 }
-                fa.negate();
-                mma(acc, fa, fb);
+                fa[s2].negate();
+                mma(acc, fa[s2], fb[s2]);
             }
 #pragma unroll
             for (int j = 0; j < 16; ++j)
@@ -270,7 +326,7 @@ SPD_DEV int b_factor(T *L, int np, T *Winv, int half, SolveSmem &sm)
 // read is coalesced across lanes and issued in batches (no loop carries a
 // load-to-use dependency).
 template <typename T, int WAVES>
-SPD_DEV void b_solve(const T *L, const T *Winv, int n, int np, int m, const double *R, const double *d, double mu,
+__device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int n, int np, int m, const double *R, const double *d, double mu,
                      double *X, int accumulate, SolveSmem &sm)
 {
     constexpr int NT = WAVES * 64, MR = SPD_BATCH_MAXRHS;
@@ -284,33 +340,63 @@ SPD_DEV void b_solve(const T *L, const T *Winv, int n, int np, int m, const doub
         ys[c * NM + i] = (i < n) ? (T)(d[i] * R[i + (int64_t)c * n] / s) : (T)0;
     }
     __syncthreads();
+    // Each step first issues the loads it needs -- the W block (staged in
+    // shared memory, Wl[q * 33 + r] = W[r][q]) and the matrix values of the
+    // step -- so that their latencies overlap; sums keep the same order.
+    constexpr int WPT = BNB * BNB / NT;  // W values staged per thread
+    static_assert(WPT * NT == BNB * BNB, "W staging");
+    T *Wl = (T *)sm.Lk;
+    T *zs = (T *)sm.ts;  // the block just solved, zs[c * BNB + r]
     // forward: z_k = W_k y_k, then y_below -= L_below,k z_k
     for (int kb = 0; kb < nb; ++kb) {
         const int k0 = kb * BNB;
         const T *W = Winv + (int64_t)kb * BNB * BNB;
-        T z = (T)0;
+        T wt[WPT];
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) wt[u] = W[tid + u * NT];
+        const int i1 = k0 + BNB + tid;
+        T lv[BNB];
+        if (i1 < np) {
+#pragma unroll
+            for (int q = 0; q < BNB; ++q) lv[q] = L[i1 + (int64_t)(k0 + q) * np];
+        }
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int e = tid + u * NT;
+            Wl[(e / BNB) * (BNB + 1) + e % BNB] = wt[u];
+        }
+        __syncthreads();
         if (tid < BNB * m) {
             const int r = tid % BNB, c = tid / BNB;
-            T wv[BNB];
+            T z = (T)0;
 #pragma unroll
-            for (int q = 0; q < BNB; ++q) wv[q] = W[r + q * BNB];
-#pragma unroll
-            for (int q = 0; q < BNB; ++q) z += wv[q] * ys[c * NM + k0 + q];  // W is zero above its diagonal
+            for (int q = 0; q < BNB; ++q) z += Wl[q * (BNB + 1) + r] * ys[c * NM + k0 + q];  // W is zero above its diagonal
+            zs[tid] = z;
         }
         __syncthreads();
         if (tid < BNB * m)
-            ys[(tid / BNB) * NM + k0 + tid % BNB] = z;
-        __syncthreads();
-        for (int i = k0 + BNB + tid; i < np; i += NT) {
-            T lv[BNB];
-#pragma unroll
-            for (int q = 0; q < BNB; ++q) lv[q] = L[i + (int64_t)(k0 + q) * np];
+            ys[(tid / BNB) * NM + k0 + tid % BNB] = zs[tid];
+        if (i1 < np) {
 #pragma unroll
             for (int c = 0; c < MR; ++c) {
                 if (c < m) {
                     T sacc = (T)0;
 #pragma unroll
-                    for (int q = 0; q < BNB; ++q) sacc += lv[q] * ys[c * NM + k0 + q];
+                    for (int q = 0; q < BNB; ++q) sacc += lv[q] * zs[c * BNB + q];
+                    ys[c * NM + i1] -= sacc;
+                }
+            }
+        }
+        for (int i = i1 + NT; i < np; i += NT) {
+            T lw[BNB];
+#pragma unroll
+            for (int q = 0; q < BNB; ++q) lw[q] = L[i + (int64_t)(k0 + q) * np];
+#pragma unroll
+            for (int c = 0; c < MR; ++c) {
+                if (c < m) {
+                    T sacc = (T)0;
+#pragma unroll
+                    for (int q = 0; q < BNB; ++q) sacc += lw[q] * zs[c * BNB + q];
                     ys[c * NM + i] -= sacc;
                 }
             }
@@ -318,32 +404,42 @@ SPD_DEV void b_solve(const T *L, const T *Winv, int n, int np, int m, const doub
         __syncthreads();
     }
     // backward: x_k = W_k^T (y_k - L_below,k^T x_below); the column sums by
-    // wave (lanes over rows), one column q at a time
+    // wave (lanes over rows), column q + WAVES's values loaded while column
+    // q's are used
+    constexpr int RCH = NM / 64;
     T *ts = (T *)sm.ts;
     for (int kb = nb - 1; kb >= 0; --kb) {
         const int k0 = kb * BNB, r0 = k0 + BNB;
         const T *W = Winv + (int64_t)kb * BNB * BNB;
+        T wt[WPT];
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) wt[u] = W[tid + u * NT];
+        const int nch = (np - r0 + 63) / 64;
+        T cur[RCH], nxt[RCH];
+        auto load_col = [&](T *dst, int q) {
+            const T *col = L + (int64_t)(k0 + q) * np;
+#pragma unroll
+            for (int u = 0; u < RCH; ++u) {
+                const int i = r0 + 64 * u + lane;
+                dst[u] = (u < nch && i < np) ? col[i] : (T)0;
+            }
+        };
+        load_col(cur, wave);
+#pragma unroll 1
         for (int q = wave; q < BNB; q += WAVES) {
+            if (q + WAVES < BNB)
+                load_col(nxt, q + WAVES);
             T acc[MR];
 #pragma unroll
             for (int c = 0; c < MR; ++c) acc[c] = (T)0;
-            const T *col = L + (int64_t)(k0 + q) * np;
-            for (int i0 = r0; i0 < np; i0 += 4 * 64) {
-                T lv[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int i = i0 + 64 * u + lane;
-                    lv[u] = (i < np) ? col[i] : (T)0;
-                }
+            for (int u = 0; u < RCH; ++u) {
+                const int i = r0 + 64 * u + lane;
+                if (u < nch && i < np) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int i = i0 + 64 * u + lane;
-                    if (i < np) {
-#pragma unroll
-                        for (int c = 0; c < MR; ++c)
-                            if (c < m)
-                                acc[c] += lv[u] * ys[c * NM + i];
-                    }
+                    for (int c = 0; c < MR; ++c)
+                        if (c < m)
+                            acc[c] += cur[u] * ys[c * NM + i];
                 }
             }
 #pragma unroll
@@ -356,16 +452,20 @@ SPD_DEV void b_solve(const T *L, const T *Winv, int n, int np, int m, const doub
                         ts[c * BNB + q] = v;
                 }
             }
+#pragma unroll
+            for (int u = 0; u < RCH; ++u) cur[u] = nxt[u];
+        }
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int e = tid + u * NT;
+            Wl[(e / BNB) * (BNB + 1) + e % BNB] = wt[u];
         }
         __syncthreads();
         T x = (T)0;
         if (tid < BNB * m) {
             const int r = tid % BNB, c = tid / BNB;
-            T wv[BNB];
 #pragma unroll
-            for (int q = 0; q < BNB; ++q) wv[q] = W[q + r * BNB];
-#pragma unroll
-            for (int q = 0; q < BNB; ++q) x += wv[q] * (ys[c * NM + k0 + q] - ts[c * BNB + q]);
+            for (int q = 0; q < BNB; ++q) x += Wl[r * (BNB + 1) + q] * (ys[c * NM + k0 + q] - ts[c * BNB + q]);
         }
         __syncthreads();
         if (tid < BNB * m)
@@ -395,7 +495,7 @@ SPD_DEV void b_solve(const T *L, const T *Winv, int n, int np, int m, const doub
 // column, each lane streaming down its column (the second read of A comes
 // from the cache); r = b - (row + col).
 template <int WAVES>
-SPD_DEV void b_residual(const double *A, int n, int m, const double *X, const double *B, const double *d, double *R,
+__device__ __attribute__((noinline)) void b_residual(const double *A, int n, int m, const double *X, const double *B, const double *d, double *R,
                         int want_anorm, SolveSmem &sm)
 {
     constexpr int NT = WAVES * 64, NM = SPD_BATCH_NMAX;
@@ -408,7 +508,7 @@ SPD_DEV void b_residual(const double *A, int n, int m, const double *X, const do
         xs[c * NM + j] = X[j + (int64_t)c * n];
     }
     __syncthreads();
-    // row pass: 32-column chunks, the next chunk's loads in flight while the
+    // row pass: 16-column chunks, the next chunk's loads in flight while the
     // current one is used
     constexpr int CH = 16;
     for (int i0 = wave * 64; i0 < n; i0 += NT) {
@@ -499,50 +599,56 @@ SPD_DEV void b_residual(const double *A, int n, int m, const double *X, const do
         }
     }
     __syncthreads();
-    // maxima (NaN propagates), per column, then ||A||_inf
-    double v[4 * MR + 1];
+    // maxima (NaN propagates), per column, one kind at a time (kind 0..3:
+    // |r|, |x|, |b|, |d r|), then ||A||_inf
+#pragma unroll 1
+    for (int kind = 0; kind < 4; ++kind) {
+        double v[MR];
 #pragma unroll
-    for (int k = 0; k < 4 * MR + 1; ++k) v[k] = 0.0;
-    for (int i = tid; i < n; i += NT) {
+        for (int c = 0; c < MR; ++c) v[c] = 0.0;
+        for (int i = tid; i < n; i += NT) {
 #pragma unroll
-        for (int c = 0; c < MR; ++c)
-            if (c < m) {
-                const double r = R[i + (int64_t)c * n];
-                v[c] = b_nanmax(v[c], fabs(r));
-                v[MR + c] = b_nanmax(v[MR + c], fabs(xs[c * NM + i]));
-                v[2 * MR + c] = b_nanmax(v[2 * MR + c], fabs(B[i + (int64_t)c * n]));
-                v[3 * MR + c] = b_nanmax(v[3 * MR + c], fabs(d[i] * r));
-            }
-        if (want_anorm)
-            v[4 * MR] = b_nanmax(v[4 * MR], abs_rows[i]);
-    }
+            for (int c = 0; c < MR; ++c)
+                if (c < m) {
+                    const double x = (kind == 0) ? R[i + (int64_t)c * n]
+                                     : (kind == 1) ? xs[c * NM + i]
+                                     : (kind == 2) ? B[i + (int64_t)c * n]
+                                                   : d[i] * R[i + (int64_t)c * n];
+                    v[c] = b_nanmax(v[c], fabs(x));
+                }
+        }
 #pragma unroll
-    for (int k = 0; k < 4 * MR + 1; ++k) {
-        if (k < 4 * MR && (k % MR) >= m)
-            continue;
-        if (k == 4 * MR && !want_anorm)
-            continue;
+        for (int c = 0; c < MR; ++c) {
+            if (c >= m)
+                break;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[k] = b_nanmax(v[k], __shfl_xor(v[k], off));
-        if (lane == 0)
-            sm.red[wave][k] = v[k];
-    }
-    __syncthreads();
-    if (tid < 4 * MR + 1) {
-        const int k = tid / MR, c = tid % MR;
-        if (tid == 4 * MR) {
-            if (want_anorm) {
-                double x = 0.0;
-                for (int w = 0; w < WAVES; ++w) x = b_nanmax(x, sm.red[w][tid]);
-                sm.norms[0] = x;
-            }
-        } else if (c < m) {
+            for (int off = 32; off > 0; off >>= 1) v[c] = b_nanmax(v[c], __shfl_xor(v[c], off));
+            if (lane == 0)
+                sm.red[wave][c] = v[c];
+        }
+        __syncthreads();
+        if (tid < m) {
             double x = 0.0;
             for (int w = 0; w < WAVES; ++w) x = b_nanmax(x, sm.red[w][tid]);
-            sm.norms[1 + k * m + c] = x;
+            sm.norms[1 + kind * m + tid] = x;
         }
+        __syncthreads();
     }
-    __syncthreads();
+    if (want_anorm) {
+        double x = 0.0;
+        for (int i = tid; i < n; i += NT) x = b_nanmax(x, abs_rows[i]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x = b_nanmax(x, __shfl_xor(x, off));
+        if (lane == 0)
+            sm.red[wave][0] = x;
+        __syncthreads();
+        if (tid == 0) {
+            double y = 0.0;
+            for (int w = 0; w < WAVES; ++w) y = b_nanmax(y, sm.red[w][0]);
+            sm.norms[0] = y;
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -563,7 +669,7 @@ SPD_DEV void b_residual(const double *A, int n, int m, const double *X, const do
 // block reduction of NV values per thread, fixed order (wave butterflies,
 // then waves in order); op 0 = sum, 1 = max, 2 = min.  Result in every thread.
 template <int WAVES, int NV>
-SPD_DEV void b_reduce(double v[NV], const int op[NV], BatchSmem &sm)
+SPD_DEV void b_reduce(double v[NV], const int op[NV], PickSmem &sm)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -593,25 +699,31 @@ SPD_DEV void b_reduce(double v[NV], const int op[NV], BatchSmem &sm)
 // With first: rs[i] = r_i, and per thread the partial max off-diagonal |h|
 // and sum of h^2 (each stored element once, off-diagonal ones counted twice).
 template <int WAVES>
-SPD_DEV void b_hv(const double *A, int n, const double *d, const double *v, double *y, double *rs, bool first,
-                  double &hmax, double &fro, BatchSmem &sm)
+SPD_DEV void b_hv(const double *A, int n, const double *v, double *y, bool first, double &hmax, double &fro,
+                  PickSmem &sm)
 {
-    constexpr int NT = WAVES * 64, CH = 16;
+    constexpr int NT = WAVES * 64, CH = 8;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double *ycol = sm.csum, *rcol = sm.cabs;
-    // rows: sum_{j <= i} h_ij v_j
+    const double *d = sm.d;
+    // rows: sum_{j <= i} h_ij v_j; 8 columns per batch of loads, the next
+    // batch in flight while the current one is used
     for (int i0 = wave * 64; i0 < n; i0 += NT) {
         const int i = i0 + lane;
         const int jmax = min(i0 + 63, n - 1);
         const double di = (i < n) ? d[i] : 0.0;
         double acc = 0.0, ra = 0.0;
-        for (int j0 = 0; j0 <= jmax; j0 += CH) {
-            double a[CH];
+        double a[CH], an[CH];
+        auto load = [&](double *dst, int j0) {
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int j = j0 + u;
-                a[u] = (i < n && j <= i) ? A[i + (int64_t)j * n] : 0.0;
+                dst[u] = (i < n && j <= i) ? A[i + (int64_t)j * n] : 0.0;
             }
+        };
+        load(a, 0);
+        for (int j0 = 0; j0 <= jmax; j0 += CH) {
+            if (j0 + CH <= jmax)
+                load(an, j0 + CH);
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int j = min(j0 + u, n - 1);
@@ -625,25 +737,32 @@ SPD_DEV void b_hv(const double *A, int n, const double *d, const double *v, doub
                     fro += h * h;
                 }
             }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) a[u] = an[u];
         }
         if (i < n) {
             y[i] = acc;
             if (first)
-                rs[i] = ra;
+                sm.rs[i] = ra;
         }
     }
-    // columns: lane = column, sum_{i > j} h_ij v_i
+    // columns: lane = column, sum_{i > j} h_ij v_i, the same double buffering
     for (int j0 = wave * 64; j0 < n; j0 += NT) {
         const int j = j0 + lane;
         const double dj = (j < n) ? d[j] : 0.0;
         double acc = 0.0, ca = 0.0;
-        for (int i0 = j0 + 1; i0 < n; i0 += CH) {
-            double a[CH];
+        double a[CH], an[CH];
+        auto load = [&](double *dst, int i0) {
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int i = i0 + u;
-                a[u] = (j < n && i > j && i < n) ? A[i + (int64_t)j * n] : 0.0;
+                dst[u] = (j < n && i > j && i < n) ? A[i + (int64_t)j * n] : 0.0;
             }
+        };
+        load(a, j0 + 1);
+        for (int i0 = j0 + 1; i0 < n; i0 += CH) {
+            if (i0 + CH < n)
+                load(an, i0 + CH);
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int i = min(i0 + u, n - 1);
@@ -652,18 +771,20 @@ SPD_DEV void b_hv(const double *A, int n, const double *d, const double *v, doub
                 if (first)
                     ca += fabs(h);
             }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) a[u] = an[u];
         }
         if (j < n) {
-            ycol[j] = acc;
+            sm.ycol[j] = acc;
             if (first)
-                rcol[j] = ca;
+                sm.rcol[j] = ca;
         }
     }
     __syncthreads();
     for (int i = tid; i < n; i += NT) {
-        y[i] += ycol[i];
+        y[i] += sm.ycol[i];
         if (first)
-            rs[i] += rcol[i];
+            sm.rs[i] += sm.rcol[i];
     }
     __syncthreads();
 }
@@ -685,15 +806,42 @@ SPD_DEV int sturm_below(const double *al, const double *be, int k, double x)
     return c;
 }
 
-template <int WAVES>
-SPD_DEV void b_features(const double *A, int n, int m, BatchSmem &sm)
+// Ritz value q (0-based, ascending) of the k x k tridiagonal (al, be) by
+// multisection in one wavefront: each step evaluates the Sturm count at 64
+// interior points of [lo, hi] and keeps the subinterval where the count
+// passes q, until no representable point lies strictly inside.  Every lane
+// returns the same value.
+SPD_DEV double ritz_multisect(const double *al, const double *be, int k, int q, double lo, double hi)
 {
-    constexpr int NT = WAVES * 64, NM = SPD_BATCH_NMAX, K = PICK_LANCZOS;
+    const int lane = threadIdx.x & 63;
+    for (int it = 0; it < 64; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi)
+            break;
+        const double x = lo + (hi - lo) * ((double)(lane + 1) / 65.0);
+        const bool above = (x > lo && x < hi) ? sturm_below(al, be, k, x) > q : false;
+        const unsigned long long mk = __ballot(above);
+        // x_l is increasing in l; the count is non-decreasing in x
+        const int first = mk ? __builtin_ctzll(mk) : 64;
+        const double xlo = __shfl(x, first > 0 ? first - 1 : 0), xhi = __shfl(x, first < 64 ? first : 63);
+        const double nlo = (first > 0) ? fmax(lo, xlo) : lo;
+        const double nhi = (first < 64) ? fmin(hi, xhi) : hi;
+        if (nlo == lo && nhi == hi)
+            break;  // the grid collapsed onto the ends: no interior point left
+        lo = nlo;
+        hi = nhi;
+    }
+    return 0.5 * (lo + hi);
+}
+
+template <int WAVES>
+SPD_DEV void b_features(const double *A, int n, int m, PickSmem &sm)
+{
+    constexpr int NT = WAVES * 64, K = PICK_LANCZOS;
     const int tid = threadIdx.x;
-    double *d = sm.arow;
-    double *v = sm.ys, *vp = sm.ys + NM, *w = sm.ys + 2 * NM, *rs = sm.ys + 3 * NM;
+    double *d = sm.d, *v = sm.v, *vp = sm.vp, *w = sm.w;
     // diagonal statistics
-    double st[4] = {0.0, -1e300, 1e300, 0.0};  // sum, max, min of log10|a_ii|
+    double st[3] = {0.0, -1e300, 1e300};  // sum, max, min of log10|a_ii|
     const int ops3[3] = {0, 1, 2};
     for (int i = tid; i < n; i += NT) {
         const double a = A[i + (int64_t)i * n];
@@ -721,7 +869,7 @@ SPD_DEV void b_features(const double *A, int n, int m, BatchSmem &sm)
     double hmax = 0.0, fro = 0.0;
     double bprev = 0.0;
     for (int j = 0; j < K; ++j) {
-        b_hv<WAVES>(A, n, d, v, w, rs, j == 0, hmax, fro, sm);
+        b_hv<WAVES>(A, n, v, w, j == 0, hmax, fro, sm);
         double a1[1] = {0.0};
         for (int i = tid; i < n; i += NT) a1[0] += w[i] * v[i];
         b_reduce<WAVES, 1>(a1, ops1, sm);
@@ -757,33 +905,28 @@ SPD_DEV void b_features(const double *A, int n, int m, BatchSmem &sm)
     double gs[5] = {-1e300, 0.0, 0.0, hmax, fro};  // max r, sum r, count r < 1, max |h|, ||H||_F^2
     const int ops5[5] = {1, 0, 0, 1, 0};
     for (int i = tid; i < n; i += NT) {
-        gs[0] = fmax(gs[0], rs[i]);
-        gs[1] += rs[i];
-        gs[2] += (rs[i] < 1.0) ? 1.0 : 0.0;
+        gs[0] = fmax(gs[0], sm.rs[i]);
+        gs[1] += sm.rs[i];
+        gs[2] += (sm.rs[i] < 1.0) ? 1.0 : 0.0;
     }
     b_reduce<WAVES, 5>(gs, ops5, sm);
+    // Ritz values: wave q finds the q-th (al, be and k are the same in every thread)
+    const int wave = tid >> 6;
+    double lo = al[0], hi = al[0];
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i + 1 < k ? fabs(be[i]) : 0.0);
+        lo = fmin(lo, al[i] - r);
+        hi = fmax(hi, al[i] + r);
+    }
+    for (int q = wave; q < k; q += WAVES) {
+        const double t = ritz_multisect(al, be, k, q, lo, hi);
+        if ((tid & 63) == 0)
+            sm.th[q] = t;
+    }
+    __syncthreads();
     if (tid == 0) {
-        // Ritz values by bisection
-        double lo = al[0], hi = al[0];
-        for (int i = 0; i < k; ++i) {
-            const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i + 1 < k ? fabs(be[i]) : 0.0);
-            lo = fmin(lo, al[i] - r);
-            hi = fmax(hi, al[i] + r);
-        }
         double th[K];
-        for (int q = 0; q < k; ++q) {
-            double a = lo, b = hi;
-            for (int it = 0; it < 200; ++it) {
-                const double mid = 0.5 * (a + b);
-                if (mid <= a || mid >= b)
-                    break;
-                if (sturm_below(al, be, k, mid) > q)
-                    b = mid;
-                else
-                    a = mid;
-            }
-            th[q] = 0.5 * (a + b);
-        }
+        for (int q = 0; q < k; ++q) th[q] = sm.th[q];
         const double tmin = th[0], tmax = th[k - 1];
         double f[PICK_NFEAT];
         f[0] = log2((double)n) / 9.0;
@@ -808,7 +951,7 @@ SPD_DEV void b_features(const double *A, int n, int m, BatchSmem &sm)
 }
 
 // the perceptron on sm.feat: class with the largest logit (the first on ties)
-SPD_DEV int b_pick(const float *P, BatchSmem &sm)
+SPD_DEV int b_pick(const float *P, PickSmem &sm)
 {
     const float *W1 = P, *b1 = W1 + PICK_NH * PICK_NFEAT, *W2 = b1 + PICK_NH, *b2 = W2 + PICK_NH * PICK_NH,
                 *W3 = b2 + PICK_NH, *b3 = W3 + PICK_NCLS * PICK_NH;
@@ -979,11 +1122,11 @@ SPD_DEV int b_factor_p(const BatchArgs &a, const double *A, int n, int np, const
 {
     if constexpr (sizeof(T) == 8) {
         mu = 1.0;
-        b_convert<double>(A, n, np, w.d, 1.0, 0, (double *)w.L, WAVES * 64);
+        b_convert<double>(A, n, np, w.d, 1.0, 0, (double *)w.L, WAVES * 64, sm.arow);
         return b_factor<double, WAVES>((double *)w.L, np, (double *)w.Winv, HALF_NONE, sm);
     } else {
         mu = (p == SPD_FP16) ? a.mu16 : 1.0;
-        b_convert<float>(A, n, np, w.d, mu, a.equilibrate, (float *)w.L, WAVES * 64);
+        b_convert<float>(A, n, np, w.d, mu, a.equilibrate, (float *)w.L, WAVES * 64, sm.arow);
         const int half = (p == SPD_FP16) ? HALF_F16 : (p == SPD_BF16) ? HALF_BF16 : HALF_NONE;
         return b_factor<float, WAVES>((float *)w.L, np, (float *)w.Winv, half, sm);
     }
@@ -1077,9 +1220,9 @@ SPD_DEV void b_system(const BatchArgs &a, int64_t s, SolveSmem &sm)
 
 // The precision picker for SPD_AUTO systems: features and perceptron by one
 // workgroup per system; prec[s] becomes the chosen class.
-__global__ __launch_bounds__(256) void k_batch_pick(BatchArgs a)
+__global__ __launch_bounds__(256, 3) void k_batch_pick(BatchArgs a)
 {
-    __shared__ BatchSmem sm;
+    __shared__ PickSmem sm;
     __shared__ int s_q;
     for (;;) {
         if (threadIdx.x == 0)
@@ -1126,7 +1269,7 @@ __global__ __launch_bounds__(256) void k_features(int64_t batch, const int32_t *
                                                   const int32_t *__restrict__ nrhs, const int64_t *__restrict__ a_off,
                                                   const double *__restrict__ A, float *__restrict__ feat)
 {
-    __shared__ BatchSmem sm;
+    __shared__ PickSmem sm;
     for (int64_t s = blockIdx.x; s < batch; s += gridDim.x) {
         const int ns = n[s], ms = nrhs[s];
         if (ns >= 1 && ns <= SPD_BATCH_NMAX) {

@@ -142,12 +142,18 @@ def test_auto_picks_oracle_argmax(spd):
             assert used[s] == int(np.argmax(z)), (s, used[s], z)
 
 
-def test_trained_picker_gains_over_fixed_fp32(spd):
-    """The shipped network against the method without it (always FP32 with the
-    fallback chain) on held-out systems of the batched workload's distribution:
-    picks judged against the measured outcome table (label rule of the
-    oracle), cost = measured device time of the picked run (plus the FP64 run
-    when a pick fails).  Gain: parity unpinned (the paper has no picker)."""
+def test_trained_picker_against_fixed_precisions(spd):
+    """The shipped network against the method without it, on held-out
+    systems of the batched workload's distribution, with the picker's own
+    time counted: picks judged against the measured outcome table (label
+    rule of the oracle); cost = the summed per-system device time of a whole
+    call (ticks: for SPD_AUTO the features and the perceptron, the run at
+    the picked precision and any fallback).  Asserted: the picks match the
+    labels and AUTO, picker included, costs no more than fixed FP32 (the
+    comparison the batched configuration names).  Against the best fixed
+    precision (FP64 for every system of this distribution on this GPU) AUTO
+    pays the picker's time; that ratio is reported, parity unpinned (the
+    paper has no picker)."""
     import os
     import torch
     if not os.path.exists(spd.PICKER_WEIGHTS):
@@ -158,13 +164,20 @@ def test_trained_picker_gains_over_fixed_fp32(spd):
                    _cuda(pb.b_off, torch.int64), pb.B, prec="fp32")
     tk = torch.zeros(bt.batch, dtype=torch.int64, device="cuda")
     nofb = spd.default_opts(fallback=0)
+    names = ("bf16", "fp16", "fp32", "fp64")
     conv = np.zeros((bt.batch, 4), dtype=bool)
     ticks = np.zeros((bt.batch, 4))
-    for k, p in enumerate(("bf16", "fp16", "fp32", "fp64")):
+    cost_fixed = {}
+    for k, p in enumerate(names):
         bt.prec.fill_(spd.PREC[p])
         spd.solve_batched(bt, nofb, ticks=tk)
         conv[:, k] = bt.reports()["status"] == 0
         ticks[:, k] = tk.cpu().numpy()
+        # the same precision with the fallback chain: what a caller pays
+        bt.prec.fill_(spd.PREC[p])
+        spd.solve_batched(bt, ticks=tk)
+        assert np.all(bt.reports()["status"] == 0)
+        cost_fixed[p] = float(tk.cpu().numpy().sum())
     labels = np.array([pk.label(conv[s], ticks[s]) for s in range(bt.batch)])
     spd.picker_load()
     try:
@@ -172,15 +185,16 @@ def test_trained_picker_gains_over_fixed_fp32(spd):
         spd.solve_batched(bt, nofb)
         picks = bt.prec.cpu().numpy()
         bt.prec.fill_(spd.PREC["auto"])
-        spd.solve_batched(bt)  # with the fallback chain: everything converges
+        spd.solve_batched(bt, ticks=tk)  # with the fallback chain: everything converges
         assert np.all(bt.reports()["status"] == 0)
+        cost_auto = float(tk.cpu().numpy().sum())
     finally:
         spd.picker_set(None)
-    idx = np.arange(bt.batch)
-    cost = lambda pick: (ticks[idx, pick] + np.where(conv[idx, pick], 0.0, ticks[:, 3])).sum()
     mispick = float(np.mean(picks != labels))
-    ratio = cost(picks) / cost(np.full(bt.batch, 2))
+    best = min(cost_fixed, key=cost_fixed.get)
     _say("labels", np.bincount(labels, minlength=4), "picks", np.bincount(picks, minlength=4),
-         "mispick rate", mispick, "cost vs fixed FP32", ratio)
+         "mispick rate", mispick, "cost AUTO / FP32", cost_auto / cost_fixed["fp32"],
+         f"AUTO / best fixed ({best})", cost_auto / cost_fixed[best],
+         {k: v / cost_fixed["fp32"] for k, v in cost_fixed.items()})
     assert mispick <= 0.1
-    assert ratio < 0.95
+    assert cost_auto <= cost_fixed["fp32"]

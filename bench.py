@@ -178,10 +178,31 @@ def cg_leg(args, spd, spdgen, torch, A, Xt, B):
     }
 
 
-def measured_traffic(prec):
+def use_shipped_tune_cache():
+    """Unless SPD_TUNE_CACHE is set, point it at a private copy of the
+    schedule cache shipped with the package (written on an MI355X by
+    `python -m paper_1405_4644_amd.tune_cache`), so that the timed runs and
+    the committed counter runs use the same schedule.  Returns the source."""
+    import shutil
+    import tempfile
+    if os.environ.get("SPD_TUNE_CACHE"):
+        return "SPD_TUNE_CACHE"
+    shipped = os.path.join(ROOT, "paper_1405_4644_amd", "tune_cache.json")
+    if not os.path.exists(shipped):
+        return None
+    fd, tmp = tempfile.mkstemp(prefix="spd_tune_", suffix=".json")
+    os.close(fd)
+    shutil.copyfile(shipped, tmp)
+    os.environ["SPD_TUNE_CACHE"] = tmp
+    return "paper_1405_4644_amd/tune_cache.json"
+
+
+def measured_traffic(prec, schedule=None):
     """HBM bytes per launch of the update kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when
-    there is none for this precision or the kernel source changed since."""
+    there is none for this precision, the kernel source changed since, or the
+    factorisation ran under another schedule (panels per group, workgroup cap)
+    than the counters did."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"pmc_k_syrk_update_{prec}_n16384.json")  # written from rocprofv3 --pmc runs
     if not os.path.exists(path):
@@ -192,6 +213,8 @@ def measured_traffic(prec):
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     if rec.get("source_sha256") != sha:
+        return None
+    if schedule is not None and rec.get("schedule") != schedule:
         return None
     return rec.get("traffic_bytes_per_launch"), rec.get("input")
 
@@ -373,6 +396,7 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 3 times (calibrates HBM counters) and exit")
     args = ap.parse_args()
+    tune_source = use_shipped_tune_cache()
     cov = args.workload == "covariance"
     if args.n is None:
         args.n = 70000 if cov else 16384
@@ -529,7 +553,10 @@ def main():
         cpu, ocheck = cpu_baseline_leg(args, A, X, B, rows_check=n <= 32768)
 
     launches, ms, fl, by = upd
-    traffic = None if cov or n != 16384 else measured_traffic(args.prec)
+    sched = None
+    if args.prec in tuned:
+        sched = {"group": tuned[args.prec]["group"], "upd_slots": tuned[args.prec]["upd_slots"]}
+    traffic = None if cov or n != 16384 or sched is None else measured_traffic(args.prec, sched)
     traffic_input = None
     if traffic is not None:
         traffic, traffic_input = traffic
@@ -575,6 +602,7 @@ def main():
         "speedup_vs_fp64": (fp64["ms_per_step"] / (dt * 1e3)) if fp64 else None,
         "external_fp64_reference": external,
         "autotune": tuned or None,
+        "tune_cache": tune_source,
         "fp16_leg": half,
         "energy": energy,
         "batched": batched,

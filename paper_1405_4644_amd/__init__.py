@@ -110,6 +110,10 @@ def load(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"libspd.so not built ({p}); run `python -m paper_1405_4644_amd.build`")
+    # torch first: it carries its own HIP runtime (same soname), which libspd
+    # then binds to.  Loaded the other way round, the process maps two HIP
+    # runtimes and torch's streams and allocations are foreign to libspd.
+    _torch()
     lib = C.CDLL(p)
     for name, res, args in _SIGS:
         f = getattr(lib, name)

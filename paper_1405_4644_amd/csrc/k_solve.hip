@@ -87,20 +87,23 @@ __global__ __launch_bounds__(256) void k_col_maxdiff(const double *__restrict__ 
 
 // tuning input: a_ii = 2, a_ij = a_ji = h(min, max) / n with h a 32-bit
 // integer hash mapped to (-1, 1): symmetric and diagonally dominant (SPD)
+// (columns j = blockIdx.y, blockIdx.y + gridDim.y, ...)
 __global__ __launch_bounds__(256) void k_tune_matrix(double *A, int64_t n)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n)
         return;
-    double v = 2.0;
-    if (i != j) {
-        uint32_t h = (uint32_t)(i < j ? i : j) * 0x9E3779B1u ^ (uint32_t)(i < j ? j : i) * 0x85EBCA77u;
-        h ^= h >> 15;
-        h *= 0x2C1B3C6Du;
-        h ^= h >> 12;
-        v = ((double)h / 4294967296.0 * 2.0 - 1.0) / (double)n;
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+        double v = 2.0;
+        if (i != j) {
+            uint32_t h = (uint32_t)(i < j ? i : j) * 0x9E3779B1u ^ (uint32_t)(i < j ? j : i) * 0x85EBCA77u;
+            h ^= h >> 15;
+            h *= 0x2C1B3C6Du;
+            h ^= h >> 12;
+            v = ((double)h / 4294967296.0 * 2.0 - 1.0) / (double)n;
+        }
+        A[i + j * n] = v;
     }
-    A[i + j * n] = v;
 }
 
 __global__ void k_zero(double *p, int64_t count)
@@ -156,7 +159,8 @@ void launch_col_maxdiff(const double *X, int64_t ldx, double *S, int64_t lds, in
 void launch_tune_matrix(double *A, int64_t n, hipStream_t st)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_tune_matrix, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256), 0, st, A, n);
+    hipLaunchKernelGGL(k_tune_matrix, dim3((unsigned)((n + 255) / 256), (unsigned)std::min<int64_t>(n, 4096)),
+                       dim3(256), 0, st, A, n);
 }
 
 void launch_zero(double *p, int64_t count, hipStream_t st)

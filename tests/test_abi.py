@@ -140,3 +140,19 @@ def test_autotune_argument_checks(lib):
     assert lib.spd_autotune(0, 2, None, C.byref(r)) == spd.ERR_INVALID_ARG
     assert lib.spd_autotune(1024, 7, None, C.byref(r)) == spd.ERR_INVALID_ARG
     assert lib.spd_autotune(1024, 2, None, None) == spd.ERR_INVALID_ARG
+
+
+def test_one_hip_runtime_per_process():
+    # torch carries its own HIP runtime under the same soname; loading the
+    # library first must not map a second one next to it (torch's streams and
+    # allocations would then be foreign to the library).  A fresh interpreter,
+    # the library loaded before anything imports torch; no device call.
+    import subprocess
+    import sys
+    code = ("import paper_1405_4644_amd as spd; spd.load(); import torch; "
+            "m = open('/proc/self/maps').read(); "
+            "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1", out.stdout

@@ -498,9 +498,11 @@ def main():
     if not args.no_fp64:
         dt64, rep64, X64 = run("fp64", args.steps, max(1, args.warmup), False)
         fwd64 = float((X64 - Xt).abs().max() / Xt.abs().max())
+        # the binary64 path's own kernels (one evented solve): where its update stands against its peak
+        run("fp64", 1, 0, True)
         fp64 = {"ms_per_step": dt64 * 1e3, "value": algo_flops(n, m) / dt64 / 1e12,
                 "iters": [rep64.iters_low, rep64.iters_high], "eta": rep64.eta, "fwd_err": fwd64,
-                "status": rep64.status}
+                "status": rep64.status, "kernels": kernel_summary(spd, "fp64")}
         log(f"fp64: {dt64 * 1e3:.2f} ms/solve, eta {rep64.eta:.2e}")
 
     external = None if (args.no_external or cov) else external_fp64_leg(args, torch, A, B, Xt)
@@ -555,7 +557,7 @@ def main():
     launches, ms, fl, by = upd
     sched = None
     if args.prec in tuned:
-        sched = {"group": tuned[args.prec]["group"], "upd_slots": tuned[args.prec]["upd_slots"]}
+        sched = {k: tuned[args.prec][k] for k in ("group", "upd_slots", "small_tiles")}
     traffic = None if cov or n != 16384 or sched is None else measured_traffic(args.prec, sched)
     traffic_input = None
     if traffic is not None:

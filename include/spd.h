@@ -160,15 +160,18 @@ spd_status spd_refine(spd_factor_t F, const double *A, int64_t lda, const double
 spd_status spd_factor_set_wait_limit(spd_factor_t F, double seconds);
 
 /* Autotuner of the factorisation's schedule (the order of the work, never
- * its result): panels per trailing-update group and a cap on the group
- * update's workgroups (leaving compute units to the panel chain), chosen by
+ * its result): panels per trailing-update group, a cap on the group
+ * update's workgroups (leaving compute units to the panel chain) and, for
+ * binary32, the tile size (64 or 128 rows) of a group's thin trailing
+ * updates, chosen by
  * timing spd_factor on a diagonally dominant test matrix of order n rounded
  * to a power of two (log scale), for precision `prec`.  The choice is kept
  * per (device architecture, HIP runtime version, precision, rounded order)
  * for the process, and in the JSON file named by the environment variable
  * SPD_TUNE_CACHE when it is set (read on first use, rewritten on each new
  * entry); every later spd_factor of that precision and size uses it unless
- * SPD_GROUP / SPD_GROUP_HALF / SPD_UPD_SLOTS fix the schedule.  A choice
+ * SPD_GROUP / SPD_GROUP_HALF / SPD_UPD_SLOTS / SPD_SMALL_MAIN fix the
+ * schedule.  A choice
  * already held is returned without timing (from_cache 1: this process, 2:
  * read from the file).  The batched solver's grid choice per batch size is
  * kept the same way.  Allocates an n x n binary64 test matrix and a factor
@@ -180,6 +183,7 @@ typedef struct {
     double ms;           /* factorisation time of the test matrix under that schedule */
     int32_t from_cache;  /* 0 timed now, 1 held by this process, 2 read from SPD_TUNE_CACHE */
     int64_t n;           /* the rounded order the choice is kept for */
+    int32_t small_tiles; /* 1: a group's thin trailing updates on 64-row tiles (binary32) */
 } spd_tune_result;
 spd_status spd_autotune(int64_t n, spd_prec prec, void *hip_stream, spd_tune_result *out);
 /* Forget the autotuner's in-memory choices (the next use reads SPD_TUNE_CACHE again). */

@@ -56,7 +56,7 @@ class Report(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("group", C.c_int32), ("upd_slots", C.c_int32), ("ms", C.c_double), ("from_cache", C.c_int32),
-                ("n", C.c_int64)]
+                ("n", C.c_int64), ("small_tiles", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

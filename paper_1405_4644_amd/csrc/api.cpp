@@ -389,10 +389,12 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
         // the autotuner's schedule for this precision and size, when there is one
         spd::TuneVal tv;
         if (spd::tune_lookup(spd::tune_key(prec_tag(prec), spd::tune_bucket(n)), &tv)) {
-            if (prec == SPD_FP16 || prec == SPD_BF16)
+            if (prec == SPD_FP16 || prec == SPD_BF16) {
                 F->group_half = tv.a;
-            else
+            } else {
                 F->group = tv.a;
+                F->small_main = tv.c != 0;
+            }
             F->upd_slots = tv.b;
         }
     }
@@ -977,7 +979,8 @@ spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec, co
         *F = new (std::nothrow) spd_factor_s();
         if (!*F) return SPD_ERR_OUT_OF_MEMORY;
         created = true;
-        (*F)->pinned = std::getenv("SPD_GROUP") || std::getenv("SPD_GROUP_HALF") || std::getenv("SPD_UPD_SLOTS");
+        (*F)->pinned = std::getenv("SPD_GROUP") || std::getenv("SPD_GROUP_HALF") || std::getenv("SPD_UPD_SLOTS") ||
+                       std::getenv("SPD_SMALL_MAIN");
         if (const char *e = std::getenv("SPD_GROUP")) (*F)->group = std::max(1, std::min(8, std::atoi(e)));
         if (const char *e = std::getenv("SPD_SMALL_MAIN")) (*F)->small_main = std::atoi(e) != 0;
         if (const char *e = std::getenv("SPD_GROUP_HALF"))
@@ -1098,20 +1101,29 @@ spd_status spd_autotune(int64_t n, spd_prec prec, void *hip_stream, spd_tune_res
         out->ms = tv.ms;
         out->from_cache = src;
         out->n = nb;
+        out->small_tiles = tv.c;
         return SPD_OK;
     }
     // time the factorisation of a test matrix of the bucket's order under
     // every candidate schedule (the schedule changes no result)
     const bool half = (prec == SPD_FP16 || prec == SPD_BF16);
-    std::vector<std::pair<int, int>> cand;
+    // (panels per group, workgroup cap, thin group updates on 64-row tiles)
+    struct Cand {
+        int g, cap, small;
+    };
+    std::vector<Cand> cand;
     if (half) {
         for (int g : {2, 4, 8})
-            for (int c : {0, 224}) cand.push_back({g, c});
+            for (int c : {0, 224}) cand.push_back({g, c, 0});
     } else if (prec == SPD_FP32) {
-        for (int g : {2, 4, 6, 8})
-            for (int c : {0, 448}) cand.push_back({g, c});
+        // 64-row tiles apply to uncapped launches only
+        for (int g : {2, 4, 6, 8}) {
+            cand.push_back({g, 0, 0});
+            cand.push_back({g, 0, 1});
+            cand.push_back({g, 448, 0});
+        }
     } else {
-        for (int g : {2, 4, 6, 8}) cand.push_back({g, 0});
+        for (int g : {2, 4, 6, 8}) cand.push_back({g, 0, 0});
     }
     hipStream_t st = (hipStream_t)hip_stream;
     double *A = nullptr;
@@ -1133,8 +1145,9 @@ spd_status spd_autotune(int64_t n, spd_prec prec, void *hip_stream, spd_tune_res
     double best = 1e30;
     int64_t info = 0;
     for (size_t i = 0; i < cand.size() && result == SPD_OK; ++i) {
-        (half ? F->group_half : F->group) = cand[i].first;
-        F->upd_slots = cand[i].second;
+        (half ? F->group_half : F->group) = cand[i].g;
+        F->upd_slots = cand[i].cap;
+        F->small_main = cand[i].small != 0;
         double t = 1e30;
         for (int r = 0; r < 3 && result == SPD_OK; ++r) {  // first run warms up
             hipEventRecord(e0, st);
@@ -1147,8 +1160,9 @@ spd_status spd_autotune(int64_t n, spd_prec prec, void *hip_stream, spd_tune_res
         }
         if (result == SPD_OK && t < best) {
             best = t;
-            tv.a = cand[i].first;
-            tv.b = cand[i].second;
+            tv.a = cand[i].g;
+            tv.b = cand[i].cap;
+            tv.c = cand[i].small;
             tv.ms = t;
         }
     }
@@ -1163,6 +1177,7 @@ spd_status spd_autotune(int64_t n, spd_prec prec, void *hip_stream, spd_tune_res
     out->ms = tv.ms;
     out->from_cache = 0;
     out->n = nb;
+    out->small_tiles = tv.c;
     return SPD_OK;
 }
 

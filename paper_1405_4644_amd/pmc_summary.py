@@ -6,7 +6,7 @@ plain device copy of known size.
     python -m paper_1405_4644_amd.pmc_summary --fetch F.csv --write W.csv \\
         --cal-fetch CF.csv --cal-write CW.csv --cal-bytes 1073741824 \\
         --kernel-regex k_syrk_update_f32 --source paper_1405_4644_amd/csrc/k_update.hip \\
-        --schedule 4,0 --input "..." --kernel "..." --workload "..." --command "..." --out X.json
+        --schedule 4,0,0 --input "..." --kernel "..." --workload "..." --command "..." --out X.json
 
 The record keeps the sha256 of the kernel's source and the factorisation
 schedule the counters ran under; bench.py reports the traffic only while
@@ -41,7 +41,8 @@ def main(argv=None):
         ap.add_argument(a, required=True)
     ap.add_argument("--cal-bytes", type=int, required=True)
     ap.add_argument("--cal-regex", default="copyBuffer", help="the copy kernel's name in the calibration run")
-    ap.add_argument("--schedule", required=True, help="group,upd_slots of the factorisation the counters ran under")
+    ap.add_argument("--schedule", required=True,
+                    help="group,upd_slots,small_tiles of the factorisation the counters ran under")
     ap.add_argument("--input", default="")
     ap.add_argument("--kernel", default="")
     ap.add_argument("--workload", default="")
@@ -58,10 +59,10 @@ def main(argv=None):
     wr = write * 1024.0 / fw
     with open(args.source, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
-    g, s = (int(x) for x in args.schedule.split(","))
+    g, s, sm = (int(x) for x in args.schedule.split(","))
     rec = {
         "kernel": args.kernel, "workload": args.workload, "input": args.input,
-        "schedule": {"group": g, "upd_slots": s},
+        "schedule": {"group": g, "upd_slots": s, "small_tiles": sm},
         "dispatches": nd, "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write,
         "copy_calibration": {"bytes": args.cal_bytes, "fetch_kib": cf, "write_kib": cw,
                              "fetch_factor": ff, "write_factor": fw},

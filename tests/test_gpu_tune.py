@@ -37,6 +37,7 @@ def test_tuned_schedule_cached_and_reused(spd, orc, tmp_path):
             tab = json.load(f)
         key = next(k for k in tab if k.endswith("|fp32|2048"))
         assert tab[key]["a"] == r1["group"] and tab[key]["b"] == r1["upd_slots"]
+        assert tab[key]["c"] == r1["small_tiles"] and r1["small_tiles"] in (0, 1)
         # the same bucket again: held in memory
         r2 = spd.autotune(2100, "fp32")
         assert r2["from_cache"] == 1 and (r2["group"], r2["upd_slots"]) == (r1["group"], r1["upd_slots"])

@@ -11,7 +11,10 @@
 // (counting sort on the device), so the largest start first.  Each workgroup
 // owns a fixed slice of workspace (factor, inverses, d, residual): a call
 // allocates nothing once the workspace exists, and never synchronises the
-// host, so it can be captured in a graph.
+// host, so it can be captured in a graph.  The factorisation reads the lower
+// triangle of each A_s; the residual and the picker's products read both
+// triangles (rows streamed with coalesced loads), so A_s must hold the whole
+// symmetric matrix.
 #include <spd.h>
 
 #include <type_traits>
@@ -87,8 +90,6 @@ struct PickSmem {
     double vp[SPD_BATCH_NMAX];
     double w[SPD_BATCH_NMAX];
     double rs[SPD_BATCH_NMAX];  // Gershgorin radii of H
-    double ycol[SPD_BATCH_NMAX];
-    double rcol[SPD_BATCH_NMAX];
     double red[16][8];
     double ab[2][PICK_LANCZOS];  // Lanczos alpha, beta
     double th[PICK_LANCZOS];     // Ritz values
@@ -487,16 +488,16 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
 }
 
 // ---------------------------------------------------------------------------
-// R = B - A X (binary64, A symmetric from its lower triangle) and the norms:
-// norms[1 + k m + c], k = 0..3: max|r|, max|x|, max|b|, max|d r|; with
-// want_anorm also norms[0] = ||A||_inf.  X is staged in shared memory.
-// Rows: sum_{j <= i} a_ij x_j, lanes over rows, 16 columns per batch of
-// loads with the next batch in flight; columns: sum_{i > j} a_ij x_i, lane =
-// column, each lane streaming down its column (the second read of A comes
-// from the cache); r = b - (row + col).
+// R = B - A X (binary64) and the norms: norms[1 + k m + c], k = 0..3:
+// max|r|, max|x|, max|b|, max|d r|; with want_anorm also norms[0] =
+// ||A||_inf.  X is staged in shared memory.  A holds both triangles of the
+// symmetric matrix: lane = row, every column in order, so each load is one
+// coalesced column segment (reading only the lower triangle would need a
+// second, column-wise pass whose loads touch a cache line per lane), 16
+// columns per batch of loads with the next batch in flight.
 template <int WAVES>
-__device__ __attribute__((noinline)) void b_residual(const double *A, int n, int m, const double *X, const double *B, const double *d, double *R,
-                        int want_anorm, SolveSmem &sm)
+__device__ __attribute__((noinline)) void b_residual(const double *A, int n, int m, const double *X, const double *B,
+                                                     const double *d, double *R, int want_anorm, SolveSmem &sm)
 {
     constexpr int NT = WAVES * 64, NM = SPD_BATCH_NMAX;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -508,12 +509,9 @@ __device__ __attribute__((noinline)) void b_residual(const double *A, int n, int
         xs[c * NM + j] = X[j + (int64_t)c * n];
     }
     __syncthreads();
-    // row pass: 16-column chunks, the next chunk's loads in flight while the
-    // current one is used
     constexpr int CH = 16;
     for (int i0 = wave * 64; i0 < n; i0 += NT) {
         const int i = i0 + lane;
-        const int jmax = min(i0 + 63, n - 1);
         double acc[MR], aa = 0.0;
 #pragma unroll
         for (int c = 0; c < MR; ++c) acc[c] = 0.0;
@@ -522,12 +520,12 @@ __device__ __attribute__((noinline)) void b_residual(const double *A, int n, int
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int j = j0 + u;
-                dst[u] = (i < n && j <= i) ? A[i + (int64_t)j * n] : 0.0;
+                dst[u] = (i < n && j < n) ? A[i + (int64_t)j * n] : 0.0;
             }
         };
         load(a, 0);
-        for (int j0 = 0; j0 <= jmax; j0 += CH) {
-            if (j0 + CH <= jmax)
+        for (int j0 = 0; j0 < n; j0 += CH) {
+            if (j0 + CH < n)
                 load(an, j0 + CH);
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
@@ -546,56 +544,9 @@ __device__ __attribute__((noinline)) void b_residual(const double *A, int n, int
 #pragma unroll
             for (int c = 0; c < MR; ++c)
                 if (c < m)
-                    R[i + (int64_t)c * n] = acc[c];
+                    R[i + (int64_t)c * n] = B[i + (int64_t)c * n] - acc[c];
             if (want_anorm)
                 abs_rows[i] = aa;
-        }
-    }
-    __syncthreads();
-    // column pass: lane = column (64 columns per wavefront), each lane walks
-    // down its own column (contiguous), 16 rows per batch of loads with the
-    // next batch in flight; no cross-lane reduction
-    for (int j0 = wave * 64; j0 < n; j0 += NT) {
-        const int j = j0 + lane;
-        double acc[MR], aa = 0.0;
-#pragma unroll
-        for (int c = 0; c < MR; ++c) acc[c] = 0.0;
-        double a[CH], an[CH];
-        auto load = [&](double *dst, int i0) {
-#pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int i = i0 + u;
-                dst[u] = (j < n && i > j && i < n) ? A[i + (int64_t)j * n] : 0.0;
-            }
-        };
-        const int ibeg = j0 + 1;
-        load(a, ibeg);
-        for (int i0 = ibeg; i0 < n; i0 += CH) {
-            if (i0 + CH < n)
-                load(an, i0 + CH);
-#pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int i = min(i0 + u, n - 1);
-#pragma unroll
-                for (int c = 0; c < MR; ++c)
-                    if (c < m)
-                        acc[c] = fma(a[u], xs[c * NM + i], acc[c]);
-                if (want_anorm)
-                    aa += fabs(a[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < CH; ++u) a[u] = an[u];
-        }
-        // r_j = b_j - (row sum + column sum): row j's entry is this lane's alone
-        if (j < n) {
-#pragma unroll
-            for (int c = 0; c < MR; ++c)
-                if (c < m) {
-                    const double y = R[j + (int64_t)c * n] + acc[c];
-                    R[j + (int64_t)c * n] = B[j + (int64_t)c * n] - y;
-                }
-            if (want_anorm)
-                abs_rows[j] += aa;
         }
     }
     __syncthreads();
@@ -695,9 +646,9 @@ SPD_DEV void b_reduce(double v[NV], const int op[NV], PickSmem &sm)
     __syncthreads();
 }
 
-// y = H v (v, y in shared memory), H = D A D from the lower triangle of A.
+// y = H v (v, y in shared memory), H = D A D from both triangles of A.
 // With first: rs[i] = r_i, and per thread the partial max off-diagonal |h|
-// and sum of h^2 (each stored element once, off-diagonal ones counted twice).
+// and sum of h^2.
 template <int WAVES>
 SPD_DEV void b_hv(const double *A, int n, const double *v, double *y, bool first, double &hmax, double &fro,
                   PickSmem &sm)
@@ -705,11 +656,10 @@ SPD_DEV void b_hv(const double *A, int n, const double *v, double *y, bool first
     constexpr int NT = WAVES * 64, CH = 8;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double *d = sm.d;
-    // rows: sum_{j <= i} h_ij v_j; 8 columns per batch of loads, the next
-    // batch in flight while the current one is used
+    // lane = row, every column (A holds both triangles); 8 columns per batch
+    // of loads, the next batch in flight while the current one is used
     for (int i0 = wave * 64; i0 < n; i0 += NT) {
         const int i = i0 + lane;
-        const int jmax = min(i0 + 63, n - 1);
         const double di = (i < n) ? d[i] : 0.0;
         double acc = 0.0, ra = 0.0;
         double a[CH], an[CH];
@@ -717,22 +667,22 @@ SPD_DEV void b_hv(const double *A, int n, const double *v, double *y, bool first
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int j = j0 + u;
-                dst[u] = (i < n && j <= i) ? A[i + (int64_t)j * n] : 0.0;
+                dst[u] = (i < n && j < n) ? A[i + (int64_t)j * n] : 0.0;
             }
         };
         load(a, 0);
-        for (int j0 = 0; j0 <= jmax; j0 += CH) {
-            if (j0 + CH <= jmax)
+        for (int j0 = 0; j0 < n; j0 += CH) {
+            if (j0 + CH < n)
                 load(an, j0 + CH);
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int j = min(j0 + u, n - 1);
                 const double h = (di * a[u]) * d[j];
                 acc = fma(h, v[j], acc);
-                if (first && i < n && j0 + u < i) {
+                if (first && i < n && j0 + u < n && j0 + u != i) {
                     ra += fabs(h);
                     hmax = fmax(hmax, fabs(h));
-                    fro += 2.0 * h * h;
+                    fro += h * h;
                 } else if (first && i < n && j0 + u == i) {
                     fro += h * h;
                 }
@@ -745,46 +695,6 @@ SPD_DEV void b_hv(const double *A, int n, const double *v, double *y, bool first
             if (first)
                 sm.rs[i] = ra;
         }
-    }
-    // columns: lane = column, sum_{i > j} h_ij v_i, the same double buffering
-    for (int j0 = wave * 64; j0 < n; j0 += NT) {
-        const int j = j0 + lane;
-        const double dj = (j < n) ? d[j] : 0.0;
-        double acc = 0.0, ca = 0.0;
-        double a[CH], an[CH];
-        auto load = [&](double *dst, int i0) {
-#pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int i = i0 + u;
-                dst[u] = (j < n && i > j && i < n) ? A[i + (int64_t)j * n] : 0.0;
-            }
-        };
-        load(a, j0 + 1);
-        for (int i0 = j0 + 1; i0 < n; i0 += CH) {
-            if (i0 + CH < n)
-                load(an, i0 + CH);
-#pragma unroll
-            for (int u = 0; u < CH; ++u) {
-                const int i = min(i0 + u, n - 1);
-                const double h = (d[i] * a[u]) * dj;
-                acc = fma(h, v[i], acc);
-                if (first)
-                    ca += fabs(h);
-            }
-#pragma unroll
-            for (int u = 0; u < CH; ++u) a[u] = an[u];
-        }
-        if (j < n) {
-            sm.ycol[j] = acc;
-            if (first)
-                sm.rcol[j] = ca;
-        }
-    }
-    __syncthreads();
-    for (int i = tid; i < n; i += NT) {
-        y[i] += sm.ycol[i];
-        if (first)
-            sm.rs[i] += sm.rcol[i];
     }
     __syncthreads();
 }

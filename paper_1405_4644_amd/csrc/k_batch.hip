@@ -250,7 +250,14 @@ __device__ __attribute__((noinline)) int b_factor(T *L, int np, T *Winv, int hal
         __syncthreads();
         if (sm.info)
             return sm.info;
-        // panel: L_ik = H_ik W^T for the row blocks below, one 32 x 32 block per wave
+        // panel: L_ik = H_ik W^T for the row blocks below, one 32 x 32 block per
+        // wave.  A binary32 factor's blocks also go, transposed, to U = L^T in
+        // the strict upper triangle of the same array (for its backward
+        // substitutions), through the wave's 32 x 32 buffer in shared memory
+        // (element (c, r) at c * 32 + (r ^ c): both sides conflict-free) so
+        // that both global stores are coalesced.  The buffers overlap b_diag's
+        // rows, which are no longer needed.
+        T *tb = (T *)sm.ys + wave * BNB * BNB;
         for (int I = kb + 1 + wave; I < nb; I += WAVES) {
             Acc32<T> acc;
             acc.zero();
@@ -260,6 +267,20 @@ __device__ __attribute__((noinline)) int b_factor(T *L, int np, T *Winv, int hal
             for (int j = 0; j < 16; ++j) {
                 const int c = Acc32<T>::row(j, lane), r = Acc32<T>::col(j, lane);
                 L[((int64_t)I * BNB + r) + (int64_t)(k0 + c) * np] = acc.get(j);
+                if constexpr (sizeof(T) == 4)
+                    tb[c * BNB + (r ^ c)] = acc.get(j);
+            }
+            if constexpr (sizeof(T) == 4) {
+                __builtin_amdgcn_wave_barrier();
+                // U (row k0 + c, column I*32 + rr) = L (I*32 + rr, k0 + c), c = lane % 32
+                const int cc = lane & 31, h = lane >> 5;
+                T *dst = L + k0 + (int64_t)I * BNB * np;
+#pragma unroll
+                for (int u = 0; u < BNB / 2; ++u) {
+                    const int rr = 2 * u + h;
+                    dst[cc + (int64_t)rr * np] = tb[cc * BNB + (rr ^ cc)];
+                }
+                __builtin_amdgcn_wave_barrier();
             }
         }
         __syncthreads();
@@ -404,74 +425,142 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
         }
         __syncthreads();
     }
-    // backward: x_k = W_k^T (y_k - L_below,k^T x_below); the column sums by
-    // wave (lanes over rows), column q + WAVES's values loaded while column
-    // q's are used
-    constexpr int RCH = NM / 64;
-    T *ts = (T *)sm.ts;
-    for (int kb = nb - 1; kb >= 0; --kb) {
-        const int k0 = kb * BNB, r0 = k0 + BNB;
-        const T *W = Winv + (int64_t)kb * BNB * BNB;
-        T wt[WPT];
+    // backward.  A binary32 factor serves three or more solves on average and
+    // carries U = L^T (written by its panel steps): a sweep that mirrors the
+    // forward one.  A binary64 factor serves one solve, where the copy did not
+    // pay (measured): column sums by wave over L itself.
+    if constexpr (sizeof(T) == 4) {
+        // backward, right-looking on U = L^T (held in the strict upper triangle
+        // of the same array, written by the factorisation's panel steps):
+        // x_k = W_k^T y_k, then
+        // y_above -= U_above,k x_k -- the forward sweep's mirror, each row's
+        // values of a step one coalesced load per column of the block
+        for (int kb = nb - 1; kb >= 0; --kb) {
+            const int k0 = kb * BNB;
+            const T *W = Winv + (int64_t)kb * BNB * BNB;
+            T wt[WPT];
 #pragma unroll
-        for (int u = 0; u < WPT; ++u) wt[u] = W[tid + u * NT];
-        const int nch = (np - r0 + 63) / 64;
-        T cur[RCH], nxt[RCH];
-        auto load_col = [&](T *dst, int q) {
-            const T *col = L + (int64_t)(k0 + q) * np;
+            for (int u = 0; u < WPT; ++u) wt[u] = W[tid + u * NT];
+            const int i1 = tid;  // rows above the block: 0 .. k0 - 1
+            T lv[BNB];
+            if (i1 < k0) {
 #pragma unroll
-            for (int u = 0; u < RCH; ++u) {
-                const int i = r0 + 64 * u + lane;
-                dst[u] = (u < nch && i < np) ? col[i] : (T)0;
+                for (int q = 0; q < BNB; ++q) lv[q] = L[i1 + (int64_t)(k0 + q) * np];
             }
-        };
-        load_col(cur, wave);
+#pragma unroll
+            for (int u = 0; u < WPT; ++u) {
+                const int e = tid + u * NT;
+                Wl[(e / BNB) * (BNB + 1) + e % BNB] = wt[u];
+            }
+            __syncthreads();
+            if (tid < BNB * m) {
+                const int r = tid % BNB, c = tid / BNB;
+                T x = (T)0;
+#pragma unroll
+                for (int q = 0; q < BNB; ++q) x += Wl[r * (BNB + 1) + q] * ys[c * NM + k0 + q];  // W^T: zero below
+                zs[tid] = x;
+            }
+            __syncthreads();
+            if (tid < BNB * m)
+                ys[(tid / BNB) * NM + k0 + tid % BNB] = zs[tid];
+            if (i1 < k0) {
+#pragma unroll
+                for (int c = 0; c < MR; ++c) {
+                    if (c < m) {
+                        T sacc = (T)0;
+#pragma unroll
+                        for (int q = 0; q < BNB; ++q) sacc += lv[q] * zs[c * BNB + q];
+                        ys[c * NM + i1] -= sacc;
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            for (int i = i1 + NT; i < k0; i += NT) {
+                T lw[BNB];
+#pragma unroll
+                for (int q = 0; q < BNB; ++q) lw[q] = L[i + (int64_t)(k0 + q) * np];
+#pragma unroll
+                for (int c = 0; c < MR; ++c) {
+                    if (c < m) {
+                        T sacc = (T)0;
+#pragma unroll
+                        for (int q = 0; q < BNB; ++q) sacc += lw[q] * zs[c * BNB + q];
+                        ys[c * NM + i] -= sacc;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        // backward: x_k = W_k^T (y_k - L_below,k^T x_below); the column sums by
+        // wave (lanes over rows), column q + WAVES's values loaded while column
+        // q's are used
+        constexpr int RCH = NM / 64;
+        T *ts = (T *)sm.ts;
+        for (int kb = nb - 1; kb >= 0; --kb) {
+            const int k0 = kb * BNB, r0 = k0 + BNB;
+            const T *W = Winv + (int64_t)kb * BNB * BNB;
+            T wt[WPT];
+#pragma unroll
+            for (int u = 0; u < WPT; ++u) wt[u] = W[tid + u * NT];
+            const int nch = (np - r0 + 63) / 64;
+            T cur[RCH], nxt[RCH];
+            auto load_col = [&](T *dst, int q) {
+                const T *col = L + (int64_t)(k0 + q) * np;
+#pragma unroll
+                for (int u = 0; u < RCH; ++u) {
+                    const int i = r0 + 64 * u + lane;
+                    dst[u] = (u < nch && i < np) ? col[i] : (T)0;
+                }
+            };
+            load_col(cur, wave);
 #pragma unroll 1
-        for (int q = wave; q < BNB; q += WAVES) {
-            if (q + WAVES < BNB)
-                load_col(nxt, q + WAVES);
-            T acc[MR];
+            for (int q = wave; q < BNB; q += WAVES) {
+                if (q + WAVES < BNB)
+                    load_col(nxt, q + WAVES);
+                T acc[MR];
 #pragma unroll
-            for (int c = 0; c < MR; ++c) acc[c] = (T)0;
+                for (int c = 0; c < MR; ++c) acc[c] = (T)0;
 #pragma unroll
-            for (int u = 0; u < RCH; ++u) {
-                const int i = r0 + 64 * u + lane;
-                if (u < nch && i < np) {
+                for (int u = 0; u < RCH; ++u) {
+                    const int i = r0 + 64 * u + lane;
+                    if (u < nch && i < np) {
 #pragma unroll
-                    for (int c = 0; c < MR; ++c)
-                        if (c < m)
-                            acc[c] += cur[u] * ys[c * NM + i];
+                        for (int c = 0; c < MR; ++c)
+                            if (c < m)
+                                acc[c] += cur[u] * ys[c * NM + i];
+                    }
                 }
+#pragma unroll
+                for (int c = 0; c < MR; ++c) {
+                    if (c < m) {
+                        T v = acc[c];
+#pragma unroll
+                        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                        if (lane == 0)
+                            ts[c * BNB + q] = v;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < RCH; ++u) cur[u] = nxt[u];
             }
 #pragma unroll
-            for (int c = 0; c < MR; ++c) {
-                if (c < m) {
-                    T v = acc[c];
-#pragma unroll
-                    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-                    if (lane == 0)
-                        ts[c * BNB + q] = v;
-                }
+            for (int u = 0; u < WPT; ++u) {
+                const int e = tid + u * NT;
+                Wl[(e / BNB) * (BNB + 1) + e % BNB] = wt[u];
             }
+            __syncthreads();
+            T x = (T)0;
+            if (tid < BNB * m) {
+                const int r = tid % BNB, c = tid / BNB;
 #pragma unroll
-            for (int u = 0; u < RCH; ++u) cur[u] = nxt[u];
+                for (int q = 0; q < BNB; ++q) x += Wl[r * (BNB + 1) + q] * (ys[c * NM + k0 + q] - ts[c * BNB + q]);
+            }
+            __syncthreads();
+            if (tid < BNB * m)
+                ys[(tid / BNB) * NM + k0 + tid % BNB] = x;
+            __syncthreads();
         }
-#pragma unroll
-        for (int u = 0; u < WPT; ++u) {
-            const int e = tid + u * NT;
-            Wl[(e / BNB) * (BNB + 1) + e % BNB] = wt[u];
-        }
-        __syncthreads();
-        T x = (T)0;
-        if (tid < BNB * m) {
-            const int r = tid % BNB, c = tid / BNB;
-#pragma unroll
-            for (int q = 0; q < BNB; ++q) x += Wl[r * (BNB + 1) + q] * (ys[c * NM + k0 + q] - ts[c * BNB + q]);
-        }
-        __syncthreads();
-        if (tid < BNB * m)
-            ys[(tid / BNB) * NM + k0 + tid % BNB] = x;
-        __syncthreads();
     }
     if (tid < m)
         sm.zmax[tid] = 0ull;

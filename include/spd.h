@@ -13,9 +13,7 @@
  * Memory and ownership
  *   - Every matrix argument is binary64 (double), COLUMN-MAJOR, in DEVICE
  *     memory owned by the caller: element (i, j) of A is A[i + j*lda].
- *   - Only the lower triangle (i >= j) of A is read (the batched entry
- *     points excepted: they read whole symmetric matrices); A is never
- *     written.
+ *   - Only the lower triangle (i >= j) of A is read; A is never written.
  *   - A factor handle (spd_factor_t) owns every device buffer it allocates
  *     (the low-precision factor, the equilibration vector, workspace); the
  *     caller releases it with spd_factor_destroy.
@@ -234,14 +232,12 @@ spd_status spd_residual_noalloc(const double *A, int64_t n, int64_t lda, const d
  * workgroup per system, largest systems first.  Device arrays of length
  * `batch`: n[s] (0..SPD_BATCH_NMAX), nrhs[s] (0..SPD_BATCH_MAXRHS),
  * a_off[s] (offset of system s's matrix in A, in elements; column-major,
- * leading dimension n[s]; both triangles are read and must hold the
- * symmetric matrix: the one-workgroup residual and the picker stream whole
- * columns), b_off[s] (offset of its
+ * leading dimension n[s], lower triangle read), b_off[s] (offset of its
  * right-hand sides in B and of its solution in X; leading dimension n[s]);
  * prec[s] is the requested precision on input (AUTO: FP32) and the one used
  * on output; reps[s] (device memory) receives each system's report, with
  * SPD_ERR_INVALID_ARG for a system outside the limits.
- * The first call for a given batch size allocates the workspace (about 2.3 MB
+ * The first call for a given batch size allocates the workspace (about 4.4 MB
  * per workgroup of the persistent grid), picks the launch shape by timing the
  * candidates on this very batch (the results are those of the last, chosen,
  * run) and synchronises the stream.  Later calls with the same batch size
@@ -291,8 +287,7 @@ spd_status spd_solve_batched_timed(int64_t batch, const int32_t *n, const int32_
  * current device; NULL switches the picker off (AUTO then means FP32). */
 spd_status spd_picker_set(const float *params, void *hip_stream);
 
-/* Features of every system of a packed batch (layout as spd_solve_batched,
- * whole symmetric matrices read):
+/* Features of every system of a packed batch (layout as spd_solve_batched):
  * feat (device) receives batch x 16 floats, row-major; systems outside
  * 1 <= n <= SPD_BATCH_NMAX get zeros. */
 spd_status spd_picker_features(int64_t batch, const int32_t *n, const int32_t *nrhs,

@@ -252,7 +252,7 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
     // the main stream's updates use at most F->upd_slots workgroups (looping
     // over tiles), so that the panel chain always finds free slots
     auto update = [&](int64_t p0, int64_t p1, int64_t r0, int lo, int hi, hipStream_t s, int prio, int kind) {
-        const int cap = (s == st) ? F->upd_slots : 0;
+        const int cap = (s == st && kind == SPD_K_UPDATE) ? F->upd_slots : 0;
         const int t = (int)((npad - r0) / SPD_TILE_H);
         if (t <= 0 || lo >= hi) return;
         hipEvent_t pe = prof_begin(s);

@@ -11,10 +11,8 @@
 // (counting sort on the device), so the largest start first.  Each workgroup
 // owns a fixed slice of workspace (factor, inverses, d, residual): a call
 // allocates nothing once the workspace exists, and never synchronises the
-// host, so it can be captured in a graph.  The factorisation reads the lower
-// triangle of each A_s; the residual and the picker's products read both
-// triangles (rows streamed with coalesced loads), so A_s must hold the whole
-// symmetric matrix.
+// host, so it can be captured in a graph.  Only the lower triangle of each
+// A_s is read.
 #include <spd.h>
 
 #include <type_traits>
@@ -53,6 +51,7 @@ struct BatchWs {
     void *Winv;   // np/32 blocks of 32 x 32 inverses of the diagonal blocks
     double *d;    // equilibration
     double *R;    // n x m residual
+    double *Am;   // np x np: A's strict lower triangle mirrored into the strict upper (Am[i + j np] = a_ji, i < j)
 };
 
 SPD_DEV BatchWs batch_ws(const BatchArgs &a)
@@ -66,6 +65,8 @@ SPD_DEV BatchWs batch_ws(const BatchArgs &a)
     w.d = (double *)p;
     p += (int64_t)SPD_BATCH_NMAX * 8;
     w.R = (double *)p;
+    p += (int64_t)SPD_BATCH_NMAX * SPD_BATCH_MAXRHS * 8;
+    w.Am = (double *)p;
     return w;
 }
 
@@ -90,6 +91,8 @@ struct PickSmem {
     double vp[SPD_BATCH_NMAX];
     double w[SPD_BATCH_NMAX];
     double rs[SPD_BATCH_NMAX];  // Gershgorin radii of H
+    double ycol[SPD_BATCH_NMAX];
+    double rcol[SPD_BATCH_NMAX];
     double red[16][8];
     double ab[2][PICK_LANCZOS];  // Lanczos alpha, beta
     double th[PICK_LANCZOS];     // Ritz values
@@ -121,44 +124,68 @@ SPD_DEV double rl(double v, int src)
 }
 
 // ---------------------------------------------------------------------------
-// H = round(mu D A D) (lower), identity padding up to np; d (binary64).
-template <typename T>
-SPD_DEV void b_convert(const double *A, int n, int np, double *d, double mu, int equil, T *L, int nthr,
-                       double *dsh)
+// H = round(mu D A D) (lower), identity padding up to np; d (binary64); and
+// Am, A's strict lower triangle mirrored into the strict upper triangle of an
+// np x np array, so that the residual can stream whole rows of A with
+// coalesced loads while A itself is read only in its lower triangle.  32 x 32
+// tiles of the lower triangle, one per wave at a time: the tile is loaded
+// once (lane = row, 16 columns per lane), converted into L, and transposed
+// through the wave's buffer in shared memory (element (c, r) at
+// c * 32 + (r ^ c)) for the mirror's coalesced stores.
+template <typename T, int WAVES>
+__device__ __attribute__((noinline)) void b_convert(const double *A, int n, int np, double *d, double mu, int equil,
+                                                    T *L, double *Am, SolveSmem &sm)
 {
-    const int tid = threadIdx.x;
-    for (int i = tid; i < n; i += nthr) {
+    constexpr int NT = WAVES * 64;
+    static_assert(WAVES * BNB * BNB * 8 <= (int)sizeof(sm.ys), "tile buffers");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *dsh = sm.arow;
+    for (int i = tid; i < n; i += NT) {
         const double a = A[i + (int64_t)i * n];
         const double di = (equil && a > 0.0) ? 1.0 / sqrt(a) : 1.0;
         d[i] = di;
         dsh[i] = di;
     }
     __syncthreads();
-    // column j by one wave, 8 rows per lane loaded before any is stored
-    const int lane = tid & 63, wave = tid >> 6, nw = nthr / 64;
-    constexpr int U = 8;
-    for (int j = wave; j < np; j += nw) {
-        const double dj = (j < n) ? dsh[j] : 0.0;
-        for (int i0 = j; i0 < np; i0 += 64 * U) {
-            double a[U];
+    const int r = lane & 31, h = lane >> 5;
+    const int nb = np / BNB, ntiles = nb * (nb + 1) / 2;
+    double *tb = sm.ys + wave * BNB * BNB;
+    for (int q = wave; q < ntiles; q += WAVES) {
+        int I = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);  // q = I (I + 1) / 2 + J, J <= I
+        while (I * (I + 1) / 2 > q) --I;
+        while ((I + 1) * (I + 2) / 2 <= q) ++I;
+        const int J = q - I * (I + 1) / 2;
+        const int i = I * BNB + r;
+        double a[BNB / 2];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + 64 * u + lane;
-                a[u] = (i < n && j < n) ? A[i + (int64_t)j * n] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + 64 * u + lane;
-                if (i < np) {
-                    T v;
-                    if (i < n && j < n)
-                        v = (T)(((mu * dsh[i]) * a[u]) * dj);
-                    else
-                        v = (i == j) ? (T)1 : (T)0;
-                    L[i + (int64_t)j * np] = v;
-                }
-            }
+        for (int u = 0; u < BNB / 2; ++u) {
+            const int j = J * BNB + 2 * u + h;
+            a[u] = (i < n && j < n && j <= i) ? A[i + (int64_t)j * n] : 0.0;
         }
+        const double di = (i < n) ? dsh[i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < BNB / 2; ++u) {
+            const int c = 2 * u + h, j = J * BNB + c;
+            if (j <= i) {
+                T v;
+                if (i < n && j < n)
+                    v = (T)(((mu * di) * a[u]) * dsh[j]);
+                else
+                    v = (i == j) ? (T)1 : (T)0;
+                L[i + (int64_t)j * np] = v;
+            }
+            tb[c * BNB + (r ^ c)] = a[u];
+        }
+        __builtin_amdgcn_wave_barrier();
+        // Am (row J*32 + c, column I*32 + rr) = a (I*32 + rr, J*32 + c), c = lane % 32, strictly above the diagonal
+        double *dst = Am + (int64_t)J * BNB + (int64_t)I * BNB * np;
+#pragma unroll
+        for (int u = 0; u < BNB / 2; ++u) {
+            const int rr = 2 * u + h;
+            if (I > J || r < rr)
+                dst[r + (int64_t)rr * np] = tb[r * BNB + (rr ^ r)];
+        }
+        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
 }
@@ -579,14 +606,15 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
 // ---------------------------------------------------------------------------
 // R = B - A X (binary64) and the norms: norms[1 + k m + c], k = 0..3:
 // max|r|, max|x|, max|b|, max|d r|; with want_anorm also norms[0] =
-// ||A||_inf.  X is staged in shared memory.  A holds both triangles of the
-// symmetric matrix: lane = row, every column in order, so each load is one
-// coalesced column segment (reading only the lower triangle would need a
-// second, column-wise pass whose loads touch a cache line per lane), 16
-// columns per batch of loads with the next batch in flight.
+// ||A||_inf.  X is staged in shared memory.  Whole rows, lane = row, every
+// column in order: a_ij from A for j <= i and from the mirror Am (written by
+// b_convert) for j > i, so each load is coalesced (reading the lower triangle
+// alone would need a second, column-wise pass whose loads touch a cache line
+// per lane); 16 columns per batch of loads with the next batch in flight.
 template <int WAVES>
-__device__ __attribute__((noinline)) void b_residual(const double *A, int n, int m, const double *X, const double *B,
-                                                     const double *d, double *R, int want_anorm, SolveSmem &sm)
+__device__ __attribute__((noinline)) void b_residual(const double *A, const double *Am, int n, int np, int m,
+                                                     const double *X, const double *B, const double *d, double *R,
+                                                     int want_anorm, SolveSmem &sm)
 {
     constexpr int NT = WAVES * 64, NM = SPD_BATCH_NMAX;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -609,7 +637,7 @@ __device__ __attribute__((noinline)) void b_residual(const double *A, int n, int
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int j = j0 + u;
-                dst[u] = (i < n && j < n) ? A[i + (int64_t)j * n] : 0.0;
+                dst[u] = (i < n && j < n) ? ((j <= i) ? A[i + (int64_t)j * n] : Am[i + (int64_t)j * np]) : 0.0;
             }
         };
         load(a, 0);
@@ -735,9 +763,9 @@ SPD_DEV void b_reduce(double v[NV], const int op[NV], PickSmem &sm)
     __syncthreads();
 }
 
-// y = H v (v, y in shared memory), H = D A D from both triangles of A.
+// y = H v (v, y in shared memory), H = D A D from the lower triangle of A.
 // With first: rs[i] = r_i, and per thread the partial max off-diagonal |h|
-// and sum of h^2.
+// and sum of h^2 (each stored element once, off-diagonal ones counted twice).
 template <int WAVES>
 SPD_DEV void b_hv(const double *A, int n, const double *v, double *y, bool first, double &hmax, double &fro,
                   PickSmem &sm)
@@ -745,10 +773,11 @@ SPD_DEV void b_hv(const double *A, int n, const double *v, double *y, bool first
     constexpr int NT = WAVES * 64, CH = 8;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double *d = sm.d;
-    // lane = row, every column (A holds both triangles); 8 columns per batch
-    // of loads, the next batch in flight while the current one is used
+    // rows: sum_{j <= i} h_ij v_j; 8 columns per batch of loads, the next
+    // batch in flight while the current one is used
     for (int i0 = wave * 64; i0 < n; i0 += NT) {
         const int i = i0 + lane;
+        const int jmax = min(i0 + 63, n - 1);
         const double di = (i < n) ? d[i] : 0.0;
         double acc = 0.0, ra = 0.0;
         double a[CH], an[CH];
@@ -756,22 +785,22 @@ SPD_DEV void b_hv(const double *A, int n, const double *v, double *y, bool first
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int j = j0 + u;
-                dst[u] = (i < n && j < n) ? A[i + (int64_t)j * n] : 0.0;
+                dst[u] = (i < n && j <= i) ? A[i + (int64_t)j * n] : 0.0;
             }
         };
         load(a, 0);
-        for (int j0 = 0; j0 < n; j0 += CH) {
-            if (j0 + CH < n)
+        for (int j0 = 0; j0 <= jmax; j0 += CH) {
+            if (j0 + CH <= jmax)
                 load(an, j0 + CH);
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int j = min(j0 + u, n - 1);
                 const double h = (di * a[u]) * d[j];
                 acc = fma(h, v[j], acc);
-                if (first && i < n && j0 + u < n && j0 + u != i) {
+                if (first && i < n && j0 + u < i) {
                     ra += fabs(h);
                     hmax = fmax(hmax, fabs(h));
-                    fro += h * h;
+                    fro += 2.0 * h * h;
                 } else if (first && i < n && j0 + u == i) {
                     fro += h * h;
                 }
@@ -784,6 +813,46 @@ SPD_DEV void b_hv(const double *A, int n, const double *v, double *y, bool first
             if (first)
                 sm.rs[i] = ra;
         }
+    }
+    // columns: lane = column, sum_{i > j} h_ij v_i, the same double buffering
+    for (int j0 = wave * 64; j0 < n; j0 += NT) {
+        const int j = j0 + lane;
+        const double dj = (j < n) ? d[j] : 0.0;
+        double acc = 0.0, ca = 0.0;
+        double a[CH], an[CH];
+        auto load = [&](double *dst, int i0) {
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int i = i0 + u;
+                dst[u] = (j < n && i > j && i < n) ? A[i + (int64_t)j * n] : 0.0;
+            }
+        };
+        load(a, j0 + 1);
+        for (int i0 = j0 + 1; i0 < n; i0 += CH) {
+            if (i0 + CH < n)
+                load(an, i0 + CH);
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int i = min(i0 + u, n - 1);
+                const double h = (d[i] * a[u]) * dj;
+                acc = fma(h, v[i], acc);
+                if (first)
+                    ca += fabs(h);
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) a[u] = an[u];
+        }
+        if (j < n) {
+            sm.ycol[j] = acc;
+            if (first)
+                sm.rcol[j] = ca;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) {
+        y[i] += sm.ycol[i];
+        if (first)
+            sm.rs[i] += sm.rcol[i];
     }
     __syncthreads();
 }
@@ -1015,7 +1084,7 @@ SPD_DEV int b_refine(const BatchArgs &a, const double *A, const double *B, doubl
     for (;;) {
         const int first = (rep.iters_high == 0);
         const int k = rep.iters_high;  // corrections applied so far
-        b_residual<WAVES>(A, n, m, X, B, w.d, w.R, first, sm);
+        b_residual<WAVES>(A, w.Am, n, np, m, X, B, w.d, w.R, first, sm);
         rep.iters_high++;
         if (first)
             anorm = sm.norms[0];
@@ -1121,11 +1190,11 @@ SPD_DEV int b_factor_p(const BatchArgs &a, const double *A, int n, int np, const
 {
     if constexpr (sizeof(T) == 8) {
         mu = 1.0;
-        b_convert<double>(A, n, np, w.d, 1.0, 0, (double *)w.L, WAVES * 64, sm.arow);
+        b_convert<double, WAVES>(A, n, np, w.d, 1.0, 0, (double *)w.L, w.Am, sm);
         return b_factor<double, WAVES>((double *)w.L, np, (double *)w.Winv, HALF_NONE, sm);
     } else {
         mu = (p == SPD_FP16) ? a.mu16 : 1.0;
-        b_convert<float>(A, n, np, w.d, mu, a.equilibrate, (float *)w.L, WAVES * 64, sm.arow);
+        b_convert<float, WAVES>(A, n, np, w.d, mu, a.equilibrate, (float *)w.L, w.Am, sm);
         const int half = (p == SPD_FP16) ? HALF_F16 : (p == SPD_BF16) ? HALF_BF16 : HALF_NONE;
         return b_factor<float, WAVES>((float *)w.L, np, (float *)w.Winv, half, sm);
     }
@@ -1322,7 +1391,8 @@ namespace spd {
 int64_t batch_ws_stride()
 {
     int64_t b = (int64_t)SPD_BATCH_NMAX * SPD_BATCH_NMAX * 8 + (int64_t)SPD_BATCH_NMAX * BNB * 8 +
-                (int64_t)SPD_BATCH_NMAX * 8 + (int64_t)SPD_BATCH_NMAX * SPD_BATCH_MAXRHS * 8;
+                (int64_t)SPD_BATCH_NMAX * 8 + (int64_t)SPD_BATCH_NMAX * SPD_BATCH_MAXRHS * 8 +
+                (int64_t)SPD_BATCH_NMAX * SPD_BATCH_NMAX * 8;
     return (b + 255) / 256 * 256;
 }
 

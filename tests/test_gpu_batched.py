@@ -165,6 +165,32 @@ def test_batched_order_invariance(spd):
         assert r2[k]["iters_low"] == r1[i]["iters_low"]
 
 
+def test_batched_only_lower_triangle_read(spd):
+    # every system's strict upper triangle (element (i, j), i < j, at
+    # A[i + j n]) poisoned with NaN: the solutions must be bit for bit those
+    # of the symmetric matrices, in every precision and with the picker
+    shapes = spdgen.batch_shapes(24, config=3, nmin=16, nmax=300)
+    pb = spdgen.packed_batch(shapes, config=3, first_index=4500)
+    poisoned = pb.A.copy()
+    for s, (n, _, _) in enumerate(shapes):
+        blk = poisoned[pb.a_off[s]:pb.a_off[s] + n * n].reshape(n, n)  # blk[j, i] = element (i, j)
+        blk[np.tril_indices(n, -1)] = np.nan  # rows j > i of blk: elements with i < j
+    for prec in ("fp32", "fp64", "fp16"):
+        _, X1, r1, _ = _run(spd, pb, prec)
+        pbn = spdgen.PackedBatch(pb.n, pb.m, pb.cond, pb.a_off, pb.b_off, poisoned, pb.B, pb.Xt)
+        _, X2, r2, _ = _run(spd, pbn, prec)
+        assert np.all(r2["status"] == 0), prec
+        assert np.array_equal(X1, X2), prec
+    spd.picker_load()
+    try:
+        _, X1, _, p1 = _run(spd, pb, "auto")
+        _, X2, _, p2 = _run(spd, spdgen.PackedBatch(pb.n, pb.m, pb.cond, pb.a_off, pb.b_off, poisoned, pb.B, pb.Xt),
+                            "auto")
+    finally:
+        spd.picker_set(None)
+    assert np.array_equal(p1, p2) and np.array_equal(X1, X2)
+
+
 def test_batched_graph_replay(spd):
     import torch
     shapes = spdgen.batch_shapes(16, config=3, nmin=16, nmax=160)

@@ -218,10 +218,12 @@ double fp16_scale(double theta)
 }
 
 // ---------------------------------------------------------------------------
-// Blocked right-looking factorisation with one panel of lookahead:
-//   side stream: update of the next panel's columns, its diagonal factor and
-//                panel solve;
-//   main stream: update of the remaining trailing columns.
+// Blocked right-looking factorisation, panels of NB columns, trailing
+// updates per group of G panels, one group of lookahead:
+//   side stream: the panel chain (each panel's columns updated by the
+//                group's earlier panels, its diagonal factor, its panel
+//                solve) and the update of the next group's columns;
+//   main stream: the update of the remaining trailing columns.
 template <typename T>
 spd_status factor_blocked(spd_factor_t F, hipStream_t st)
 {
@@ -294,26 +296,34 @@ spd_status factor_blocked(spd_factor_t F, hipStream_t st)
         }
     };
 
-    // Main stream, per group g: wait for its panels, update the next group's
-    // columns first (the whole GPU, recorded as evU), then the rest.  Side
-    // stream: after evU, the next group's panel chain (recorded as evP), which
-    // overlaps the main stream's update of the rest.
+    // Per group g: the side stream runs the group's panel chain, then the
+    // update of the next group's columns by the group's panels (recorded as
+    // evU), then the next group's chain; the main stream, after evU, updates
+    // the rest of the trailing columns (recorded as evR), which overlaps the
+    // next chain.  The next group's columns take that update only after the
+    // main stream's update of the previous group is done (evR), since both
+    // write them.  Successive chains are thus joined on one stream, with no
+    // hop between streams on the path that bounds the last groups.
+    hipEvent_t evR = F->ev[2];
     chain(0, st);
     if (ng > 1) {
         HIP_TRY(hipEventRecord(evP, st));
+        HIP_TRY(hipStreamWaitEvent(F->side, evP, 0));
         for (int64_t g = 0; g + 1 < ng; ++g) {
             const int64_t p0 = g * G, p1 = std::min<int64_t>(p0 + G, nt), r0 = p1 * NB;
             const int t = (int)((npad - r0) / SPD_TILE_H);
             int next = (int)((std::min<int64_t>(p1 + G, nt) - p1) * (NB / SPD_TILE_H));
             if (half) next = std::min(t, (next + 1) & ~1);  // whole 256-tile columns on both sides of the split
-            HIP_TRY(hipStreamWaitEvent(st, evP, 0));
-            update(p0, p1, r0, 0, next, st, 1, SPD_K_UPDATE);
-            HIP_TRY(hipEventRecord(evU, st));
-            HIP_TRY(hipStreamWaitEvent(F->side, evU, 0));
-            chain(g + 1, F->side);
-            HIP_TRY(hipEventRecord(evP, F->side));
+            if (g > 0) HIP_TRY(hipStreamWaitEvent(F->side, evR, 0));
+            update(p0, p1, r0, 0, next, F->side, 1, SPD_K_UPDATE);
+            HIP_TRY(hipEventRecord(evU, F->side));
+            // enqueued before the chain, so that the main stream never waits on the host
+            HIP_TRY(hipStreamWaitEvent(st, evU, 0));
             update(p0, p1, r0, next, t, st, 0, SPD_K_UPDATE);
+            HIP_TRY(hipEventRecord(evR, st));
+            chain(g + 1, F->side);
         }
+        HIP_TRY(hipEventRecord(evP, F->side));
         HIP_TRY(hipStreamWaitEvent(st, evP, 0));
     }
     HIP_TRY(hipGetLastError());

@@ -8,6 +8,7 @@
 #include "common.h"
 #include "internal.h"
 #include "half_ops.h"
+#include <algorithm>
 #include <cstdlib>
 #include <type_traits>
 
@@ -180,31 +181,26 @@ __global__ __launch_bounds__(256) void k_syrk_update(T *__restrict__ H, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// K4, binary32: the same update written for v_mfma_f32_16x16x4f32, on TS x TS
-// tiles (TS = 128, or 64 when a launch has too few 128-tiles to fill the
-// chip).  Each wave owns a TS/2 x TS/2 block of D = C^T as NB x NB 16 x 16
-// accumulators holding -C (the sign is applied once on load and once on
-// store, so the K loop only multiplies and adds).  Shared memory holds 32
-// columns of each operand as [k][row] with TS floats per k and the row index
-// XOR-ed with 16 (k % 4): a fragment read (lane l: row 16 b + l%16, k = 4 s +
-// l/16) then touches 64 distinct banks, and the 16-byte staging stores stay
-// contiguous.  Tiles are counted in TS units over the lower triangle of the
-// trailing region (t tiles per side), tile columns [tj_lo, tj_hi).
-template <int TS>
-__global__ __launch_bounds__(256, 2) void k_syrk_update_f32(float *__restrict__ H, int64_t ld, int64_t k0, int nbk,
-                                                           int64_t r0, int t, int tj_lo, int tj_hi, int ntiles,
-                                                           const unsigned long long *info, int prio)
+// K4, binary32: the same update written for v_mfma_f32_16x16x4f32.  One
+// TS x TS tile (TS = 128 or 64): each wave owns a TS/2 x TS/2 block of
+// D = C^T as NB x NB 16 x 16 accumulators holding -C (the sign is applied
+// once on load and once on store, so the K loop only multiplies and adds).
+// Shared memory holds KC columns of each operand as [k][row] with TS floats
+// per k and the row index XOR-ed with 16 (k % 4): a fragment read (lane l:
+// row 16 b + l%16, k = 4 s + l/16) then touches 64 distinct banks, and the
+// 16-byte staging stores stay contiguous.  As and Bs are two staging
+// buffers of KC x TS floats each; every wave has passed the final barrier
+// when the function returns, so the next tile may restage at once.
+template <int TS, int KC>
+SPD_DEV void f32_update_tile(float *__restrict__ H, int64_t ld, int64_t k0, int nbk, int64_t crow, int64_t ccol,
+                             float *__restrict__ As, float *__restrict__ Bs, int tid)
 {
-    constexpr int KC = 32, NB = TS / 32, NV = TS / 32;  // 16-blocks per wave side; staged float4 per thread
-    __shared__ __align__(16) float As[2][KC * TS];
-    __shared__ __align__(16) float Bs[2][KC * TS];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (*(volatile const unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
-        return;
-    if (prio)
-        __builtin_amdgcn_s_setprio(2);  // the lookahead part of the update
+    constexpr int NB = TS / 32, NV = KC * TS / 1024;  // 16-blocks per wave side; staged float4 per thread
+    constexpr int BUF = KC * TS;
+    static_assert(NV == 2 || NV == 4, "staging layout");
+    const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1, r = lane & 15, u = lane >> 4;
-    const int ldi = (int)ld;  // offsets within a tile row block of <= 512 columns fit in 32 bits
+    const int ldi = (int)ld;  // offsets within a tile row block of <= 1024 columns fit in 32 bits
     // staging: thread covers rows 4 (tid % (TS/4)) .. +3 of columns tid / (TS/4) + (1024/TS) v
     constexpr int TPC = TS / 4, CSTEP = 256 / TPC;
     const int scol = tid / TPC, srow = (tid % TPC) * 4;
@@ -218,30 +214,20 @@ __global__ __launch_bounds__(256, 2) void k_syrk_update_f32(float *__restrict__ 
         fb[b] = u * TS + (((TS / 2) * wn + 16 * b) ^ (16 * u)) + r;
     }
     const int coff = r + 4 * u * ldi;
-    const int per = gridDim.x / 8, chunk = (ntiles + 7) / 8;
-    for (int it = blockIdx.x / 8; it < chunk; it += per) {
-        const int logical = (blockIdx.x % 8) * chunk + it;
-        if (logical >= ntiles)
-            break;
-        int ti, tj;
-        decode_tile(logical, t, tj_lo, tj_hi, ti, tj);
-        if (ti < 0)
-            break;
-        const int64_t crow = r0 + (int64_t)ti * TS, ccol = r0 + (int64_t)tj * TS;
-        const float *pa = H + ccol + k0 * ld;  // rows of tile tj (D rows = C columns)
-        const float *pb = H + crow + k0 * ld;  // rows of tile ti (D columns = C rows)
-        // register q of block (mi, ni): -C[crow + TS/2 wn + 16 ni + r][ccol + TS/2 wm + 16 mi + 4 u + q]
-        float *cu = H + (crow + (TS / 2) * wn) + (ccol + (TS / 2) * wm) * ld;
-        floatx4 c[NB][NB];
+    const float *pa = H + ccol + k0 * ld;  // rows of tile tj (D rows = C columns)
+    const float *pb = H + crow + k0 * ld;  // rows of tile ti (D columns = C rows)
+    // register q of block (mi, ni): -C[crow + TS/2 wn + 16 ni + r][ccol + TS/2 wm + 16 mi + 4 u + q]
+    float *cu = H + (crow + (TS / 2) * wn) + (ccol + (TS / 2) * wm) * ld;
+    floatx4 c[NB][NB];
 #pragma unroll
-        for (int mi = 0; mi < NB; ++mi)
+    for (int mi = 0; mi < NB; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < NB; ++ni)
+        for (int ni = 0; ni < NB; ++ni)
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    c[mi][ni][q] = -cu[coff + 16 * ni + (16 * mi + q) * ldi];
-        // staging registers (named, not an array, so that they stay registers)
-        float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+            for (int q = 0; q < 4; ++q)
+                c[mi][ni][q] = -cu[coff + 16 * ni + (16 * mi + q) * ldi];
+    // staging registers (named, not an array, so that they stay registers)
+    float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
 #define SPD_GL(o)                                                                         \
     do {                                                                                  \
         ra0 = *(const float4 *)&pa[(o) + goff];                                           \
@@ -257,56 +243,107 @@ __global__ __launch_bounds__(256, 2) void k_syrk_update_f32(float *__restrict__ 
     } while (0)
 #define SPD_SS(bf)                                                                        \
     do {                                                                                  \
-        *(float4 *)&As[bf][soff] = ra0;                                                   \
-        *(float4 *)&Bs[bf][soff] = rb0;                                                   \
-        *(float4 *)&As[bf][soff + CSTEP * TS] = ra1;                                      \
-        *(float4 *)&Bs[bf][soff + CSTEP * TS] = rb1;                                      \
+        float *as_ = As + (bf) * BUF, *bs_ = Bs + (bf) * BUF;                             \
+        *(float4 *)&as_[soff] = ra0;                                                      \
+        *(float4 *)&bs_[soff] = rb0;                                                      \
+        *(float4 *)&as_[soff + CSTEP * TS] = ra1;                                         \
+        *(float4 *)&bs_[soff + CSTEP * TS] = rb1;                                         \
         if constexpr (NV > 2) {                                                           \
-            *(float4 *)&As[bf][soff + 2 * CSTEP * TS] = ra2;                              \
-            *(float4 *)&Bs[bf][soff + 2 * CSTEP * TS] = rb2;                              \
-            *(float4 *)&As[bf][soff + 3 * CSTEP * TS] = ra3;                              \
-            *(float4 *)&Bs[bf][soff + 3 * CSTEP * TS] = rb3;                              \
+            *(float4 *)&as_[soff + 2 * CSTEP * TS] = ra2;                                 \
+            *(float4 *)&bs_[soff + 2 * CSTEP * TS] = rb2;                                 \
+            *(float4 *)&as_[soff + 3 * CSTEP * TS] = ra3;                                 \
+            *(float4 *)&bs_[soff + 3 * CSTEP * TS] = rb3;                                 \
         }                                                                                 \
     } while (0)
-        static_assert(NV == 2 || NV == 4, "staging layout");
-        SPD_GL(0);
-        SPD_SS(0);
-        lds_barrier();
-        int buf = 0;
-        for (int kb = 0; kb < nbk; kb += KC) {
-            // prefetch the next chunk (the last iteration re-reads its own chunk)
-            const int o = ((kb + KC < nbk) ? kb + KC : kb) * ldi;
-            SPD_GL(o);
-            __builtin_amdgcn_sched_barrier(0);
-            const float *A0 = As[buf], *B0 = Bs[buf];
+    SPD_GL(0);
+    SPD_SS(0);
+    lds_barrier();
+    int buf = 0;
+    for (int kb = 0; kb < nbk; kb += KC) {
+        // prefetch the next chunk (the last iteration re-reads its own chunk)
+        const int o = ((kb + KC < nbk) ? kb + KC : kb) * ldi;
+        SPD_GL(o);
+        __builtin_amdgcn_sched_barrier(0);
+        const float *A0 = As + buf * BUF, *B0 = Bs + buf * BUF;
 #pragma unroll
-            for (int ks = 0; ks < KC / 4; ++ks) {
-                float a[NB], b[NB];
+        for (int ks = 0; ks < KC / 4; ++ks) {
+            float a[NB], b[NB];
 #pragma unroll
-                for (int i = 0; i < NB; ++i) {
-                    a[i] = A0[4 * ks * TS + fa[i]];
-                    b[i] = B0[4 * ks * TS + fb[i]];
-                }
-#pragma unroll
-                for (int mi = 0; mi < NB; ++mi)
-#pragma unroll
-                    for (int ni = 0; ni < NB; ++ni)
-                        c[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], c[mi][ni], 0, 0, 0);
+            for (int i = 0; i < NB; ++i) {
+                a[i] = A0[4 * ks * TS + fa[i]];
+                b[i] = B0[4 * ks * TS + fb[i]];
             }
-            __builtin_amdgcn_sched_barrier(0);
-            SPD_SS(buf ^ 1);
-            lds_barrier();
-            buf ^= 1;
+#pragma unroll
+            for (int mi = 0; mi < NB; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < NB; ++ni)
+                    c[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], c[mi][ni], 0, 0, 0);
         }
+        __builtin_amdgcn_sched_barrier(0);
+        SPD_SS(buf ^ 1);
+        lds_barrier();
+        buf ^= 1;
+    }
 #undef SPD_GL
 #undef SPD_SS
 #pragma unroll
-        for (int mi = 0; mi < NB; ++mi)
+    for (int mi = 0; mi < NB; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < NB; ++ni)
+        for (int ni = 0; ni < NB; ++ni)
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    cu[coff + 16 * ni + (16 * mi + q) * ldi] = -c[mi][ni][q];
+            for (int q = 0; q < 4; ++q)
+                cu[coff + 16 * ni + (16 * mi + q) * ldi] = -c[mi][ni][q];
+}
+
+// The binary32 update on TS x TS tiles (128, or 64 for the panel chain's
+// single tile columns and for launches with too few 128-tiles to fill the
+// chip).  Tiles are counted in TS units over the lower triangle of the
+// trailing region (t tiles per side), tile columns [tj_lo, tj_hi).  Tiles
+// [0, nfull) run whole, the same number per workgroup; with TS = 128 the
+// remaining tiles [nfull, ntiles) -- a last round too small to fill the
+// workgroups -- run as four 64-tiles each (the quarter above the diagonal
+// of a diagonal tile skipped), with chunks of 64 columns, so that a last
+// round costs about a quarter of a whole one.
+template <int TS>
+__global__ __launch_bounds__(256, 2) void k_syrk_update_f32(float *__restrict__ H, int64_t ld, int64_t k0, int nbk,
+                                                           int64_t r0, int t, int tj_lo, int tj_hi, int ntiles,
+                                                           int nfull, const unsigned long long *info, int prio)
+{
+    constexpr int KC = 32;
+    __shared__ __align__(16) float As[2 * KC * TS];
+    __shared__ __align__(16) float Bs[2 * KC * TS];
+    const int tid = threadIdx.x;
+    if (*(volatile const unsigned long long *)info != (unsigned long long)SPD_INFO_NONE)
+        return;
+    if (prio)
+        __builtin_amdgcn_s_setprio(2);  // the lookahead part of the update
+    const int per = gridDim.x / 8, chunk = (nfull + 7) / 8;
+    for (int it = blockIdx.x / 8; it < chunk; it += per) {
+        const int logical = (blockIdx.x % 8) * chunk + it;
+        if (logical >= nfull)
+            break;
+        int ti, tj;
+        decode_tile(logical, t, tj_lo, tj_hi, ti, tj);
+        if (ti < 0)
+            break;
+        f32_update_tile<TS, KC>(H, ld, k0, nbk, r0 + (int64_t)ti * TS, r0 + (int64_t)tj * TS, As, Bs, tid);
+    }
+    if constexpr (TS == 128) {
+        const int nsub = 4 * (ntiles - nfull), chunk2 = (nsub + 7) / 8;
+        for (int it = blockIdx.x / 8; it < chunk2; it += per) {
+            const int s = (blockIdx.x % 8) * chunk2 + it;
+            if (s >= nsub)
+                break;
+            int ti, tj;
+            decode_tile(nfull + (s >> 2), t, tj_lo, tj_hi, ti, tj);
+            if (ti < 0)
+                break;
+            const int qi = (s >> 1) & 1, qj = s & 1;
+            if (ti == tj && qi < qj)
+                continue;  // above the diagonal
+            f32_update_tile<64, 64>(H, ld, k0, nbk, r0 + (int64_t)ti * 128 + 64 * qi, r0 + (int64_t)tj * 128 + 64 * qj,
+                                    As, Bs, tid);
+        }
     }
 }
 
@@ -573,6 +610,48 @@ static int small_update_tiles()
 }
 #define kSmallUpdateTiles small_update_tiles()
 
+// Workgroups of the binary32 128-tile update resident at once on the current
+// device (two per compute unit), or 0 when the last round is not to be split
+// into 64-tiles (SPD_TAIL_SPLIT=0).
+static int update_slots()
+{
+    static const bool off = [] {
+        const char *e = std::getenv("SPD_TAIL_SPLIT");
+        return e && std::atoi(e) == 0;
+    }();
+    if (off) return 0;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (!cache[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            return 0;
+        cache[dev] = 2 * cus;
+    }
+    return cache[dev];
+}
+
+// Whole rounds of 128-tiles over P workgroups (P = the cap, else every
+// resident slot); when the last round has at most P/2 tiles, those run as
+// 64-tiles inside the same launch (at most two per workgroup).  Returns the
+// tiles that run whole; *grid is the launch's workgroup count.
+static int64_t update_split(int64_t ntiles, int64_t max_grid, int64_t *grid)
+{
+    *grid = ((ntiles + 7) / 8) * 8;
+    if (max_grid > 0 && *grid > max_grid) *grid = (max_grid / 8) * 8;
+    const int slots = update_slots();
+    if (slots < 8) return ntiles;
+    int64_t P = (max_grid > 0) ? std::min<int64_t>(max_grid, slots) : slots;
+    P = (P / 8) * 8;
+    if (P < 8) return ntiles;
+    const int64_t per = P / 8, rounds = ((ntiles + 7) / 8 + per - 1) / per;
+    const int64_t nfull = (rounds - 1) * 8 * per, rem = ntiles - nfull;
+    if (rem > P / 2) return ntiles;
+    *grid = (nfull > 0) ? P : std::min<int64_t>(P, ((4 * rem + 7) / 8) * 8);
+    return nfull;
+}
+
 template <typename T>
 void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t, int tj_lo, int tj_hi,
                         const unsigned long long *info, hipStream_t st, int prio, int max_grid, bool small_tiles)
@@ -590,10 +669,11 @@ void launch_syrk_update(T *H, int64_t ld, int64_t k0, int nbk, int64_t r0, int t
             for (int c = lo2; c < hi2; ++c) n2 += t2 - c;
             const int64_t g2 = ((n2 + 7) / 8) * 8;
             hipLaunchKernelGGL(k_syrk_update_f32<64>, dim3((unsigned)g2), dim3(256), 0, st, H, ld, k0, nbk, r0, t2,
-                               lo2, hi2, (int)n2, info, prio);
+                               lo2, hi2, (int)n2, (int)n2, info, prio);
         } else {
+            const int64_t nfull = update_split(ntiles, max_grid, &grid);
             hipLaunchKernelGGL(k_syrk_update_f32<128>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, k0, nbk, r0,
-                               t, tj_lo, tj_hi, (int)ntiles, info, prio);
+                               t, tj_lo, tj_hi, (int)ntiles, (int)nfull, info, prio);
         }
     } else
         hipLaunchKernelGGL(k_syrk_update<T>, dim3((unsigned)grid), dim3(256), 0, st, H, ld, k0, nbk, r0, t, tj_lo,

@@ -147,10 +147,14 @@ def test_trained_picker_against_fixed_precisions(spd):
     systems of the batched workload's distribution.  Each system is solved
     at every precision (no fallback: the outcome table, labelled by the
     oracle's rule from measured device time) and at every precision with the
-    fallback chain (what a caller pays).  Asserted: the picks match the
-    labels (at most 15 % mispicks), and solving each system at its picked
-    precision costs no more than the best single precision for the whole
-    batch (summed device time of the fallback runs, within 5 %).  The picker's own time is measured too (the
+    fallback chain (what a caller pays).  Asserted: at most 10 % of the
+    picks are wrong, a wrong pick being one that does not converge or costs
+    more than 10 % over the labelled precision's time for that system (the
+    labels of near-ties between binary32 and binary64 go either way with a
+    few per cent of clock noise, so plain agreement is only reported), and
+    solving each system at its picked precision costs no more than the best
+    single precision for the whole batch (summed device time of the
+    fallback runs, within 5 %).  The picker's own time is measured too (the
     AUTO call's device time minus that of its picks) and reported with the
     whole-call ratios: its four Lanczos products read each matrix four times
     at HBM speed, which this distribution's best fixed precision does not
@@ -194,12 +198,14 @@ def test_trained_picker_against_fixed_precisions(spd):
     cost_fixed = {p: float(ticks_fb[:, k].sum()) for k, p in enumerate(names)}
     best = min(cost_fixed, key=cost_fixed.get)
     cost_picks = float(ticks_fb[idx, picks].sum())
-    mispick = float(np.mean(picks != labels))
-    _say("labels", np.bincount(labels, minlength=4), "picks", np.bincount(picks, minlength=4),
-         "mispick rate", mispick, f"picks / best fixed ({best})", cost_picks / cost_fixed[best],
-         "picker share of the AUTO call", (cost_auto - cost_picks) / cost_auto,
-         "AUTO call / FP32", cost_auto / cost_fixed["fp32"], f"AUTO call / {best}", cost_auto / cost_fixed[best])
+    disagree = float(np.mean(picks != labels))
     # labels and costs come from per-system device clocks of separate runs
     # (a few per cent of noise, and the label rule's own 2 % band)
-    assert mispick <= 0.15
+    wrong = ~conv[idx, picks] | (ticks[idx, picks] > 1.10 * ticks[idx, labels])
+    _say("labels", np.bincount(labels, minlength=4), "picks", np.bincount(picks, minlength=4),
+         "disagreement", disagree, "wrong picks", float(wrong.mean()),
+         f"picks / best fixed ({best})", cost_picks / cost_fixed[best],
+         "picker share of the AUTO call", (cost_auto - cost_picks) / cost_auto,
+         "AUTO call / FP32", cost_auto / cost_fixed["fp32"], f"AUTO call / {best}", cost_auto / cost_fixed[best])
+    assert float(wrong.mean()) <= 0.10
     assert cost_picks <= 1.05 * cost_fixed[best]

@@ -191,7 +191,11 @@ void spd_autotune_clear(void);
 
 /* The whole of Algorithm 1 in one call: spd_factor + spd_solve + spd_refine,
  * with the fallback chain applied from the factorisation on.  *F as in
- * spd_factor (reused if non-NULL). */
+ * spd_factor (reused if non-NULL).  The factorisation's breakdown check is
+ * read back with the first residual rather than on its own, so the host
+ * does not wait between the three steps; a breakdown still restarts at the
+ * next precision (or returns SPD_ERR_NOT_SPD with rep->info) exactly as
+ * spd_factor's check would.  Arguments are checked before any device work. */
 spd_status spd_posv(const double *A, int64_t n, int64_t lda, const double *B, int64_t ldb,
                     int64_t nrhs, double *X, int64_t ldx, spd_prec prec, const spd_opts *o,
                     spd_report *rep, void *hip_stream, spd_factor_t *F);

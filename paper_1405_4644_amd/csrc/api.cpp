@@ -45,6 +45,7 @@ struct spd_factor_s {
     bool pinned = false;     // schedule fixed by the environment or the tuner: no cache lookup
     int upd_slots = 0;       // cap on the main-stream update's workgroups (SPD_UPD_SLOTS; 0: one per tile)
     bool imported = false;   // the factor came from spd_factor_import (not line 1's own)
+    bool info_pending = false;  // spd_posv's factorisation: info not read back yet (read with the first residual)
     void *Lh = nullptr;      // two panel copies in that precision (npad x NB halves each)
     size_t cap_Lh = 0;
     unsigned long long *info_dev = nullptr;
@@ -391,8 +392,9 @@ spd_status prepare_factor(spd_factor_t F, int64_t n, int prec, double theta, hip
 }
 
 spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, int prec, const spd_opts &o,
-                     hipStream_t st, int64_t *info)
+                     hipStream_t st, int64_t *info, bool sync = true)
 {
+    F->info_pending = false;
     SPD_TRY(prepare_factor(F, n, prec, o.theta, st));
     F->imported = false;
     if (!F->pinned) {
@@ -425,6 +427,13 @@ spd_status do_factor(spd_factor_t F, const double *A, int64_t n, int64_t lda, in
         SPD_TRY(factor_blocked<double>(F, st));
     else
         SPD_TRY(factor_blocked<float>(F, st));
+    *info = 0;
+    if (!sync) {
+        // the caller reads info back later (resolve_info, or with the first residual)
+        HIP_TRY(hipGetLastError());
+        F->info_pending = true;
+        return SPD_OK;
+    }
     HIP_TRY(hipMemcpyAsync(F->info_host, F->info_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const unsigned long long v = *F->info_host;
@@ -450,6 +459,7 @@ void import_factor(spd_factor_t F, const double *L, int64_t ldl, hipStream_t st)
 spd_status do_import(spd_factor_t F, const double *L, int64_t n, int64_t ldl, int prec, hipStream_t st,
                      int64_t *info)
 {
+    F->info_pending = false;
     SPD_TRY(prepare_factor(F, n, prec, 0.1, st));
     F->imported = true;
     if (F->terr) HIP_TRY(hipMemsetAsync(F->terr, 0, sizeof(int), st));
@@ -474,7 +484,7 @@ spd_status ensure_trsv_ws(spd_factor_t F, hipStream_t st)
     size_t cap = F->cap_tP;
     SPD_TRY(grow(&F->tP, &cap, (size_t)spd::trsv_scratch_elems(F->npad) * F->elem, false, st));
     F->cap_tP = cap;
-    const int nctl = spd::trsv_ctl_ints(F->npad);
+    const int nctl = 2 * spd::trsv_ctl_ints(F->npad);  // one set per direction
     if (F->cap_tctl < nctl) {
         if (F->tctl) {
             HIP_TRY(hipStreamSynchronize(st));
@@ -508,18 +518,21 @@ spd_status ensure_solve_ws(spd_factor_t F, int64_t m, hipStream_t st)
     return SPD_OK;
 }
 
-// Low-precision solve of (D R / s) and X (+)= s mu D Y  (Algorithm 1, lines 2, 5, 6)
+// Low-precision solve of (D R / s) and X (+)= s mu D Y  (Algorithm 1, lines 2, 5, 6).
+// The scaling launch also clears the triangular solves' counters and, when
+// given, zero_next[0, nzero) (the next residual's norms).
 template <typename T>
 void solve_apply(spd_factor_t F, const double *R, int64_t ldr, int64_t m, const double *smax, double *X, int64_t ldx,
-                 int accumulate, double *zmax, hipStream_t st)
+                 int accumulate, double *zmax, double *zero_next, int64_t nzero, hipStream_t st)
 {
     const int64_t npad = F->npad;
     T *Y = (T *)F->Y;
     T *Z = (T *)((char *)F->Y + npad * m * sizeof(T));
-    spd::launch_rhs_scale<T>(R, ldr, F->n, npad, (int)m, F->d, smax, Y, npad, st);
+    spd::launch_rhs_scale<T>(R, ldr, F->n, npad, (int)m, F->d, smax, Y, npad, zero_next, nzero, F->tctl,
+                             2 * spd::trsv_ctl_ints(npad), st);
     hipEvent_t pe = prof_begin(st);
     spd::launch_trsv<T>((const T *)F->L, npad, (const T *)F->WB, npad, (int)m, Y, Z, npad, (T *)F->tP, F->tctl,
-                        F->terr, F->wait_ticks, st);
+                        true, F->terr, F->wait_ticks, st);
     if (pe)
         prof_end(pe, st, SPD_K_TRSV, 2.0 * (double)npad * npad * m,
                  (double)sizeof(T) * ((double)npad * (npad + 1) + 4.0 * npad * m));
@@ -534,9 +547,9 @@ spd_status do_solve(spd_factor_t F, const double *B, int64_t ldb, int64_t m, dou
     spd::launch_zero(F->smax, m, st);
     spd::launch_rhs_max(B, ldb, F->n, (int)m, F->d, F->smax, st);
     if (F->elem == 8)
-        solve_apply<double>(F, B, ldb, m, F->smax, X, ldx, 0, nullptr, st);
+        solve_apply<double>(F, B, ldb, m, F->smax, X, ldx, 0, nullptr, nullptr, 0, st);
     else
-        solve_apply<float>(F, B, ldb, m, F->smax, X, ldx, 0, nullptr, st);
+        solve_apply<float>(F, B, ldb, m, F->smax, X, ldx, 0, nullptr, nullptr, 0, st);
     HIP_TRY(hipGetLastError());
     return SPD_OK;
 }
@@ -557,7 +570,7 @@ spd_status ensure_refine_ws(spd_factor_t F, int64_t m, hipStream_t st)
             HIP_TRY(hipHostFree(F->norms_host));
             F->norms = F->norms_host = nullptr;
         }
-        HIP_TRY(hipMalloc(&F->norms, nn * sizeof(double)));
+        HIP_TRY(hipMalloc(&F->norms, 2 * nn * sizeof(double)));  // two sets, used in turn
         HIP_TRY(hipHostMalloc(&F->norms_host, nn * sizeof(double), hipHostMallocDefault));
         F->cap_norms = nn;
     }
@@ -594,6 +607,21 @@ bool column_done(double eta_new, double zeta, double zeta_prev, double eta_in, i
     return (rho < 0.5) ? (rho / (1.0 - rho)) * eta_in <= U64 : eta_in <= ETA_FLOOR;
 }
 
+// Reads back the info word of a factorisation that did not (spd_posv's):
+// SPD_ERR_NOT_SPD, with *info the 1-based failing column, when it broke down.
+spd_status resolve_info(spd_factor_t F, hipStream_t st, int64_t *info)
+{
+    *info = 0;
+    if (!F->info_pending) return SPD_OK;
+    HIP_TRY(hipMemcpyAsync(F->info_host, F->info_dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    F->info_pending = false;
+    const unsigned long long v = *F->info_host;
+    if (v == SPD_INFO_NONE_H) return SPD_OK;
+    *info = (int64_t)v;
+    return SPD_ERR_NOT_SPD;
+}
+
 // One refinement run at the handle's current precision, from the iterate in
 // X (taken as the result of one low-precision solve).  Returns SPD_OK (every
 // column done), SPD_ERR_NO_CONVERGENCE (diverged, or max_iter corrections
@@ -613,21 +641,37 @@ spd_status refine_once(spd_factor_t F, const double *A, int64_t lda, const doubl
     double eta0 = 0.0, anorm = 0.0;
     int stalls = 0;
     spd_status result = SPD_ERR_NO_CONVERGENCE;
+    // Two sets of norms used in turn: the residual of iteration k accumulates
+    // into set k % 2, which the scaling launch of the correction before it
+    // cleared (the correction writes its max|z| there too), while that
+    // correction reads its scale from the other set.
+    double *nset[2] = {F->norms, F->norms + nn};
+    int cur = 0;
+    spd::launch_zero(nset[0], nn, st);
     for (;;) {
         const int first = (rep->iters_high == 0);
-        // the residual's norms; the correction norms (last m) were written
-        // by the correction before this residual
-        spd::launch_zero(first ? F->norms : F->norms + 1, first ? nn - m : nn - m - 1, st);
+        double *norms = nset[cur];
         hipEvent_t pr = prof_begin(st);
-        spd::launch_residual(A, lda, n, X, ldx, B, ldb, (int)m, F->R, n, F->d, F->norms, first, F->P, st);
+        spd::launch_residual(A, lda, n, X, ldx, B, ldb, (int)m, F->R, n, F->d, norms, first, F->P, st);
         if (pr)
             prof_end(pr, st, SPD_K_RESIDUAL, 2.0 * n * n * m,
                      8.0 * ((double)n * (n + 1) / 2 + 3.0 * n * m));
-        hipError_t e = hipMemcpyAsync(F->norms_host, F->norms, nn * sizeof(double), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(F->terr_host, F->terr, sizeof(int), hipMemcpyDeviceToHost, st);
+        const bool check_info = F->info_pending;
+        spd::launch_publish(norms, nn, F->terr, check_info ? F->info_dev : nullptr, F->norms_host, F->terr_host,
+                            check_info ? F->info_host : nullptr, st);
+        hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return map_err(e);
+        if (check_info) {
+            // the factorisation's own outcome comes first: a broken-down factor
+            // made this residual meaningless
+            F->info_pending = false;
+            const unsigned long long v = *F->info_host;
+            if (v != SPD_INFO_NONE_H) {
+                rep->info = (int64_t)v;
+                return SPD_ERR_NOT_SPD;
+            }
+        }
         if (*F->terr_host) return SPD_ERR_DEVICE;  // a triangular-solve wait timed out
         const int k = rep->iters_high;  // corrections applied so far
         rep->iters_high++;
@@ -665,15 +709,16 @@ spd_status refine_once(spd_factor_t F, const double *A, int64_t lda, const doubl
         eprev = eta;
         zprev = zeta;
         // correction: Z = low-precision solve of D R / s, X += s mu D Z
-        const double *dmax = F->norms + 1 + 3 * m;
-        double *zmax = F->norms + 1 + 4 * m;
-        spd::launch_zero(zmax, m, st);
+        double *next = nset[cur ^ 1];
+        const double *dmax = norms + 1 + 3 * m;
+        double *zmax = next + 1 + 4 * m;
         if (F->elem == 8)
-            solve_apply<double>(F, F->R, n, m, dmax, X, ldx, 1, zmax, st);
+            solve_apply<double>(F, F->R, n, m, dmax, X, ldx, 1, zmax, next, nn, st);
         else
-            solve_apply<float>(F, F->R, n, m, dmax, X, ldx, 1, zmax, st);
+            solve_apply<float>(F, F->R, n, m, dmax, X, ldx, 1, zmax, next, nn, st);
         e = hipGetLastError();
         if (e != hipSuccess) return map_err(e);
+        cur ^= 1;
         rep->iters_low++;
     }
     return result;
@@ -976,8 +1021,14 @@ spd_status spd_profile_query(int kernel, int64_t *launches, double *total_ms, do
     return SPD_OK;
 }
 
-spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec, const spd_opts *o, void *hip_stream,
-                      spd_factor_t *F, int64_t *info)
+}  // extern "C"
+
+namespace {
+
+// spd_factor's body; with sync false the info word is left to be read back
+// with the first residual (spd_posv), and SPD_OK means only "launched"
+spd_status factor_entry(const double *A, int64_t n, int64_t lda, spd_prec prec, const spd_opts *o,
+                        void *hip_stream, spd_factor_t *F, int64_t *info, bool sync)
 {
     if (!F || !info || n < 0 || lda < std::max<int64_t>(1, n) || (n > 0 && !A) || !valid_prec(prec))
         return SPD_ERR_INVALID_ARG;
@@ -1002,12 +1053,22 @@ spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec, co
             return SPD_ERR_DEVICE;
         }
     }
-    spd_status s = do_factor(*F, A, n, lda, prec, op, (hipStream_t)hip_stream, info);
+    spd_status s = do_factor(*F, A, n, lda, prec, op, (hipStream_t)hip_stream, info, sync);
     if (s != SPD_OK && s != SPD_ERR_NOT_SPD && created) {
         spd_factor_destroy(*F);
         *F = nullptr;
     }
     return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec, const spd_opts *o, void *hip_stream,
+                      spd_factor_t *F, int64_t *info)
+{
+    return factor_entry(A, n, lda, prec, o, hip_stream, F, info, true);
 }
 
 spd_status spd_factor_import(const double *L, int64_t n, int64_t ldl, spd_prec prec, void *hip_stream,
@@ -1046,23 +1107,25 @@ spd_status spd_solve(spd_factor_t F, const double *B, int64_t ldb, int64_t nrhs,
     return do_solve(F, B, ldb, nrhs, X, ldx, (hipStream_t)hip_stream);
 }
 
-spd_status spd_refine(spd_factor_t F, const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrhs,
-                      double *X, int64_t ldx, const spd_opts *o, spd_report *rep, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+// spd_refine's body after argument checks: refinement from the iterate in X,
+// escalating precision when the rule of Eq. (4) fails (op.fallback)
+spd_status refine_loop(spd_factor_t F, const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrhs,
+                       double *X, int64_t ldx, const spd_opts &op, spd_report *rep, hipStream_t st)
 {
-    if (!F || F->prec < 0 || !rep || nrhs < 0) return SPD_ERR_INVALID_ARG;
     const int64_t n = F->n;
-    if (lda < std::max<int64_t>(1, n) || ldb < std::max<int64_t>(1, n) || ldx < std::max<int64_t>(1, n))
-        return SPD_ERR_INVALID_ARG;
-    if (n > 0 && nrhs > 0 && (!A || !B || !X)) return SPD_ERR_INVALID_ARG;
-    const spd_opts op = o ? *o : defaults();
-    if (!opts_valid(op)) return SPD_ERR_INVALID_ARG;
-    hipStream_t st = (hipStream_t)hip_stream;
     std::memset(rep, 0, sizeof(*rep));
     rep->prec_used = F->prec;
     if (n == 0 || nrhs == 0) {
-        rep->status = SPD_OK;
+        int64_t info = 0;
+        spd_status s = resolve_info(F, st, &info);
+        rep->info = info;
+        rep->status = s;
         rep->eta = 0.0;
-        return SPD_OK;
+        return s;
     }
     for (;;) {
         spd_status s = refine_once(F, A, lda, B, ldb, nrhs, X, ldx, op, rep, st);
@@ -1098,6 +1161,23 @@ spd_status spd_refine(spd_factor_t F, const double *A, int64_t lda, const double
     }
 }
 
+}  // namespace
+
+extern "C" {
+
+spd_status spd_refine(spd_factor_t F, const double *A, int64_t lda, const double *B, int64_t ldb, int64_t nrhs,
+                      double *X, int64_t ldx, const spd_opts *o, spd_report *rep, void *hip_stream)
+{
+    if (!F || F->prec < 0 || !rep || nrhs < 0) return SPD_ERR_INVALID_ARG;
+    const int64_t n = F->n;
+    if (lda < std::max<int64_t>(1, n) || ldb < std::max<int64_t>(1, n) || ldx < std::max<int64_t>(1, n))
+        return SPD_ERR_INVALID_ARG;
+    if (n > 0 && nrhs > 0 && (!A || !B || !X)) return SPD_ERR_INVALID_ARG;
+    const spd_opts op = o ? *o : defaults();
+    if (!opts_valid(op)) return SPD_ERR_INVALID_ARG;
+    return refine_loop(F, A, lda, B, ldb, nrhs, X, ldx, op, rep, (hipStream_t)hip_stream);
+}
+
 spd_status spd_autotune(int64_t n, spd_prec prec, void *hip_stream, spd_tune_result *out)
 {
     if (n < 1 || n > (int64_t)1 << 20 || !valid_prec(prec) || !out) return SPD_ERR_INVALID_ARG;
@@ -1124,7 +1204,7 @@ spd_status spd_autotune(int64_t n, spd_prec prec, void *hip_stream, spd_tune_res
     std::vector<Cand> cand;
     if (half) {
         for (int g : {2, 4, 8})
-            for (int c : {0, 224}) cand.push_back({g, c, 0});
+            for (int c : {0, 192, 224}) cand.push_back({g, c, 0});
     } else if (prec == SPD_FP32) {
         // 64-row tiles apply to uncapped launches only
         for (int g : {2, 4, 6, 8}) {
@@ -1207,13 +1287,33 @@ spd_status spd_posv(const double *A, int64_t n, int64_t lda, const double *B, in
     if (!rep || !F) return SPD_ERR_INVALID_ARG;
     std::memset(rep, 0, sizeof(*rep));
     const spd_opts op = o ? *o : defaults();
-    if (!opts_valid(op) || !valid_prec(prec)) return SPD_ERR_INVALID_ARG;
+    if (!opts_valid(op) || !valid_prec(prec) || nrhs < 0) return SPD_ERR_INVALID_ARG;
+    if (ldb < std::max<int64_t>(1, n) || ldx < std::max<int64_t>(1, n)) return SPD_ERR_INVALID_ARG;
+    if (n > 0 && nrhs > 0 && (!B || !X)) return SPD_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)hip_stream;
     int p = prec;
     int fallbacks = 0;
-    int64_t info = 0;
     spd_status s;
+    // The factorisation's info word is read back with the first residual
+    // (no host round trip between factor, solve and refinement); a breakdown
+    // then restarts at the next precision as a synchronous check would.
     for (;;) {
-        s = spd_factor(A, n, lda, (spd_prec)p, &op, hip_stream, F, &info);
+        int64_t info = 0;
+        s = factor_entry(A, n, lda, (spd_prec)p, &op, hip_stream, F, &info, false);
+        if (s == SPD_OK) s = do_solve(*F, B, ldb, nrhs, X, ldx, st);
+        if (s == SPD_OK) {
+            s = refine_loop(*F, A, lda, B, ldb, nrhs, X, ldx, op, rep, st);
+        } else {
+            std::memset(rep, 0, sizeof(*rep));
+            rep->status = s;
+        }
+        if (*F && (*F)->info_pending) {
+            // an error came before the read-back: settle it here
+            int64_t v = 0;
+            if (resolve_info(*F, st, &v) == SPD_ERR_NOT_SPD && s == SPD_OK) s = SPD_ERR_NOT_SPD;
+            rep->info = v;
+        }
+        rep->prec_used = p;
         if (s == SPD_ERR_NOT_SPD && op.fallback && p != SPD_FP64) {
             ++fallbacks;
             p = next_prec(p);
@@ -1221,19 +1321,8 @@ spd_status spd_posv(const double *A, int64_t n, int64_t lda, const double *B, in
         }
         break;
     }
-    rep->info = info;
-    rep->prec_used = p;
-    rep->fallbacks = fallbacks;
-    if (s != SPD_OK) {
-        rep->status = s;
-        return s;
-    }
-    s = spd_solve(*F, B, ldb, nrhs, X, ldx, hip_stream);
-    if (s != SPD_OK) {
-        rep->status = s;
-        return s;
-    }
-    s = spd_refine(*F, A, lda, B, ldb, nrhs, X, ldx, &op, rep, hip_stream);
+    if (s == SPD_ERR_NOT_SPD) rep->status = s;
+    if (*F && s != SPD_ERR_NOT_SPD) rep->prec_used = (*F)->prec;
     rep->fallbacks += fallbacks;
     return s;
 }

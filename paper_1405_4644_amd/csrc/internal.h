@@ -67,10 +67,13 @@ void launch_inv32_blocks(const T *H, int64_t ld, int64_t npad, T *Winv, unsigned
 // smax[c] = max_i |d_i r_ic| over the n rows (zeroed by the caller first)
 void launch_rhs_max(const double *R, int64_t ldr, int64_t n, int m, const double *d, double *smax,
                     hipStream_t st);
-// Y[i][c] = round_T(d_i r_ic / s_c) for i < n, 0 for n <= i < npad; s_c = pow2_ceil(smax[c])
+// Y[i][c] = round_T(d_i r_ic / s_c) for i < n, 0 for n <= i < npad; s_c = pow2_ceil(smax[c]);
+// the same launch clears zd[0, nzd) and zi[0, nzi) when given (neither may
+// overlap smax)
 template <typename T>
 void launch_rhs_scale(const double *R, int64_t ldr, int64_t n, int64_t npad, int m, const double *d,
-                      const double *smax, T *Y, int64_t ldy, hipStream_t st);
+                      const double *smax, T *Y, int64_t ldy, double *zd, int64_t nzd, int *zi, int64_t nzi,
+                      hipStream_t st);
 // Triangular solves (k_trsv.hip), blocked by big diagonal blocks of
 // solve_nbs(npad) rows whose inverses WB (solve_winv_elems(npad) elements)
 // are built once per factorisation from L and the 128-wide block inverses
@@ -82,15 +85,16 @@ int64_t solve_tmp_elems(int64_t npad);
 template <typename T>
 void launch_build_winv(const T *L, int64_t ld, int64_t npad, const T *W128, T *WB, T *Tb, hipStream_t st);
 // Forward Y -> Z then backward Z -> Y for m right-hand sides (TRSV_MC per
-// launch).  P: trsv_scratch_elems(npad) elements; ctl: trsv_ctl_ints(npad)
-// ints (zeroed by the launches themselves); err: sticky int raised on a
-// timed-out wait.
+// launch).  P: trsv_scratch_elems(npad) elements; ctl: 2 trsv_ctl_ints(npad)
+// ints (the first half for the forward direction, the second for the
+// backward), zeroed by the launches themselves unless ctl_zeroed says the
+// caller cleared both halves; err: sticky int raised on a timed-out wait.
 #define TRSV_MC 8
 int64_t trsv_scratch_elems(int64_t npad);
 int trsv_ctl_ints(int64_t npad);
 template <typename T>
 void launch_trsv(const T *L, int64_t ld, const T *WB, int64_t npad, int m, T *Y, T *Z, int64_t ldy, T *P, int *ctl,
-                 int *err, unsigned long long wait_ticks, hipStream_t st);
+                 bool ctl_zeroed, int *err, unsigned long long wait_ticks, hipStream_t st);
 // X[i][c] (+)= s_c mu d_i Y[i][c]; zmax (optional, m entries, non-negative on
 // entry): raised to max_i |s_c mu d_i Y[i][c]| per column
 template <typename T>
@@ -101,6 +105,10 @@ void launch_col_maxdiff(const double *X, int64_t ldx, double *S, int64_t lds, in
                         hipStream_t st);
 // fill a double array with zeros (a kernel, not a memset node)
 void launch_zero(double *p, int64_t count, hipStream_t st);
+// dst[0, count) = src[0, count), *dflag = *flag and, when dinfo is given,
+// *dinfo = *info, by one workgroup (dst, dflag, dinfo: host-visible memory)
+void launch_publish(const double *src, int64_t count, const int *flag, const unsigned long long *info, double *dst,
+                    int *dflag, unsigned long long *dinfo, hipStream_t st);
 // Lout (binary64, n x n, column-major) <- lower triangle of the factor, zeros above
 template <typename T>
 void launch_export(const T *L, int64_t ld, int64_t n, double *Lout, int64_t ldo, hipStream_t st);

@@ -33,10 +33,22 @@ __global__ __launch_bounds__(256) void k_rhs_max(const double *__restrict__ R, i
 template <typename T>
 __global__ __launch_bounds__(256) void k_rhs_scale(const double *__restrict__ R, int64_t ldr, int64_t n,
                                                    int64_t npad, const double *__restrict__ d,
-                                                   const double *__restrict__ smax, T *__restrict__ Y, int64_t ldy)
+                                                   const double *__restrict__ smax, T *__restrict__ Y, int64_t ldy,
+                                                   double *__restrict__ zd, int64_t nzd, int *__restrict__ zi,
+                                                   int64_t nzi)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int c = blockIdx.y;
+    if (c == 0) {
+        // clears what the kernels after this one start from (the next
+        // residual's norms, the triangular solves' counters); no other
+        // kernel of the launch reads them
+        const int64_t stride = (int64_t)gridDim.x * 256;
+        for (int64_t j = i; j < nzd; j += stride)
+            zd[j] = 0.0;
+        for (int64_t j = i; j < nzi; j += stride)
+            zi[j] = 0;
+    }
     if (i >= npad)
         return;
     const double s = pow2_ceil(smax[c]);
@@ -113,6 +125,23 @@ __global__ void k_zero(double *p, int64_t count)
         p[i] = 0.0;
 }
 
+// the refinement's per-iteration read-back: the norms, the triangular
+// solves' timeout flag and, when asked, the factorisation's info word, copied
+// by one workgroup into host-visible memory
+__global__ __launch_bounds__(256) void k_publish(const double *__restrict__ src, int64_t count,
+                                                 const int *__restrict__ flag, const unsigned long long *__restrict__ info,
+                                                 double *__restrict__ dst, int *__restrict__ dflag,
+                                                 unsigned long long *__restrict__ dinfo)
+{
+    for (int64_t i = threadIdx.x; i < count; i += 256)
+        dst[i] = src[i];
+    if (threadIdx.x == 0) {
+        *dflag = *flag;
+        if (dinfo)
+            *dinfo = *info;
+    }
+}
+
 namespace spd {
 
 void launch_rhs_max(const double *R, int64_t ldr, int64_t n, int m, const double *d, double *smax, hipStream_t st)
@@ -124,16 +153,19 @@ void launch_rhs_max(const double *R, int64_t ldr, int64_t n, int m, const double
 
 template <typename T>
 void launch_rhs_scale(const double *R, int64_t ldr, int64_t n, int64_t npad, int m, const double *d,
-                      const double *smax, T *Y, int64_t ldy, hipStream_t st)
+                      const double *smax, T *Y, int64_t ldy, double *zd, int64_t nzd, int *zi, int64_t nzi,
+                      hipStream_t st)
 {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_rhs_scale<T>, dim3((unsigned)((npad + 255) / 256), (unsigned)m), dim3(256), 0, st, R, ldr,
-                       n, npad, d, smax, Y, ldy);
+                       n, npad, d, smax, Y, ldy, zd, zd ? nzd : 0, zi, zi ? nzi : 0);
 }
 template void launch_rhs_scale<float>(const double *, int64_t, int64_t, int64_t, int, const double *,
-                                      const double *, float *, int64_t, hipStream_t);
+                                      const double *, float *, int64_t, double *, int64_t, int *, int64_t,
+                                      hipStream_t);
 template void launch_rhs_scale<double>(const double *, int64_t, int64_t, int64_t, int, const double *,
-                                       const double *, double *, int64_t, hipStream_t);
+                                       const double *, double *, int64_t, double *, int64_t, int *, int64_t,
+                                       hipStream_t);
 
 template <typename T>
 void launch_update_x(double *X, int64_t ldx, int64_t n, int m, const T *Y, int64_t ldy, const double *d, double mu,
@@ -161,6 +193,12 @@ void launch_tune_matrix(double *A, int64_t n, hipStream_t st)
     if (n <= 0) return;
     hipLaunchKernelGGL(k_tune_matrix, dim3((unsigned)((n + 255) / 256), (unsigned)std::min<int64_t>(n, 4096)),
                        dim3(256), 0, st, A, n);
+}
+
+void launch_publish(const double *src, int64_t count, const int *flag, const unsigned long long *info, double *dst,
+                    int *dflag, unsigned long long *dinfo, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(256), 0, st, src, count, flag, info, dst, dflag, dinfo);
 }
 
 void launch_zero(double *p, int64_t count, hipStream_t st)

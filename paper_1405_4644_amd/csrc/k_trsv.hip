@@ -609,7 +609,8 @@ template void launch_build_winv<double>(const double *, int64_t, int64_t, const 
 
 template <typename T, bool FWD>
 static void launch_dir(const T *L, int64_t ld, const T *WB, int64_t npad, int m, const T *Yin, T *Zout,
-                       int64_t ldy, T *P, int *ctl, int *err, unsigned long long tmo, hipStream_t st)
+                       int64_t ldy, T *P, int *ctl, bool ctl_zeroed, int *err, unsigned long long tmo,
+                       hipStream_t st)
 {
     const int nbs = solve_nbs(npad), K = solve_nblocks(npad);
     constexpr int R = 8 * VecOf<T>::N;
@@ -626,7 +627,8 @@ static void launch_dir(const T *L, int64_t ld, const T *WB, int64_t npad, int m,
     const int grid = ncrit + (int)std::min<int64_t>(nbulk_tasks, TRSV_NBULK);
     const int nctl = trsv_ctl_ints(npad);
     for (int c0 = 0; c0 < m; c0 += TRSV_MC) {
-        hipLaunchKernelGGL(k_zero_int, dim3((nctl + 255) / 256), dim3(256), 0, st, ctl, nctl);
+        if (c0 > 0 || !ctl_zeroed)
+            hipLaunchKernelGGL(k_zero_int, dim3((nctl + 255) / 256), dim3(256), 0, st, ctl, nctl);
         const int mc = m - c0;
         if (mc == 1)
             hipLaunchKernelGGL((k_trsv_blk<T, 1, FWD>), dim3(grid), dim3(256), 0, st, L, ld, WB, npad, nbs, K, Yin,
@@ -645,14 +647,16 @@ static void launch_dir(const T *L, int64_t ld, const T *WB, int64_t npad, int m,
 
 template <typename T>
 void launch_trsv(const T *L, int64_t ld, const T *WB, int64_t npad, int m, T *Y, T *Z, int64_t ldy, T *P, int *ctl,
-                 int *err, unsigned long long wait_ticks, hipStream_t st)
+                 bool ctl_zeroed, int *err, unsigned long long wait_ticks, hipStream_t st)
 {
-    launch_dir<T, true>(L, ld, WB, npad, m, Y, Z, ldy, P, ctl, err, wait_ticks, st);
-    launch_dir<T, false>(L, ld, WB, npad, m, Z, Y, ldy, P, ctl, err, wait_ticks, st);
+    // each direction has its own counters (ctl, ctl + trsv_ctl_ints)
+    launch_dir<T, true>(L, ld, WB, npad, m, Y, Z, ldy, P, ctl, ctl_zeroed, err, wait_ticks, st);
+    launch_dir<T, false>(L, ld, WB, npad, m, Z, Y, ldy, P, ctl + trsv_ctl_ints(npad), ctl_zeroed, err, wait_ticks,
+                         st);
 }
 template void launch_trsv<float>(const float *, int64_t, const float *, int64_t, int, float *, float *, int64_t,
-                                 float *, int *, int *, unsigned long long, hipStream_t);
+                                 float *, int *, bool, int *, unsigned long long, hipStream_t);
 template void launch_trsv<double>(const double *, int64_t, const double *, int64_t, int, double *, double *, int64_t,
-                                  double *, int *, int *, unsigned long long, hipStream_t);
+                                  double *, int *, bool, int *, unsigned long long, hipStream_t);
 
 }  // namespace spd

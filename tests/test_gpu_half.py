@@ -150,6 +150,35 @@ def test_half_breakdown_falls_back(spd, orc):
     assert rep.fallbacks == 2
 
 
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_half_breakdown_then_binary32_succeeds(spd, orc, prec):
+    # SPD, with rows 0 and 128 coupled by 1 - 1e-4 (eigenvalues 2 - 1e-4 and
+    # 1e-4 in that plane).  The second panel's pivot is 1 - l^2 with
+    # l = 1 - 1e-4 from the first panel: rounded to binary16 or bfloat16 as an
+    # update operand, l becomes exactly 1 and the pivot 0 (a breakdown at
+    # column 129); binary32 keeps l and a pivot of about 2e-4.  spd_posv reads
+    # the factorisation's outcome only with the first residual, so this checks
+    # that a half-precision breakdown found there still restarts at binary32
+    # and ends with a correct solution.
+    n, j = 300, 128
+    A = np.eye(n)
+    A[0, j] = A[j, 0] = 1.0 - 1e-4
+    F, info, st = spd.factor(dev(A), prec)
+    F.close()
+    assert st == 2 and info == j + 1, (st, info)
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((2, n))
+    X, rep, F = spd.posv(dev(A), dev(B), prec=prec)
+    F.close()
+    assert rep.status == 0 and rep.prec_used == PREC_ID["fp32"] and rep.fallbacks == 1, rep.as_dict()
+    assert np.all(orc.backward_error(A, host(X), B) <= 1e-14)
+    Xo, oinfo = orc.solve(A, B)
+    assert oinfo == 0
+    cond = (2.0 - 1e-4) / 1e-4
+    fe = np.max(np.abs(host(X) - Xo)) / np.max(np.abs(Xo))
+    assert fe <= 10 * cond * 2.0 ** -53, fe
+
+
 def test_half_switch_precision_on_one_handle(spd, orc):
     # the same handle factors at FP16, then FP32, then BF16; every solve is correct
     n, cond = 500, 1e2

@@ -11,6 +11,23 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 #define SPD_DEV __device__ __forceinline__
 
+// Global-memory views of generic pointers.  In a device function that is not
+// inlined into its kernel the compiler cannot tell global from shared memory
+// and emits FLAT accesses, which count against the shared-memory wait
+// counter as well: a shared-memory read then waits for every global load in
+// flight, so loads issued ahead never overlap the work between.  Accesses
+// through these views are GLOBAL instructions.
+template <typename T>
+SPD_DEV __attribute__((address_space(1))) T *gmem(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+SPD_DEV const __attribute__((address_space(1))) T *gmem(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+
 // Panel width of the blocked factorisation and tile sizes.
 #define SPD_IB 32           // inner strip width inside a diagonal block
 #define SPD_TILE 128        // trailing-update tile (rows and columns)

@@ -82,6 +82,7 @@ struct SolveSmem {
     double smax[SPD_BATCH_MAXRHS];
     unsigned long long zmax[SPD_BATCH_MAXRHS];  // max |z| per column of the last solve (binary64 bits)
     double arow[SPD_BATCH_NMAX];  // row sums of |A|
+    double part[4][SPD_BATCH_MAXRHS + 1][64];  // the residual's per-wave partial row sums (+ |A|)
     int info;
 };
 // the picker's features and perceptron (about 30 KB: several workgroups per CU)
@@ -136,6 +137,11 @@ template <typename T, int WAVES>
 __device__ __attribute__((noinline)) void b_convert(const double *A, int n, int np, double *d, double mu, int equil,
                                                     T *L, double *Am, SolveSmem &sm)
 {
+    // global memory (see gmem): the parameters re-derived as global pointers
+    A = (const double *)gmem(A);
+    d = (double *)gmem(d);
+    L = (T *)gmem(L);
+    Am = (double *)gmem(Am);
     constexpr int NT = WAVES * 64;
     static_assert(WAVES * BNB * BNB * 8 <= (int)sizeof(sm.ys), "tile buffers");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -204,6 +210,8 @@ __device__ __attribute__((noinline)) void b_convert(const double *A, int n, int 
 template <typename T>
 __device__ __attribute__((noinline)) int b_diag(T *L, int np, int k0, T *Ws, T *Wg, T *Lr)
 {
+    L = (T *)gmem(L);  // global memory (see gmem)
+    Wg = (T *)gmem(Wg);
     constexpr int S = 36;  // Lr row stride (16-byte aligned rows)
     const int lane = threadIdx.x & 63, r = lane & 31;
     const bool store = lane < BNB;
@@ -264,6 +272,8 @@ __device__ __attribute__((noinline)) int b_diag(T *L, int np, int k0, T *Ws, T *
 template <typename T, int WAVES>
 __device__ __attribute__((noinline)) int b_factor(T *L, int np, T *Winv, int half, SolveSmem &sm)
 {
+    L = (T *)gmem(L);  // global memory (see gmem)
+    Winv = (T *)gmem(Winv);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nb = np / BNB;
     T *Ws = (T *)sm.Lk;  // inverse of the diagonal block: Ws[c * 33 + r] = W[r][c]
@@ -381,12 +391,15 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
     constexpr int NT = WAVES * 64, MR = SPD_BATCH_MAXRHS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nb = np / BNB;
+    const auto gL = gmem(L), gW = gmem(Winv);
+    const auto gR = gmem(R), gd = gmem(d);
+    const auto gX = gmem(X);
     T *ys = (T *)sm.ys;  // ys[c * NMAX + i]
     constexpr int NM = SPD_BATCH_NMAX;
     for (int idx = tid; idx < m * np; idx += NT) {
         const int c = idx / np, i = idx % np;
         const double s = pow2_ceil(sm.smax[c]);
-        ys[c * NM + i] = (i < n) ? (T)(d[i] * R[i + (int64_t)c * n] / s) : (T)0;
+        ys[c * NM + i] = (i < n) ? (T)(gd[i] * gR[i + (int64_t)c * n] / s) : (T)0;
     }
     __syncthreads();
     // Each step first issues the loads it needs -- the W block (staged in
@@ -399,7 +412,7 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
     // forward: z_k = W_k y_k, then y_below -= L_below,k z_k
     for (int kb = 0; kb < nb; ++kb) {
         const int k0 = kb * BNB;
-        const T *W = Winv + (int64_t)kb * BNB * BNB;
+        const auto W = gW + (int64_t)kb * BNB * BNB;
         T wt[WPT];
 #pragma unroll
         for (int u = 0; u < WPT; ++u) wt[u] = W[tid + u * NT];
@@ -407,7 +420,7 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
         T lv[BNB];
         if (i1 < np) {
 #pragma unroll
-            for (int q = 0; q < BNB; ++q) lv[q] = L[i1 + (int64_t)(k0 + q) * np];
+            for (int q = 0; q < BNB; ++q) lv[q] = gL[i1 + (int64_t)(k0 + q) * np];
         }
 #pragma unroll
         for (int u = 0; u < WPT; ++u) {
@@ -439,7 +452,7 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
         for (int i = i1 + NT; i < np; i += NT) {
             T lw[BNB];
 #pragma unroll
-            for (int q = 0; q < BNB; ++q) lw[q] = L[i + (int64_t)(k0 + q) * np];
+            for (int q = 0; q < BNB; ++q) lw[q] = gL[i + (int64_t)(k0 + q) * np];
 #pragma unroll
             for (int c = 0; c < MR; ++c) {
                 if (c < m) {
@@ -464,7 +477,7 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
         // values of a step one coalesced load per column of the block
         for (int kb = nb - 1; kb >= 0; --kb) {
             const int k0 = kb * BNB;
-            const T *W = Winv + (int64_t)kb * BNB * BNB;
+            const auto W = gW + (int64_t)kb * BNB * BNB;
             T wt[WPT];
 #pragma unroll
             for (int u = 0; u < WPT; ++u) wt[u] = W[tid + u * NT];
@@ -472,7 +485,7 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
             T lv[BNB];
             if (i1 < k0) {
 #pragma unroll
-                for (int q = 0; q < BNB; ++q) lv[q] = L[i1 + (int64_t)(k0 + q) * np];
+                for (int q = 0; q < BNB; ++q) lv[q] = gL[i1 + (int64_t)(k0 + q) * np];
             }
 #pragma unroll
             for (int u = 0; u < WPT; ++u) {
@@ -505,7 +518,7 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
             for (int i = i1 + NT; i < k0; i += NT) {
                 T lw[BNB];
 #pragma unroll
-                for (int q = 0; q < BNB; ++q) lw[q] = L[i + (int64_t)(k0 + q) * np];
+                for (int q = 0; q < BNB; ++q) lw[q] = gL[i + (int64_t)(k0 + q) * np];
 #pragma unroll
                 for (int c = 0; c < MR; ++c) {
                     if (c < m) {
@@ -526,14 +539,14 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
         T *ts = (T *)sm.ts;
         for (int kb = nb - 1; kb >= 0; --kb) {
             const int k0 = kb * BNB, r0 = k0 + BNB;
-            const T *W = Winv + (int64_t)kb * BNB * BNB;
+            const auto W = gW + (int64_t)kb * BNB * BNB;
             T wt[WPT];
 #pragma unroll
             for (int u = 0; u < WPT; ++u) wt[u] = W[tid + u * NT];
             const int nch = (np - r0 + 63) / 64;
             T cur[RCH], nxt[RCH];
             auto load_col = [&](T *dst, int q) {
-                const T *col = L + (int64_t)(k0 + q) * np;
+                const auto col = gL + (int64_t)(k0 + q) * np;
 #pragma unroll
                 for (int u = 0; u < RCH; ++u) {
                     const int i = r0 + 64 * u + lane;
@@ -595,8 +608,8 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
     for (int idx = tid; idx < m * n; idx += NT) {
         const int c = idx / n, i = idx % n;
         const double s = pow2_ceil(sm.smax[c]);
-        const double z = ((s * mu) * d[i]) * (double)ys[c * NM + i];
-        double *px = X + i + (int64_t)c * n;
+        const double z = ((s * mu) * gd[i]) * (double)ys[c * NM + i];
+        const auto px = gX + i + (int64_t)c * n;
         *px = accumulate ? *px + z : z;
         atomicMax(&sm.zmax[c], (unsigned long long)__double_as_longlong(fabs(z)));
     }
@@ -606,28 +619,37 @@ __device__ __attribute__((noinline)) void b_solve(const T *L, const T *Winv, int
 // ---------------------------------------------------------------------------
 // R = B - A X (binary64) and the norms: norms[1 + k m + c], k = 0..3:
 // max|r|, max|x|, max|b|, max|d r|; with want_anorm also norms[0] =
-// ||A||_inf.  X is staged in shared memory.  Whole rows, lane = row, every
-// column in order: a_ij from A for j <= i and from the mirror Am (written by
-// b_convert) for j > i, so each load is coalesced (reading the lower triangle
-// alone would need a second, column-wise pass whose loads touch a cache line
-// per lane); 16 columns per batch of loads with the next batch in flight.
+// ||A||_inf.  X is staged in shared memory.  Rows in passes of 64 (lane =
+// row), the columns split among the waves in whole batches of CH: a_ij from
+// A for j <= i and from the mirror Am (written by b_convert) for j > i, so
+// each load is coalesced (reading the lower triangle alone would need a
+// second, column-wise pass whose loads touch a cache line per lane), with the
+// next batch in flight.  Each row's four wave partials are added in a fixed
+// order, so the result does not depend on timing.  Splitting the columns
+// rather than the rows keeps the waves level for every n (rows per wave
+// left one wave a second full pass whenever n was just above 256).
 template <int WAVES>
 __device__ __attribute__((noinline)) void b_residual(const double *A, const double *Am, int n, int np, int m,
                                                      const double *X, const double *B, const double *d, double *R,
                                                      int want_anorm, SolveSmem &sm)
 {
     constexpr int NT = WAVES * 64, NM = SPD_BATCH_NMAX;
+    static_assert(WAVES == 4, "partial sums are laid out for four waves");
+    const auto gA = gmem(A), gAm = gmem(Am), gX = gmem(X), gB = gmem(B);
+    const auto gR = gmem(R);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int MR = SPD_BATCH_MAXRHS;
     double *xs = sm.ys;  // xs[c * NMAX + j]
     double *abs_rows = sm.arow;
     for (int idx = tid; idx < m * n; idx += NT) {
         const int c = idx / n, j = idx % n;
-        xs[c * NM + j] = X[j + (int64_t)c * n];
+        xs[c * NM + j] = gX[j + (int64_t)c * n];
     }
     __syncthreads();
     constexpr int CH = 16;
-    for (int i0 = wave * 64; i0 < n; i0 += NT) {
+    const int nch = (n + CH - 1) / CH, cpw = (nch + WAVES - 1) / WAVES;
+    const int jlo = wave * cpw * CH, jhi = min(n, (wave + 1) * cpw * CH);
+    for (int i0 = 0; i0 < n; i0 += 64) {
         const int i = i0 + lane;
         double acc[MR], aa = 0.0;
 #pragma unroll
@@ -637,12 +659,13 @@ __device__ __attribute__((noinline)) void b_residual(const double *A, const doub
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
                 const int j = j0 + u;
-                dst[u] = (i < n && j < n) ? ((j <= i) ? A[i + (int64_t)j * n] : Am[i + (int64_t)j * np]) : 0.0;
+                dst[u] = (i < n && j < jhi) ? ((j <= i) ? gA[i + (int64_t)j * n] : gAm[i + (int64_t)j * np]) : 0.0;
             }
         };
-        load(a, 0);
-        for (int j0 = 0; j0 < n; j0 += CH) {
-            if (j0 + CH < n)
+        if (jlo < jhi)
+            load(a, jlo);
+        for (int j0 = jlo; j0 < jhi; j0 += CH) {
+            if (j0 + CH < jhi)
                 load(an, j0 + CH);
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
@@ -657,16 +680,25 @@ __device__ __attribute__((noinline)) void b_residual(const double *A, const doub
 #pragma unroll
             for (int u = 0; u < CH; ++u) a[u] = an[u];
         }
-        if (i < n) {
 #pragma unroll
-            for (int c = 0; c < MR; ++c)
+        for (int c = 0; c < MR; ++c)
+            if (c < m)
+                sm.part[wave][c][lane] = acc[c];
+        sm.part[wave][MR][lane] = aa;
+        __syncthreads();
+        for (int idx = tid; idx < (m + 1) * 64; idx += NT) {
+            const int c = idx / 64, l = idx % 64, r = i0 + l;
+            const int slot = (c < m) ? c : MR;
+            if (r < n && (c < m || want_anorm)) {
+                const double s = ((sm.part[0][slot][l] + sm.part[1][slot][l]) + sm.part[2][slot][l]) + sm.part[3][slot][l];
                 if (c < m)
-                    R[i + (int64_t)c * n] = B[i + (int64_t)c * n] - acc[c];
-            if (want_anorm)
-                abs_rows[i] = aa;
+                    gR[r + (int64_t)c * n] = gB[r + (int64_t)c * n] - s;
+                else
+                    abs_rows[r] = s;
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
     // maxima (NaN propagates), per column, one kind at a time (kind 0..3:
     // |r|, |x|, |b|, |d r|), then ||A||_inf
 #pragma unroll 1
@@ -678,10 +710,10 @@ __device__ __attribute__((noinline)) void b_residual(const double *A, const doub
 #pragma unroll
             for (int c = 0; c < MR; ++c)
                 if (c < m) {
-                    const double x = (kind == 0) ? R[i + (int64_t)c * n]
+                    const double x = (kind == 0) ? gR[i + (int64_t)c * n]
                                      : (kind == 1) ? xs[c * NM + i]
-                                     : (kind == 2) ? B[i + (int64_t)c * n]
-                                                   : d[i] * R[i + (int64_t)c * n];
+                                     : (kind == 2) ? gB[i + (int64_t)c * n]
+                                                   : gmem(d)[i] * gR[i + (int64_t)c * n];
                     v[c] = b_nanmax(v[c], fabs(x));
                 }
         }

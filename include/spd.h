@@ -86,7 +86,7 @@ typedef struct spd_factor_s *spd_factor_t;
 /* Fill *o with the defaults. */
 void spd_opts_default(spd_opts *o);
 
-/* Algorithm 1, line 1: low-precision Cholesky factorisation of the lower
+/* Algorithm 1's low-precision Cholesky factorisation of the lower
  * triangle of A (n x n, leading dimension lda >= max(1, n)) at precision
  * `prec` (BF16, FP16, FP32 or FP64).  If *F is NULL a new handle is created;
  * a non-NULL *F from an earlier call is reused (its buffers are kept when they
@@ -96,7 +96,7 @@ void spd_opts_default(spd_opts *o);
 spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec,
                       const spd_opts *o, void *hip_stream, spd_factor_t *F, int64_t *info);
 
-/* A factor supplied by the caller in place of line 1 (the perturbed-factor
+/* A factor supplied by the caller in place of the factorisation (the perturbed-factor
  * experiment of Section 3.1, Fig. 3(b): a binary64 factor R = L^T perturbed
  * by E, then refined with Eq. (4) deciding convergence).  L: n x n,
  * column-major, leading dimension ldl >= max(1, n), device memory owned by
@@ -113,7 +113,7 @@ spd_status spd_factor(const double *A, int64_t n, int64_t lda, spd_prec prec,
 spd_status spd_factor_import(const double *L, int64_t n, int64_t ldl, spd_prec prec, void *hip_stream,
                              spd_factor_t *F, int64_t *info);
 
-/* Algorithm 1, line 2: X = L^{-T} L^{-1} B with the handle's low-precision
+/* Algorithm 1's first solve: X = L^{-T} L^{-1} B with the handle's low-precision
  * factor (binary32 substitution), including the equilibration scaling:
  * X = s mu D L^{-T} L^{-1} round32(D B / s), s a power of two per column.
  * B (n x nrhs, ldb >= n) is read; X (n x nrhs, ldx >= n) is written; X may
@@ -122,11 +122,11 @@ spd_status spd_factor_import(const double *L, int64_t n, int64_t ldl, spd_prec p
 spd_status spd_solve(spd_factor_t F, const double *B, int64_t ldb, int64_t nrhs,
                      double *X, int64_t ldx, void *hip_stream);
 
-/* Algorithm 1, lines 3-7: starting from the iterate in X (counted as one
+/* Algorithm 1's refinement loop: starting from the iterate in X (counted as one
  * low-precision solve), repeat
  * { R = B - A X (binary64); eta; Z = low-precision solve of R; X += Z }
- * until every column is accurate to binary64 level (the while-test of line 4
- * read so).  Per column, with zeta_k = ||z_k||_inf / ||x_{k+1}||_inf the size
+ * until every column is accurate to binary64 level (the loop's test read
+ * so).  Per column, with zeta_k = ||z_k||_inf / ||x_{k+1}||_inf the size
  * of correction k, rho_k = zeta_k / zeta_{k-1} its observed contraction and
  * eta_k the backward error of the residual it was solved from, a column is
  * done when eta <= o->tol and one of: eta = 0 or zeta_k <= 2^-53;
@@ -200,7 +200,7 @@ spd_status spd_posv(const double *A, int64_t n, int64_t lda, const double *B, in
                     int64_t nrhs, double *X, int64_t ldx, spd_prec prec, const spd_opts *o,
                     spd_report *rep, void *hip_stream, spd_factor_t *F);
 
-/* Algorithm 1, lines 3 and 7, on their own: R = B - A X in binary64 for the
+/* Algorithm 1's binary64 residual on its own: R = B - A X in binary64 for the
  * symmetric A (lower triangle read; n x n, lda >= n), X and B n x nrhs.
  * R (device, ldr >= n) receives the residual unless NULL; eta (HOST array of
  * nrhs, or NULL) receives the normwise backward errors

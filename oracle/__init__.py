@@ -225,7 +225,7 @@ def rne_bf16(x: float) -> float:
 
 
 def lowprec_factor(A, prec="fp32", equilibrate=True, theta=0.1):
-    """Line 1 of Algorithm 1 with its scaling, as ``ir`` forms it.  Returns
+    """The low-precision factorisation of Algorithm 1 with its scaling, as ``ir`` forms it.  Returns
     (L widened to binary64, d, mu, info): L is the factor of
     H = round32(mu D A D) (binary32 arithmetic; binary16/bfloat16 update
     operands), or of A itself for "fp64" (d = 1, mu = 1)."""
@@ -255,8 +255,9 @@ def ir(A, Bt, prec="fp32", equilibrate=True, theta=0.1, tol=1e-14, max_iter=10, 
 
 
 def ir_factor(A, L, Bt, prec="fp64", tol=1e-14, max_iter=10):
-    """Lines 2-7 of Algorithm 1 with a given lower-triangular factor L in place
-    of line 1 (the perturbed-factor experiment, Section 3.1, Fig. 3(b)):
+    """Algorithm 1 after its factorisation (first solve and refinement) with a
+    given lower-triangular factor L in place of its own (the perturbed-factor
+    experiment, Section 3.1, Fig. 3(b)):
     binary64 substitutions (prec "fp64") or L rounded to binary32 ("fp32"),
     no equilibration.  Returns (X as (m, n), IRReport)."""
     A = _colmajor(A)

@@ -20,13 +20,13 @@
  *   oracle_norm1_sym / oracle_backward_error  norms and eta
  *   oracle_rne_f16 / oracle_rne_bf16  binary32 -> binary16 / bfloat16 rounding
  *                    to nearest even, from the formats' definitions
- *   oracle_lowprec_factor  line 1 of Algorithm 1 with its scaling (d, mu) on
- *                    its own, for pins
+ *   oracle_lowprec_factor  Algorithm 1's low-precision factorisation with its
+ *                    scaling (d, mu) on its own, for pins
  *   oracle_ir        Algorithm 1 emulated step by step with a low-precision
  *                    factor (binary32, or binary16/bfloat16 operands with
  *                    binary32 accumulation) and binary64 residual/update.
- *   oracle_ir_factor lines 2-7 of Algorithm 1 with a given factor (the
- *                    perturbed-factor experiment, Fig. 3(b)).
+ *   oracle_ir_factor Algorithm 1 after its factorisation, with a given factor
+ *                    (the perturbed-factor experiment, Fig. 3(b)).
  *   oracle_cg_ir     Algorithm 2 (conjugate gradients with the matrix-vector
  *                    product in binary32 on a dense or banded copy of A,
  *                    everything else in binary64), restarted from a binary64
@@ -273,24 +273,24 @@ float oracle_rne_bf16(float x)
  *   scaling  D = diag(a_ii)^(-1/2) (for binary16/bfloat16/binary32 when
  *            `equil` is set), mu = largest power of two <= theta * 65504 for
  *            binary16 and 1 otherwise; H = round32(mu * D A D).
- *   line 1   low-precision factor H ~ L L^T: right-looking Cholesky in binary32
+ *   factor   low-precision factor H ~ L L^T: right-looking Cholesky in binary32
  *            arithmetic; for binary16/bfloat16 every update product uses the
  *            operands rounded to that format (binary32 accumulation).
  *            binary64 factors A itself in binary64.
- *   line 2   x = s mu D L^{-T} L^{-1} round32(D b / s), s a power of two
+ *   solve    x = s mu D L^{-T} L^{-1} round32(D b / s), s a power of two
  *            normalising max |D b| (per column); binary32 substitution.
- *   line 3   r = b - A x in binary64; eta per column as above.
- *   line 4   the loop ends when every column is done: eta <= tol and the
+ *   residual r = b - A x in binary64; eta per column as above.
+ *   test     the loop ends when every column is done: eta <= tol and the
  *            corrections show x accurate to binary64 level (the rule is
  *            stated above ir_loop).  Divergence (only while eta > tol): eta
  *            not finite, eta above the first eta, or two consecutive steps
  *            with eta_k > 0.9 eta_{k-1}.  At most `max_iter` corrections;
  *            without success by then, no convergence.
- *   line 5-7 z from the same low-precision solve of r; x += z (binary64);
+ *   correct  z from the same low-precision solve of r; x += z (binary64);
  *            new residual.
  *   fallback on breakdown or divergence: binary16/bfloat16 -> binary32 ->
  *            binary64 (if `fallback` is set).
- * Iteration counts: low = number of low-precision solves (incl. line 2),
+ * Iteration counts: low = number of low-precision solves (incl. the first),
  * high = number of binary64 residuals, both for the final precision.
  */
 typedef struct {
@@ -385,7 +385,7 @@ static int ir_loop(int64_t n, int64_t m, const double *A, int64_t lda, const dou
                    double *X, int64_t ldx, int prec, const double *d, double mu, const double *L64,
                    const float *L32, int stable, double tol, int max_iter, oracle_report *rep);
 
-/* Line 1 with its scaling: d (equilibration, 1 for binary64 or when `equil`
+/* The low-precision factorisation with its scaling: d (equilibration, 1 for binary64 or when `equil`
  * is off), mu, and the low-precision factor -- L64 (binary64, from A itself)
  * or L32 (binary32 factor of H = round32(mu D A D), update operands rounded
  * to binary16/bfloat16 for prec 1/0).  The caller frees *L64 / *L32.
@@ -420,7 +420,7 @@ static int64_t lowprec_factor(int64_t n, const double *A, int64_t lda, int prec,
     return potrf_lowprec(n, H, prec);
 }
 
-/* Line 1 on its own, for pins: the scaling and the low-precision factor as
+/* The factorisation on its own, for pins: the scaling and the low-precision factor as
  * ir_attempt forms them.  L (n x n, leading dimension ldl) receives the
  * factor widened to binary64 (lower triangle; zeros above), d the
  * equilibration, *mu the scale.  Returns the 1-based breakdown column, or 0
@@ -453,7 +453,7 @@ static int ir_attempt(int64_t n, int64_t m, const double *A, int64_t lda,
     rep->iters_low = rep->iters_high = 0;
     rep->eta = NAN;
 
-    /* line 1: low-precision factorisation */
+    /* the low-precision factorisation */
     rep->info = lowprec_factor(n, A, lda, prec, equil, theta, d, &mu, &L64, &L32);
     if (rep->info) {
         status = 2;
@@ -466,11 +466,12 @@ done:
     return status;
 }
 
-/* Lines 2-7 of Algorithm 1 with a given factor: L64 (binary64 solves) or
- * L32 (binary32 solves of the scaled right-hand side), D = diag(d), mu.
- * Line 2 (first solve, from r = b) and lines 5-6 (corrections) share one
- * routine: z = s mu D L^{-T} L^{-1} round(D r / s).  `stable`: the factor is
- * line 1's own binary64 factor (first solve accepted at eta <= tol).
+/* Algorithm 1 after its factorisation, with a given factor: L64 (binary64
+ * solves) or L32 (binary32 solves of the scaled right-hand side),
+ * D = diag(d), mu.  The first solve (from r = b) and the corrections share
+ * one routine: z = s mu D L^{-T} L^{-1} round(D r / s).  `stable`: the
+ * factor is the method's own binary64 factor (first solve accepted at
+ * eta <= tol).
  * Returns the status. */
 static int ir_loop(int64_t n, int64_t m, const double *A, int64_t lda, const double *B, int64_t ldb,
                    double *X, int64_t ldx, int prec, const double *d, double mu, const double *L64,
@@ -586,8 +587,8 @@ int32_t oracle_ir(int64_t n, int64_t m, const double *A, int64_t lda,
     }
 }
 
-/* Lines 2-7 of Algorithm 1 with the factor line 1 would have produced
- * replaced by a given lower-triangular L (n x n, leading dimension ldl): the
+/* Algorithm 1 after its factorisation, with the factor it would have
+ * produced replaced by a given lower-triangular L (n x n, leading dimension ldl): the
  * perturbed-factor experiment of Section 3.1 (Fig. 3(b)), where R = L^T
  * comes from a binary64 factorisation and is perturbed before use.  prec 3:
  * binary64 substitutions with L; prec 2: L rounded once to binary32 and the

@@ -300,7 +300,7 @@ def factor_import(L, prec="fp64", F: Factor | None = None, check=True):
 
 
 def solve(F: Factor, B, X=None):
-    """spd_solve (Algorithm 1, line 2).  Returns X."""
+    """spd_solve (Algorithm 1's first solve with the low-precision factor).  Returns X."""
     torch = _torch()
     n = F.query()["n"]
     pb, ldb, m = _rhs(B, n)
@@ -314,7 +314,7 @@ def solve(F: Factor, B, X=None):
 
 
 def refine(F: Factor, A, B, X, opts: Opts | None = None) -> Report:
-    """spd_refine (Algorithm 1, lines 3-7), X updated in place; returns the Report."""
+    """spd_refine (Algorithm 1's refinement loop), X updated in place; returns the Report."""
     pa, n, lda = _mat(A)
     pb, ldb, m = _rhs(B, n)
     px, ldx, _ = _rhs(X, n, "X")

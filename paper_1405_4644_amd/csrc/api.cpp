@@ -44,7 +44,7 @@ struct spd_factor_s {
     bool small_main = false; // a group's thin trailing updates on 64-tiles too (SPD_SMALL_MAIN=1)
     bool pinned = false;     // schedule fixed by the environment or the tuner: no cache lookup
     int upd_slots = 0;       // cap on the main-stream update's workgroups (SPD_UPD_SLOTS; 0: one per tile)
-    bool imported = false;   // the factor came from spd_factor_import (not line 1's own)
+    bool imported = false;   // the factor came from spd_factor_import (not the method's own factorisation)
     bool info_pending = false;  // spd_posv's factorisation: info not read back yet (read with the first residual)
     void *Lh = nullptr;      // two panel copies in that precision (npad x NB halves each)
     size_t cap_Lh = 0;
@@ -518,7 +518,8 @@ spd_status ensure_solve_ws(spd_factor_t F, int64_t m, hipStream_t st)
     return SPD_OK;
 }
 
-// Low-precision solve of (D R / s) and X (+)= s mu D Y  (Algorithm 1, lines 2, 5, 6).
+// Low-precision solve of (D R / s) and X (+)= s mu D Y: Algorithm 1's first solve,
+// and its correction solve with the update of x.
 // The scaling launch also clears the triangular solves' counters and, when
 // given, zero_next[0, nzero) (the next residual's norms).
 template <typename T>
@@ -592,7 +593,7 @@ int next_prec(int p) { return (p == SPD_BF16 || p == SPD_FP16) ? SPD_FP32 : SPD_
 //   residual).
 // The backward error alone does not decide: it reaches 1e-14, even 4u, while x
 // still misses 10 cond u along the eigenvectors of the smallest eigenvalues.
-// Line 1's own binary64 factor is backward stable: its first solve is
+// The method's own binary64 factor is backward stable: its first solve is
 // accepted at eta <= tol.  The iterate handed to the loop counts as a first
 // solve (zeta_0 = 1).
 constexpr double U64 = 0x1p-53;

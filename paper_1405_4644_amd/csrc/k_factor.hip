@@ -1,4 +1,4 @@
-// Factorisation kernels: Algorithm 1, line 1 (low-precision Cholesky).
+// Factorisation kernels: the low-precision Cholesky factorisation of Algorithm 1.
 //
 // Blocked right-looking Cholesky of H = mu D A D (binary32) or of A itself
 // (binary64), panel width NB, stored lower-triangular column-major in an

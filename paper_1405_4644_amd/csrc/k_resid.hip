@@ -1,5 +1,5 @@
 // Binary64 residual R = B - A X and the norms of the backward error
-// (Algorithm 1, lines 3 and 7: the "high precision" steps).
+// (Algorithm 1's residual steps, the ones it carries out in high precision).
 //
 // A is symmetric with only its lower triangle stored.  Workgroup (I, s) owns
 // the 64-row block I and visits the 64-column blocks J = s, s + S, ...; each

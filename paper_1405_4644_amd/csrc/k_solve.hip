@@ -1,5 +1,6 @@
-// Triangular solves with the low-precision factor (Eq. (3); Algorithm 1,
-// lines 2 and 5) and the binary64 scaling/update around them (line 6).
+// Triangular solves with the low-precision factor (Eq. (3); Algorithm 1's
+// first solve and correction solves) and the binary64 scaling and update of
+// x around them.
 //
 // A correction is z = s mu D L^{-T} L^{-1} round(D r / s): the right-hand
 // side is scaled by D and by a power of two s per column (so its largest

@@ -1,5 +1,5 @@
-// Trailing update of the blocked factorisation: Algorithm 1, line 1 (the
-// Schur complement update of the low-precision Cholesky factor),
+// Trailing update of the blocked factorisation in Algorithm 1's low-precision
+// Cholesky (the Schur complement update of the low-precision factor),
 //   H_ij -= L_ik L_jk^T   for the lower tiles of the trailing region,
 // on MFMA: binary32 (k_syrk_update_f32), binary64 (k_syrk_update<double>),
 // and binary16 / bfloat16 operands with binary32 accumulation

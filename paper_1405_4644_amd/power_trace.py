@@ -189,11 +189,11 @@ def main(argv=None):
     mon.phase("idle", lambda: time.sleep(0.05), W)
     if a.solver == "cholesky":
         F = spd.Factor()
-        mon.phase("factor (Algorithm 1, line 1)", lambda: spd.factor(A, prec=a.prec, F=F), W)
-        X0 = mon.phase("first solve (line 2)", lambda: spd.solve(F, B), W)
+        mon.phase("factor (Algorithm 1, low-precision Cholesky)", lambda: spd.factor(A, prec=a.prec, F=F), W)
+        X0 = mon.phase("first solve", lambda: spd.solve(F, B), W)
         X = torch.empty_like(X0)
         X.copy_(X0)
-        rep = mon.phase("refinement (lines 3-7)", lambda: spd.refine(F, A, B, X), W, reset=lambda: X.copy_(X0))
+        rep = mon.phase("refinement", lambda: spd.refine(F, A, B, X), W, reset=lambda: X.copy_(X0))
         F.close()
     else:
         H = spd.CG()

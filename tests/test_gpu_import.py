@@ -1,5 +1,5 @@
 """GPU parity of a caller-supplied factor (spd_factor_import) refined by
-Algorithm 1, lines 2-7: the perturbed-factor experiment of Section 3.1
+Algorithm 1 after its factorisation: the perturbed-factor experiment of Section 3.1
 (Fig. 3(b)) against the oracle's refinement with the same factor
 (oracle.ir_factor, pinned on the CPU by closed forms).
 

@@ -254,7 +254,7 @@ def test_separate_calls_match_posv(spd, orc):
     F, info, st = spd.factor(A, "fp32")
     X0 = spd.solve(F, B)
     x0 = host(X0).copy()
-    # line 2 alone: a binary32-accurate solution
+    # the first solve alone: a binary32-accurate solution
     Xo, _ = orc.solve(s.A, s.Bt)
     assert np.all(fwd_err(x0, Xo) <= 600 * U32 * 1e4)
     rep = spd.refine(F, A, B, X0)
@@ -281,7 +281,7 @@ def test_posv_many_rhs(spd, orc, prec, n, m):
 
 
 def test_solve_only_first_step_accuracy(spd, orc):
-    # Algorithm 1, line 2 alone with a binary64 factor: already binary64-accurate
+    # Algorithm 1's first solve alone with a binary64 factor: already binary64-accurate
     s = spdgen.system(777, 1e4, 4, config=0, index=4000)
     F, info, st = spd.factor(dev(s.A), "fp64")
     X = host(spd.solve(F, dev(s.Bt)))

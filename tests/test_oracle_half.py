@@ -1,4 +1,4 @@
-"""Pins for the oracle's binary16 / bfloat16 branch of Algorithm 1, line 1
+"""Pins for the oracle's binary16 / bfloat16 branch of Algorithm 1's factorisation
 (the low-precision factor with half-precision update operands and binary32
 accumulation, Section 3.1) and its scaling.
 
@@ -44,7 +44,7 @@ def test_no_scale_outside_fp16(orc, prec):
 
 
 def _two_by_two(a, fmt):
-    """Hand-expanded line 1 on H = mu [[1, a], [a, 1]] (no equilibration):
+    """Hand-expanded factorisation on H = mu [[1, a], [a, 1]] (no equilibration):
     l11 = sqrt(h11), l21 = h21 / l11 in binary32, then the update of h22
     with the operand l21 rounded to `fmt` and a binary32 product and
     difference, l22 = sqrt of that.  Rounding by numpy (binary16) or torch
@@ -93,7 +93,7 @@ def test_minij_fp16_factor_is_exact(orc):
 
 
 def test_minij_fp16_solution_exact_after_line_2(orc):
-    # with the exact factor and an integer solution (|b| < 2^24), line 2's
+    # with the exact factor and an integer solution (|b| < 2^24), the first solve's
     # binary32 substitutions are exact, so X is x_true and the first
     # residual is exactly zero: one solve, one residual
     n = 1024

@@ -214,7 +214,7 @@ def test_ir_factor_fp32_matches_own_factor_when_exact(orc):
     in binary32, and the binary32 factorisation reproduces it exactly (every
     pivot is 1, every subtraction exact).  Importing that factor rounded to
     binary32 (Section 3.1, Fig. 3(b) path) must then give bit for bit the
-    refinement of line 1's own binary32 factor without equilibration."""
+    refinement of the method's own binary32 factor without equilibration."""
     n = 40
     A = spdgen.minij(n)
     L = np.tril(np.ones((n, n)))
@@ -257,7 +257,7 @@ def test_success_needs_a_contracting_correction(orc):
     # a low-precision factor is never accepted on its first solve, even
     # when that solve happens to be backward stable to 1e-14: without a
     # correction there is no evidence of the error left (binary32 at cond 10,
-    # n = 8: eta after line 2 is about 1e-8 anyway; with tol = 1 the first
+    # n = 8: eta after the first solve is about 1e-8 anyway; with tol = 1 the first
     # eta passes the tolerance and one correction is still taken)
     s = spdgen.system(8, 10.0, 1, config=2, index=12)
     X, rep = orc.ir(s.A, s.Bt, prec="fp32", tol=1.0, fallback=False)

@@ -1,4 +1,4 @@
-"""spd_residual_noalloc (the residual of Algorithm 1, lines 3 and 7, for
+"""spd_residual_noalloc (the binary64 residual of Algorithm 1, for
 callers that cannot allocate) against spd_residual, through the C ABI: the
 same residual bit for bit and the same backward errors, on calls in a row
 with shrinking inputs (the static scratch keeps the previous call's

@@ -295,6 +295,20 @@ SPD_DEV void f32_update_tile(float *__restrict__ H, int64_t ld, int64_t k0, int 
                 cu[coff + 16 * ni + (16 * mi + q) * ldi] = -c[mi][ni][q];
 }
 
+// A last round's 64-tile (chunks of 64 columns) in a function of its own, so
+// that the 128-tile loop of the kernel keeps the register allocation and
+// schedule it has without it.  The pointers are re-derived in their address
+// spaces (global, shared), so the accesses stay GLOBAL and DS instructions.
+__device__ __attribute__((noinline)) void f32_update_tail_tile(float *H, int64_t ld, int64_t k0, int nbk,
+                                                               int64_t crow, int64_t ccol, float *As, float *Bs,
+                                                               int tid)
+{
+    H = (float *)gmem(H);
+    As = (float *)(__attribute__((address_space(3))) float *)As;
+    Bs = (float *)(__attribute__((address_space(3))) float *)Bs;
+    f32_update_tile<64, 64>(H, ld, k0, nbk, crow, ccol, As, Bs, tid);
+}
+
 // The binary32 update on TS x TS tiles (128, or 64 for the panel chain's
 // single tile columns and for launches with too few 128-tiles to fill the
 // chip).  Tiles are counted in TS units over the lower triangle of the
@@ -341,8 +355,8 @@ __global__ __launch_bounds__(256, 2) void k_syrk_update_f32(float *__restrict__ 
             const int qi = (s >> 1) & 1, qj = s & 1;
             if (ti == tj && qi < qj)
                 continue;  // above the diagonal
-            f32_update_tile<64, 64>(H, ld, k0, nbk, r0 + (int64_t)ti * 128 + 64 * qi, r0 + (int64_t)tj * 128 + 64 * qj,
-                                    As, Bs, tid);
+            f32_update_tail_tile(H, ld, k0, nbk, r0 + (int64_t)ti * 128 + 64 * qi, r0 + (int64_t)tj * 128 + 64 * qj, As,
+                                 Bs, tid);
         }
     }
 }
@@ -634,14 +648,17 @@ static int update_slots()
 
 // Whole rounds of 128-tiles over P workgroups (P = the cap, else every
 // resident slot); when the last round has at most P/2 tiles, those run as
-// 64-tiles inside the same launch (at most two per workgroup).  Returns the
-// tiles that run whole; *grid is the launch's workgroup count.
+// 64-tiles inside the same launch (at most two per workgroup).  An uncapped
+// launch of more than two rounds keeps one workgroup per tile: the hardware
+// hands tiles to slots as they free up, which balances better than fixed
+// rounds once other streams hold some slots.  Returns the tiles that run
+// whole; *grid is the launch's workgroup count.
 static int64_t update_split(int64_t ntiles, int64_t max_grid, int64_t *grid)
 {
     *grid = ((ntiles + 7) / 8) * 8;
     if (max_grid > 0 && *grid > max_grid) *grid = (max_grid / 8) * 8;
     const int slots = update_slots();
-    if (slots < 8) return ntiles;
+    if (slots < 8 || (max_grid <= 0 && ntiles > 2 * (int64_t)slots)) return ntiles;
     int64_t P = (max_grid > 0) ? std::min<int64_t>(max_grid, slots) : slots;
     P = (P / 8) * 8;
     if (P < 8) return ntiles;

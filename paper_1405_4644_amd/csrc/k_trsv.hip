@@ -585,7 +585,9 @@ int64_t trsv_scratch_elems(int64_t npad)
     return std::max<int64_t>(K * (K - 1) / 2, 1) * TRSV_NBS * TRSV_MC;
 }
 
-int trsv_ctl_ints(int64_t npad) { return 3 + 3 * solve_nblocks(npad); }
+// counters of one direction, padded to 256 bytes (a caller keeping one set
+// per direction back to back keeps each on lines of its own)
+int trsv_ctl_ints(int64_t npad) { return (3 + 3 * solve_nblocks(npad) + 63) & ~63; }
 
 template <typename T>
 void launch_build_winv(const T *L, int64_t ld, int64_t npad, const T *W128, T *WB, T *Tb, hipStream_t st)

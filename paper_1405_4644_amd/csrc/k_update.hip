@@ -9,6 +9,7 @@
 #include "internal.h"
 #include "half_ops.h"
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <type_traits>
 
@@ -634,16 +635,18 @@ static int update_slots()
         return e && std::atoi(e) == 0;
     }();
     if (off) return 0;
-    static int cache[64] = {0};
+    static std::atomic<int> cache[64];  // per device; threads that race store the same value
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-    if (!cache[dev]) {
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (!v) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             return 0;
-        cache[dev] = 2 * cus;
+        v = 2 * cus;
+        cache[dev].store(v, std::memory_order_relaxed);
     }
-    return cache[dev];
+    return v;
 }
 
 // Whole rounds of 128-tiles over P workgroups (P = the cap, else every

@@ -145,14 +145,15 @@ def test_auto_picks_oracle_argmax(spd):
 def test_trained_picker_against_fixed_precisions(spd):
     """The shipped network against the method without it, on held-out
     systems of the batched workload's distribution.  Each system is solved
-    at every precision (no fallback: the outcome table, labelled by the
-    oracle's rule from measured device time) and at every precision with the
-    fallback chain (what a caller pays).  Asserted: at most 10 % of the
-    picks are wrong, a wrong pick being one that does not converge or costs
-    more than 10 % over the labelled precision's time for that system (the
-    labels of near-ties between binary32 and binary64 go either way with a
-    few per cent of clock noise, so plain agreement is only reported), and
-    solving each system at its picked precision costs no more than the best
+    at every precision (no fallback, three times: the outcome table, each
+    system's time the least of the three, labelled by the oracle's rule) and
+    at every precision with the fallback chain (what a caller pays).
+    Asserted: at most 10 % of the picks are wrong, a wrong pick being one
+    that does not converge or costs more than 10 % over the labelled
+    precision's time for that system (the labels of near-ties between
+    binary32 and binary64 go either way with a few per cent of clock noise,
+    so plain agreement is only reported), and solving each system at its
+    picked precision costs no more than the best
     single precision for the whole batch (summed device time of the
     fallback runs, within 5 %).  The picker's own time is measured too (the
     AUTO call's device time minus that of its picks) and reported with the
@@ -174,10 +175,13 @@ def test_trained_picker_against_fixed_precisions(spd):
     ticks = np.zeros((bt.batch, 4))
     ticks_fb = np.zeros((bt.batch, 4))
     for k, p in enumerate(names):
-        bt.prec.fill_(spd.PREC[p])
-        spd.solve_batched(bt, nofb, ticks=tk)
-        conv[:, k] = bt.reports()["status"] == 0
-        ticks[:, k] = tk.cpu().numpy()
+        conv[:, k] = True
+        ticks[:, k] = np.inf
+        for _ in range(3):  # per-system minimum over repeats: co-resident workgroups perturb one run's clocks
+            bt.prec.fill_(spd.PREC[p])
+            spd.solve_batched(bt, nofb, ticks=tk)
+            conv[:, k] &= bt.reports()["status"] == 0
+            ticks[:, k] = np.minimum(ticks[:, k], tk.cpu().numpy())
         bt.prec.fill_(spd.PREC[p])
         spd.solve_batched(bt, ticks=tk)
         assert np.all(bt.reports()["status"] == 0)
@@ -199,8 +203,8 @@ def test_trained_picker_against_fixed_precisions(spd):
     best = min(cost_fixed, key=cost_fixed.get)
     cost_picks = float(ticks_fb[idx, picks].sum())
     disagree = float(np.mean(picks != labels))
-    # labels and costs come from per-system device clocks of separate runs
-    # (a few per cent of noise, and the label rule's own 2 % band)
+    # labels and costs come from per-system device clocks (a few per cent
+    # of noise left after the minimum, and the label rule's own 2 % band)
     wrong = ~conv[idx, picks] | (ticks[idx, picks] > 1.10 * ticks[idx, labels])
     _say("labels", np.bincount(labels, minlength=4), "picks", np.bincount(picks, minlength=4),
          "disagreement", disagree, "wrong picks", float(wrong.mean()),
